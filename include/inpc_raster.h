@@ -1,0 +1,220 @@
+/*
+ * inpc_raster.h -- C ABI of the MI355X (gfx950) point rasterizer of
+ * "A Bag of Tricks for Efficient Implicit Neural Point Clouds".
+ *
+ * What is computed (paper, Sec. 2 "Rendering Feature Maps", Sec. 3.2 and
+ * Appendix A): a point cloud with positions p_i, opacities o_i and feature
+ * vectors f_i is projected into a pinhole camera; every point becomes a
+ * bilinear 2x2 splat (weights summing to one) or, at inference, a small
+ * isotropic screen-space Gaussian (dilation variance 0.16, cut at 3 sigma);
+ * the fragments of every pixel are alpha-blended front to back in depth
+ * order (Eq. (1)) and composited with a background; the backward pass
+ * returns the exact gradients of Eq. (1), including zero-alpha fragments
+ * (Eq. (2) and the surrounding text).  The screen is cut into square tiles
+ * (Sec. 3.2 "Tiled Rendering"); each tile gets the list of points whose
+ * footprint meets it, ordered by (depth key, point index).
+ *
+ * Conventions for every entry point
+ *  - Array arguments are DEVICE pointers owned by the caller unless stated
+ *    otherwise.  The library never allocates or frees device memory and
+ *    keeps no device state between calls; the only scratch memory it uses
+ *    is the caller's workspace `ws` of at least inpc_workspace_bytes().
+ *  - Every call is asynchronous on `stream` (a hipStream_t passed as void*,
+ *    NULL = the null stream) and never synchronises, except
+ *    inpc_check_sync().
+ *  - Host-side argument checks run before any launch and return
+ *    INPC_ERR_INVALID (null pointer, n < 0, tile not 8/16/32, channels
+ *    outside [1, 64], non-positive image size, tile count not fitting 32
+ *    bits, workspace too small for n).  Launch failures return INPC_ERR_HIP;
+ *    inpc_last_error() then holds a message for the calling thread.
+ *  - Data-dependent capacity overflow (more tile copies than the workspace
+ *    holds, e.g. Gaussians larger than opts.max_radius) cannot be seen on
+ *    the host without a sync: the kernels set a flag in the workspace and
+ *    skip their work; inpc_check_sync() reports it as INPC_ERR_CAPACITY.
+ *  - Discrete decisions (culling, footprints, tile membership, sort keys)
+ *    use IEEE FP32 with one rounding per operation and no fused
+ *    multiply-add, so they are reproducible bit for bit.
+ *  - Layouts: positions [n][3], uv [n][2], features [n][C] (row per
+ *    point), images planar [C][H][W], per-pixel planes [H][W].
+ */
+#ifndef INPC_RASTER_H
+#define INPC_RASTER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t inpc_status_t;
+enum {
+    INPC_OK = 0,
+    INPC_ERR_INVALID = -1,     /* bad argument, detected on the host before any launch */
+    INPC_ERR_CAPACITY = -2,    /* workspace copy capacity exceeded (reported by inpc_check_sync) */
+    INPC_ERR_HIP = -3,         /* a HIP runtime call failed; see inpc_last_error() */
+    INPC_ERR_UNSUPPORTED = -4  /* valid but not implemented combination */
+};
+
+enum { INPC_SPLAT_BILINEAR = 0, INPC_SPLAT_GAUSSIAN = 1 };
+enum { INPC_F32 = 0, INPC_F16 = 1, INPC_BF16 = 2 };
+
+/* Pinhole camera, OpenCV axes (+z forward, +y down).  A world point p goes
+ * to camera space as X = R p + t (R row-major), then u = fx X/Z + cx,
+ * v = fy Y/Z + cy.  Pixel (x, y) covers [x, x+1) x [y, y+1).  Points with
+ * Z <= z_near (or NaN) are culled. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    float z_near;
+} inpc_camera_t;
+
+typedef struct {
+    int32_t splat;      /* INPC_SPLAT_BILINEAR or INPC_SPLAT_GAUSSIAN */
+    int32_t tile;       /* tile edge in pixels: 8, 16 or 32 (Sec. 3.2 uses 8) */
+    float t_min;        /* fragment k is blended iff the transmittance in front of it is >= t_min;
+                           0 blends every fragment (exact Eq. (1)); typical 1e-4 */
+    float dilation;     /* Gaussian: variance added to r^2 (paper: 0.16) */
+    float cutoff;       /* Gaussian: truncation in standard deviations (paper: 3) */
+    float max_radius;   /* Gaussian: largest radius_px any point may have; sizes the workspace */
+} inpc_opts_t;
+
+/* Bytes of workspace needed for n points with this camera and options.
+ * Worst case, no sync: bilinear splats make at most 4 tile copies per point,
+ * Gaussians at most the tile count of a (2 R + 1)^2 box with R from
+ * max_radius.  Returns 0 for invalid arguments. */
+size_t inpc_workspace_bytes(int64_t n, const inpc_camera_t* cam, const inpc_opts_t* opts);
+
+/* Bytes of the per-pixel forward state the backward pass reads (12 per pixel). */
+size_t inpc_state_bytes(const inpc_camera_t* cam);
+
+/* Number of tiles, ceil(W/T) * ceil(H/T); tile t covers columns
+ * [T (t mod ntx), ...) and rows [T (t div ntx), ...).  0 if invalid. */
+int64_t inpc_num_tiles(const inpc_camera_t* cam, const inpc_opts_t* opts);
+
+/*
+ * Step 1 -- project, cull, key (Sec. 2: points rasterized into a calibrated
+ * camera; Sec. 3.2: 32-bit depth keys).
+ *   pos      [n][3] f32 world positions
+ *   radius   [n] f32 Gaussian standard deviation in pixels (before
+ *            dilation), NULL for bilinear splats
+ *   uv       [n][2] f32 out: image coordinates
+ *   depth_key[n] u32 out: bit pattern of camera-space Z (monotone in Z > 0)
+ *   ntiles   [n] u32 out: tiles the footprint meets, 0 for culled points
+ * Also counts copies per tile into the workspace for step 2.
+ */
+inpc_status_t inpc_project(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
+                           const float* pos, const float* radius, float* uv,
+                           uint32_t* depth_key, uint32_t* ntiles, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/*
+ * Step 2 -- bin (Sec. 3.2 "Tiled Rendering": one copy of a point per tile
+ * its footprint meets).  Exclusive scan of the per-tile counts gathered by
+ * inpc_project into tile_ranges, then one (depth key, point index) copy per
+ * touched tile into the workspace buckets.
+ *   uv, radius, depth_key, ntiles: outputs of inpc_project
+ *   tile_ranges [num_tiles + 1] u32 out: tile t owns list[tile_ranges[t] ..
+ *               tile_ranges[t+1]); tile_ranges[num_tiles] = total copies M
+ */
+inpc_status_t inpc_bin(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
+                       const float* uv, const float* radius, const uint32_t* depth_key,
+                       const uint32_t* ntiles, uint32_t* tile_ranges, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/*
+ * Step 3 -- depth sort per tile (Sec. 3.2: depth-sorted per-tile lists).
+ * Sorts every tile's bucket by (depth key ascending, point index
+ * ascending) -- the same order the paper's split sort (stable depth sort,
+ * then stable tile sort) produces -- and writes the point indices.
+ *   n           the point count the workspace was prepared for by
+ *               inpc_project / inpc_bin
+ *   tile_ranges output of inpc_bin
+ *   list        [inpc_copy_capacity(n, cam, opts)] u32 out; the first
+ *               tile_ranges[num_tiles] entries are written
+ */
+inpc_status_t inpc_sort(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
+                        const uint32_t* tile_ranges, uint32_t* list, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* Copy capacity (list entries) of a workspace sized for n points. */
+int64_t inpc_copy_capacity(int64_t n, const inpc_camera_t* cam, const inpc_opts_t* opts);
+
+/*
+ * Step 4 -- blend forward (Eq. (1), front to back, then the background).
+ * For every pixel, the fragments of its tile's list in order: alpha = o w
+ * (w bilinear weight or Gaussian value), F += T alpha f, T *= 1 - alpha;
+ * stops before the first fragment whose T < t_min; finally F += T f_bg.
+ *   opacity    [n] f32 in [0, 1]
+ *   feat       [n][C] features, dtype INPC_F32 / INPC_F16 / INPC_BF16
+ *              (blending and accumulation are FP32 for every dtype)
+ *   bg         [C] f32 constant background features, or NULL (zero)
+ *   out        [C][H][W] f32 out: feature image
+ *   t_final    [H][W] f32 out: transmittance behind the last blended fragment
+ *   n_contrib  [H][W] u32 out: number of blended fragments
+ *   state      inpc_state_bytes() bytes out, read by inpc_blend_backward;
+ *              may be NULL when no backward pass follows
+ */
+inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
+                                 const float* uv, const float* radius, const float* opacity,
+                                 const void* feat, int32_t C, int32_t dtype, const float* bg,
+                                 const uint32_t* tile_ranges, const uint32_t* list, float* out,
+                                 float* t_final, uint32_t* n_contrib, void* state,
+                                 void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Step 5 -- blend backward (Appendix A, Eq. (2), with the sign of the
+ * background term that differentiating Eq. (1) gives, and without skipping
+ * zero-alpha fragments).  Replays every pixel's blended fragments back to
+ * front and accumulates, for loss L = sum G . F + sum G_T T_final:
+ *   dL/dalpha_k = T_k (G . f_k - G . B_k) - G_T T_k prod_{j>k} (1 - alpha_j),
+ * B_k the blend of everything behind fragment k including the background;
+ * then dL/df, dL/do = w dL/dalpha, dL/d(u,v) = o dw/d(u,v) dL/dalpha.
+ * Bilinear splats only (INPC_ERR_UNSUPPORTED for Gaussians).
+ *   ntiles, tile_ranges, list: from steps 1-3 (recomputed or kept)
+ *   t_final, state: from inpc_blend_forward with the same inputs
+ *   grad_out   [C][H][W] f32 dL/dF
+ *   grad_t     [H][W] f32 dL/dT_final, or NULL
+ *   grad_feat  [n][C] f32 out (FP32 for every feature dtype)
+ *   grad_opacity [n] f32 out
+ *   grad_uv    [n][2] f32 out (input of inpc_project_backward)
+ *   grad_bg    [C] f32 out, or NULL
+ * Every output element is written (zero for culled points).
+ */
+inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
+                                  const float* uv, const float* opacity, const void* feat,
+                                  int32_t C, int32_t dtype, const float* bg,
+                                  const uint32_t* ntiles, const uint32_t* tile_ranges,
+                                  const uint32_t* list, const float* t_final, const void* state,
+                                  const float* grad_out, const float* grad_t, float* grad_feat,
+                                  float* grad_opacity, float* grad_uv, float* grad_bg,
+                                  void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Step 6 -- project backward: dL/dX = G_u fx/Z, dL/dY = G_v fy/Z,
+ * dL/dZ = -(G_u fx X + G_v fy Y)/Z^2, dL/dp = R^T (dL/dX, dL/dY, dL/dZ);
+ * zero for culled points (ntiles == 0).
+ *   grad_uv [n][2] f32, grad_pos [n][3] f32 out
+ */
+inpc_status_t inpc_project_backward(const inpc_camera_t* cam, int64_t n, const float* pos,
+                                    const uint32_t* ntiles, const float* grad_uv,
+                                    float* grad_pos, void* stream);
+
+/* The only synchronising call: waits for `stream`, then returns
+ * INPC_ERR_CAPACITY if any kernel since the workspace was last reset (by
+ * inpc_project) ran out of copy capacity, INPC_OK otherwise. */
+inpc_status_t inpc_check_sync(void* ws, size_t ws_bytes, void* stream);
+
+/* Static description of a status code. */
+const char* inpc_status_string(inpc_status_t status);
+
+/* Message of the last INPC_ERR_INVALID / INPC_ERR_HIP on the calling thread. */
+const char* inpc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* INPC_RASTER_H */

@@ -1,0 +1,23 @@
+"""MI355X (gfx950) point rasterizer of "A Bag of Tricks for Efficient Implicit
+Neural Point Clouds": project, bin, per-tile depth sort, alpha blend (bilinear
+2x2 splats or screen-space Gaussians), and the backward pass, as HIP kernels
+behind a C ABI (include/inpc_raster.h).
+"""
+from . import _lib  # noqa: F401
+from .raster import (  # noqa: F401
+    Binning,
+    RasterSettings,
+    Workspace,
+    blend_backward,
+    blend_forward,
+    camera_struct,
+    check_capacity,
+    project_backward,
+    project_bin_sort,
+    rasterize,
+)
+
+__all__ = [
+    "Binning", "RasterSettings", "Workspace", "blend_backward", "blend_forward",
+    "camera_struct", "check_capacity", "project_backward", "project_bin_sort", "rasterize",
+]

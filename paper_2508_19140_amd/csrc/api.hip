@@ -1,0 +1,393 @@
+// C ABI of the rasterizer: argument checks, workspace layout, launches.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "common.h"
+#include "inpc_raster.h"
+#include "internal.h"
+
+namespace inpc {
+namespace {
+
+thread_local char g_err[512] = "";
+
+inpc_status_t fail(inpc_status_t st, const char* fmt, const char* what) {
+  snprintf(g_err, sizeof(g_err), fmt, what);
+  return st;
+}
+
+inpc_status_t hip_fail(hipError_t e, const char* where) {
+  snprintf(g_err, sizeof(g_err), "%s: %s", where, hipGetErrorString(e));
+  return INPC_ERR_HIP;
+}
+
+bool valid_cam(const inpc_camera_t* c) {
+  return c && c->width > 0 && c->height > 0 && c->width < 32767 && c->height < 32767 &&
+         isfinite(c->fx) && isfinite(c->fy) && isfinite(c->cx) && isfinite(c->cy);
+}
+
+bool valid_opts(const inpc_opts_t* o) {
+  return o && (o->tile == 8 || o->tile == 16 || o->tile == 32) &&
+         (o->splat == INPC_SPLAT_BILINEAR || o->splat == INPC_SPLAT_GAUSSIAN) &&
+         o->t_min >= 0.f && o->t_min <= 1.f &&
+         (o->splat == INPC_SPLAT_BILINEAR ||
+          (o->dilation >= 0.f && o->cutoff > 0.f && o->max_radius >= 0.f &&
+           isfinite(o->max_radius)));
+}
+
+int64_t num_tiles(const inpc_camera_t* c, const inpc_opts_t* o) {
+  const int64_t ntx = (c->width + o->tile - 1) / o->tile;
+  const int64_t nty = (c->height + o->tile - 1) / o->tile;
+  return ntx * nty;
+}
+
+// Most tiles a single point can touch.
+int64_t max_tiles_per_point(const inpc_camera_t* c, const inpc_opts_t* o) {
+  if (o->splat == INPC_SPLAT_BILINEAR) return 4;
+  const double R = (double)o->cutoff * sqrt((double)o->max_radius * o->max_radius + o->dilation);
+  const int64_t span = (int64_t)floor(2.0 * R + 1e-3) + 1;  // pixels per axis
+  const int64_t per_axis = (span + o->tile - 1) / o->tile + 1;
+  const int64_t ntx = (c->width + o->tile - 1) / o->tile, nty = (c->height + o->tile - 1) / o->tile;
+  return std::min(per_axis, ntx) * std::min(per_axis, nty);
+}
+
+int64_t copy_capacity(int64_t n, const inpc_camera_t* c, const inpc_opts_t* o) {
+  return n * max_tiles_per_point(c, o);
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t flags, tile_count, cursor, list_w, list_m, list_l, list_x, bkey, bidx, xkey, xidx, total;
+};
+
+Layout layout(int64_t n, const inpc_camera_t* c, const inpc_opts_t* o) {
+  const size_t nt = (size_t)num_tiles(c, o);
+  const size_t cap = (size_t)std::max<int64_t>(copy_capacity(n, c, o), 1);
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  L.flags = take(kFlagSlots * 4);
+  L.tile_count = take(nt * 4);
+  L.cursor = take(nt * 4);
+  L.list_w = take(nt * 4);
+  L.list_m = take(nt * 4);
+  L.list_l = take(nt * 4);
+  L.list_x = take(nt * 4);
+  L.bkey = take(cap * 4);
+  L.bidx = take(cap * 4);
+  L.xkey = take(cap * 4);
+  L.xidx = take(cap * 4);
+  L.total = off;
+  return L;
+}
+
+Ws make_ws(void* ws, int64_t n, const inpc_camera_t* c, const inpc_opts_t* o) {
+  const Layout L = layout(n, c, o);
+  char* b = static_cast<char*>(ws);
+  Ws w;
+  w.flags = reinterpret_cast<uint32_t*>(b + L.flags);
+  w.tile_count = reinterpret_cast<uint32_t*>(b + L.tile_count);
+  w.cursor = reinterpret_cast<uint32_t*>(b + L.cursor);
+  w.list_w = reinterpret_cast<uint32_t*>(b + L.list_w);
+  w.list_m = reinterpret_cast<uint32_t*>(b + L.list_m);
+  w.list_l = reinterpret_cast<uint32_t*>(b + L.list_l);
+  w.list_x = reinterpret_cast<uint32_t*>(b + L.list_x);
+  w.bkey = reinterpret_cast<uint32_t*>(b + L.bkey);
+  w.bidx = reinterpret_cast<uint32_t*>(b + L.bidx);
+  w.xkey = reinterpret_cast<uint32_t*>(b + L.xkey);
+  w.xidx = reinterpret_cast<uint32_t*>(b + L.xidx);
+  w.cap = (uint32_t)std::min<int64_t>(copy_capacity(n, c, o), 0xffffffffLL);
+  return w;
+}
+
+Cam to_cam(const inpc_camera_t* c) {
+  Cam k;
+  k.W = c->width;
+  k.H = c->height;
+  k.fx = c->fx; k.fy = c->fy; k.cx = c->cx; k.cy = c->cy;
+  memcpy(k.R, c->R, sizeof(k.R));
+  memcpy(k.t, c->t, sizeof(k.t));
+  k.z_near = c->z_near;
+  return k;
+}
+
+Opts to_opts(const inpc_camera_t* c, const inpc_opts_t* o) {
+  Opts k;
+  k.splat = o->splat;
+  k.T = o->tile;
+  k.ntx = (c->width + o->tile - 1) / o->tile;
+  k.nty = (c->height + o->tile - 1) / o->tile;
+  k.t_min = o->t_min;
+  k.dilation = o->dilation;
+  k.cutoff = o->cutoff;
+  return k;
+}
+
+// Common checks for entry points that take the workspace.
+inpc_status_t check_common(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
+                           const void* ws, size_t ws_bytes) {
+  if (!valid_cam(cam)) return fail(INPC_ERR_INVALID, "invalid camera%s", "");
+  if (!valid_opts(opts)) return fail(INPC_ERR_INVALID, "invalid options%s", "");
+  if (n < 0 || n > (int64_t)0x7fffffff) return fail(INPC_ERR_INVALID, "n out of range%s", "");
+  if (num_tiles(cam, opts) >= (int64_t)0xffffffffLL)
+    return fail(INPC_ERR_INVALID, "tile count does not fit 32 bits%s", "");
+  if (copy_capacity(n, cam, opts) > (int64_t)0xffffffffLL)
+    return fail(INPC_ERR_INVALID, "copy capacity does not fit 32 bits%s", "");
+  if (!ws) return fail(INPC_ERR_INVALID, "null %s", "workspace");
+  if (ws_bytes < layout(n, cam, opts).total)
+    return fail(INPC_ERR_INVALID, "workspace smaller than inpc_workspace_bytes()%s", "");
+  return INPC_OK;
+}
+
+#define REQUIRE(ptr, name) \
+  if (!(ptr)) return fail(INPC_ERR_INVALID, "null %s", name)
+
+}  // namespace
+}  // namespace inpc
+
+using namespace inpc;
+
+extern "C" {
+
+size_t inpc_workspace_bytes(int64_t n, const inpc_camera_t* cam, const inpc_opts_t* opts) {
+  if (n < 0 || !valid_cam(cam) || !valid_opts(opts)) return 0;
+  return layout(n, cam, opts).total;
+}
+
+size_t inpc_state_bytes(const inpc_camera_t* cam) {
+  if (!valid_cam(cam)) return 0;
+  return (size_t)cam->width * cam->height * 12;
+}
+
+int64_t inpc_num_tiles(const inpc_camera_t* cam, const inpc_opts_t* opts) {
+  if (!valid_cam(cam) || !valid_opts(opts)) return 0;
+  return num_tiles(cam, opts);
+}
+
+int64_t inpc_copy_capacity(int64_t n, const inpc_camera_t* cam, const inpc_opts_t* opts) {
+  if (n < 0 || !valid_cam(cam) || !valid_opts(opts)) return 0;
+  return copy_capacity(n, cam, opts);
+}
+
+inpc_status_t inpc_project(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
+                           const float* pos, const float* radius, float* uv,
+                           uint32_t* depth_key, uint32_t* ntiles, void* ws, size_t ws_bytes,
+                           void* stream) {
+  inpc_status_t st = check_common(cam, opts, n, ws, ws_bytes);
+  if (st != INPC_OK) return st;
+  if (n > 0) {
+    REQUIRE(pos, "pos");
+    REQUIRE(uv, "uv");
+    REQUIRE(depth_key, "depth_key");
+    REQUIRE(ntiles, "ntiles");
+    if (opts->splat == INPC_SPLAT_GAUSSIAN) REQUIRE(radius, "radius");
+  }
+  const Ws w = make_ws(ws, n, cam, opts);
+  hipError_t e = launch_project(to_cam(cam), to_opts(cam, opts), n, pos,
+                                opts->splat == INPC_SPLAT_GAUSSIAN ? radius : nullptr, uv,
+                                depth_key, ntiles, w, (hipStream_t)stream);
+  return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_project");
+}
+
+inpc_status_t inpc_bin(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
+                       const float* uv, const float* radius, const uint32_t* depth_key,
+                       const uint32_t* ntiles, uint32_t* tile_ranges, void* ws,
+                       size_t ws_bytes, void* stream) {
+  inpc_status_t st = check_common(cam, opts, n, ws, ws_bytes);
+  if (st != INPC_OK) return st;
+  REQUIRE(tile_ranges, "tile_ranges");
+  if (n > 0) {
+    REQUIRE(uv, "uv");
+    REQUIRE(depth_key, "depth_key");
+    REQUIRE(ntiles, "ntiles");
+    if (opts->splat == INPC_SPLAT_GAUSSIAN) REQUIRE(radius, "radius");
+  }
+  const Ws w = make_ws(ws, n, cam, opts);
+  hipError_t e = launch_bin(to_cam(cam), to_opts(cam, opts), n, uv,
+                            opts->splat == INPC_SPLAT_GAUSSIAN ? radius : nullptr, depth_key,
+                            ntiles, tile_ranges, w, (hipStream_t)stream);
+  return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_bin");
+}
+
+inpc_status_t inpc_sort(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
+                        const uint32_t* tile_ranges, uint32_t* list, void* ws, size_t ws_bytes,
+                        void* stream) {
+  inpc_status_t st = check_common(cam, opts, n, ws, ws_bytes);
+  if (st != INPC_OK) return st;
+  REQUIRE(tile_ranges, "tile_ranges");
+  REQUIRE(list, "list");
+  const Ws w = make_ws(ws, n, cam, opts);
+  hipError_t e = launch_sort(tile_ranges, w, list, num_tiles(cam, opts), (hipStream_t)stream);
+  return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_sort");
+}
+
+static inpc_status_t blend_checks(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
+                                  int32_t C, int32_t dtype, const void* ws, size_t ws_bytes) {
+  inpc_status_t st = check_common(cam, opts, n, ws, ws_bytes);
+  if (st != INPC_OK) return st;
+  if (C < 1 || C > 64) return fail(INPC_ERR_INVALID, "channels must be in [1, 64]%s", "");
+  if (dtype != INPC_F32 && dtype != INPC_F16 && dtype != INPC_BF16)
+    return fail(INPC_ERR_INVALID, "unknown feature dtype%s", "");
+  if (C > 32) return fail(INPC_ERR_UNSUPPORTED, "more than 32 channels%s", "");
+  if (opts->tile == 32) return fail(INPC_ERR_UNSUPPORTED, "blending with 32x32 tiles%s", "");
+  return INPC_OK;
+}
+
+inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
+                                 const float* uv, const float* radius, const float* opacity,
+                                 const void* feat, int32_t C, int32_t dtype, const float* bg,
+                                 const uint32_t* tile_ranges, const uint32_t* list, float* out,
+                                 float* t_final, uint32_t* n_contrib, void* state, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  inpc_status_t st = blend_checks(cam, opts, n, C, dtype, ws, ws_bytes);
+  if (st != INPC_OK) return st;
+  REQUIRE(tile_ranges, "tile_ranges");
+  REQUIRE(list, "list");
+  REQUIRE(out, "out");
+  REQUIRE(t_final, "t_final");
+  REQUIRE(n_contrib, "n_contrib");
+  if (n > 0) {
+    REQUIRE(uv, "uv");
+    REQUIRE(opacity, "opacity");
+    REQUIRE(feat, "feat");
+    if (opts->splat == INPC_SPLAT_GAUSSIAN) REQUIRE(radius, "radius");
+  }
+  const Ws w = make_ws(ws, n, cam, opts);
+  BlendArgs a;
+  memset(&a, 0, sizeof(a));
+  a.cam = to_cam(cam);
+  a.opts = to_opts(cam, opts);
+  a.n = n;
+  a.uv = uv;
+  a.radius = radius;
+  a.opacity = opacity;
+  a.feat = feat;
+  a.C = C;
+  a.dtype = dtype;
+  a.bg = bg;
+  a.ranges = tile_ranges;
+  a.list = list;
+  a.out = out;
+  a.t_final = t_final;
+  a.n_contrib = n_contrib;
+  if (state && opts->splat == INPC_SPLAT_BILINEAR) {
+    const size_t P = (size_t)cam->width * cam->height;
+    a.st_last = static_cast<uint32_t*>(state);
+    a.st_anchor = a.st_last + P;
+    a.st_tanchor = reinterpret_cast<float*>(a.st_anchor + P);
+  }
+  a.flags = w.flags;
+  hipError_t e = launch_blend_forward(a, (hipStream_t)stream);
+  return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_blend_forward");
+}
+
+inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
+                                  const float* uv, const float* opacity, const void* feat,
+                                  int32_t C, int32_t dtype, const float* bg,
+                                  const uint32_t* ntiles, const uint32_t* tile_ranges,
+                                  const uint32_t* list, const float* t_final, const void* state,
+                                  const float* grad_out, const float* grad_t, float* grad_feat,
+                                  float* grad_opacity, float* grad_uv, float* grad_bg, void* ws,
+                                  size_t ws_bytes, void* stream) {
+  inpc_status_t st = blend_checks(cam, opts, n, C, dtype, ws, ws_bytes);
+  if (st != INPC_OK) return st;
+  if (opts->splat != INPC_SPLAT_BILINEAR)
+    return fail(INPC_ERR_UNSUPPORTED, "backward of Gaussian splats%s", "");
+  REQUIRE(tile_ranges, "tile_ranges");
+  REQUIRE(list, "list");
+  REQUIRE(t_final, "t_final");
+  REQUIRE(state, "state");
+  REQUIRE(grad_out, "grad_out");
+  if (n > 0) {
+    REQUIRE(uv, "uv");
+    REQUIRE(opacity, "opacity");
+    REQUIRE(feat, "feat");
+    REQUIRE(ntiles, "ntiles");
+    REQUIRE(grad_feat, "grad_feat");
+    REQUIRE(grad_opacity, "grad_opacity");
+    REQUIRE(grad_uv, "grad_uv");
+  }
+  const Ws w = make_ws(ws, n, cam, opts);
+  BlendArgs a;
+  memset(&a, 0, sizeof(a));
+  a.cam = to_cam(cam);
+  a.opts = to_opts(cam, opts);
+  a.n = n;
+  a.uv = uv;
+  a.opacity = opacity;
+  a.feat = feat;
+  a.C = C;
+  a.dtype = dtype;
+  a.bg = bg;
+  a.ranges = tile_ranges;
+  a.list = list;
+  a.t_final = const_cast<float*>(t_final);
+  const size_t P = (size_t)cam->width * cam->height;
+  a.st_last = static_cast<uint32_t*>(const_cast<void*>(state));
+  a.st_anchor = a.st_last + P;
+  a.st_tanchor = reinterpret_cast<float*>(a.st_anchor + P);
+  a.ntiles = ntiles;
+  a.grad_out = grad_out;
+  a.grad_t = grad_t;
+  a.grad_feat = grad_feat;
+  a.grad_opacity = grad_opacity;
+  a.grad_uv = grad_uv;
+  a.grad_bg = grad_bg;
+  a.flags = w.flags;
+  hipError_t e = launch_blend_backward(a, (hipStream_t)stream);
+  return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_blend_backward");
+}
+
+inpc_status_t inpc_project_backward(const inpc_camera_t* cam, int64_t n, const float* pos,
+                                    const uint32_t* ntiles, const float* grad_uv,
+                                    float* grad_pos, void* stream) {
+  if (!valid_cam(cam)) return fail(INPC_ERR_INVALID, "invalid camera%s", "");
+  if (n < 0 || n > (int64_t)0x7fffffff) return fail(INPC_ERR_INVALID, "n out of range%s", "");
+  if (n > 0) {
+    REQUIRE(pos, "pos");
+    REQUIRE(ntiles, "ntiles");
+    REQUIRE(grad_uv, "grad_uv");
+    REQUIRE(grad_pos, "grad_pos");
+  }
+  hipError_t e = launch_project_backward(to_cam(cam), n, pos, ntiles, grad_uv, grad_pos,
+                                         (hipStream_t)stream);
+  return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_project_backward");
+}
+
+inpc_status_t inpc_check_sync(void* ws, size_t ws_bytes, void* stream) {
+  REQUIRE(ws, "workspace");
+  if (ws_bytes < kFlagSlots * 4) return fail(INPC_ERR_INVALID, "workspace too small%s", "");
+  uint32_t flag = 0;
+  hipError_t e = hipMemcpyAsync(&flag, ws, sizeof(flag), hipMemcpyDeviceToHost, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "inpc_check_sync");
+  if (flag) {
+    snprintf(g_err, sizeof(g_err), "tile copies exceeded the workspace capacity");
+    return INPC_ERR_CAPACITY;
+  }
+  return INPC_OK;
+}
+
+const char* inpc_status_string(inpc_status_t s) {
+  switch (s) {
+    case INPC_OK: return "ok";
+    case INPC_ERR_INVALID: return "invalid argument";
+    case INPC_ERR_CAPACITY: return "workspace capacity exceeded";
+    case INPC_ERR_HIP: return "HIP runtime error";
+    case INPC_ERR_UNSUPPORTED: return "unsupported combination";
+    default: return "unknown status";
+  }
+}
+
+const char* inpc_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -1,0 +1,499 @@
+// Per-tile alpha blending, forward and backward.
+//
+// One workgroup per tile, one thread per pixel (an 8x8 tile is exactly one
+// 64-wide wavefront).  The tile's depth-ordered list is consumed in chunks:
+// the chunk's points are staged in LDS, and for bilinear splats each point
+// sets its bit in the 64-bit "which points cover me" mask of the (at most
+// four) pixels it covers, so a pixel then visits only its own fragments, in
+// list order, by walking the set bits.  Gaussians cover most of a tile, so
+// there every pixel tests every staged point.
+//
+// Forward (Eq. (1) of the paper, Appendix A, then the background): per pixel
+// T = 1; for each fragment in order: stop if T < t_min; alpha = o w;
+// F += T alpha f; T *= 1 - alpha.  F += T f_bg at the end.  The transmittance
+// sequence is computed with one rounding per operation so that the
+// termination decision is reproducible.
+//
+// Backward (Eq. (2), with the background sign that differentiation gives
+// and without skipping zero-alpha fragments): per pixel the blended
+// fragments are replayed back to front.  T_k is recovered from the next
+// fragment's T by T_k = T_{k+1} / (1 - alpha_k), starting from the
+// transmittance the forward pass recorded in front of the last blended
+// fragment with T > 0 (so an alpha = 1 fragment never divides by zero).
+// The per-fragment terms land in per-(point, corner) LDS slots; one thread
+// per point then sums its corners, and the point's gradient is written with
+// plain stores when the point lies in this tile only, or added with
+// atomics otherwise.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "common.h"
+#include "internal.h"
+
+namespace inpc {
+namespace {
+
+template <typename FT>
+__device__ __forceinline__ float to_f32(FT v);
+template <>
+__device__ __forceinline__ float to_f32<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ float to_f32<__half>(__half v) { return __half2float(v); }
+template <>
+__device__ __forceinline__ float to_f32<__hip_bfloat16>(__hip_bfloat16 v) {
+  return __bfloat162float(v);
+}
+
+template <int T>
+struct TileGeom {
+  static constexpr int NTH = T * T;
+  static constexpr int CHUNK = NTH < 256 ? NTH : 256;
+  static constexpr int MW = CHUNK / 64;
+};
+
+constexpr int fpad(int CP) { return CP + 4; }  // LDS row stride of staged features
+
+__device__ __forceinline__ uint32_t pack_xy(int x0, int y0) {
+  return (uint32_t)(x0 + 1) | ((uint32_t)(y0 + 1) << 16);
+}
+__device__ __forceinline__ int unpack_x(uint32_t p) { return (int)(p & 0xffffu) - 1; }
+__device__ __forceinline__ int unpack_y(uint32_t p) { return (int)(p >> 16) - 1; }
+
+template <int CP, typename FT>
+__device__ __forceinline__ void stage_features(const FT* __restrict__ feat, uint32_t idx, int C,
+                                               float* __restrict__ dst) {
+  const FT* row = feat + (size_t)idx * C;
+#pragma unroll
+  for (int c = 0; c < CP; ++c) dst[c] = c < C ? to_f32<FT>(row[c]) : 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// Forward, bilinear splats
+// ---------------------------------------------------------------------------
+template <int T, int CP, typename FT>
+__global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear(BlendArgs a) {
+  using G = TileGeom<T>;
+  __shared__ float4 s_geo[G::CHUNK];
+  __shared__ float s_feat[G::CHUNK * fpad(CP)];
+  __shared__ unsigned long long s_mask[G::NTH * G::MW];
+  if (a.flags[kFlagOverflow]) return;
+
+  const int tid = threadIdx.x;
+  const uint32_t tile = blockIdx.x;
+  const int tx = (int)(tile % (uint32_t)a.opts.ntx), ty = (int)(tile / (uint32_t)a.opts.ntx);
+  const int lx = tid % T, ly = tid / T;
+  const int px = tx * T + lx, py = ty * T + ly;
+  const bool inside = px < a.cam.W && py < a.cam.H;
+  const uint32_t start = a.ranges[tile], end = a.ranges[tile + 1];
+  const FT* feat = reinterpret_cast<const FT*>(a.feat);
+  const float t_min = a.opts.t_min;
+
+  float F[CP];
+#pragma unroll
+  for (int c = 0; c < CP; ++c) F[c] = 0.f;
+  float Tr = 1.f, t_anchor = 1.f;
+  uint32_t cnt = 0, last = 0, anchor = 0;
+  bool done = !inside;
+
+  for (uint32_t base = start; base < end; base += G::CHUNK) {
+    if (__syncthreads_count(!done) == 0) break;
+    const uint32_t nh = min((uint32_t)G::CHUNK, end - base);
+    if (tid < G::CHUNK && (uint32_t)tid < nh) {
+      const uint32_t idx = a.list[base + tid];
+      const float2 p = reinterpret_cast<const float2*>(a.uv)[idx];
+      const Footprint f = bilinear_footprint(p.x, p.y, a.cam.W, a.cam.H);
+      s_geo[tid] = make_float4(f.a, f.b, a.opacity[idx], __uint_as_float(pack_xy(f.x0, f.y0)));
+      stage_features<CP, FT>(feat, idx, a.C, s_feat + tid * fpad(CP));
+    }
+#pragma unroll
+    for (int w = 0; w < G::MW; ++w) s_mask[tid * G::MW + w] = 0ull;
+    __syncthreads();
+    if (tid < G::CHUNK && (uint32_t)tid < nh) {
+      const uint32_t pk = __float_as_uint(s_geo[tid].w);
+      const int x0 = unpack_x(pk) - tx * T, y0 = unpack_y(pk) - ty * T;
+      const unsigned long long bit = 1ull << (tid & 63);
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          const int qx = x0 + dx, qy = y0 + dy;
+          if (qx >= 0 && qx < T && qy >= 0 && qy < T)
+            atomicOr(&s_mask[(qy * T + qx) * G::MW + (tid >> 6)], bit);
+        }
+    }
+    __syncthreads();
+    if (!done) {
+      for (int w = 0; w < G::MW && !done; ++w) {
+        unsigned long long m = s_mask[tid * G::MW + w];
+        while (m) {
+          const int j = __ffsll(m) - 1;
+          m &= m - 1;
+          const int kk = w * 64 + j;
+          const float4 g = s_geo[kk];
+          const uint32_t pk = __float_as_uint(g.w);
+          const int dx = px - unpack_x(pk), dy = py - unpack_y(pk);
+          const float wx = dx ? g.x : fsub(1.f, g.x);
+          const float wy = dy ? g.y : fsub(1.f, g.y);
+          const float al = fmul(g.z, fmul(wx, wy));
+          if (Tr < t_min) {
+            done = true;
+            break;
+          }
+          const float wt = Tr * al;
+          const float* fr = s_feat + kk * fpad(CP);
+#pragma unroll
+          for (int c = 0; c < CP; ++c) F[c] = fmaf(wt, fr[c], F[c]);
+          const uint32_t q = base - start + (uint32_t)kk + 1u;
+          if (Tr > 0.f) {
+            anchor = q;
+            t_anchor = Tr;
+          }
+          Tr = fmul(Tr, fsub(1.f, al));
+          ++cnt;
+          last = q;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!inside) return;
+  const int64_t P = (int64_t)a.cam.W * a.cam.H;
+  const int64_t p = (int64_t)py * a.cam.W + px;
+#pragma unroll
+  for (int c = 0; c < CP; ++c)
+    if (c < a.C) a.out[c * P + p] = a.bg ? fmaf(Tr, a.bg[c], F[c]) : F[c];
+  a.t_final[p] = Tr;
+  a.n_contrib[p] = cnt;
+  if (a.st_last) {
+    a.st_last[p] = last;
+    a.st_anchor[p] = anchor;
+    a.st_tanchor[p] = t_anchor;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward, screen-space Gaussians (inference)
+// ---------------------------------------------------------------------------
+template <int T, int CP, typename FT>
+__global__ __launch_bounds__(T* T) void k_blend_fwd_gauss(BlendArgs a) {
+  using G = TileGeom<T>;
+  __shared__ float4 s_g0[G::CHUNK];  // u, v, o, s2
+  __shared__ float4 s_g1[G::CHUNK];  // thr, packed (px0, py0), packed (px1, py1), -
+  __shared__ float s_feat[G::CHUNK * fpad(CP)];
+  if (a.flags[kFlagOverflow]) return;
+
+  const int tid = threadIdx.x;
+  const uint32_t tile = blockIdx.x;
+  const int tx = (int)(tile % (uint32_t)a.opts.ntx), ty = (int)(tile / (uint32_t)a.opts.ntx);
+  const int px = tx * T + tid % T, py = ty * T + tid / T;
+  const bool inside = px < a.cam.W && py < a.cam.H;
+  const uint32_t start = a.ranges[tile], end = a.ranges[tile + 1];
+  const FT* feat = reinterpret_cast<const FT*>(a.feat);
+  const float t_min = a.opts.t_min;
+  const float pxc = fadd((float)px, 0.5f), pyc = fadd((float)py, 0.5f);
+
+  float F[CP];
+#pragma unroll
+  for (int c = 0; c < CP; ++c) F[c] = 0.f;
+  float Tr = 1.f;
+  uint32_t cnt = 0;
+  bool done = !inside;
+
+  for (uint32_t base = start; base < end; base += G::CHUNK) {
+    if (__syncthreads_count(!done) == 0) break;
+    const uint32_t nh = min((uint32_t)G::CHUNK, end - base);
+    if (tid < G::CHUNK && (uint32_t)tid < nh) {
+      const uint32_t idx = a.list[base + tid];
+      const float2 p = reinterpret_cast<const float2*>(a.uv)[idx];
+      const Footprint f = gaussian_footprint(p.x, p.y, a.radius[idx], a.cam.W, a.cam.H,
+                                             a.opts.dilation, a.opts.cutoff);
+      s_g0[tid] = make_float4(p.x, p.y, a.opacity[idx], f.s2);
+      s_g1[tid] = make_float4(f.thr, __uint_as_float(pack_xy(f.px0, f.py0)),
+                              __uint_as_float(pack_xy(f.px1, f.py1)), 0.f);
+      stage_features<CP, FT>(feat, idx, a.C, s_feat + tid * fpad(CP));
+    }
+    __syncthreads();
+    if (!done) {
+      for (uint32_t kk = 0; kk < nh; ++kk) {
+        const float4 g1 = s_g1[kk];
+        const uint32_t lo = __float_as_uint(g1.y), hi = __float_as_uint(g1.z);
+        if (px < unpack_x(lo) || px > unpack_x(hi) || py < unpack_y(lo) || py > unpack_y(hi))
+          continue;
+        const float4 g0 = s_g0[kk];
+        const float dx = fsub(pxc, g0.x), dy = fsub(pyc, g0.y);
+        const float d2 = fadd(fmul(dx, dx), fmul(dy, dy));
+        if (!(d2 <= g1.x)) continue;
+        if (Tr < t_min) {
+          done = true;
+          break;
+        }
+        const float al = g0.z * expf(-0.5f * d2 / g0.w);
+        const float wt = Tr * al;
+        const float* fr = s_feat + kk * fpad(CP);
+#pragma unroll
+        for (int c = 0; c < CP; ++c) F[c] = fmaf(wt, fr[c], F[c]);
+        Tr = fmul(Tr, fsub(1.f, al));
+        ++cnt;
+      }
+    }
+    __syncthreads();
+  }
+  if (!inside) return;
+  const int64_t P = (int64_t)a.cam.W * a.cam.H;
+  const int64_t p = (int64_t)py * a.cam.W + px;
+#pragma unroll
+  for (int c = 0; c < CP; ++c)
+    if (c < a.C) a.out[c * P + p] = a.bg ? fmaf(Tr, a.bg[c], F[c]) : F[c];
+  a.t_final[p] = Tr;
+  a.n_contrib[p] = cnt;
+}
+
+// ---------------------------------------------------------------------------
+// Backward, bilinear splats
+// ---------------------------------------------------------------------------
+template <int T, int CP, typename FT>
+__global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
+  using G = TileGeom<T>;
+  __shared__ float4 s_geo[G::CHUNK];
+  __shared__ float s_feat[G::CHUNK * fpad(CP)];
+  __shared__ unsigned long long s_mask[G::NTH * G::MW];
+  __shared__ float2 s_acc[G::CHUNK * 4];    // per (point, corner): (T alpha, dL/dalpha)
+  __shared__ float s_G[G::NTH * fpad(CP)];  // dL/dF of every pixel of the tile
+  __shared__ uint32_t s_red[G::NTH / 64];
+  if (a.flags[kFlagOverflow]) return;
+
+  const int tid = threadIdx.x;
+  const uint32_t tile = blockIdx.x;
+  const int tx = (int)(tile % (uint32_t)a.opts.ntx), ty = (int)(tile / (uint32_t)a.opts.ntx);
+  const int lx = tid % T, ly = tid / T;
+  const int px = tx * T + lx, py = ty * T + ly;
+  const bool inside = px < a.cam.W && py < a.cam.H;
+  const uint32_t start = a.ranges[tile], end = a.ranges[tile + 1];
+  const uint32_t n = end - start;
+  const FT* feat = reinterpret_cast<const FT*>(a.feat);
+  const int64_t P = (int64_t)a.cam.W * a.cam.H;
+  const int64_t p = (int64_t)py * a.cam.W + px;
+  const int C = a.C;
+
+  float Gv[CP];
+  float gB = 0.f, GT = 0.f, Tf = 0.f, t_anchor = 0.f;
+  uint32_t last = 0, anchor = 0;
+#pragma unroll
+  for (int c = 0; c < CP; ++c) Gv[c] = (inside && c < C) ? a.grad_out[c * P + p] : 0.f;
+  if (inside) {
+    GT = a.grad_t ? a.grad_t[p] : 0.f;
+    last = a.st_last[p];
+    anchor = a.st_anchor[p];
+    t_anchor = a.st_tanchor[p];
+    Tf = a.t_final[p];
+    if (a.bg)
+      for (int c = 0; c < C; ++c) gB = fmaf(Gv[c], a.bg[c], gB);
+  }
+#pragma unroll
+  for (int c = 0; c < CP; ++c) s_G[tid * fpad(CP) + c] = Gv[c];
+
+  // background gradient: sum over pixels of T_final * G
+  if (a.grad_bg) {
+    for (int c = 0; c < C; ++c) {
+      float v = Tf * Gv[c];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if ((tid & 63) == 0) atomicAdd(&a.grad_bg[c], v);
+    }
+  }
+
+  // block maximum of `last`
+  uint32_t ml = last;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) ml = max(ml, (uint32_t)__shfl_xor((int)ml, o, 64));
+  if ((tid & 63) == 0) s_red[tid >> 6] = ml;
+  __syncthreads();
+  uint32_t maxlast = 0;
+#pragma unroll
+  for (int w = 0; w < G::NTH / 64; ++w) maxlast = max(maxlast, s_red[w]);
+
+  float Pi = 1.f, Tcur = 0.f;
+  const int nchunks = (int)((n + G::CHUNK - 1) / G::CHUNK);
+  for (int ci = nchunks - 1; ci >= 0; --ci) {
+    const uint32_t rb = (uint32_t)ci * G::CHUNK;  // relative base of the chunk
+    const uint32_t nh = min((uint32_t)G::CHUNK, n - rb);
+    const bool active = rb < maxlast;
+    uint32_t idx = 0;
+    bool single = false;
+    if (tid < G::CHUNK && (uint32_t)tid < nh) {
+      idx = a.list[start + rb + tid];
+      single = a.ntiles[idx] == 1;
+      if (active) {
+        const float2 pp = reinterpret_cast<const float2*>(a.uv)[idx];
+        const Footprint f = bilinear_footprint(pp.x, pp.y, a.cam.W, a.cam.H);
+        s_geo[tid] = make_float4(f.a, f.b, a.opacity[idx], __uint_as_float(pack_xy(f.x0, f.y0)));
+        stage_features<CP, FT>(feat, idx, C, s_feat + tid * fpad(CP));
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s_acc[tid * 4 + k] = make_float2(0.f, 0.f);
+    }
+    if (active) {
+#pragma unroll
+      for (int w = 0; w < G::MW; ++w) s_mask[tid * G::MW + w] = 0ull;
+    }
+    __syncthreads();
+    if (active && tid < G::CHUNK && (uint32_t)tid < nh) {
+      const uint32_t pk = __float_as_uint(s_geo[tid].w);
+      const int x0 = unpack_x(pk) - tx * T, y0 = unpack_y(pk) - ty * T;
+      const unsigned long long bit = 1ull << (tid & 63);
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          const int qx = x0 + dx, qy = y0 + dy;
+          if (qx >= 0 && qx < T && qy >= 0 && qy < T)
+            atomicOr(&s_mask[(qy * T + qx) * G::MW + (tid >> 6)], bit);
+        }
+    }
+    __syncthreads();
+    if (active && last > rb) {
+      for (int w = G::MW - 1; w >= 0; --w) {
+        unsigned long long m = s_mask[tid * G::MW + w];
+        const uint32_t wb = rb + (uint32_t)w * 64;  // relative position of bit 0
+        if (last <= wb) continue;
+        const uint32_t lim = last - wb;             // positions < last are blended
+        if (lim < 64) m &= (1ull << lim) - 1ull;
+        while (m) {
+          const int j = 63 - __clzll(m);
+          m &= ~(1ull << j);
+          const int kk = w * 64 + j;
+          const uint32_t q1 = wb + (uint32_t)j + 1u;  // one past the relative position
+          const float4 g = s_geo[kk];
+          const uint32_t pk = __float_as_uint(g.w);
+          const int dx = px - unpack_x(pk), dy = py - unpack_y(pk);
+          const float wx = dx ? g.x : fsub(1.f, g.x);
+          const float wy = dy ? g.y : fsub(1.f, g.y);
+          const float al = fmul(g.z, fmul(wx, wy));
+          const float om = fsub(1.f, al);
+          float Tk;
+          if (q1 > anchor)
+            Tk = 0.f;
+          else if (q1 == anchor)
+            Tk = t_anchor;
+          else
+            Tk = fdiv(Tcur, om);
+          const float* fr = s_feat + kk * fpad(CP);
+          float gf = 0.f;
+#pragma unroll
+          for (int c = 0; c < CP; ++c) gf = fmaf(Gv[c], fr[c], gf);
+          const float da = Tk * (gf - gB) - GT * Tk * Pi;
+          s_acc[kk * 4 + dy * 2 + dx] = make_float2(Tk * al, da);
+          gB = fmaf(al, gf, om * gB);
+          Pi = Pi * om;
+          Tcur = Tk;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < G::CHUNK && (uint32_t)tid < nh) {
+      float gfeat[CP];
+#pragma unroll
+      for (int c = 0; c < CP; ++c) gfeat[c] = 0.f;
+      float go = 0.f, gu = 0.f, gv = 0.f;
+      if (active) {
+        const float4 g = s_geo[tid];
+        const uint32_t pk = __float_as_uint(g.w);
+        const int x0 = unpack_x(pk) - tx * T, y0 = unpack_y(pk) - ty * T;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int dx = k & 1, dy = k >> 1;
+          const int qx = x0 + dx, qy = y0 + dy;
+          if (qx < 0 || qx >= T || qy < 0 || qy >= T) continue;
+          const float2 acc = s_acc[tid * 4 + k];
+          const float* gp = s_G + (qy * T + qx) * fpad(CP);
+#pragma unroll
+          for (int c = 0; c < CP; ++c) gfeat[c] = fmaf(acc.x, gp[c], gfeat[c]);
+          const float wx = dx ? g.x : 1.f - g.x;
+          const float wy = dy ? g.y : 1.f - g.y;
+          go = fmaf(wx * wy, acc.y, go);
+          gu = fmaf((dx ? 1.f : -1.f) * wy, acc.y, gu);
+          gv = fmaf((dy ? 1.f : -1.f) * wx, acc.y, gv);
+        }
+        gu *= g.z;
+        gv *= g.z;
+      }
+      float* dst = a.grad_feat + (size_t)idx * C;
+      if (single) {
+#pragma unroll
+        for (int c = 0; c < CP; ++c)
+          if (c < C) dst[c] = gfeat[c];
+        a.grad_opacity[idx] = go;
+        reinterpret_cast<float2*>(a.grad_uv)[idx] = make_float2(gu, gv);
+      } else if (active) {
+#pragma unroll
+        for (int c = 0; c < CP; ++c)
+          if (c < C && gfeat[c] != 0.f) atomicAdd(dst + c, gfeat[c]);
+        if (go != 0.f) atomicAdd(a.grad_opacity + idx, go);
+        if (gu != 0.f) atomicAdd(a.grad_uv + 2 * (size_t)idx, gu);
+        if (gv != 0.f) atomicAdd(a.grad_uv + 2 * (size_t)idx + 1, gv);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int T, int CP, typename FT>
+hipError_t fwd_launch(const BlendArgs& a, hipStream_t s) {
+  const int64_t nt = (int64_t)a.opts.ntx * a.opts.nty;
+  if (a.opts.splat == INPC_SPLAT_BILINEAR)
+    hipLaunchKernelGGL((k_blend_fwd_bilinear<T, CP, FT>), dim3((unsigned)nt), dim3(T * T), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_blend_fwd_gauss<T, CP, FT>), dim3((unsigned)nt), dim3(T * T), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int T, int CP, typename FT>
+hipError_t bwd_launch(const BlendArgs& a, hipStream_t s) {
+  const int64_t nt = (int64_t)a.opts.ntx * a.opts.nty;
+  hipLaunchKernelGGL((k_blend_bwd_bilinear<T, CP, FT>), dim3((unsigned)nt), dim3(T * T), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int T, typename FT, bool FWD>
+hipError_t dispatch_cp(const BlendArgs& a, hipStream_t s) {
+  if (a.C <= 4) return FWD ? fwd_launch<T, 4, FT>(a, s) : bwd_launch<T, 4, FT>(a, s);
+  if (a.C <= 8) return FWD ? fwd_launch<T, 8, FT>(a, s) : bwd_launch<T, 8, FT>(a, s);
+  if (a.C <= 16) return FWD ? fwd_launch<T, 16, FT>(a, s) : bwd_launch<T, 16, FT>(a, s);
+  return FWD ? fwd_launch<T, 32, FT>(a, s) : bwd_launch<T, 32, FT>(a, s);
+}
+
+template <typename FT, bool FWD>
+hipError_t dispatch_t(const BlendArgs& a, hipStream_t s) {
+  switch (a.opts.T) {
+    case 8: return dispatch_cp<8, FT, FWD>(a, s);
+    case 16: return dispatch_cp<16, FT, FWD>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <bool FWD>
+hipError_t dispatch(const BlendArgs& a, hipStream_t s) {
+  switch (a.dtype) {
+    case INPC_F32: return dispatch_t<float, FWD>(a, s);
+    case INPC_F16: return dispatch_t<__half, FWD>(a, s);
+    case INPC_BF16: return dispatch_t<__hip_bfloat16, FWD>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_blend_forward(const BlendArgs& a, hipStream_t s) {
+  if (a.opts.ntx == 0 || a.opts.nty == 0) return hipSuccess;
+  return dispatch<true>(a, s);
+}
+
+hipError_t launch_blend_backward(const BlendArgs& a, hipStream_t s) {
+  hipError_t e = launch_grad_init(a.n, a.C, a.ntiles, a.grad_feat, a.grad_opacity, a.grad_uv,
+                                  a.grad_bg, s);
+  if (e != hipSuccess) return e;
+  if (a.opts.ntx == 0 || a.opts.nty == 0) return hipSuccess;
+  return dispatch<false>(a, s);
+}
+
+}  // namespace inpc

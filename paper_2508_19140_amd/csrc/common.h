@@ -1,0 +1,167 @@
+// Device-side definitions shared by the rasterizer kernels.
+//
+// Decision arithmetic (projection, footprints, tile membership) is written
+// with explicitly rounded FP32 intrinsics so that the compiler can neither
+// fuse nor reorder it; the whole library is also built with
+// -ffp-contract=off.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "inpc_raster.h"
+
+namespace inpc {
+
+constexpr int kWave = 64;
+
+// Sort size classes (tile copy counts).
+constexpr uint32_t kSortCapW = 256;
+constexpr uint32_t kSortCapM = 2048;
+constexpr uint32_t kSortCapL = 16384;
+
+// Camera in kernel-argument form (by value).
+struct Cam {
+  int W, H;
+  float fx, fy, cx, cy;
+  float R[9];
+  float t[3];
+  float z_near;
+};
+
+struct Opts {
+  int splat;
+  int T;     // tile edge
+  int ntx, nty;
+  float t_min, dilation, cutoff;
+};
+
+// Workspace flag slots.
+enum : int {
+  kFlagOverflow = 0,
+  kFlagCountW = 1,   // tiles sorted by one wavefront (n <= 256)
+  kFlagCountM = 2,   // tiles sorted by a 256-thread block (n <= 2048)
+  kFlagCountL = 3,   // tiles sorted by a 1024-thread block (n <= 16384)
+  kFlagCountX = 4,   // larger tiles, sorted through global memory
+  kFlagSlots = 16
+};
+
+// Pointers into the caller's workspace.
+struct Ws {
+  uint32_t* flags;       // [kFlagSlots]
+  uint32_t* tile_count;  // [nt]   copies per tile (filled by project)
+  uint32_t* cursor;      // [nt]   scatter cursors
+  uint32_t* list_w;      // [nt]   tile ids per sort class
+  uint32_t* list_m;      // [nt]
+  uint32_t* list_l;      // [nt]
+  uint32_t* list_x;      // [nt]
+  uint32_t* bkey;        // [cap]  bucketed depth keys
+  uint32_t* bidx;        // [cap]  bucketed point indices
+  uint32_t* xkey;        // [cap]  ping-pong scratch for large tiles
+  uint32_t* xidx;        // [cap]
+  uint32_t cap;          // copy capacity
+};
+
+__device__ __forceinline__ float fmul(float a, float b) { return __fmul_rn(a, b); }
+__device__ __forceinline__ float fadd(float a, float b) { return __fadd_rn(a, b); }
+__device__ __forceinline__ float fsub(float a, float b) { return __fsub_rn(a, b); }
+__device__ __forceinline__ float fdiv(float a, float b) { return __fdiv_rn(a, b); }
+
+// Camera-space position and image coordinates of one point.
+struct Proj {
+  float X, Y, Z, u, v;
+  bool in_front;
+};
+
+__device__ __forceinline__ Proj project_point(const Cam& c, float x, float y, float z) {
+  Proj p;
+  p.X = fadd(fadd(fadd(fmul(c.R[0], x), fmul(c.R[1], y)), fmul(c.R[2], z)), c.t[0]);
+  p.Y = fadd(fadd(fadd(fmul(c.R[3], x), fmul(c.R[4], y)), fmul(c.R[5], z)), c.t[1]);
+  p.Z = fadd(fadd(fadd(fmul(c.R[6], x), fmul(c.R[7], y)), fmul(c.R[8], z)), c.t[2]);
+  p.in_front = p.Z > c.z_near;  // false for NaN
+  p.u = fadd(fmul(c.fx, fdiv(p.X, p.Z)), c.cx);
+  p.v = fadd(fmul(c.fy, fdiv(p.Y, p.Z)), c.cy);
+  return p;
+}
+
+// Pixel rectangle (inclusive, clipped to the image) that can hold a point's
+// fragments, plus the quantities the blend needs.
+struct Footprint {
+  bool visible;
+  int px0, py0, px1, py1;
+  // bilinear
+  int x0, y0;
+  float a, b;
+  // Gaussian
+  float s2, thr;
+};
+
+// Bilinear 2x2 splat: the four pixels whose centres surround (u, v).
+__device__ __forceinline__ Footprint bilinear_footprint(float u, float v, int W, int H) {
+  Footprint f;
+  const float Wf = (float)W, Hf = (float)H;
+  f.visible = (u >= -0.5f) && (u < fadd(Wf, 0.5f)) && (v >= -0.5f) && (v < fadd(Hf, 0.5f));
+  f.s2 = 0.f;
+  f.thr = 0.f;
+  if (!f.visible) {
+    f.px0 = f.py0 = 0; f.px1 = f.py1 = -1; f.x0 = f.y0 = 0; f.a = f.b = 0.f;
+    return f;
+  }
+  const float xs = fsub(u, 0.5f), ys = fsub(v, 0.5f);
+  const float fx0 = floorf(xs), fy0 = floorf(ys);
+  f.x0 = (int)fx0;
+  f.y0 = (int)fy0;
+  f.a = fsub(xs, fx0);
+  f.b = fsub(ys, fy0);
+  f.px0 = f.x0 < 0 ? 0 : f.x0;
+  f.py0 = f.y0 < 0 ? 0 : f.y0;
+  f.px1 = f.x0 + 1 > W - 1 ? W - 1 : f.x0 + 1;
+  f.py1 = f.y0 + 1 > H - 1 ? H - 1 : f.y0 + 1;
+  return f;
+}
+
+// Isotropic screen-space Gaussian with variance r^2 + dilation, truncated at
+// `cutoff` standard deviations.
+__device__ __forceinline__ Footprint gaussian_footprint(float u, float v, float r, int W, int H,
+                                                        float dilation, float cutoff) {
+  Footprint f;
+  f.x0 = f.y0 = 0;
+  f.a = f.b = 0.f;
+  const float s2 = fadd(fmul(r, r), dilation);
+  const float Rc = fmul(cutoff, __fsqrt_rn(s2));
+  const float xs = fsub(u, 0.5f), ys = fsub(v, 0.5f);
+  float lx = ceilf(fsub(xs, Rc)), hx = floorf(fadd(xs, Rc));
+  float ly = ceilf(fsub(ys, Rc)), hy = floorf(fadd(ys, Rc));
+  lx = lx < 0.f ? 0.f : lx;
+  ly = ly < 0.f ? 0.f : ly;
+  hx = hx > (float)(W - 1) ? (float)(W - 1) : hx;
+  hy = hy > (float)(H - 1) ? (float)(H - 1) : hy;
+  f.visible = (lx <= hx) && (ly <= hy);
+  if (!f.visible) {
+    f.px0 = f.py0 = 0; f.px1 = f.py1 = -1; f.s2 = f.thr = 0.f;
+    return f;
+  }
+  f.px0 = (int)lx; f.px1 = (int)hx;
+  f.py0 = (int)ly; f.py1 = (int)hy;
+  f.s2 = s2;
+  f.thr = fmul(fmul(cutoff, cutoff), s2);
+  return f;
+}
+
+__device__ __forceinline__ Footprint footprint(const Opts& o, const Cam& c, float u, float v,
+                                               float r) {
+  return o.splat == INPC_SPLAT_BILINEAR ? bilinear_footprint(u, v, c.W, c.H)
+                                        : gaussian_footprint(u, v, r, c.W, c.H, o.dilation,
+                                                             o.cutoff);
+}
+
+// Wave-wide helpers (wave64).
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+}  // namespace inpc

@@ -1,0 +1,59 @@
+// Host-side launchers shared between the kernel files and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace inpc {
+
+struct BlendArgs {
+  Cam cam;
+  Opts opts;
+  int64_t n;
+  const float* uv;
+  const float* radius;
+  const float* opacity;
+  const void* feat;
+  int C;
+  int dtype;
+  const float* bg;
+  const uint32_t* ranges;
+  const uint32_t* list;
+  // forward outputs
+  float* out;
+  float* t_final;
+  uint32_t* n_contrib;
+  uint32_t* st_last;    // [P] one past the tile-list position of the last blended fragment
+  uint32_t* st_anchor;  // [P] one past the position of the last blended fragment with T > 0
+  float* st_tanchor;    // [P] transmittance in front of that fragment
+  // backward
+  const uint32_t* ntiles;
+  const float* grad_out;
+  const float* grad_t;
+  float* grad_feat;
+  float* grad_opacity;
+  float* grad_uv;
+  float* grad_bg;
+  const uint32_t* flags;
+};
+
+hipError_t launch_clear(uint32_t* p, size_t n, hipStream_t s);
+hipError_t launch_project(const Cam& cam, const Opts& o, int64_t n, const float* pos,
+                          const float* radius, float* uv, uint32_t* key, uint32_t* ntiles,
+                          const Ws& ws, hipStream_t s);
+hipError_t launch_bin(const Cam& cam, const Opts& o, int64_t n, const float* uv,
+                      const float* radius, const uint32_t* key, const uint32_t* ntiles,
+                      uint32_t* ranges, const Ws& ws, hipStream_t s);
+hipError_t launch_sort(const uint32_t* ranges, const Ws& ws, uint32_t* list, int64_t nt,
+                       hipStream_t s);
+hipError_t launch_grad_init(int64_t n, int C, const uint32_t* ntiles, float* grad_feat,
+                            float* grad_opacity, float* grad_uv, float* grad_bg, hipStream_t s);
+hipError_t launch_blend_forward(const BlendArgs& a, hipStream_t s);
+hipError_t launch_blend_backward(const BlendArgs& a, hipStream_t s);
+hipError_t launch_project_backward(const Cam& cam, int64_t n, const float* pos,
+                                   const uint32_t* ntiles, const float* grad_uv, float* grad_pos,
+                                   hipStream_t s);
+
+}  // namespace inpc

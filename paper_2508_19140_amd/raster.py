@@ -1,0 +1,242 @@
+"""PyTorch front end of the HIP rasterizer.
+
+PyTorch provides device memory and the current stream; every step of the
+rasterizer runs in the HIP library (libinpc_raster.so) through the C ABI.
+
+    out, t_final, n_contrib = rasterize(pos, opacity, feat, camera)
+
+`rasterize` is differentiable with respect to positions, opacities, features
+and the background (bilinear splats).  The backward pass re-runs project /
+bin / sort instead of keeping the tile lists (set keep_lists=True to keep
+them), and reads only a 12-byte per-pixel state saved by the forward pass.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import NamedTuple, Optional
+
+import torch
+
+from . import _lib as L
+
+_DTYPES = {torch.float32: L.DTYPE_F32, torch.float16: L.DTYPE_F16, torch.bfloat16: L.DTYPE_BF16}
+
+
+@dataclasses.dataclass(frozen=True)
+class RasterSettings:
+    splat: str = "bilinear"     # or "gaussian" (forward only)
+    tile: int = 8               # 8, 16 or 32 pixels
+    t_min: float = 1e-4         # blend fragment k iff transmittance in front of it >= t_min
+    dilation: float = 0.16      # Gaussian dilation variance
+    cutoff: float = 3.0         # Gaussian truncation in standard deviations
+    max_radius: float = 3.0     # largest Gaussian radius (px); sizes the workspace
+    keep_lists: bool = False    # keep tile lists for the backward instead of recomputing
+
+    def opts(self) -> L.Opts:
+        splat = {"bilinear": L.SPLAT_BILINEAR, "gaussian": L.SPLAT_GAUSSIAN}[self.splat]
+        return L.make_opts(splat, self.tile, self.t_min, self.dilation, self.cutoff,
+                           self.max_radius)
+
+
+def camera_struct(cam) -> L.Camera:
+    """Accepts an object with width, height, fx, fy, cx, cy, R (3x3), t (3),
+    z_near attributes (for example scenes.Camera) or an L.Camera."""
+    if isinstance(cam, L.Camera):
+        return cam
+    R = torch.as_tensor(cam.R, dtype=torch.float32).reshape(-1).tolist()
+    t = torch.as_tensor(cam.t, dtype=torch.float32).reshape(-1).tolist()
+    return L.make_camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, R, t,
+                         getattr(cam, "z_near", 0.2))
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Workspace:
+    """Device scratch for one rasterizer: grown on demand, reused across calls."""
+
+    def __init__(self):
+        self.buf: Optional[torch.Tensor] = None
+
+    def get(self, n: int, cam: L.Camera, opts: L.Opts, device) -> torch.Tensor:
+        size = int(L.lib().inpc_workspace_bytes(n, ctypes.byref(cam), ctypes.byref(opts)))
+        if size == 0:
+            raise ValueError("invalid camera or rasterizer settings")
+        if self.buf is None or self.buf.numel() < size or self.buf.device != torch.device(device):
+            self.buf = None
+            self.buf = torch.empty(size, dtype=torch.uint8, device=device)
+        return self.buf
+
+
+_default_ws = {}
+
+
+def default_workspace(device) -> Workspace:
+    key = str(torch.device(device))
+    if key not in _default_ws:
+        _default_ws[key] = Workspace()
+    return _default_ws[key]
+
+
+class Binning(NamedTuple):
+    uv: torch.Tensor        # [n, 2] f32
+    key: torch.Tensor       # [n] depth keys (int32 storage of u32)
+    ntiles: torch.Tensor    # [n] tiles touched (int32 storage of u32), 0 = culled
+    ranges: torch.Tensor    # [num_tiles + 1] (int32 storage of u32)
+    list: torch.Tensor      # [copy capacity] point indices (int32 storage of u32)
+
+
+def project_bin_sort(pos: torch.Tensor, cam: L.Camera, opts: L.Opts, ws: torch.Tensor,
+                     radius: Optional[torch.Tensor] = None) -> Binning:
+    """Steps 1-3: project, bin into tiles, sort every tile by (depth, index)."""
+    dev = pos.device
+    n = pos.shape[0]
+    lib = L.lib()
+    nt = int(lib.inpc_num_tiles(ctypes.byref(cam), ctypes.byref(opts)))
+    cap = int(lib.inpc_copy_capacity(n, ctypes.byref(cam), ctypes.byref(opts)))
+    uv = torch.empty(n, 2, dtype=torch.float32, device=dev)
+    key = torch.empty(n, dtype=torch.int32, device=dev)
+    ntiles = torch.empty(n, dtype=torch.int32, device=dev)
+    ranges = torch.empty(nt + 1, dtype=torch.int32, device=dev)
+    lst = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    s = _stream(dev)
+    cb, ob = ctypes.byref(cam), ctypes.byref(opts)
+    wsb = ws.numel()
+    L.call("inpc_project", cb, ob, n, _p(pos), _p(radius), _p(uv), _p(key), _p(ntiles), _p(ws),
+           wsb, s)
+    L.call("inpc_bin", cb, ob, n, _p(uv), _p(radius), _p(key), _p(ntiles), _p(ranges), _p(ws),
+           wsb, s)
+    L.call("inpc_sort", cb, ob, n, _p(ranges), _p(lst), _p(ws), wsb, s)
+    return Binning(uv, key, ntiles, ranges, lst)
+
+
+def blend_forward(b: Binning, opacity, feat, cam: L.Camera, opts: L.Opts, ws: torch.Tensor,
+                  bg=None, radius=None, with_state=True):
+    """Step 4.  Returns out [C,H,W], t_final [H,W], n_contrib [H,W], state."""
+    dev = opacity.device
+    n, C = feat.shape
+    H, W = cam.height, cam.width
+    out = torch.empty(C, H, W, dtype=torch.float32, device=dev)
+    t_final = torch.empty(H, W, dtype=torch.float32, device=dev)
+    n_contrib = torch.empty(H, W, dtype=torch.int32, device=dev)
+    state = None
+    if with_state:
+        state = torch.empty(int(L.lib().inpc_state_bytes(ctypes.byref(cam))), dtype=torch.uint8,
+                            device=dev)
+    L.call("inpc_blend_forward", ctypes.byref(cam), ctypes.byref(opts), n, _p(b.uv), _p(radius),
+           _p(opacity), _p(feat), C, _DTYPES[feat.dtype], _p(bg), _p(b.ranges), _p(b.list),
+           _p(out), _p(t_final), _p(n_contrib), _p(state), _p(ws), ws.numel(), _stream(dev))
+    return out, t_final, n_contrib, state
+
+
+def blend_backward(b: Binning, opacity, feat, cam: L.Camera, opts: L.Opts, ws: torch.Tensor,
+                   t_final, state, grad_out, grad_t=None, bg=None):
+    """Step 5.  Returns grad_feat [n,C] f32, grad_opacity [n], grad_uv [n,2], grad_bg [C]|None."""
+    dev = opacity.device
+    n, C = feat.shape
+    grad_feat = torch.empty(n, C, dtype=torch.float32, device=dev)
+    grad_opacity = torch.empty(n, dtype=torch.float32, device=dev)
+    grad_uv = torch.empty(n, 2, dtype=torch.float32, device=dev)
+    grad_bg = torch.empty(C, dtype=torch.float32, device=dev) if bg is not None else None
+    L.call("inpc_blend_backward", ctypes.byref(cam), ctypes.byref(opts), n, _p(b.uv),
+           _p(opacity), _p(feat), C, _DTYPES[feat.dtype], _p(bg), _p(b.ntiles), _p(b.ranges),
+           _p(b.list), _p(t_final), _p(state), _p(grad_out), _p(grad_t), _p(grad_feat),
+           _p(grad_opacity), _p(grad_uv), _p(grad_bg), _p(ws), ws.numel(), _stream(dev))
+    return grad_feat, grad_opacity, grad_uv, grad_bg
+
+
+def project_backward(pos, b: Binning, cam: L.Camera, grad_uv):
+    """Step 6.  Returns grad_pos [n, 3]."""
+    grad_pos = torch.empty_like(pos)
+    L.call("inpc_project_backward", ctypes.byref(cam), pos.shape[0], _p(pos), _p(b.ntiles),
+           _p(grad_uv), _p(grad_pos), _stream(pos.device))
+    return grad_pos
+
+
+def check_capacity(ws: torch.Tensor):
+    """Synchronises the current stream and raises if a kernel ran out of copy capacity."""
+    L.call("inpc_check_sync", _p(ws), ws.numel(), _stream(ws.device))
+
+
+def _check_inputs(pos, opacity, feat, bg, radius, settings):
+    if not pos.is_cuda:
+        raise ValueError("rasterize runs on the GPU: inputs must be device tensors")
+    if pos.dtype != torch.float32 or pos.dim() != 2 or pos.shape[1] != 3:
+        raise ValueError("pos must be float32 [N, 3]")
+    n = pos.shape[0]
+    if opacity.dtype != torch.float32 or opacity.shape != (n,):
+        raise ValueError("opacity must be float32 [N]")
+    if feat.dim() != 2 or feat.shape[0] != n or feat.dtype not in _DTYPES:
+        raise ValueError("feat must be [N, C] float32 / float16 / bfloat16")
+    if bg is not None and (bg.dtype != torch.float32 or bg.shape != (feat.shape[1],)):
+        raise ValueError("bg must be float32 [C]")
+    if settings.splat == "gaussian":
+        if radius is None or radius.dtype != torch.float32 or radius.shape != (n,):
+            raise ValueError("Gaussian splats need radius float32 [N]")
+
+
+class _RasterizeFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, pos, opacity, feat, bg, radius, cam, settings, workspace):
+        opts = settings.opts()
+        ws = workspace.get(pos.shape[0], cam, opts, pos.device)
+        b = project_bin_sort(pos, cam, opts, ws, radius)
+        out, t_final, n_contrib, state = blend_forward(
+            b, opacity, feat, cam, opts, ws, bg, radius,
+            with_state=settings.splat == "bilinear")
+        ctx.cam, ctx.settings, ctx.workspace = cam, settings, workspace
+        ctx.has_bg = bg is not None
+        saved = [pos, opacity, feat, bg if bg is not None else torch.empty(0, device=pos.device),
+                 t_final, state if state is not None else torch.empty(0, device=pos.device)]
+        if settings.keep_lists:
+            saved += list(b)
+        ctx.save_for_backward(*saved)
+        ctx.mark_non_differentiable(n_contrib)
+        return out, t_final, n_contrib
+
+    @staticmethod
+    def backward(ctx, g_out, g_t, _g_n):
+        if ctx.settings.splat != "bilinear":
+            raise NotImplementedError("the backward pass covers bilinear splats")
+        saved = ctx.saved_tensors
+        pos, opacity, feat, bg, t_final, state = saved[:6]
+        bg = bg if ctx.has_bg else None
+        cam, opts = ctx.cam, ctx.settings.opts()
+        ws = ctx.workspace.get(pos.shape[0], cam, opts, pos.device)
+        if ctx.settings.keep_lists:
+            b = Binning(*saved[6:])
+        else:
+            b = project_bin_sort(pos, cam, opts, ws)
+        g_out = g_out.contiguous() if g_out is not None else torch.zeros(
+            feat.shape[1], cam.height, cam.width, device=pos.device)
+        g_t = g_t.contiguous() if g_t is not None else None
+        gf, go, guv, gbg = blend_backward(b, opacity, feat, cam, opts, ws, t_final, state, g_out,
+                                          g_t, bg)
+        gpos = project_backward(pos, b, cam, guv)
+        if feat.dtype != torch.float32:
+            gf = gf.to(feat.dtype)
+        return gpos, go, gf, gbg, None, None, None, None
+
+
+def rasterize(pos: torch.Tensor, opacity: torch.Tensor, feat: torch.Tensor, camera,
+              bg: Optional[torch.Tensor] = None, radius: Optional[torch.Tensor] = None,
+              settings: RasterSettings = RasterSettings(),
+              workspace: Optional[Workspace] = None):
+    """Render a feature image.
+
+    pos [N,3] f32, opacity [N] f32 in [0,1], feat [N,C] f32/f16/bf16,
+    bg [C] f32 or None, radius [N] f32 (Gaussian splats).
+    Returns out [C,H,W] f32, t_final [H,W] f32, n_contrib [H,W] int32.
+    """
+    _check_inputs(pos, opacity, feat, bg, radius, settings)
+    cam = camera_struct(camera)
+    ws = workspace if workspace is not None else default_workspace(pos.device)
+    return _RasterizeFn.apply(pos.contiguous(), opacity.contiguous(), feat.contiguous(),
+                              None if bg is None else bg.contiguous(),
+                              None if radius is None else radius.contiguous(), cam, settings, ws)

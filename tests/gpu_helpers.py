@@ -1,0 +1,100 @@
+"""Helpers for the GPU parity tests: run the HIP path step by step through
+the C ABI binding and compare against the CPU oracle."""
+import numpy as np
+import torch
+
+import oracle
+import paper_2508_19140_amd as inpc
+from paper_2508_19140_amd import _lib as L
+
+DEV = "cuda:0"
+
+
+def settings_opts(splat="bilinear", tile=8, t_min=1e-4, max_radius=3.0):
+    return inpc.RasterSettings(splat=splat, tile=tile, t_min=t_min, max_radius=max_radius)
+
+
+def run_gpu(scene, settings, bg=None, feat_dtype=torch.float32, backward=True, feat=None):
+    """All steps on the GPU; returns numpy copies of every intermediate."""
+    cam = inpc.camera_struct(scene.camera)
+    opts = settings.opts()
+    pos = torch.from_numpy(scene.pos).to(DEV)
+    op = torch.from_numpy(scene.opacity).to(DEV)
+    ft = torch.from_numpy(scene.feat if feat is None else feat).to(DEV).to(feat_dtype)
+    rad = None if scene.radius is None else torch.from_numpy(scene.radius).to(DEV)
+    bgt = None if bg is None else torch.as_tensor(bg, dtype=torch.float32, device=DEV)
+    ws = inpc.Workspace().get(pos.shape[0], cam, opts, DEV)
+    b = inpc.project_bin_sort(pos, cam, opts, ws, rad if settings.splat == "gaussian" else None)
+    out, tf, nc, state = inpc.blend_forward(b, op, ft, cam, opts, ws, bgt, rad,
+                                            with_state=settings.splat == "bilinear")
+    inpc.check_capacity(ws)
+    r = dict(uv=b.uv.cpu().numpy(), key=b.key.cpu().numpy().view(np.uint32),
+             ntiles=b.ntiles.cpu().numpy().view(np.uint32),
+             ranges=b.ranges.cpu().numpy().view(np.uint32), list=b.list.cpu().numpy().view(np.uint32),
+             out=out.cpu().numpy(), t_final=tf.cpu().numpy(), n_contrib=nc.cpu().numpy().view(np.uint32))
+    if backward and scene.grad is not None and settings.splat == "bilinear":
+        g = torch.from_numpy(scene.grad).to(DEV)
+        gt = None if scene.grad_t is None else torch.from_numpy(scene.grad_t).to(DEV)
+        gf, go, guv, gbg = inpc.blend_backward(b, op, ft, cam, opts, ws, tf, state, g, gt, bgt)
+        gpos = inpc.project_backward(pos, b, cam, guv)
+        torch.cuda.synchronize()
+        r.update(grad_feat=gf.cpu().numpy(), grad_opacity=go.cpu().numpy(),
+                 grad_uv=guv.cpu().numpy(), grad_pos=gpos.cpu().numpy(),
+                 grad_bg=None if gbg is None else gbg.cpu().numpy())
+    return r
+
+
+def run_oracle(scene, settings, bg=None, feat=None, backward=True):
+    splat = 0 if settings.splat == "bilinear" else 1
+    f = scene.feat if feat is None else feat
+    proj = oracle.project(scene.camera, scene.pos, scene.radius, splat=splat, tile=settings.tile)
+    tl = oracle.tile_lists(scene.camera, scene.pos, scene.radius, splat=splat, tile=settings.tile)
+    go = scene.grad if (backward and splat == 0) else None
+    rr = oracle.render(scene.camera, scene.pos, scene.opacity, f, radius=scene.radius, bg=bg,
+                       splat=splat, tile=settings.tile, t_min=settings.t_min, grad_out=go,
+                       grad_t=scene.grad_t if go is not None else None)
+    return proj, tl, rr
+
+
+def assert_binning_exact(g, proj, tl):
+    vis = proj["visible"]
+    np.testing.assert_array_equal(g["ntiles"] > 0, vis)
+    np.testing.assert_array_equal(g["ntiles"], proj["ntiles"])
+    np.testing.assert_array_equal(g["uv"][vis].view(np.uint32), proj["uv"][vis].view(np.uint32))
+    np.testing.assert_array_equal(g["key"][vis], proj["key"][vis])
+    np.testing.assert_array_equal(g["ranges"].astype(np.int64), tl["ranges"])
+    M = int(tl["ranges"][-1])
+    np.testing.assert_array_equal(g["list"][:M], tl["list"])
+
+
+def assert_close(name, gpu, ref, ref_abs, rel=1e-5, abs_=1e-6, mask=None):
+    gpu = np.asarray(gpu, np.float64)
+    ref = np.asarray(ref, np.float64)
+    ref_abs = np.asarray(ref_abs, np.float64)
+    if mask is not None:
+        gpu, ref, ref_abs = gpu[..., mask], ref[..., mask], ref_abs[..., mask]
+    ok, st = oracle.within_tolerance(gpu, ref, ref_abs, rel=rel, abs_=abs_)
+    assert st["n_bad"] == 0, f"{name}: {st}"
+    return st
+
+
+def assert_forward(g, rr, flags_ok=None):
+    mask = None if flags_ok is None else flags_ok
+    if mask is None:
+        np.testing.assert_array_equal(g["n_contrib"], rr["n_contrib"])
+    else:
+        np.testing.assert_array_equal(g["n_contrib"][mask], rr["n_contrib"][mask])
+    s1 = assert_close("out", g["out"], rr["out"], rr["out_abs"], mask=mask)
+    s2 = assert_close("t_final", g["t_final"], rr["t_final"], rr["t_final"], mask=mask)
+    return dict(out=s1, t_final=s2)
+
+
+def assert_backward(g, rr, grad_out=None):
+    st = {}
+    for k in ("grad_feat", "grad_opacity", "grad_uv", "grad_pos"):
+        st[k] = assert_close(k, g[k], rr[k], rr[k + "_abs"])
+    if rr.get("grad_bg") is not None:
+        # sum over pixels of T_final G: bounded by the sum of the magnitudes
+        mag = np.abs(rr["t_final"][None] * np.asarray(grad_out, np.float64)).sum(axis=(1, 2))
+        st["grad_bg"] = assert_close("grad_bg", g["grad_bg"], rr["grad_bg"], mag)
+    return st

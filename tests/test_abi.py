@@ -1,0 +1,118 @@
+"""The C ABI library loads, exports every function include/inpc_raster.h
+declares, and rejects bad arguments on the host before any launch (no GPU
+needed: every call here returns before touching the device)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2508_19140_amd import _lib as L
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "inpc_raster.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(inpc_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(L.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def cam(w=64, h=48):
+    return L.make_camera(w, h, 32.0, 32.0, w / 2, h / 2, [1, 0, 0, 0, 1, 0, 0, 0, 1], [0, 0, 0])
+
+
+def test_workspace_and_sizes():
+    lib = L.lib()
+    c, o = cam(), L.make_opts(tile=8)
+    assert lib.inpc_num_tiles(ctypes.byref(c), ctypes.byref(o)) == 8 * 6
+    assert lib.inpc_copy_capacity(1000, ctypes.byref(c), ctypes.byref(o)) == 4000
+    assert lib.inpc_state_bytes(ctypes.byref(c)) == 64 * 48 * 12
+    ws = lib.inpc_workspace_bytes(1000, ctypes.byref(c), ctypes.byref(o))
+    assert ws >= 4 * 4000 * 4
+    assert lib.inpc_workspace_bytes(2000, ctypes.byref(c), ctypes.byref(o)) > ws
+    # Gaussian capacity grows with the largest radius
+    g1 = L.make_opts(splat=L.SPLAT_GAUSSIAN, tile=8, max_radius=1.0)
+    g3 = L.make_opts(splat=L.SPLAT_GAUSSIAN, tile=8, max_radius=3.0)
+    assert lib.inpc_copy_capacity(10, ctypes.byref(c), ctypes.byref(g3)) > \
+        lib.inpc_copy_capacity(10, ctypes.byref(c), ctypes.byref(g1))
+    # invalid settings give 0
+    assert lib.inpc_workspace_bytes(10, ctypes.byref(c), ctypes.byref(L.make_opts(tile=12))) == 0
+    assert lib.inpc_workspace_bytes(-1, ctypes.byref(c), ctypes.byref(o)) == 0
+    assert lib.inpc_num_tiles(ctypes.byref(cam(0, 10)), ctypes.byref(o)) == 0
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: the calls fail before any launch
+
+
+@pytest.mark.parametrize("case", ["null_cam", "bad_tile", "neg_n", "null_ws", "small_ws",
+                                  "null_pos", "gauss_no_radius"])
+def test_project_rejects_bad_arguments(case):
+    lib = L.lib()
+    c, o = cam(), L.make_opts(tile=8)
+    n = 100
+    ws_bytes = lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(o))
+    args = dict(cam=ctypes.byref(c), opts=ctypes.byref(o), n=n, pos=FAKE, radius=None, uv=FAKE,
+                key=FAKE, ntiles=FAKE, ws=FAKE, ws_bytes=ws_bytes)
+    if case == "null_cam":
+        args["cam"] = None
+    elif case == "bad_tile":
+        args["opts"] = ctypes.byref(L.make_opts(tile=4))
+    elif case == "neg_n":
+        args["n"] = -5
+    elif case == "null_ws":
+        args["ws"] = None
+    elif case == "small_ws":
+        args["ws_bytes"] = ws_bytes - 1
+    elif case == "null_pos":
+        args["pos"] = None
+    elif case == "gauss_no_radius":
+        g = L.make_opts(splat=L.SPLAT_GAUSSIAN, max_radius=3.0)
+        args["opts"] = ctypes.byref(g)
+        args["ws_bytes"] = lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(g))
+    st = lib.inpc_project(*args.values(), None)
+    assert st == L.INPC_ERR_INVALID
+    assert lib.inpc_last_error()
+
+
+def test_blend_rejects_bad_channels_and_dtype():
+    lib = L.lib()
+    c, o = cam(), L.make_opts(tile=8)
+    n = 10
+    wsb = lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(o))
+    base = [ctypes.byref(c), ctypes.byref(o), n, FAKE, None, FAKE, FAKE]
+    tail = [None, FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, wsb, None]
+    assert lib.inpc_blend_forward(*base, 0, L.DTYPE_F32, *tail) == L.INPC_ERR_INVALID
+    assert lib.inpc_blend_forward(*base, 65, L.DTYPE_F32, *tail) == L.INPC_ERR_INVALID
+    assert lib.inpc_blend_forward(*base, 4, 7, *tail) == L.INPC_ERR_INVALID
+    assert lib.inpc_blend_forward(*base, 48, L.DTYPE_F32, *tail) == L.INPC_ERR_UNSUPPORTED
+
+
+def test_backward_rejects_gaussians():
+    lib = L.lib()
+    c = cam()
+    g = L.make_opts(splat=L.SPLAT_GAUSSIAN, max_radius=2.0)
+    n = 10
+    wsb = lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(g))
+    st = lib.inpc_blend_backward(ctypes.byref(c), ctypes.byref(g), n, FAKE, FAKE, FAKE, 4,
+                                 L.DTYPE_F32, None, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None,
+                                 FAKE, FAKE, FAKE, None, FAKE, wsb, None)
+    assert st == L.INPC_ERR_UNSUPPORTED
+
+
+def test_status_strings():
+    lib = L.lib()
+    for s in (L.INPC_OK, L.INPC_ERR_INVALID, L.INPC_ERR_CAPACITY, L.INPC_ERR_HIP,
+              L.INPC_ERR_UNSUPPORTED):
+        assert lib.inpc_status_string(s)

@@ -1,0 +1,175 @@
+"""GPU parity: the HIP path against the CPU oracle on the same seeded inputs.
+
+Binning, depth keys, per-tile counts and lists must match bit for bit;
+images and gradients within 1e-5 relative / 1e-6 absolute, where the
+relative part is taken against max(|oracle|, sum of the magnitudes of the
+terms the element accumulates)."""
+import numpy as np
+import pytest
+import torch
+
+from scenes import CONFIGS, SceneSpec, make_camera, make_scene, tiny_scene
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+from gpu_helpers import (  # noqa: E402
+    assert_backward, assert_binning_exact, assert_forward, run_gpu, run_oracle, settings_opts)
+
+
+def small_c2(n=1 << 17, W=320, H=180, seed=0, channels=16):
+    spec = SceneSpec(n=n, s=4.0, z_lo=2.0, z_hi=20.0, width=W, height=H, channels=channels,
+                     feat_dist="normal", opacity_range=(0.05, 0.95), with_grad=True, seed=seed)
+    return make_scene(spec)
+
+
+def test_c1_forward_full_config():
+    """50,000 points, 256x256, 4 channels, 8x8 tiles: every intermediate."""
+    sc = make_scene(CONFIGS["C1"])
+    st = settings_opts()
+    g = run_gpu(sc, st, backward=False)
+    proj, tl, rr = run_oracle(sc, st, backward=False)
+    assert_binning_exact(g, proj, tl)
+    assert_forward(g, rr)
+
+
+@pytest.mark.parametrize("tile", [8, 16])
+def test_c2_downscaled_forward_backward(tile):
+    sc = small_c2()
+    st = settings_opts(tile=tile)
+    g = run_gpu(sc, st)
+    proj, tl, rr = run_oracle(sc, st)
+    assert_binning_exact(g, proj, tl)
+    assert_forward(g, rr)
+    assert_backward(g, rr, sc.grad)
+
+
+def test_background_grad_t_and_exact_eq1():
+    """t_min = 0 (every fragment blended), constant background, dL/dT_final."""
+    sc = tiny_scene(3000, 77, 45, channels=5, seed=3, with_grad_t=True)
+    bg = np.array([0.5, -1.0, 0.25, 2.0, 0.0])
+    st = settings_opts(t_min=0.0)
+    g = run_gpu(sc, st, bg=bg)
+    proj, tl, rr = run_oracle(sc, st, bg=bg)
+    assert_binning_exact(g, proj, tl)
+    assert_forward(g, rr)
+    assert_backward(g, rr, sc.grad)
+
+
+def test_sort_size_classes_and_ties():
+    """Points packed into a few tiles (tiles beyond the 256 / 2048 / 16384
+    class limits) plus a fronto-parallel plane at one depth (long runs of
+    equal keys, resolved by point index)."""
+    rng = np.random.default_rng(5)
+    W, H = 48, 40
+    cam = make_camera(W, H, 24.0)
+    n_dense, n_plane, n_rest = 40000, 5000, 3000
+    z = rng.uniform(3.0, 5.0, n_dense)
+    u = rng.uniform(2.0, 14.0, n_dense)
+    v = rng.uniform(2.0, 14.0, n_dense)
+    dense = np.stack([(u - cam.cx) * z / cam.fx, (v - cam.cy) * z / cam.fy, z], 1)
+    zp = 4.0
+    up = rng.uniform(20.0, 40.0, n_plane)
+    vp = rng.uniform(20.0, 30.0, n_plane)
+    plane = np.stack([(up - cam.cx) * zp / cam.fx, (vp - cam.cy) * zp / cam.fy,
+                      np.full(n_plane, zp)], 1)
+    zr = rng.uniform(2.0, 8.0, n_rest)
+    ur = rng.uniform(-2, W + 2, n_rest)
+    vr = rng.uniform(-2, H + 2, n_rest)
+    rest = np.stack([(ur - cam.cx) * zr / cam.fx, (vr - cam.cy) * zr / cam.fy, zr], 1)
+    pos = np.concatenate([dense, plane, rest]).astype(np.float32)
+    perm = rng.permutation(len(pos))
+    pos = pos[perm]
+    from scenes import Scene
+    n = len(pos)
+    sc = Scene(pos=pos, opacity=rng.uniform(0.05, 0.95, n).astype(np.float32),
+               feat=rng.standard_normal((n, 3)).astype(np.float32), camera=cam,
+               grad=rng.standard_normal((3, H, W)).astype(np.float32))
+    for tile in (8, 16):
+        st = settings_opts(tile=tile)
+        g = run_gpu(sc, st)
+        proj, tl, rr = run_oracle(sc, st)
+        counts = np.diff(tl["ranges"])
+        if tile == 16:
+            assert counts.max() > 16384  # exercises the global-memory sort
+        assert (counts > 2048).any() and ((counts > 256) & (counts <= 2048)).any()
+        assert_binning_exact(g, proj, tl)
+        assert_forward(g, rr)
+        assert_backward(g, rr, sc.grad)
+
+
+@pytest.mark.parametrize("W,H,tile", [(37, 23, 8), (1, 1, 8), (129, 7, 16)])
+def test_ragged_images(W, H, tile):
+    sc = tiny_scene(800, W, H, channels=3, seed=W + H)
+    st = settings_opts(tile=tile)
+    g = run_gpu(sc, st)
+    proj, tl, rr = run_oracle(sc, st)
+    assert_binning_exact(g, proj, tl)
+    assert_forward(g, rr)
+    assert_backward(g, rr, sc.grad)
+
+
+def test_empty_and_culled():
+    st = settings_opts()
+    sc = tiny_scene(0, 16, 16, channels=2, seed=0)
+    g = run_gpu(sc, st)
+    assert (g["out"] == 0).all() and (g["t_final"] == 1).all() and (g["n_contrib"] == 0).all()
+    sc = tiny_scene(50, 16, 16, channels=2, seed=1)
+    sc.pos[:, 2] = -1.0  # behind the camera
+    sc.pos[:3] = np.nan
+    g = run_gpu(sc, st)
+    assert (g["ntiles"] == 0).all() and (g["out"] == 0).all()
+    assert (g["grad_feat"] == 0).all() and (g["grad_pos"] == 0).all()
+
+
+def test_alpha_one_occlusion():
+    """o = 1 at a pixel centre in front: the pixel is exactly its features."""
+    cam = make_camera(16, 16, 16.0)
+    u = v = 7.5
+    pos = np.array([[(u - 8) * z / 16, (v - 8) * z / 16, z] for z in (4.0, 2.0, 6.0)], np.float32)
+    from scenes import Scene
+    sc = Scene(pos=pos, opacity=np.array([0.7, 1.0, 0.4], np.float32),
+               feat=np.array([[1.0, 2.0], [0.25, -0.5], [3.0, 3.0]], np.float32), camera=cam,
+               grad=np.random.default_rng(0).standard_normal((2, 16, 16)).astype(np.float32))
+    st = settings_opts()
+    g = run_gpu(sc, st)
+    proj, tl, rr = run_oracle(sc, st)
+    np.testing.assert_array_equal(g["out"][:, 7, 7], [0.25, -0.5])
+    assert g["t_final"][7, 7] == 0.0 and g["n_contrib"][7, 7] == 1
+    assert_forward(g, rr)
+    assert_backward(g, rr, sc.grad)
+
+
+def test_gaussian_forward():
+    sc = tiny_scene(4000, 96, 64, channels=4, seed=11, radius_range=(0.5, 3.0))
+    for tile in (8, 16):
+        st = settings_opts(splat="gaussian", tile=tile)
+        g = run_gpu(sc, st, backward=False)
+        proj, tl, rr = run_oracle(sc, st, backward=False)
+        assert_binning_exact(g, proj, tl)
+        ok = rr["flags"] == 0  # pixels whose FP64 T sits on the t_min threshold are excluded
+        assert ok.mean() > 0.99
+        assert_forward(g, rr, flags_ok=ok)
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16])
+def test_mixed_precision_features(dtype):
+    """Features stored in 16 bits, FP32 blending: exact parity with the
+    oracle run on the same (quantised) features."""
+    sc = small_c2(n=1 << 16, channels=32)
+    q = torch.from_numpy(sc.feat).to(dtype).float().numpy()
+    st = settings_opts()
+    g = run_gpu(sc, st, feat_dtype=dtype)
+    proj, tl, rr = run_oracle(sc, st, feat=q)
+    assert_binning_exact(g, proj, tl)
+    assert_forward(g, rr)
+    assert_backward(g, rr, sc.grad)
+
+
+def test_forward_deterministic():
+    sc = small_c2(n=1 << 16)
+    st = settings_opts()
+    a = run_gpu(sc, st, backward=False)
+    b = run_gpu(sc, st, backward=False)
+    for k in ("list", "ranges", "out", "t_final", "n_contrib"):
+        np.testing.assert_array_equal(a[k], b[k])
