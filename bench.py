@@ -1,0 +1,280 @@
+"""Benchmark: forward + backward rasterization of 2^23 points at 1920x1080.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+One step is one training pass of the whole rasterizer on one view, exactly
+what rasterize(...) followed by .backward() runs:
+  forward : project -> bin -> sort -> blend forward
+  backward: project -> bin -> sort (lists recomputed, not stored)
+            -> blend backward -> project backward
+Inputs (a seeded synthetic scene shaped like the paper's view-specific
+clouds) are resident in HBM before the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="H", choices=["H", "C2"])
+    ap.add_argument("--tile", type=int, default=8)
+    ap.add_argument("--keep-lists", action="store_true",
+                    help="backward reuses the forward's tile lists instead of recomputing them")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="run only this many untimed steps (for rocprofv3) and exit")
+    return ap.parse_args()
+
+
+class Step:
+    """Preallocated buffers and the ABI calls of one fwd+bwd pass."""
+
+    def __init__(self, sc, tile, keep_lists, dev):
+        import torch
+        import paper_2508_19140_amd as inpc
+        from paper_2508_19140_amd import _lib as L
+        self.torch, self.L = torch, L
+        self.cam = inpc.camera_struct(sc.camera)
+        self.opts = inpc.RasterSettings(tile=tile).opts()
+        self.keep_lists = keep_lists
+        n, C = sc.feat.shape
+        self.n, self.C = n, C
+        self.pos = torch.from_numpy(sc.pos).to(dev)
+        self.op = torch.from_numpy(sc.opacity).to(dev)
+        self.feat = torch.from_numpy(sc.feat).to(dev)
+        self.grad = torch.from_numpy(sc.grad).to(dev)
+        lib = L.lib()
+        cb, ob = ctypes.byref(self.cam), ctypes.byref(self.opts)
+        self.cb, self.ob = cb, ob
+        nt = int(lib.inpc_num_tiles(cb, ob))
+        cap = int(lib.inpc_copy_capacity(n, cb, ob))
+        self.nt = nt
+        wsb = int(lib.inpc_workspace_bytes(n, cb, ob))
+        self.ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        H, W = sc.camera.height, sc.camera.width
+        self.P = H * W
+        i32 = torch.int32
+        mk = lambda *s, dt=torch.float32: torch.empty(*s, dtype=dt, device=dev)
+        self.uv, self.key, self.ntiles = mk(n, 2), mk(n, dt=i32), mk(n, dt=i32)
+        self.ranges, self.list = mk(nt + 1, dt=i32), mk(cap, dt=i32)
+        self.out, self.tf, self.nc = mk(C, H, W), mk(H, W), mk(H, W, dt=i32)
+        self.state = mk(int(lib.inpc_state_bytes(cb)), dt=torch.uint8)
+        self.gf, self.go, self.guv, self.gpos = mk(n, C), mk(n), mk(n, 2), mk(n, 3)
+        self.scratch = mk(int(lib.inpc_backward_scratch_bytes(n, C, cb, ob)), dt=torch.uint8)
+        self.lib = lib
+        p = lambda t: ctypes.c_void_p(t.data_ptr())
+        self.p = p
+        self.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def _chk(self, st, name):
+        if st != 0:
+            raise RuntimeError(f"{name}: {self.lib.inpc_last_error().decode()}")
+
+    def project(self):
+        p, lib = self.p, self.lib
+        self._chk(lib.inpc_project(self.cb, self.ob, self.n, p(self.pos), None, p(self.uv),
+                                   p(self.key), p(self.ntiles), p(self.ws), self.ws.numel(),
+                                   self.stream), "project")
+
+    def bin(self):
+        p, lib = self.p, self.lib
+        self._chk(lib.inpc_bin(self.cb, self.ob, self.n, p(self.uv), None, p(self.key),
+                               p(self.ntiles), p(self.ranges), p(self.ws), self.ws.numel(),
+                               self.stream), "bin")
+
+    def sort(self):
+        p, lib = self.p, self.lib
+        self._chk(lib.inpc_sort(self.cb, self.ob, self.n, p(self.ranges), p(self.list), p(self.ws),
+                                self.ws.numel(), self.stream), "sort")
+
+    def blend_fwd(self):
+        p, lib = self.p, self.lib
+        self._chk(lib.inpc_blend_forward(self.cb, self.ob, self.n, p(self.uv), None, p(self.op),
+                                         p(self.feat), self.C, 0, None, p(self.ranges),
+                                         p(self.list), p(self.out), p(self.tf), p(self.nc),
+                                         p(self.state), p(self.ws), self.ws.numel(), self.stream),
+                  "blend_forward")
+
+    def blend_bwd(self):
+        p, lib = self.p, self.lib
+        self._chk(lib.inpc_blend_backward(self.cb, self.ob, self.n, p(self.uv), p(self.op),
+                                          p(self.feat), self.C, 0, None, p(self.ntiles),
+                                          p(self.ranges), p(self.list), p(self.tf), p(self.state),
+                                          p(self.grad), None, p(self.gf), p(self.go), p(self.guv),
+                                          None, p(self.scratch), self.scratch.numel(), p(self.ws),
+                                          self.ws.numel(), self.stream),
+                  "blend_backward")
+
+    def project_bwd(self):
+        p, lib = self.p, self.lib
+        self._chk(lib.inpc_project_backward(self.cb, self.n, p(self.pos), p(self.ntiles),
+                                            p(self.guv), p(self.gpos), self.stream),
+                  "project_backward")
+
+    def phases(self):
+        fwd = [("project", self.project), ("bin", self.bin), ("sort", self.sort),
+               ("blend_fwd", self.blend_fwd)]
+        bwd = [] if self.keep_lists else [("project", self.project), ("bin", self.bin),
+                                          ("sort", self.sort)]
+        bwd += [("blend_bwd", self.blend_bwd), ("project_bwd", self.project_bwd)]
+        return fwd + bwd
+
+    def run(self):
+        for _, f in self.phases():
+            f()
+
+
+def byte_models(n, V, M, P, C, nt, bf=4):
+    """Algorithmic bytes: the B_min / B_method models and per-kernel minima."""
+    D = M / max(V, 1)
+    b_min = 2 * n * (16 + C * bf) + n * (16 + 4 * C) + 12 * D * V + 8 * P * (C + 1)
+    b_sort = 64 * V + 24 * D * V
+    per_kernel = {
+        # read positions, write uv + key + ntiles
+        "project": 12 * n + 16 * n,
+        # read ntiles, uv and key of visible points; write one (key, index) copy per tile
+        "bin": 4 * n + 12 * V + 8 * M + 8 * nt,
+        # read the bucket, write the list
+        "sort": 8 * M + 4 * M + 4 * nt,
+        # list + point data once + image, t_final, n_contrib and state written
+        "blend_fwd": 4 * M + 4 * nt + V * (12 + C * bf) + P * (4 * C + 20),
+        # list + point data + ntiles once + G, t_final, state read + gradients written
+        "blend_bwd": 4 * M + 4 * nt + V * (16 + C * bf) + P * (4 * C + 16) + n * (4 * C + 12),
+        # positions, ntiles, grad_uv read; grad_pos written
+        "project_bwd": 12 * n + 4 * n + 8 * n + 12 * n,
+    }
+    return b_min, b_min + 2 * b_sort, per_kernel
+
+
+def cpu_baseline(sc):
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    oracle.render(sc.camera, sc.pos, sc.opacity, sc.feat, grad_out=sc.grad)
+    dt = time.perf_counter() - t0
+    return {"value": sc.n / dt, "unit": "points/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"one full fwd+bwd frame of the same scene ({sc.n} points, "
+                      f"{sc.camera.width}x{sc.camera.height}, C={sc.feat.shape[1]}), "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU: the rasterizer shards by view, one view per GPU, "
+              "and this build measures the single-GPU path only (--gpus 1).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from scenes import CONFIGS, make_scene
+
+    spec = CONFIGS[args.config]
+    sc = make_scene(spec)
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    step = Step(sc, args.tile, args.keep_lists, dev)
+
+    if args.profile_steps:
+        for _ in range(args.profile_steps):
+            step.run()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_steps": args.profile_steps}), flush=True)
+        return
+
+    for _ in range(args.warmup):
+        step.run()
+    torch.cuda.synchronize()
+    # whole-step timing
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+
+    # per-phase timing (HIP events on the library's stream, between calls)
+    names = [nm for nm, _ in step.phases()]
+    acc = {}
+    reps = max(3, min(args.steps, 10))
+    for _ in range(reps):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+        evs[0].record()
+        for i, (nm, f) in enumerate(step.phases()):
+            f()
+            evs[i + 1].record()
+        torch.cuda.synchronize()
+        for i, nm in enumerate(names):
+            acc.setdefault(nm, []).append(evs[i].elapsed_time(evs[i + 1]))
+    phase_ms = {}
+    for i, nm in enumerate(names):
+        phase_ms[nm] = phase_ms.get(nm, 0.0) + float(np.median(acc[nm]))
+
+    ntiles = step.ntiles.cpu().numpy()
+    V = int((ntiles > 0).sum())
+    M = int(step.ranges[-1].item())
+    n, C, P = step.n, step.C, step.P
+    b_min, b_method, per_kernel = byte_models(n, V, M, P, C, step.nt)
+    count = {nm: names.count(nm) for nm in set(names)}
+    per_launch_ms = {nm: phase_ms[nm] / 1.0 for nm in phase_ms}
+    # per launch: phases that run twice were summed above over both occurrences
+    for nm in per_launch_ms:
+        per_launch_ms[nm] = phase_ms[nm] / count[nm]
+    dominant = max(phase_ms, key=lambda k: phase_ms[k])
+    dom_bytes = per_kernel[dominant]
+    dom_gbs = dom_bytes / (per_launch_ms[dominant] * 1e-3) / 1e9
+    t_s = ms * 1e-3
+    res = {
+        "metric": "points rasterized/s fwd+bwd at 1080p (8M pts); achieved HBM GB/s vs roofline",
+        "value": n / t_s,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded scene: 70% of points on 4 planes/spheres, 30% uniform)",
+        "config": {"workload": f"{args.config}: {n} points, {sc.camera.width}x{sc.camera.height}, "
+                               f"C={C}, bilinear, tile {args.tile}, fwd+bwd, "
+                               f"{'lists kept' if args.keep_lists else 'lists recomputed in bwd'}",
+                   "points": n, "width": sc.camera.width, "height": sc.camera.height,
+                   "channels": C, "tile": args.tile, "keep_lists": args.keep_lists},
+        "visible_points_per_s": V / t_s,
+        "frames_per_s": 1.0 / t_s,
+        "V": V, "M": M, "D": M / max(V, 1),
+        "B_min_GBps": b_min / t_s / 1e9,
+        "B_method_GBps": b_method / t_s / 1e9,
+        "B_min_frac": b_min / t_s / 1e9 / HBM_PEAK_GBS,
+        "B_method_frac": b_method / t_s / 1e9 / HBM_PEAK_GBS,
+        "phase_ms": phase_ms,
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": dom_gbs,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS,
+                     "bytes_per_launch": dom_bytes, "ms_per_launch": per_launch_ms[dominant],
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(sc)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

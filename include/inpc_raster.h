@@ -181,6 +181,10 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
  *   grad_opacity [n] f32 out
  *   grad_uv    [n][2] f32 out (input of inpc_project_backward)
  *   grad_bg    [C] f32 out, or NULL
+ *   scratch    device scratch of inpc_backward_scratch_bytes(n, C, ...) bytes
+ *              (per-tile shares of the gradients of points split over
+ *              several tiles; no floating-point atomics are used, so the
+ *              result is deterministic)
  * Every output element is written (zero for culled points).
  */
 inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
@@ -190,7 +194,13 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
                                   const uint32_t* list, const float* t_final, const void* state,
                                   const float* grad_out, const float* grad_t, float* grad_feat,
                                   float* grad_opacity, float* grad_uv, float* grad_bg,
-                                  void* ws, size_t ws_bytes, void* stream);
+                                  void* scratch, size_t scratch_bytes, void* ws, size_t ws_bytes,
+                                  void* stream);
+
+/* Bytes of the scratch inpc_blend_backward needs for n points and C channels
+ * (16 C + 48 bytes or more per point, plus 4 C per tile).  0 if invalid. */
+size_t inpc_backward_scratch_bytes(int64_t n, int32_t C, const inpc_camera_t* cam,
+                                   const inpc_opts_t* opts);
 
 /*
  * Step 6 -- project backward: dL/dX = G_u fx/Z, dL/dY = G_v fy/Z,

@@ -62,12 +62,20 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t flags, tile_count, cursor, list_w, list_m, list_l, list_x, bkey, bidx, xkey, xidx, total;
+  size_t flags, tile_count, cursor, seg_w, seg_m, seg_l, seg_x, seg_b0, seg_b1, bucket, xbucket,
+      total;
 };
 
+// Segment-list capacities.  Every non-empty tile starts one segment; an MSD
+// split of a segment with more than kSortCapM copies makes at most 256
+// sub-segments, and at most cap / (kSortCapM + 1) segments are ever split
+// per round (two rounds).
 Layout layout(int64_t n, const inpc_camera_t* c, const inpc_opts_t* o) {
   const size_t nt = (size_t)num_tiles(c, o);
   const size_t cap = (size_t)std::max<int64_t>(copy_capacity(n, c, o), 1);
+  const size_t big = cap / (kSortCapM + 1) + 1;
+  const size_t small_segs = nt + 2 * 256 * big;
+  const size_t big_segs = nt + big;
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -78,14 +86,14 @@ Layout layout(int64_t n, const inpc_camera_t* c, const inpc_opts_t* o) {
   L.flags = take(kFlagSlots * 4);
   L.tile_count = take(nt * 4);
   L.cursor = take(nt * 4);
-  L.list_w = take(nt * 4);
-  L.list_m = take(nt * 4);
-  L.list_l = take(nt * 4);
-  L.list_x = take(nt * 4);
-  L.bkey = take(cap * 4);
-  L.bidx = take(cap * 4);
-  L.xkey = take(cap * 4);
-  L.xidx = take(cap * 4);
+  L.seg_w = take(small_segs * 8);
+  L.seg_m = take(small_segs * 8);
+  L.seg_l = take(big_segs * 8);
+  L.seg_x = take(big_segs * 8);
+  L.seg_b0 = take(big_segs * 8);
+  L.seg_b1 = take(big_segs * 8);
+  L.bucket = take(cap * 8);
+  L.xbucket = take(cap * 8);
   L.total = off;
   return L;
 }
@@ -97,16 +105,23 @@ Ws make_ws(void* ws, int64_t n, const inpc_camera_t* c, const inpc_opts_t* o) {
   w.flags = reinterpret_cast<uint32_t*>(b + L.flags);
   w.tile_count = reinterpret_cast<uint32_t*>(b + L.tile_count);
   w.cursor = reinterpret_cast<uint32_t*>(b + L.cursor);
-  w.list_w = reinterpret_cast<uint32_t*>(b + L.list_w);
-  w.list_m = reinterpret_cast<uint32_t*>(b + L.list_m);
-  w.list_l = reinterpret_cast<uint32_t*>(b + L.list_l);
-  w.list_x = reinterpret_cast<uint32_t*>(b + L.list_x);
-  w.bkey = reinterpret_cast<uint32_t*>(b + L.bkey);
-  w.bidx = reinterpret_cast<uint32_t*>(b + L.bidx);
-  w.xkey = reinterpret_cast<uint32_t*>(b + L.xkey);
-  w.xidx = reinterpret_cast<uint32_t*>(b + L.xidx);
+  w.seg_w = reinterpret_cast<uint2*>(b + L.seg_w);
+  w.seg_m = reinterpret_cast<uint2*>(b + L.seg_m);
+  w.seg_l = reinterpret_cast<uint2*>(b + L.seg_l);
+  w.seg_x = reinterpret_cast<uint2*>(b + L.seg_x);
+  w.seg_b0 = reinterpret_cast<uint2*>(b + L.seg_b0);
+  w.seg_b1 = reinterpret_cast<uint2*>(b + L.seg_b1);
+  w.bucket = reinterpret_cast<uint2*>(b + L.bucket);
+  w.xbucket = reinterpret_cast<uint2*>(b + L.xbucket);
   w.cap = (uint32_t)std::min<int64_t>(copy_capacity(n, c, o), 0xffffffffLL);
   return w;
+}
+
+// Backward scratch: per-(point, tile slot) partial gradients, then the
+// per-tile background shares.
+size_t scratch_bytes(int64_t n, int C, const inpc_camera_t* c, const inpc_opts_t* o) {
+  return align_up((size_t)n * 4 * partial_stride(C) * 4) +
+         align_up((size_t)num_tiles(c, o) * C * 4);
 }
 
 Cam to_cam(const inpc_camera_t* c) {
@@ -161,6 +176,12 @@ extern "C" {
 size_t inpc_workspace_bytes(int64_t n, const inpc_camera_t* cam, const inpc_opts_t* opts) {
   if (n < 0 || !valid_cam(cam) || !valid_opts(opts)) return 0;
   return layout(n, cam, opts).total;
+}
+
+size_t inpc_backward_scratch_bytes(int64_t n, int32_t C, const inpc_camera_t* cam,
+                                   const inpc_opts_t* opts) {
+  if (n < 0 || C < 1 || C > 64 || !valid_cam(cam) || !valid_opts(opts)) return 0;
+  return scratch_bytes(n, C, cam, opts);
 }
 
 size_t inpc_state_bytes(const inpc_camera_t* cam) {
@@ -226,7 +247,7 @@ inpc_status_t inpc_sort(const inpc_camera_t* cam, const inpc_opts_t* opts, int64
   REQUIRE(tile_ranges, "tile_ranges");
   REQUIRE(list, "list");
   const Ws w = make_ws(ws, n, cam, opts);
-  hipError_t e = launch_sort(tile_ranges, w, list, num_tiles(cam, opts), (hipStream_t)stream);
+  hipError_t e = launch_sort(w, list, num_tiles(cam, opts), (hipStream_t)stream);
   return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_sort");
 }
 
@@ -296,12 +317,16 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
                                   const uint32_t* ntiles, const uint32_t* tile_ranges,
                                   const uint32_t* list, const float* t_final, const void* state,
                                   const float* grad_out, const float* grad_t, float* grad_feat,
-                                  float* grad_opacity, float* grad_uv, float* grad_bg, void* ws,
-                                  size_t ws_bytes, void* stream) {
+                                  float* grad_opacity, float* grad_uv, float* grad_bg,
+                                  void* scratch, size_t scratch_size, void* ws, size_t ws_bytes,
+                                  void* stream) {
   inpc_status_t st = blend_checks(cam, opts, n, C, dtype, ws, ws_bytes);
   if (st != INPC_OK) return st;
   if (opts->splat != INPC_SPLAT_BILINEAR)
     return fail(INPC_ERR_UNSUPPORTED, "backward of Gaussian splats%s", "");
+  REQUIRE(scratch, "scratch");
+  if (scratch_size < scratch_bytes(n, C, cam, opts))
+    return fail(INPC_ERR_INVALID, "scratch smaller than inpc_backward_scratch_bytes()%s", "");
   REQUIRE(tile_ranges, "tile_ranges");
   REQUIRE(list, "list");
   REQUIRE(t_final, "t_final");
@@ -342,6 +367,12 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
   a.grad_opacity = grad_opacity;
   a.grad_uv = grad_uv;
   a.grad_bg = grad_bg;
+  a.pstride = partial_stride(C);
+  a.partial = static_cast<float*>(scratch);
+  a.bg_partial = grad_bg ? reinterpret_cast<float*>(
+                               static_cast<char*>(scratch) +
+                               align_up((size_t)n * 4 * partial_stride(C) * 4))
+                         : nullptr;
   a.flags = w.flags;
   hipError_t e = launch_blend_backward(a, (hipStream_t)stream);
   return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_blend_backward");

@@ -21,9 +21,11 @@
 // transmittance the forward pass recorded in front of the last blended
 // fragment with T > 0 (so an alpha = 1 fragment never divides by zero).
 // The per-fragment terms land in per-(point, corner) LDS slots; one thread
-// per point then sums its corners, and the point's gradient is written with
-// plain stores when the point lies in this tile only, or added with
-// atomics otherwise.
+// per point then sums its corners.  A point that lies in this tile only gets
+// its gradient written directly; a point split over several tiles writes
+// this tile's share into its own slot of a partial buffer, and a gather pass
+// adds the shares -- no floating-point atomics, so the backward is
+// deterministic.
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
@@ -32,17 +34,6 @@
 
 namespace inpc {
 namespace {
-
-template <typename FT>
-__device__ __forceinline__ float to_f32(FT v);
-template <>
-__device__ __forceinline__ float to_f32<float>(float v) { return v; }
-template <>
-__device__ __forceinline__ float to_f32<__half>(__half v) { return __half2float(v); }
-template <>
-__device__ __forceinline__ float to_f32<__hip_bfloat16>(__hip_bfloat16 v) {
-  return __bfloat162float(v);
-}
 
 template <int T>
 struct TileGeom {
@@ -59,12 +50,80 @@ __device__ __forceinline__ uint32_t pack_xy(int x0, int y0) {
 __device__ __forceinline__ int unpack_x(uint32_t p) { return (int)(p & 0xffffu) - 1; }
 __device__ __forceinline__ int unpack_y(uint32_t p) { return (int)(p >> 16) - 1; }
 
+template <typename FT>
+__device__ __forceinline__ float half_bits_to_f32(uint32_t b);
+template <>
+__device__ __forceinline__ float half_bits_to_f32<__half>(uint32_t b) {
+  return __half2float(__ushort_as_half((unsigned short)(b & 0xffffu)));
+}
+template <>
+__device__ __forceinline__ float half_bits_to_f32<__hip_bfloat16>(uint32_t b) {
+  return __uint_as_float((b & 0xffffu) << 16);  // bf16 -> f32 is exact
+}
+
+// Copy one feature row (C values, dtype FT) into dst[0..CP) as FP32, with
+// 16-byte loads when the row is exactly CP wide.
 template <int CP, typename FT>
 __device__ __forceinline__ void stage_features(const FT* __restrict__ feat, uint32_t idx, int C,
                                                float* __restrict__ dst) {
   const FT* row = feat + (size_t)idx * C;
+  if (C == CP) {
+    if constexpr (sizeof(FT) == 4) {
+      const float4* r4 = reinterpret_cast<const float4*>(row);
+      float4* d4 = reinterpret_cast<float4*>(dst);
 #pragma unroll
-  for (int c = 0; c < CP; ++c) dst[c] = c < C ? to_f32<FT>(row[c]) : 0.f;
+      for (int q = 0; q < CP / 4; ++q) d4[q] = r4[q];
+    } else if constexpr (CP % 8 == 0) {
+      const uint4* r4 = reinterpret_cast<const uint4*>(row);
+#pragma unroll
+      for (int q = 0; q < CP / 8; ++q) {
+        const uint4 v = r4[q];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          dst[8 * q + 2 * k] = half_bits_to_f32<FT>(w[k]);
+          dst[8 * q + 2 * k + 1] = half_bits_to_f32<FT>(w[k] >> 16);
+        }
+      }
+    } else {
+      const uint2* r2 = reinterpret_cast<const uint2*>(row);
+#pragma unroll
+      for (int q = 0; q < CP / 4; ++q) {
+        const uint2 v = r2[q];
+        dst[4 * q] = half_bits_to_f32<FT>(v.x);
+        dst[4 * q + 1] = half_bits_to_f32<FT>(v.x >> 16);
+        dst[4 * q + 2] = half_bits_to_f32<FT>(v.y);
+        dst[4 * q + 3] = half_bits_to_f32<FT>(v.y >> 16);
+      }
+    }
+  } else {
+    const uint16_t* r16 = reinterpret_cast<const uint16_t*>(row);
+#pragma unroll
+    for (int c = 0; c < CP; ++c) {
+      float v = 0.f;
+      if (c < C) {
+        if constexpr (sizeof(FT) == 4)
+          v = reinterpret_cast<const float*>(row)[c];
+        else
+          v = half_bits_to_f32<FT>(r16[c]);
+      }
+      dst[c] = v;
+    }
+  }
+}
+
+// Store CP floats of which the first C are meaningful.
+template <int CP>
+__device__ __forceinline__ void store_row(float* __restrict__ dst, const float (&v)[CP], int C) {
+  if (C == CP) {
+    float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll
+    for (int q = 0; q < CP / 4; ++q) d4[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < CP; ++c)
+      if (c < C) dst[c] = v[c];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -74,7 +133,7 @@ template <int T, int CP, typename FT>
 __global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear(BlendArgs a) {
   using G = TileGeom<T>;
   __shared__ float4 s_geo[G::CHUNK];
-  __shared__ float s_feat[G::CHUNK * fpad(CP)];
+  __shared__ __align__(16) float s_feat[G::CHUNK * fpad(CP)];
   __shared__ unsigned long long s_mask[G::NTH * G::MW];
   if (a.flags[kFlagOverflow]) return;
 
@@ -140,17 +199,23 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear(BlendArgs a) {
             break;
           }
           const float wt = Tr * al;
-          const float* fr = s_feat + kk * fpad(CP);
+          const float4* fr = reinterpret_cast<const float4*>(s_feat + kk * fpad(CP));
 #pragma unroll
-          for (int c = 0; c < CP; ++c) F[c] = fmaf(wt, fr[c], F[c]);
-          const uint32_t q = base - start + (uint32_t)kk + 1u;
+          for (int q = 0; q < CP / 4; ++q) {
+            const float4 f4 = fr[q];
+            F[4 * q] = fmaf(wt, f4.x, F[4 * q]);
+            F[4 * q + 1] = fmaf(wt, f4.y, F[4 * q + 1]);
+            F[4 * q + 2] = fmaf(wt, f4.z, F[4 * q + 2]);
+            F[4 * q + 3] = fmaf(wt, f4.w, F[4 * q + 3]);
+          }
+          const uint32_t q1 = base - start + (uint32_t)kk + 1u;
           if (Tr > 0.f) {
-            anchor = q;
+            anchor = q1;
             t_anchor = Tr;
           }
           Tr = fmul(Tr, fsub(1.f, al));
           ++cnt;
-          last = q;
+          last = q1;
         }
       }
     }
@@ -179,7 +244,7 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_gauss(BlendArgs a) {
   using G = TileGeom<T>;
   __shared__ float4 s_g0[G::CHUNK];  // u, v, o, s2
   __shared__ float4 s_g1[G::CHUNK];  // thr, packed (px0, py0), packed (px1, py1), -
-  __shared__ float s_feat[G::CHUNK * fpad(CP)];
+  __shared__ __align__(16) float s_feat[G::CHUNK * fpad(CP)];
   if (a.flags[kFlagOverflow]) return;
 
   const int tid = threadIdx.x;
@@ -229,9 +294,15 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_gauss(BlendArgs a) {
         }
         const float al = g0.z * expf(-0.5f * d2 / g0.w);
         const float wt = Tr * al;
-        const float* fr = s_feat + kk * fpad(CP);
+        const float4* fr = reinterpret_cast<const float4*>(s_feat + kk * fpad(CP));
 #pragma unroll
-        for (int c = 0; c < CP; ++c) F[c] = fmaf(wt, fr[c], F[c]);
+        for (int q = 0; q < CP / 4; ++q) {
+          const float4 f4 = fr[q];
+          F[4 * q] = fmaf(wt, f4.x, F[4 * q]);
+          F[4 * q + 1] = fmaf(wt, f4.y, F[4 * q + 1]);
+          F[4 * q + 2] = fmaf(wt, f4.z, F[4 * q + 2]);
+          F[4 * q + 3] = fmaf(wt, f4.w, F[4 * q + 3]);
+        }
         Tr = fmul(Tr, fsub(1.f, al));
         ++cnt;
       }
@@ -254,12 +325,13 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_gauss(BlendArgs a) {
 template <int T, int CP, typename FT>
 __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
   using G = TileGeom<T>;
+  constexpr int SH = T == 8 ? 3 : (T == 16 ? 4 : 5);
   __shared__ float4 s_geo[G::CHUNK];
-  __shared__ float s_feat[G::CHUNK * fpad(CP)];
+  __shared__ __align__(16) float s_feat[G::CHUNK * fpad(CP)];
   __shared__ unsigned long long s_mask[G::NTH * G::MW];
-  __shared__ float2 s_acc[G::CHUNK * 4];    // per (point, corner): (T alpha, dL/dalpha)
-  __shared__ float s_G[G::NTH * fpad(CP)];  // dL/dF of every pixel of the tile
-  __shared__ uint32_t s_red[G::NTH / 64];
+  __shared__ float2 s_acc[G::CHUNK * 4];                  // per (point, corner): (T alpha, dL/dalpha)
+  __shared__ __align__(16) float s_G[G::NTH * fpad(CP)];  // dL/dF of every pixel of the tile
+  __shared__ float s_red[G::NTH / 64][CP];
   if (a.flags[kFlagOverflow]) return;
 
   const int tid = threadIdx.x;
@@ -292,13 +364,14 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
 #pragma unroll
   for (int c = 0; c < CP; ++c) s_G[tid * fpad(CP) + c] = Gv[c];
 
-  // background gradient: sum over pixels of T_final * G
-  if (a.grad_bg) {
-    for (int c = 0; c < C; ++c) {
+  // background: this tile's share of sum_p T_final G
+  if (a.bg_partial) {
+#pragma unroll
+    for (int c = 0; c < CP; ++c) {
       float v = Tf * Gv[c];
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-      if ((tid & 63) == 0) atomicAdd(&a.grad_bg[c], v);
+      if ((tid & 63) == 0) s_red[tid >> 6][c] = v;
     }
   }
 
@@ -306,11 +379,18 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
   uint32_t ml = last;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) ml = max(ml, (uint32_t)__shfl_xor((int)ml, o, 64));
-  if ((tid & 63) == 0) s_red[tid >> 6] = ml;
+  __shared__ uint32_t s_ml[G::NTH / 64];
+  if ((tid & 63) == 0) s_ml[tid >> 6] = ml;
   __syncthreads();
   uint32_t maxlast = 0;
 #pragma unroll
-  for (int w = 0; w < G::NTH / 64; ++w) maxlast = max(maxlast, s_red[w]);
+  for (int w = 0; w < G::NTH / 64; ++w) maxlast = max(maxlast, s_ml[w]);
+  if (a.bg_partial && tid < C) {
+    float v = 0.f;
+#pragma unroll
+    for (int w = 0; w < G::NTH / 64; ++w) v += s_red[w][tid];
+    a.bg_partial[(size_t)tile * C + tid] = v;
+  }
 
   float Pi = 1.f, Tcur = 0.f;
   const int nchunks = (int)((n + G::CHUNK - 1) / G::CHUNK);
@@ -318,16 +398,15 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
     const uint32_t rb = (uint32_t)ci * G::CHUNK;  // relative base of the chunk
     const uint32_t nh = min((uint32_t)G::CHUNK, n - rb);
     const bool active = rb < maxlast;
-    uint32_t idx = 0;
-    bool single = false;
+    uint32_t idx = 0, nt_pt = 0;
     if (tid < G::CHUNK && (uint32_t)tid < nh) {
       idx = a.list[start + rb + tid];
-      single = a.ntiles[idx] == 1;
-      if (active) {
+      nt_pt = a.ntiles[idx];
+      if (active || nt_pt > 1) {
         const float2 pp = reinterpret_cast<const float2*>(a.uv)[idx];
         const Footprint f = bilinear_footprint(pp.x, pp.y, a.cam.W, a.cam.H);
         s_geo[tid] = make_float4(f.a, f.b, a.opacity[idx], __uint_as_float(pack_xy(f.x0, f.y0)));
-        stage_features<CP, FT>(feat, idx, C, s_feat + tid * fpad(CP));
+        if (active) stage_features<CP, FT>(feat, idx, C, s_feat + tid * fpad(CP));
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k) s_acc[tid * 4 + k] = make_float2(0.f, 0.f);
@@ -377,10 +456,16 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
             Tk = t_anchor;
           else
             Tk = fdiv(Tcur, om);
-          const float* fr = s_feat + kk * fpad(CP);
+          const float4* fr = reinterpret_cast<const float4*>(s_feat + kk * fpad(CP));
           float gf = 0.f;
 #pragma unroll
-          for (int c = 0; c < CP; ++c) gf = fmaf(Gv[c], fr[c], gf);
+          for (int q = 0; q < CP / 4; ++q) {
+            const float4 f4 = fr[q];
+            gf = fmaf(Gv[4 * q], f4.x, gf);
+            gf = fmaf(Gv[4 * q + 1], f4.y, gf);
+            gf = fmaf(Gv[4 * q + 2], f4.z, gf);
+            gf = fmaf(Gv[4 * q + 3], f4.w, gf);
+          }
           const float da = Tk * (gf - gB) - GT * Tk * Pi;
           s_acc[kk * 4 + dy * 2 + dx] = make_float2(Tk * al, da);
           gB = fmaf(al, gf, om * gB);
@@ -390,24 +475,31 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
       }
     }
     __syncthreads();
-    if (tid < G::CHUNK && (uint32_t)tid < nh) {
+    if (tid < G::CHUNK && (uint32_t)tid < nh && nt_pt > 0) {
       float gfeat[CP];
 #pragma unroll
       for (int c = 0; c < CP; ++c) gfeat[c] = 0.f;
       float go = 0.f, gu = 0.f, gv = 0.f;
+      const float4 g = s_geo[tid];
+      const uint32_t pk = __float_as_uint(g.w);
+      const int X0 = unpack_x(pk), Y0 = unpack_y(pk);
       if (active) {
-        const float4 g = s_geo[tid];
-        const uint32_t pk = __float_as_uint(g.w);
-        const int x0 = unpack_x(pk) - tx * T, y0 = unpack_y(pk) - ty * T;
+        const int x0 = X0 - tx * T, y0 = Y0 - ty * T;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const int dx = k & 1, dy = k >> 1;
           const int qx = x0 + dx, qy = y0 + dy;
           if (qx < 0 || qx >= T || qy < 0 || qy >= T) continue;
           const float2 acc = s_acc[tid * 4 + k];
-          const float* gp = s_G + (qy * T + qx) * fpad(CP);
+          const float4* gp = reinterpret_cast<const float4*>(s_G + (qy * T + qx) * fpad(CP));
 #pragma unroll
-          for (int c = 0; c < CP; ++c) gfeat[c] = fmaf(acc.x, gp[c], gfeat[c]);
+          for (int q = 0; q < CP / 4; ++q) {
+            const float4 g4 = gp[q];
+            gfeat[4 * q] = fmaf(acc.x, g4.x, gfeat[4 * q]);
+            gfeat[4 * q + 1] = fmaf(acc.x, g4.y, gfeat[4 * q + 1]);
+            gfeat[4 * q + 2] = fmaf(acc.x, g4.z, gfeat[4 * q + 2]);
+            gfeat[4 * q + 3] = fmaf(acc.x, g4.w, gfeat[4 * q + 3]);
+          }
           const float wx = dx ? g.x : 1.f - g.x;
           const float wy = dy ? g.y : 1.f - g.y;
           go = fmaf(wx * wy, acc.y, go);
@@ -417,24 +509,83 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
         gu *= g.z;
         gv *= g.z;
       }
-      float* dst = a.grad_feat + (size_t)idx * C;
-      if (single) {
-#pragma unroll
-        for (int c = 0; c < CP; ++c)
-          if (c < C) dst[c] = gfeat[c];
+      if (nt_pt == 1) {
+        store_row<CP>(a.grad_feat + (size_t)idx * C, gfeat, C);
         a.grad_opacity[idx] = go;
         reinterpret_cast<float2*>(a.grad_uv)[idx] = make_float2(gu, gv);
-      } else if (active) {
+      } else {
+        // this tile's slot among the (at most 2 x 2) tiles of the point
+        const int tx0 = max(X0, 0) >> SH, ty0 = max(Y0, 0) >> SH;
+        const int slot = (tx - tx0) + 2 * (ty - ty0);
+        float* dst = a.partial + ((size_t)idx * 4 + slot) * a.pstride;
+        float4* d4 = reinterpret_cast<float4*>(dst);
 #pragma unroll
-        for (int c = 0; c < CP; ++c)
-          if (c < C && gfeat[c] != 0.f) atomicAdd(dst + c, gfeat[c]);
-        if (go != 0.f) atomicAdd(a.grad_opacity + idx, go);
-        if (gu != 0.f) atomicAdd(a.grad_uv + 2 * (size_t)idx, gu);
-        if (gv != 0.f) atomicAdd(a.grad_uv + 2 * (size_t)idx + 1, gv);
+        for (int q = 0; q < CP / 4; ++q)
+          d4[q] = make_float4(gfeat[4 * q], gfeat[4 * q + 1], gfeat[4 * q + 2], gfeat[4 * q + 3]);
+        dst[C] = go;
+        dst[C + 1] = gu;
+        dst[C + 2] = gv;
       }
     }
     __syncthreads();
   }
+}
+
+// Gradients of points that no single tile owns: sums of the per-tile shares
+// for points split over 2 or 4 tiles, zeros for culled points.
+template <int CP>
+__global__ __launch_bounds__(256) void k_grad_gather(BlendArgs a) {
+  const int sh = a.opts.T == 8 ? 3 : (a.opts.T == 16 ? 4 : 5);
+  const int C = a.C;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t nt = a.ntiles[i];
+    if (nt == 1) continue;
+    float gfeat[CP];
+#pragma unroll
+    for (int c = 0; c < CP; ++c) gfeat[c] = 0.f;
+    float go = 0.f, gu = 0.f, gv = 0.f;
+    if (nt > 1) {
+      const float2 pp = reinterpret_cast<const float2*>(a.uv)[i];
+      const Footprint f = bilinear_footprint(pp.x, pp.y, a.cam.W, a.cam.H);
+      const int tx0 = f.px0 >> sh, tx1 = f.px1 >> sh, ty0 = f.py0 >> sh, ty1 = f.py1 >> sh;
+      for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) {
+          const float* src = a.partial + ((size_t)i * 4 + (tx - tx0) + 2 * (ty - ty0)) * a.pstride;
+          const float4* s4 = reinterpret_cast<const float4*>(src);
+#pragma unroll
+          for (int q = 0; q < CP / 4; ++q) {
+            const float4 v = s4[q];
+            gfeat[4 * q] += v.x;
+            gfeat[4 * q + 1] += v.y;
+            gfeat[4 * q + 2] += v.z;
+            gfeat[4 * q + 3] += v.w;
+          }
+          go += src[C];
+          gu += src[C + 1];
+          gv += src[C + 2];
+        }
+    }
+    store_row<CP>(a.grad_feat + (size_t)i * C, gfeat, C);
+    a.grad_opacity[i] = go;
+    reinterpret_cast<float2*>(a.grad_uv)[i] = make_float2(gu, gv);
+  }
+}
+
+// grad_bg[c] = sum over tiles of the per-tile shares (one block per channel).
+__global__ __launch_bounds__(256) void k_bg_reduce(const float* __restrict__ part, int64_t nt, int C,
+                                                   float* __restrict__ grad_bg) {
+  __shared__ float s[256];
+  const int c = blockIdx.x;
+  float v = 0.f;
+  for (int64_t t = threadIdx.x; t < nt; t += 256) v += part[t * C + c];
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grad_bg[c] = s[0];
 }
 
 template <int T, int CP, typename FT>
@@ -451,6 +602,17 @@ template <int T, int CP, typename FT>
 hipError_t bwd_launch(const BlendArgs& a, hipStream_t s) {
   const int64_t nt = (int64_t)a.opts.ntx * a.opts.nty;
   hipLaunchKernelGGL((k_blend_bwd_bilinear<T, CP, FT>), dim3((unsigned)nt), dim3(T * T), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (a.n > 0) {
+    const int64_t g = std::min<int64_t>((a.n + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL((k_grad_gather<CP>), dim3((unsigned)g), dim3(256), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (a.grad_bg)
+    hipLaunchKernelGGL(k_bg_reduce, dim3((unsigned)a.C), dim3(256), 0, s, a.bg_partial, nt, a.C,
+                       a.grad_bg);
   return hipGetLastError();
 }
 
@@ -489,9 +651,6 @@ hipError_t launch_blend_forward(const BlendArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_blend_backward(const BlendArgs& a, hipStream_t s) {
-  hipError_t e = launch_grad_init(a.n, a.C, a.ntiles, a.grad_feat, a.grad_opacity, a.grad_uv,
-                                  a.grad_bg, s);
-  if (e != hipSuccess) return e;
   if (a.opts.ntx == 0 || a.opts.nty == 0) return hipSuccess;
   return dispatch<false>(a, s);
 }

@@ -17,10 +17,13 @@ namespace inpc {
 
 constexpr int kWave = 64;
 
-// Sort size classes (tile copy counts).
+// Sort size classes (segment copy counts).
 constexpr uint32_t kSortCapW = 256;
 constexpr uint32_t kSortCapM = 2048;
 constexpr uint32_t kSortCapL = 16384;
+
+// Largest tile count whose per-workgroup histogram fits in LDS (144 KiB).
+constexpr int kLdsBins = 36864;
 
 // Camera in kernel-argument form (by value).
 struct Cam {
@@ -41,26 +44,29 @@ struct Opts {
 // Workspace flag slots.
 enum : int {
   kFlagOverflow = 0,
-  kFlagCountW = 1,   // tiles sorted by one wavefront (n <= 256)
-  kFlagCountM = 2,   // tiles sorted by a 256-thread block (n <= 2048)
-  kFlagCountL = 3,   // tiles sorted by a 1024-thread block (n <= 16384)
-  kFlagCountX = 4,   // larger tiles, sorted through global memory
+  kFlagCountW = 1,   // segments sorted by one wavefront (n <= 256)
+  kFlagCountM = 2,   // segments sorted by a 256-thread block (n <= 2048)
+  kFlagCountL = 3,   // segments LSD-sorted by a 1024-thread block (n <= 16384)
+  kFlagCountX = 4,   // larger segments, sorted through global memory
+  kFlagCountB0 = 5,  // tiles to split (2048 < n <= 16384)
+  kFlagCountB1 = 6,  // sub-segments to split a second time
   kFlagSlots = 16
 };
 
-// Pointers into the caller's workspace.
+// Pointers into the caller's workspace.  Segment lists hold (start, count)
+// pairs of bucket ranges.
 struct Ws {
   uint32_t* flags;       // [kFlagSlots]
   uint32_t* tile_count;  // [nt]   copies per tile (filled by project)
   uint32_t* cursor;      // [nt]   scatter cursors
-  uint32_t* list_w;      // [nt]   tile ids per sort class
-  uint32_t* list_m;      // [nt]
-  uint32_t* list_l;      // [nt]
-  uint32_t* list_x;      // [nt]
-  uint32_t* bkey;        // [cap]  bucketed depth keys
-  uint32_t* bidx;        // [cap]  bucketed point indices
-  uint32_t* xkey;        // [cap]  ping-pong scratch for large tiles
-  uint32_t* xidx;        // [cap]
+  uint2* seg_w;          // segment lists per sort class
+  uint2* seg_m;
+  uint2* seg_l;
+  uint2* seg_x;
+  uint2* seg_b0;
+  uint2* seg_b1;
+  uint2* bucket;         // [cap]  (depth key, point index) copies, bucketed by tile
+  uint2* xbucket;        // [cap]  ping-pong scratch for segments beyond the LDS capacity
   uint32_t cap;          // copy capacity
 };
 

@@ -36,8 +36,21 @@ struct BlendArgs {
   float* grad_opacity;
   float* grad_uv;
   float* grad_bg;
+  float* partial;     // [n][4][pstride] per-(point, tile slot) gradients of multi-tile points
+  float* bg_partial;  // [num_tiles][C] per-tile background gradients
+  int pstride;        // floats per partial record (C + 3 rounded up to 4)
   const uint32_t* flags;
 };
+
+// Channel capacity of the kernel instantiation used for C channels.
+inline int channel_capacity(int C) { return C <= 4 ? 4 : (C <= 8 ? 8 : (C <= 16 ? 16 : 32)); }
+
+// Floats per partial gradient record: C features, opacity, u, v; at least
+// the channel capacity (records are written with 16-byte stores).
+inline int partial_stride(int C) {
+  const int s = (C + 3 + 3) / 4 * 4;
+  return s > channel_capacity(C) ? s : channel_capacity(C);
+}
 
 hipError_t launch_clear(uint32_t* p, size_t n, hipStream_t s);
 hipError_t launch_project(const Cam& cam, const Opts& o, int64_t n, const float* pos,
@@ -46,10 +59,7 @@ hipError_t launch_project(const Cam& cam, const Opts& o, int64_t n, const float*
 hipError_t launch_bin(const Cam& cam, const Opts& o, int64_t n, const float* uv,
                       const float* radius, const uint32_t* key, const uint32_t* ntiles,
                       uint32_t* ranges, const Ws& ws, hipStream_t s);
-hipError_t launch_sort(const uint32_t* ranges, const Ws& ws, uint32_t* list, int64_t nt,
-                       hipStream_t s);
-hipError_t launch_grad_init(int64_t n, int C, const uint32_t* ntiles, float* grad_feat,
-                            float* grad_opacity, float* grad_uv, float* grad_bg, hipStream_t s);
+hipError_t launch_sort(const Ws& ws, uint32_t* list, int64_t nt, hipStream_t s);
 hipError_t launch_blend_forward(const BlendArgs& a, hipStream_t s);
 hipError_t launch_blend_backward(const BlendArgs& a, hipStream_t s);
 hipError_t launch_project_backward(const Cam& cam, int64_t n, const float* pos,

@@ -2,14 +2,18 @@
 //
 // Step 1 (Sec. 2 and Sec. 3.2 of the paper): every point is moved into
 // camera space, projected, culled against the near plane and the image, and
-// given its 32-bit depth key and the set of tiles its footprint meets.  The
-// per-tile copy counts are accumulated here with atomics (only counts: no
-// order depends on them).
-// Step 2 (Sec. 3.2, "Tiled Rendering"): one exclusive scan over the tile
-// counts places every tile's bucket; every visible point then drops one
+// given its 32-bit depth key and the set of tiles its footprint meets.
+// Step 2 (Sec. 3.2, "Tiled Rendering"): one exclusive scan over the per-tile
+// copy counts places every tile's bucket; every visible point then drops one
 // (depth key, index) copy into the bucket of each tile it touches.  The
 // order inside a bucket is irrelevant because the sort that follows orders
 // every bucket by the unique pair (depth key, point index).
+//
+// Counting and slot reservation are privatised per workgroup: a workgroup
+// histograms the tiles of a large chunk of points in LDS and then issues one
+// global atomic per non-empty tile, instead of one per copy.  The points are
+// in random order, so hot tiles (thousands of copies) would otherwise
+// serialise on a single global counter.
 #include "common.h"
 #include "internal.h"
 
@@ -17,6 +21,7 @@ namespace inpc {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kBinBlock = 1024;  // threads of the privatised counting / scatter blocks
 
 __device__ __forceinline__ int tile_shift(int T) { return T == 8 ? 3 : (T == 16 ? 4 : 5); }
 
@@ -26,150 +31,237 @@ __global__ void k_clear(uint32_t* __restrict__ p, size_t n) {
     p[i] = 0u;
 }
 
-__global__ __launch_bounds__(kBlock) void k_project(Cam cam, Opts o, int64_t n,
-                                                    const float* __restrict__ pos,
-                                                    const float* __restrict__ radius,
-                                                    float2* __restrict__ uv,
-                                                    uint32_t* __restrict__ key,
-                                                    uint32_t* __restrict__ ntiles,
-                                                    uint32_t* __restrict__ tile_count) {
+// Project one point; returns its tile rectangle (empty when culled).
+struct TileRect {
+  int tx0, ty0, tx1, ty1;
+  __device__ __forceinline__ uint32_t count() const {
+    return tx1 < tx0 ? 0u : (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+  }
+};
+
+__device__ __forceinline__ TileRect tile_rect(const Footprint& f, int sh) {
+  TileRect r;
+  if (!f.visible) {
+    r.tx0 = r.ty0 = 0;
+    r.tx1 = r.ty1 = -1;
+    return r;
+  }
+  r.tx0 = f.px0 >> sh; r.tx1 = f.px1 >> sh;
+  r.ty0 = f.py0 >> sh; r.ty1 = f.py1 >> sh;
+  return r;
+}
+
+__device__ __forceinline__ TileRect project_one(const Cam& cam, const Opts& o, int sh,
+                                                const float* __restrict__ pos,
+                                                const float* __restrict__ radius, int64_t i,
+                                                float2* __restrict__ uv,
+                                                uint32_t* __restrict__ key,
+                                                uint32_t* __restrict__ ntiles) {
+  const float x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+  const Proj p = project_point(cam, x, y, z);
+  Footprint f;
+  f.visible = false;
+  if (p.in_front) f = footprint(o, cam, p.u, p.v, radius ? radius[i] : 0.f);
+  uv[i] = make_float2(p.u, p.v);
+  key[i] = __float_as_uint(p.Z);
+  const TileRect r = tile_rect(f, sh);
+  ntiles[i] = r.count();
+  return r;
+}
+
+// Points [b * chunk, (b + 1) * chunk) of block b.
+struct Chunk {
+  int64_t begin, end;
+};
+__device__ __forceinline__ Chunk chunk_of(int64_t n, int64_t chunk) {
+  Chunk c;
+  c.begin = (int64_t)blockIdx.x * chunk;
+  c.end = c.begin + chunk < n ? c.begin + chunk : n;
+  return c;
+}
+
+// Step 1 with per-workgroup tile histograms in LDS (nt <= kLdsBins).
+__global__ __launch_bounds__(kBinBlock) void k_project_count(Cam cam, Opts o, int64_t n,
+                                                             int64_t chunk,
+                                                             const float* __restrict__ pos,
+                                                             const float* __restrict__ radius,
+                                                             float2* __restrict__ uv,
+                                                             uint32_t* __restrict__ key,
+                                                             uint32_t* __restrict__ ntiles,
+                                                             uint32_t* __restrict__ tile_count) {
+  __shared__ uint32_t bins[kLdsBins];
+  const int nt = o.ntx * o.nty;
+  for (int t = threadIdx.x; t < nt; t += kBinBlock) bins[t] = 0u;
+  __syncthreads();
   const int sh = tile_shift(o.T);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const float x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
-    const Proj p = project_point(cam, x, y, z);
-    bool vis = p.in_front;
-    Footprint f;
-    if (vis) {
-      f = footprint(o, cam, p.u, p.v, radius ? radius[i] : 0.f);
-      vis = f.visible;
-    }
-    uv[i] = make_float2(p.u, p.v);
-    key[i] = __float_as_uint(p.Z);
-    uint32_t nt = 0;
-    if (vis) {
-      const int tx0 = f.px0 >> sh, tx1 = f.px1 >> sh, ty0 = f.py0 >> sh, ty1 = f.py1 >> sh;
-      nt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-      for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&tile_count[ty * o.ntx + tx], 1u);
-    }
-    ntiles[i] = nt;
+  const Chunk c = chunk_of(n, chunk);
+  for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBinBlock) {
+    const TileRect r = project_one(cam, o, sh, pos, radius, i, uv, key, ntiles);
+    for (int ty = r.ty0; ty <= r.ty1; ++ty)
+      for (int tx = r.tx0; tx <= r.tx1; ++tx) atomicAdd(&bins[ty * o.ntx + tx], 1u);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nt; t += kBinBlock) {
+    const uint32_t v = bins[t];
+    if (v) atomicAdd(&tile_count[t], v);
   }
 }
 
-// Block-wide inclusive scan of 64-bit values (1024 threads).
-__device__ uint64_t block_scan_u64(uint64_t v, uint64_t* s) {
-  const int t = threadIdx.x;
-  s[t] = v;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const uint64_t add = t >= o ? s[t - o] : 0ull;
-    __syncthreads();
-    s[t] += add;
-    __syncthreads();
+// Step 1 for very large tile counts: one global atomic per copy.
+__global__ __launch_bounds__(kBlock) void k_project_count_global(
+    Cam cam, Opts o, int64_t n, const float* __restrict__ pos, const float* __restrict__ radius,
+    float2* __restrict__ uv, uint32_t* __restrict__ key, uint32_t* __restrict__ ntiles,
+    uint32_t* __restrict__ tile_count) {
+  const int sh = tile_shift(o.T);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const TileRect r = project_one(cam, o, sh, pos, radius, i, uv, key, ntiles);
+    for (int ty = r.ty0; ty <= r.ty1; ++ty)
+      for (int tx = r.tx0; tx <= r.tx1; ++tx) atomicAdd(&tile_count[ty * o.ntx + tx], 1u);
   }
-  const uint64_t r = s[t];
-  __syncthreads();
-  return r;
 }
 
 __device__ __forceinline__ int sort_class(uint32_t c) {
   return c == 0 ? -1 : (c <= kSortCapW ? 0 : (c <= kSortCapM ? 1 : (c <= kSortCapL ? 2 : 3)));
 }
 
+// Inclusive scan of one 64-bit value per thread over a 1024-thread block;
+// also returns the block total.
+__device__ uint64_t block_incl_scan_u64(uint64_t v, uint64_t* s_wave, uint64_t& total) {
+  const uint32_t lane = __lane_id(), w = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t t = __shfl_up(v, o, 64);
+    if (lane >= (uint32_t)o) v += t;
+  }
+  if (lane == 63) s_wave[w] = v;
+  __syncthreads();
+  uint64_t pre = 0;
+  total = 0;
+  for (uint32_t k = 0; k < 16; ++k) {
+    const uint64_t x = s_wave[k];
+    if (k < w) pre += x;
+    total += x;
+  }
+  __syncthreads();
+  return v + pre;
+}
+
 // Single 1024-thread block: ranges = exclusive scan of the tile counts,
-// scatter cursors, and the tile lists of the four sort classes (in tile
-// order).  Flags an overflow when the copies exceed the capacity.
+// scatter cursors, and the initial sort segments (one per non-empty tile, in
+// tile order, per size class), in chunks of 8192 tiles (8 consecutive tiles
+// per thread).  Flags an overflow when the copies exceed the capacity.
 __global__ __launch_bounds__(1024) void k_scan(int64_t nt, const uint32_t* __restrict__ count,
                                                uint32_t* __restrict__ ranges,
                                                uint32_t* __restrict__ cursor, Ws ws) {
-  __shared__ uint64_t s[1024];
-  const int t = threadIdx.x;
-  const int64_t seg = (nt + 1023) / 1024;
-  const int64_t b = min<int64_t>(nt, t * seg), e = min<int64_t>(nt, b + seg);
-  uint64_t tot = 0, cwm = 0, clx = 0;  // packed class counts: (W | M << 32), (L | X << 32)
-  for (int64_t i = b; i < e; ++i) {
-    const uint32_t c = count[i];
-    tot += c;
-    const int k = sort_class(c);
-    if (k == 0) cwm += 1ull;
-    if (k == 1) cwm += 1ull << 32;
-    if (k == 2) clx += 1ull;
-    if (k == 3) clx += 1ull << 32;
+  __shared__ uint64_t s_wave[16];
+  constexpr int PER = 8;
+  uint64_t base = 0;                       // copies before this chunk
+  uint32_t cb[4] = {0u, 0u, 0u, 0u};       // class list sizes before this chunk
+  uint2* lists[4] = {ws.seg_w, ws.seg_m, ws.seg_b0, ws.seg_x};
+  for (int64_t c0 = 0; c0 < nt; c0 += 1024 * PER) {
+    const int64_t b = c0 + (int64_t)threadIdx.x * PER;
+    uint32_t v[PER];
+    uint64_t tot = 0, cls = 0;  // class counts packed 16 bits each (<= 8192 per chunk)
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      v[k] = b + k < nt ? count[b + k] : 0u;
+      tot += v[k];
+      const int c = sort_class(v[k]);
+      if (c >= 0) cls += 1ull << (16 * c);
+    }
+    uint64_t tot_all, cls_all;
+    uint64_t off = block_incl_scan_u64(tot, s_wave, tot_all) - tot + base;
+    uint64_t coff = block_incl_scan_u64(cls, s_wave, cls_all) - cls;
+    uint32_t pos[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) pos[c] = cb[c] + (uint32_t)((coff >> (16 * c)) & 0xffffu);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      if (b + k >= nt) break;
+      ranges[b + k] = (uint32_t)off;
+      cursor[b + k] = (uint32_t)off;
+      const int c = sort_class(v[k]);
+      if (c >= 0) lists[c][pos[c]++] = make_uint2((uint32_t)off, v[k]);
+      off += v[k];
+    }
+    base += tot_all;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) cb[c] += (uint32_t)((cls_all >> (16 * c)) & 0xffffu);
   }
-  const uint64_t incl = block_scan_u64(tot, s);
-  const uint64_t iwm = block_scan_u64(cwm, s);
-  const uint64_t ilx = block_scan_u64(clx, s);
-  uint64_t off = incl - tot;
-  uint32_t ow = (uint32_t)(iwm - cwm), om = (uint32_t)((iwm - cwm) >> 32);
-  uint32_t ol = (uint32_t)(ilx - clx), ox = (uint32_t)((ilx - clx) >> 32);
-  for (int64_t i = b; i < e; ++i) {
-    const uint32_t c = count[i];
-    ranges[i] = (uint32_t)off;
-    cursor[i] = (uint32_t)off;
-    off += c;
-    const int k = sort_class(c);
-    if (k == 0) ws.list_w[ow++] = (uint32_t)i;
-    if (k == 1) ws.list_m[om++] = (uint32_t)i;
-    if (k == 2) ws.list_l[ol++] = (uint32_t)i;
-    if (k == 3) ws.list_x[ox++] = (uint32_t)i;
-  }
-  if (t == 1023) {
-    ranges[nt] = (uint32_t)incl;
-    ws.flags[kFlagCountW] = (uint32_t)iwm;
-    ws.flags[kFlagCountM] = (uint32_t)(iwm >> 32);
-    ws.flags[kFlagCountL] = (uint32_t)ilx;
-    ws.flags[kFlagCountX] = (uint32_t)(ilx >> 32);
-    if (incl > (uint64_t)ws.cap) ws.flags[kFlagOverflow] = 1u;
+  if (threadIdx.x == 0) {
+    ranges[nt] = (uint32_t)base;
+    ws.flags[kFlagCountW] = cb[0];
+    ws.flags[kFlagCountM] = cb[1];
+    ws.flags[kFlagCountB0] = cb[2];
+    ws.flags[kFlagCountX] = cb[3];
+    if (base > (uint64_t)ws.cap) ws.flags[kFlagOverflow] = 1u;
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter(Cam cam, Opts o, int64_t n,
-                                                    const float2* __restrict__ uv,
-                                                    const float* __restrict__ radius,
-                                                    const uint32_t* __restrict__ key,
-                                                    const uint32_t* __restrict__ ntiles,
-                                                    uint32_t* __restrict__ cursor,
-                                                    uint32_t* __restrict__ bkey,
-                                                    uint32_t* __restrict__ bidx, uint32_t cap,
-                                                    const uint32_t* __restrict__ flags) {
+// Step 2 with per-workgroup slot reservation: histogram the chunk's tiles in
+// LDS, reserve one contiguous run per non-empty tile with a single global
+// atomic, then hand out slots inside the run with LDS atomics.
+__global__ __launch_bounds__(kBinBlock) void k_scatter(Cam cam, Opts o, int64_t n, int64_t chunk,
+                                                       const float2* __restrict__ uv,
+                                                       const float* __restrict__ radius,
+                                                       const uint32_t* __restrict__ key,
+                                                       const uint32_t* __restrict__ ntiles,
+                                                       uint32_t* __restrict__ cursor,
+                                                       uint2* __restrict__ bucket, uint32_t cap,
+                                                       const uint32_t* __restrict__ flags) {
+  __shared__ uint32_t bins[kLdsBins];
+  if (flags[kFlagOverflow]) return;
+  const int nt = o.ntx * o.nty;
+  for (int t = threadIdx.x; t < nt; t += kBinBlock) bins[t] = 0u;
+  __syncthreads();
+  const int sh = tile_shift(o.T);
+  const Chunk c = chunk_of(n, chunk);
+  for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBinBlock) {
+    if (ntiles[i] == 0) continue;
+    const float2 p = uv[i];
+    const TileRect r = tile_rect(footprint(o, cam, p.x, p.y, radius ? radius[i] : 0.f), sh);
+    for (int ty = r.ty0; ty <= r.ty1; ++ty)
+      for (int tx = r.tx0; tx <= r.tx1; ++tx) atomicAdd(&bins[ty * o.ntx + tx], 1u);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nt; t += kBinBlock) {
+    const uint32_t v = bins[t];
+    if (v) bins[t] = atomicAdd(&cursor[t], v);
+  }
+  __syncthreads();
+  for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBinBlock) {
+    if (ntiles[i] == 0) continue;
+    const float2 p = uv[i];
+    const TileRect r = tile_rect(footprint(o, cam, p.x, p.y, radius ? radius[i] : 0.f), sh);
+    const uint2 e = make_uint2(key[i], (uint32_t)i);
+    for (int ty = r.ty0; ty <= r.ty1; ++ty)
+      for (int tx = r.tx0; tx <= r.tx1; ++tx) {
+        const uint32_t slot = atomicAdd(&bins[ty * o.ntx + tx], 1u);
+        if (slot < cap) bucket[slot] = e;  // always true when the counts of step 1 hold
+      }
+  }
+}
+
+// Step 2 for very large tile counts: one global atomic per copy.
+__global__ __launch_bounds__(kBlock) void k_scatter_global(
+    Cam cam, Opts o, int64_t n, const float2* __restrict__ uv, const float* __restrict__ radius,
+    const uint32_t* __restrict__ key, const uint32_t* __restrict__ ntiles,
+    uint32_t* __restrict__ cursor, uint2* __restrict__ bucket, uint32_t cap,
+    const uint32_t* __restrict__ flags) {
   if (flags[kFlagOverflow]) return;
   const int sh = tile_shift(o.T);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     if (ntiles[i] == 0) continue;
     const float2 p = uv[i];
-    const Footprint f = footprint(o, cam, p.x, p.y, radius ? radius[i] : 0.f);
-    const uint32_t k = key[i];
-    const int tx0 = f.px0 >> sh, tx1 = f.px1 >> sh, ty0 = f.py0 >> sh, ty1 = f.py1 >> sh;
-    for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx) {
+    const TileRect r = tile_rect(footprint(o, cam, p.x, p.y, radius ? radius[i] : 0.f), sh);
+    const uint2 e = make_uint2(key[i], (uint32_t)i);
+    for (int ty = r.ty0; ty <= r.ty1; ++ty)
+      for (int tx = r.tx0; tx <= r.tx1; ++tx) {
         const uint32_t slot = atomicAdd(&cursor[ty * o.ntx + tx], 1u);
-        if (slot < cap) {  // always true when the counts of step 1 hold
-          bkey[slot] = k;
-          bidx[slot] = (uint32_t)i;
-        }
+        if (slot < cap) bucket[slot] = e;
       }
-  }
-}
-
-// Gradients of points that no single tile owns (culled points and points
-// split over several tiles) start at zero; single-tile points are written
-// with plain stores by the blend backward.
-__global__ __launch_bounds__(kBlock) void k_grad_init(int64_t n, int C,
-                                                      const uint32_t* __restrict__ ntiles,
-                                                      float* __restrict__ grad_feat,
-                                                      float* __restrict__ grad_opacity,
-                                                      float2* __restrict__ grad_uv,
-                                                      float* __restrict__ grad_bg) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid == 0 && grad_bg)
-    for (int c = 0; c < C; ++c) grad_bg[c] = 0.f;
-  for (int64_t i = gid; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    if (ntiles[i] == 1) continue;
-    for (int c = 0; c < C; ++c) grad_feat[i * C + c] = 0.f;
-    grad_opacity[i] = 0.f;
-    grad_uv[i] = make_float2(0.f, 0.f);
   }
 }
 
@@ -204,12 +296,21 @@ int grid_for(int64_t n, int block) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 1 << 20));
 }
 
+// Points per privatised block: one wave of blocks over the whole GPU for
+// large clouds, at least 8192 points per block so the per-block flush of the
+// tile histogram stays small next to the copies it replaces.
+int64_t bin_chunk(int64_t n) {
+  const int64_t per = (n + 255) / 256;
+  const int64_t c = std::max<int64_t>(8192, per);
+  return (c + kBinBlock - 1) / kBinBlock * kBinBlock;
+}
+
 }  // namespace
 
 hipError_t launch_clear(uint32_t* p, size_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_clear, dim3((unsigned)std::min<size_t>((n + 255) / 256, 4096)), dim3(256), 0, s,
-                     p, n);
+  hipLaunchKernelGGL(k_clear, dim3((unsigned)std::min<size_t>((n + 255) / 256, 4096)), dim3(256),
+                     0, s, p, n);
   return hipGetLastError();
 }
 
@@ -222,8 +323,16 @@ hipError_t launch_project(const Cam& cam, const Opts& o, int64_t n, const float*
   e = launch_clear(ws.flags, kFlagSlots, s);
   if (e != hipSuccess) return e;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_project, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, cam, o, n, pos,
-                     radius, reinterpret_cast<float2*>(uv), key, ntiles, ws.tile_count);
+  if (nt <= kLdsBins) {
+    const int64_t chunk = bin_chunk(n);
+    hipLaunchKernelGGL(k_project_count, dim3((unsigned)((n + chunk - 1) / chunk)), dim3(kBinBlock),
+                       0, s, cam, o, n, chunk, pos, radius, reinterpret_cast<float2*>(uv), key,
+                       ntiles, ws.tile_count);
+  } else {
+    hipLaunchKernelGGL(k_project_count_global, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, cam,
+                       o, n, pos, radius, reinterpret_cast<float2*>(uv), key, ntiles,
+                       ws.tile_count);
+  }
   return hipGetLastError();
 }
 
@@ -234,17 +343,16 @@ hipError_t launch_bin(const Cam& cam, const Opts& o, int64_t n, const float* uv,
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, nt, ws.tile_count, ranges, ws.cursor, ws);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || n == 0) return e;
-  hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, cam, o, n,
-                     reinterpret_cast<const float2*>(uv), radius, key, ntiles, ws.cursor, ws.bkey,
-                     ws.bidx, ws.cap, ws.flags);
-  return hipGetLastError();
-}
-
-hipError_t launch_grad_init(int64_t n, int C, const uint32_t* ntiles, float* grad_feat,
-                            float* grad_opacity, float* grad_uv, float* grad_bg, hipStream_t s) {
-  hipLaunchKernelGGL(k_grad_init, dim3(grid_for(std::max<int64_t>(n, 1), kBlock)), dim3(kBlock), 0, s,
-                     n, C, ntiles, grad_feat, grad_opacity, reinterpret_cast<float2*>(grad_uv),
-                     grad_bg);
+  if (nt <= kLdsBins) {
+    const int64_t chunk = bin_chunk(n);
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)((n + chunk - 1) / chunk)), dim3(kBinBlock), 0, s,
+                       cam, o, n, chunk, reinterpret_cast<const float2*>(uv), radius, key, ntiles,
+                       ws.cursor, ws.bucket, ws.cap, ws.flags);
+  } else {
+    hipLaunchKernelGGL(k_scatter_global, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, cam, o, n,
+                       reinterpret_cast<const float2*>(uv), radius, key, ntiles, ws.cursor,
+                       ws.bucket, ws.cap, ws.flags);
+  }
   return hipGetLastError();
 }
 

@@ -5,21 +5,29 @@
 // leaves every tile's copies ordered by (depth key, point index).  Here the
 // copies are first bucketed by tile (inpc_bin) and every bucket is then
 // sorted on its own, which yields the same order with far less memory
-// traffic: the bucket of a tile is loaded once, sorted in LDS and written
-// once.
+// traffic: a bucket is loaded once, sorted in LDS and written once.
 //
-// Each bucket is sorted by an LSD radix sort on the depth key minus the
-// bucket's smallest key (8-bit digits, only as many passes as the key range
-// needs).  Ranks inside a wavefront come from 8 ballots per element (the
-// lanes sharing a digit), so no element order is ever decided by an atomic.
-// Equal depth keys are then put in point-index order; a bucket with a long
-// run of equal keys is re-sorted on the full (key, index) pair instead.
+// Work items are segments [start, start + n) of the bucket array; every
+// non-empty tile starts as one segment.  By size:
+//   n <= 64     rank sort by one wavefront (each lane counts the smaller
+//               (key, index) pairs)
+//   n <= 256    LSD radix sort by one wavefront, 4 elements per lane
+//   n <= 2048   LSD radix sort by a 256-thread block, 8 elements per lane
+//   n <= 16384  MSD split: one 1024-thread block loads the segment into LDS,
+//               buckets it by the top 8 bits of the (key, index) pair
+//               relative to the segment's range, writes it back in place and
+//               queues the sub-segments (which are then sorted on their own;
+//               concatenated in digit order they give the sorted segment).
+//               Two split rounds; what is still larger is LSD-sorted by a
+//               1024-thread block.
+//   larger      LSD radix sort through global memory by a 1024-thread block.
 //
-// Size classes (chosen per tile by inpc_bin):
-//   W: n <= 256    one wavefront per tile, 4 elements per lane
-//   M: n <= 2048   256 threads, 8 elements per lane
-//   L: n <= 16384  1024 threads, 16 elements per lane
-//   X: larger      1024 threads, rounds of 16384 through global memory
+// The LSD sorts rank elements inside a wavefront with 8 ballots per element
+// (the lanes sharing a digit), so no order is decided by an atomic.  They
+// run on the depth key minus the segment's smallest key; equal keys are then
+// put in index order, and a segment with a long run of equal keys is re-sorted
+// on the full (key, index) pair.  Element placement by LDS atomics happens only
+// in the MSD split, whose sub-segments are fully sorted afterwards.
 #include "common.h"
 #include "internal.h"
 
@@ -90,13 +98,13 @@ struct Digits {
   __device__ __forceinline__ int passes() const { return nidx + nkey; }
 };
 
-// Shared-memory layout of one sorter (one tile at a time).
+// Shared-memory layout of one sorter (one segment at a time).
 struct SortSmem {
   uint32_t* key;   // [CAP]
   uint32_t* idx;   // [CAP]
   uint32_t* hist;  // [NW * 256]
   uint32_t* off;   // [256] digit offsets / running bases
-  uint32_t* red;   // [32] reduction scratch
+  uint32_t* red;   // [64] reduction scratch
 };
 
 // Rank every element among the NW*ITEMS*64 striped elements by digit,
@@ -112,12 +120,11 @@ __device__ __forceinline__ void block_rank(const uint32_t (&d)[ITEMS], const boo
   uint32_t* hist = sm.hist + w * 256;
   for (uint32_t k = lane; k < 256; k += 64) hist[k] = 0;
   bsync<true>();
-  uint32_t local[ITEMS];
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     const uint64_t m = match8(d[j]) & __ballot(valid[j]);
     const uint32_t pre = valid[j] ? hist[d[j]] : 0u;
-    local[j] = pre + mbcnt64(m);
+    rank[j] = pre + mbcnt64(m);
     const bool leader = valid[j] && (mbcnt64(m) == 0);
     if (leader) hist[d[j]] = pre + (uint32_t)__popcll(m);
     bsync<true>();
@@ -137,7 +144,6 @@ __device__ __forceinline__ void block_rank(const uint32_t (&d)[ITEMS], const boo
     if (running) {
       const uint32_t base = sm.off[dd];
       sm.off[dd] = base + acc;  // next round starts after this one
-      // shift this round's per-wave prefixes by the running base
 #pragma unroll
       for (int ww = 0; ww < NW; ++ww) sm.hist[ww * 256 + dd] += base;
     } else {
@@ -166,18 +172,16 @@ __device__ __forceinline__ void block_rank(const uint32_t (&d)[ITEMS], const boo
   }
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
-    if (valid[j]) {
-      rank[j] = local[j] + hist[d[j]] + (running ? 0u : sm.off[d[j]]);
-    }
+    if (valid[j]) rank[j] += hist[d[j]] + (running ? 0u : sm.off[d[j]]);
   }
   bsync<WAVE_ONLY>();
 }
 
-// Sort n <= NW*ITEMS*64 (key, idx) pairs of one tile entirely in LDS and
+// Sort n <= NW*ITEMS*64 (key, idx) pairs of one segment entirely in LDS and
 // write the point indices in (key, idx) order to out[0..n).
 template <int NW, int ITEMS, bool WAVE_ONLY>
-__device__ void sort_tile_lds(const uint32_t* __restrict__ gkey, const uint32_t* __restrict__ gidx,
-                              uint32_t n, uint32_t* __restrict__ out, const SortSmem& sm) {
+__device__ void sort_segment_lds(const uint2* __restrict__ seg, uint32_t n,
+                                 uint32_t* __restrict__ out, const SortSmem& sm) {
   constexpr int PER_WAVE = ITEMS * 64;
   const uint32_t lane = __lane_id();
   const uint32_t w = WAVE_ONLY ? 0u : (threadIdx.x >> 6);
@@ -192,8 +196,9 @@ __device__ void sort_tile_lds(const uint32_t* __restrict__ gkey, const uint32_t*
   for (int j = 0; j < ITEMS; ++j) {
     const uint32_t e = base_e + j * 64 + lane;
     valid[j] = e < n;
-    key[j] = valid[j] ? gkey[e] : 0u;
-    idx[j] = valid[j] ? gidx[e] : 0u;
+    const uint2 v = valid[j] ? seg[e] : make_uint2(0u, 0u);
+    key[j] = v.x;
+    idx[j] = v.y;
     if (valid[j]) {
       kmin = min(kmin, key[j]); kmax = max(kmax, key[j]);
       imin = min(imin, idx[j]); imax = max(imax, idx[j]);
@@ -224,12 +229,13 @@ __device__ void sort_tile_lds(const uint32_t* __restrict__ gkey, const uint32_t*
   for (int attempt = 0; attempt < 2; ++attempt) {
     if (attempt == 1) {
       // long runs of equal keys: sort the full (key, index) pair, starting
-      // again from the unsorted bucket
+      // again from the unsorted segment
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j) {
         const uint32_t e = base_e + j * 64 + lane;
-        key[j] = valid[j] ? gkey[e] : 0u;
-        idx[j] = valid[j] ? gidx[e] : 0u;
+        const uint2 v = valid[j] ? seg[e] : make_uint2(0u, 0u);
+        key[j] = v.x;
+        idx[j] = v.y;
       }
       dp.nidx = (int)((nbits(imax - imin) + 7) / 8);
     }
@@ -259,7 +265,7 @@ __device__ void sort_tile_lds(const uint32_t* __restrict__ gkey, const uint32_t*
       }
     }
     if (np == 0) {
-      // a single key value: the order is the index order
+      // a single key value: keep the loaded order, fixed below
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j) {
         const uint32_t e = base_e + j * 64 + lane;
@@ -311,39 +317,54 @@ __device__ void sort_tile_lds(const uint32_t* __restrict__ gkey, const uint32_t*
   bsync<WAVE_ONLY>();
 }
 
-// Class W: one wavefront per tile, four tiles per 256-thread block.
+// n <= 64: every lane counts the (key, index) pairs smaller than its own.
+__device__ void rank_sort_wave(const uint2* __restrict__ seg, uint32_t n,
+                               uint32_t* __restrict__ out, uint2* __restrict__ s) {
+  const uint32_t lane = __lane_id();
+  const bool valid = lane < n;
+  const uint2 v = valid ? seg[lane] : make_uint2(0u, 0u);
+  s[lane] = v;
+  bsync<true>();
+  uint32_t r = 0;
+  for (uint32_t m = 0; m < n; ++m) {
+    const uint2 o = s[m];
+    r += (o.x < v.x) || (o.x == v.x && o.y < v.y);
+  }
+  if (valid) out[r] = v.y;
+  bsync<true>();
+}
+
+// Segments of at most 256 copies: one wavefront each, four per block.
 constexpr int kW_ITEMS = 4;
 constexpr int kW_CAP = kW_ITEMS * 64;
 
-__global__ __launch_bounds__(256) void k_sort_w(const uint32_t* __restrict__ ranges,
-                                                const uint32_t* __restrict__ tiles,
+__global__ __launch_bounds__(256) void k_sort_w(const uint2* __restrict__ segs,
                                                 const uint32_t* __restrict__ flags,
-                                                const uint32_t* __restrict__ bkey,
-                                                const uint32_t* __restrict__ bidx,
+                                                const uint2* __restrict__ bucket,
                                                 uint32_t* __restrict__ list) {
   __shared__ uint32_t s_key[4][kW_CAP];
   __shared__ uint32_t s_idx[4][kW_CAP];
   __shared__ uint32_t s_hist[4][256];
   __shared__ uint32_t s_off[4][256];
-  __shared__ uint32_t s_red[4][32];
+  __shared__ uint32_t s_red[4][64];
   if (flags[kFlagOverflow]) return;
   const uint32_t w = threadIdx.x >> 6;
   SortSmem sm{s_key[w], s_idx[w], s_hist[w], s_off[w], s_red[w]};
   const uint32_t count = flags[kFlagCountW];
   for (uint32_t i = blockIdx.x * 4 + w; i < count; i += gridDim.x * 4) {
-    const uint32_t t = tiles[i];
-    const uint32_t s = ranges[t], n = ranges[t + 1] - s;
-    sort_tile_lds<1, kW_ITEMS, true>(bkey + s, bidx + s, n, list + s, sm);
+    const uint2 sg = segs[i];
+    if (sg.y <= 64)
+      rank_sort_wave(bucket + sg.x, sg.y, list + sg.x, reinterpret_cast<uint2*>(s_key[w]));
+    else
+      sort_segment_lds<1, kW_ITEMS, true>(bucket + sg.x, sg.y, list + sg.x, sm);
   }
 }
 
-// Classes M and L: one block per tile.
+// Segments of at most NW*ITEMS*64 copies: one block each.
 template <int NW, int ITEMS, int FLAG>
-__global__ __launch_bounds__(NW * 64) void k_sort_block(const uint32_t* __restrict__ ranges,
-                                                        const uint32_t* __restrict__ tiles,
+__global__ __launch_bounds__(NW * 64) void k_sort_block(const uint2* __restrict__ segs,
                                                         const uint32_t* __restrict__ flags,
-                                                        const uint32_t* __restrict__ bkey,
-                                                        const uint32_t* __restrict__ bidx,
+                                                        const uint2* __restrict__ bucket,
                                                         uint32_t* __restrict__ list) {
   constexpr int CAP = NW * ITEMS * 64;
   __shared__ uint32_t s_key[CAP];
@@ -355,44 +376,124 @@ __global__ __launch_bounds__(NW * 64) void k_sort_block(const uint32_t* __restri
   SortSmem sm{s_key, s_idx, s_hist, s_off, s_red};
   const uint32_t count = flags[FLAG];
   for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
-    const uint32_t t = tiles[i];
-    const uint32_t s = ranges[t], n = ranges[t + 1] - s;
-    sort_tile_lds<NW, ITEMS, false>(bkey + s, bidx + s, n, list + s, sm);
+    const uint2 sg = segs[i];
+    sort_segment_lds<NW, ITEMS, false>(bucket + sg.x, sg.y, list + sg.x, sm);
   }
 }
 
-// Class X: tiles larger than the LDS capacity.  LSD passes over the full
+// Append one segment per thread (threads with an empty segment pass n = 0)
+// to the class lists: one global atomic per (block, class).
+__device__ void push_segments(uint2 sg, bool split_again, const Ws& ws, uint32_t* s_cnt,
+                              uint32_t* s_base) {
+  int c = 3;  // 0: W, 1: M, 2: split again / L, 3: none
+  if (sg.y > 0) c = sg.y <= kSortCapW ? 0 : (sg.y <= kSortCapM ? 1 : 2);
+  if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  uint32_t my = 0;
+  if (c < 3) my = atomicAdd(&s_cnt[c], 1u);
+  __syncthreads();
+  if (threadIdx.x < 3 && s_cnt[threadIdx.x]) {
+    const int cc = (int)threadIdx.x;
+    const int slot = cc == 0 ? kFlagCountW
+                             : (cc == 1 ? kFlagCountM : (split_again ? kFlagCountB1 : kFlagCountL));
+    s_base[cc] = atomicAdd(&ws.flags[slot], s_cnt[cc]);
+  }
+  __syncthreads();
+  if (c < 3) {
+    uint2* dst = c == 0 ? ws.seg_w : (c == 1 ? ws.seg_m : (split_again ? ws.seg_b1 : ws.seg_l));
+    dst[s_base[c] + my] = sg;
+  }
+  __syncthreads();
+}
+
+// MSD split of segments with 2048 < n <= 16384 copies (in place).
+__global__ __launch_bounds__(1024) void k_split(int round, Ws ws) {
+  __shared__ uint2 s_e[kSortCapL];
+  __shared__ uint32_t s_cnt[256], s_off[256];
+  __shared__ uint32_t s_red[64];
+  __shared__ uint32_t s_pc[3], s_pb[3];
+  if (ws.flags[kFlagOverflow]) return;
+  const uint2* segs = round == 0 ? ws.seg_b0 : ws.seg_b1;
+  const uint32_t count = ws.flags[round == 0 ? kFlagCountB0 : kFlagCountB1];
+  const uint32_t lane = __lane_id(), w = threadIdx.x >> 6;
+  for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+    const uint2 sg = segs[i];
+    const uint32_t n = sg.y;
+    uint2* g = ws.bucket + sg.x;
+    uint32_t kmin = 0xffffffffu, kmax = 0, imin = 0xffffffffu, imax = 0;
+    for (uint32_t e = threadIdx.x; e < n; e += 1024) {
+      const uint2 v = g[e];
+      s_e[e] = v;
+      kmin = min(kmin, v.x); kmax = max(kmax, v.x);
+      imin = min(imin, v.y); imax = max(imax, v.y);
+    }
+    if (threadIdx.x < 256) s_cnt[threadIdx.x] = 0;
+    kmin = wave_min(kmin); kmax = wave_max(kmax);
+    imin = wave_min(imin); imax = wave_max(imax);
+    if (lane == 0) {
+      s_red[w * 4 + 0] = kmin; s_red[w * 4 + 1] = kmax;
+      s_red[w * 4 + 2] = imin; s_red[w * 4 + 3] = imax;
+    }
+    __syncthreads();
+    kmin = 0xffffffffu; kmax = 0; imin = 0xffffffffu; imax = 0;
+    for (int ww = 0; ww < 16; ++ww) {
+      kmin = min(kmin, s_red[ww * 4 + 0]); kmax = max(kmax, s_red[ww * 4 + 1]);
+      imin = min(imin, s_red[ww * 4 + 2]); imax = max(imax, s_red[ww * 4 + 3]);
+    }
+    // digit: top 8 bits of ((key - kmin) << ib) | (idx - imin)
+    const uint32_t ib = nbits(imax - imin);
+    const uint32_t total = nbits(kmax - kmin) + ib;
+    const uint32_t sh = total > 8 ? total - 8 : 0;
+    const uint32_t k0 = kmin, i0 = imin;
+    auto digit = [=](uint2 v) -> uint32_t {
+      const uint64_t c = ((uint64_t)(v.x - k0) << ib) | (uint64_t)(v.y - i0);
+      return (uint32_t)(c >> sh);
+    };
+    for (uint32_t e = threadIdx.x; e < n; e += 1024) atomicAdd(&s_cnt[digit(s_e[e])], 1u);
+    __syncthreads();
+    if (w == 0) {
+      uint32_t t4[4], s = 0;
+      for (int q = 0; q < 4; ++q) { t4[q] = s_cnt[lane * 4 + q]; s += t4[q]; }
+      uint32_t ex = wave_incl_scan(s) - s;
+      for (int q = 0; q < 4; ++q) { s_off[lane * 4 + q] = ex; ex += t4[q]; }
+    }
+    __syncthreads();
+    // sub-segment descriptors, taken before the offsets are consumed
+    uint2 sub = make_uint2(0u, 0u);
+    if (threadIdx.x < 256) sub = make_uint2(sg.x + s_off[threadIdx.x], s_cnt[threadIdx.x]);
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < n; e += 1024) {
+      const uint2 v = s_e[e];
+      g[atomicAdd(&s_off[digit(v)], 1u)] = v;
+    }
+    push_segments(sub, round == 0, ws, s_pc, s_pb);
+  }
+}
+
+// Segments larger than the LDS capacity.  LSD passes over the full
 // (key, index) pair through global memory, in rounds of NW*ITEMS*64
-// elements; each pass first histograms the whole tile so that every round
+// elements; each pass first histograms the whole segment so that every round
 // knows where each digit's run starts.
 template <int NW, int ITEMS>
-__global__ __launch_bounds__(NW * 64) void k_sort_x(const uint32_t* __restrict__ ranges,
-                                                    const uint32_t* __restrict__ tiles,
-                                                    const uint32_t* __restrict__ flags,
-                                                    uint32_t* __restrict__ bkey,
-                                                    uint32_t* __restrict__ bidx,
-                                                    uint32_t* __restrict__ xkey,
-                                                    uint32_t* __restrict__ xidx,
-                                                    uint32_t* __restrict__ list) {
+__global__ __launch_bounds__(NW * 64) void k_sort_x(Ws ws, uint32_t* __restrict__ list) {
   constexpr int ROUND = NW * ITEMS * 64;
   __shared__ uint32_t s_hist[NW * 256];
   __shared__ uint32_t s_off[256];
   __shared__ uint32_t s_red[64];
   __shared__ uint32_t s_glob[256];
-  if (flags[kFlagOverflow]) return;
+  if (ws.flags[kFlagOverflow]) return;
   SortSmem sm{nullptr, nullptr, s_hist, s_off, s_red};
   const uint32_t lane = __lane_id();
   const uint32_t w = threadIdx.x >> 6;
-  const uint32_t count = flags[kFlagCountX];
+  const uint32_t count = ws.flags[kFlagCountX];
   for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
-    const uint32_t t = tiles[i];
-    const uint32_t s = ranges[t], n = ranges[t + 1] - s;
-    // key and index ranges
+    const uint2 sg = ws.seg_x[i];
+    const uint32_t s = sg.x, n = sg.y;
     uint32_t kmin = 0xffffffffu, kmax = 0, imin = 0xffffffffu, imax = 0;
     for (uint32_t e = threadIdx.x; e < n; e += NW * 64) {
-      const uint32_t k = bkey[s + e], x = bidx[s + e];
-      kmin = min(kmin, k); kmax = max(kmax, k);
-      imin = min(imin, x); imax = max(imax, x);
+      const uint2 v = ws.bucket[s + e];
+      kmin = min(kmin, v.x); kmax = max(kmax, v.x);
+      imin = min(imin, v.y); imax = max(imax, v.y);
     }
     kmin = wave_min(kmin); kmax = wave_max(kmax);
     imin = wave_min(imin); imax = wave_max(imax);
@@ -413,12 +514,15 @@ __global__ __launch_bounds__(NW * 64) void k_sort_x(const uint32_t* __restrict__
     dp.nkey = (int)((nbits(kmax - kmin) + 7) / 8);
     dp.nidx = (int)((nbits(imax - imin) + 7) / 8);
     const int np = dp.passes();
-    uint32_t *sk = bkey + s, *si = bidx + s, *dk = xkey + s, *di = xidx + s;
+    uint2* src = ws.bucket + s;
+    uint2* dst = ws.xbucket + s;
     for (int p = 0; p < np; ++p) {
-      // histogram of this pass's digit over the whole tile
       for (int k = threadIdx.x; k < 256; k += NW * 64) s_glob[k] = 0;
       __syncthreads();
-      for (uint32_t e = threadIdx.x; e < n; e += NW * 64) atomicAdd(&s_glob[dp.get(sk[e], si[e], p)], 1u);
+      for (uint32_t e = threadIdx.x; e < n; e += NW * 64) {
+        const uint2 v = src[e];
+        atomicAdd(&s_glob[dp.get(v.x, v.y, p)], 1u);
+      }
       __syncthreads();
       if (w == 0) {
         uint32_t t4[4], sum = 0;
@@ -428,37 +532,35 @@ __global__ __launch_bounds__(NW * 64) void k_sort_x(const uint32_t* __restrict__
       }
       __syncthreads();
       const bool last = p + 1 == np;
-      uint32_t* out_idx = last ? list + s : di;
       for (uint32_t r0 = 0; r0 < n; r0 += ROUND) {
-        uint32_t key[ITEMS], idx[ITEMS], dg[ITEMS], rank[ITEMS];
+        uint2 v[ITEMS];
+        uint32_t dg[ITEMS], rank[ITEMS];
         bool valid[ITEMS];
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
           const uint32_t e = r0 + w * ITEMS * 64 + j * 64 + lane;
           valid[j] = e < n;
-          key[j] = valid[j] ? sk[e] : 0u;
-          idx[j] = valid[j] ? si[e] : 0u;
-          dg[j] = dp.get(key[j], idx[j], p);
+          v[j] = valid[j] ? src[e] : make_uint2(0u, 0u);
+          dg[j] = dp.get(v[j].x, v[j].y, p);
         }
         block_rank<NW, ITEMS, false>(dg, valid, rank, sm, true);
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
           if (valid[j]) {
-            if (!last) dk[rank[j]] = key[j];
-            out_idx[rank[j]] = idx[j];
+            if (last)
+              list[s + rank[j]] = v[j].y;
+            else
+              dst[rank[j]] = v[j];
           }
         }
       }
       __syncthreads();
-      if (!last) {
-        uint32_t* tk = sk; sk = dk; dk = tk;
-        uint32_t* ti = si; si = di; di = ti;
-      }
-      __threadfence_block();
-      __syncthreads();
+      uint2* t = src;
+      src = dst;
+      dst = t;
     }
     if (np == 0) {
-      for (uint32_t e = threadIdx.x; e < n; e += NW * 64) list[s + e] = bidx[s + e];
+      for (uint32_t e = threadIdx.x; e < n; e += NW * 64) list[s + e] = ws.bucket[s + e].y;
     }
     __syncthreads();
   }
@@ -466,20 +568,20 @@ __global__ __launch_bounds__(NW * 64) void k_sort_x(const uint32_t* __restrict__
 
 }  // namespace
 
-hipError_t launch_sort(const uint32_t* ranges, const Ws& ws, uint32_t* list, int64_t nt,
-                       hipStream_t stream) {
-  const int grid_w = (int)std::min<int64_t>((nt + 3) / 4, 4096);
-  hipLaunchKernelGGL(k_sort_w, dim3(std::max(grid_w, 1)), dim3(256), 0, stream, ranges, ws.list_w,
-                     ws.flags, ws.bkey, ws.bidx, list);
-  const int grid_m = (int)std::min<int64_t>(nt, 2048);
-  hipLaunchKernelGGL((k_sort_block<4, 8, kFlagCountM>), dim3(std::max(grid_m, 1)), dim3(256), 0, stream,
-                     ranges, ws.list_m, ws.flags, ws.bkey, ws.bidx, list);
-  const int grid_l = (int)std::min<int64_t>(nt, 512);
-  hipLaunchKernelGGL((k_sort_block<16, 16, kFlagCountL>), dim3(std::max(grid_l, 1)), dim3(1024), 0,
-                     stream, ranges, ws.list_l, ws.flags, ws.bkey, ws.bidx, list);
-  const int grid_x = (int)std::min<int64_t>(nt, 256);
-  hipLaunchKernelGGL((k_sort_x<16, 16>), dim3(std::max(grid_x, 1)), dim3(1024), 0, stream, ranges,
-                     ws.list_x, ws.flags, ws.bkey, ws.bidx, ws.xkey, ws.xidx, list);
+hipError_t launch_sort(const Ws& ws, uint32_t* list, int64_t nt, hipStream_t stream) {
+  const int64_t big_max = std::max<int64_t>(1, (int64_t)ws.cap / (int64_t)(kSortCapM + 1));
+  const int grid_split = (int)std::min<int64_t>(big_max, 1024);
+  hipLaunchKernelGGL(k_split, dim3(grid_split), dim3(1024), 0, stream, 0, ws);
+  hipLaunchKernelGGL(k_split, dim3(grid_split), dim3(1024), 0, stream, 1, ws);
+  const int grid_w = (int)std::min<int64_t>((nt + 3) / 4 + (int64_t)ws.cap / 256, 8192);
+  hipLaunchKernelGGL(k_sort_w, dim3(std::max(grid_w, 1)), dim3(256), 0, stream, ws.seg_w, ws.flags,
+                     ws.bucket, list);
+  const int grid_m = (int)std::min<int64_t>(nt + (int64_t)ws.cap / 2048, 4096);
+  hipLaunchKernelGGL((k_sort_block<4, 8, kFlagCountM>), dim3(std::max(grid_m, 1)), dim3(256), 0,
+                     stream, ws.seg_m, ws.flags, ws.bucket, list);
+  hipLaunchKernelGGL((k_sort_block<16, 16, kFlagCountL>), dim3(grid_split), dim3(1024), 0, stream,
+                     ws.seg_l, ws.flags, ws.bucket, list);
+  hipLaunchKernelGGL((k_sort_x<16, 16>), dim3(256), dim3(1024), 0, stream, ws, list);
   return hipGetLastError();
 }
 

@@ -135,8 +135,12 @@ def blend_forward(b: Binning, opacity, feat, cam: L.Camera, opts: L.Opts, ws: to
     return out, t_final, n_contrib, state
 
 
+def backward_scratch_bytes(n: int, C: int, cam: L.Camera, opts: L.Opts) -> int:
+    return int(L.lib().inpc_backward_scratch_bytes(n, C, ctypes.byref(cam), ctypes.byref(opts)))
+
+
 def blend_backward(b: Binning, opacity, feat, cam: L.Camera, opts: L.Opts, ws: torch.Tensor,
-                   t_final, state, grad_out, grad_t=None, bg=None):
+                   t_final, state, grad_out, grad_t=None, bg=None, scratch=None):
     """Step 5.  Returns grad_feat [n,C] f32, grad_opacity [n], grad_uv [n,2], grad_bg [C]|None."""
     dev = opacity.device
     n, C = feat.shape
@@ -144,10 +148,14 @@ def blend_backward(b: Binning, opacity, feat, cam: L.Camera, opts: L.Opts, ws: t
     grad_opacity = torch.empty(n, dtype=torch.float32, device=dev)
     grad_uv = torch.empty(n, 2, dtype=torch.float32, device=dev)
     grad_bg = torch.empty(C, dtype=torch.float32, device=dev) if bg is not None else None
+    if scratch is None:
+        scratch = torch.empty(backward_scratch_bytes(n, C, cam, opts), dtype=torch.uint8,
+                              device=dev)
     L.call("inpc_blend_backward", ctypes.byref(cam), ctypes.byref(opts), n, _p(b.uv),
            _p(opacity), _p(feat), C, _DTYPES[feat.dtype], _p(bg), _p(b.ntiles), _p(b.ranges),
            _p(b.list), _p(t_final), _p(state), _p(grad_out), _p(grad_t), _p(grad_feat),
-           _p(grad_opacity), _p(grad_uv), _p(grad_bg), _p(ws), ws.numel(), _stream(dev))
+           _p(grad_opacity), _p(grad_uv), _p(grad_bg), _p(scratch), scratch.numel(), _p(ws),
+           ws.numel(), _stream(dev))
     return grad_feat, grad_opacity, grad_uv, grad_bg
 
 

@@ -107,8 +107,21 @@ def test_backward_rejects_gaussians():
     wsb = lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(g))
     st = lib.inpc_blend_backward(ctypes.byref(c), ctypes.byref(g), n, FAKE, FAKE, FAKE, 4,
                                  L.DTYPE_F32, None, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None,
-                                 FAKE, FAKE, FAKE, None, FAKE, wsb, None)
+                                 FAKE, FAKE, FAKE, None, FAKE, 1 << 20, FAKE, wsb, None)
     assert st == L.INPC_ERR_UNSUPPORTED
+
+
+def test_backward_rejects_small_scratch():
+    lib = L.lib()
+    c, o = cam(), L.make_opts(tile=8)
+    n, C = 10, 4
+    wsb = lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(o))
+    need = lib.inpc_backward_scratch_bytes(n, C, ctypes.byref(c), ctypes.byref(o))
+    assert need >= n * 4 * 8 * 4
+    args = [ctypes.byref(c), ctypes.byref(o), n, FAKE, FAKE, FAKE, C, L.DTYPE_F32, None, FAKE,
+            FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, FAKE, None]
+    assert lib.inpc_blend_backward(*args, FAKE, need - 1, FAKE, wsb, None) == L.INPC_ERR_INVALID
+    assert lib.inpc_blend_backward(*args, None, need, FAKE, wsb, None) == L.INPC_ERR_INVALID
 
 
 def test_status_strings():
