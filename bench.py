@@ -71,8 +71,9 @@ class Step:
         mk = lambda *s, dt=torch.float32: torch.empty(*s, dtype=dt, device=dev)
         self.uv, self.key, self.ntiles = mk(n, 2), mk(n, dt=i32), mk(n, dt=i32)
         self.ranges, self.list = mk(nt + 1, dt=i32), mk(cap, dt=i32)
+        self.order = mk(nt, dt=i32)
         self.out, self.tf, self.nc = mk(C, H, W), mk(H, W), mk(H, W, dt=i32)
-        self.state = mk(int(lib.inpc_state_bytes(cb)), dt=torch.uint8)
+        self.state = mk(int(lib.inpc_state_bytes(cb, ob)), dt=torch.uint8)
         self.gf, self.go, self.guv, self.gpos = mk(n, C), mk(n), mk(n, 2), mk(n, 3)
         self.scratch = mk(int(lib.inpc_backward_scratch_bytes(n, C, cb, ob)), dt=torch.uint8)
         self.lib = lib
@@ -93,7 +94,8 @@ class Step:
     def bin(self):
         p, lib = self.p, self.lib
         self._chk(lib.inpc_bin(self.cb, self.ob, self.n, p(self.uv), None, p(self.key),
-                               p(self.ntiles), p(self.ranges), p(self.ws), self.ws.numel(),
+                               p(self.ntiles), p(self.ranges), p(self.order), p(self.ws),
+                               self.ws.numel(),
                                self.stream), "bin")
 
     def sort(self):
@@ -105,6 +107,7 @@ class Step:
         p, lib = self.p, self.lib
         self._chk(lib.inpc_blend_forward(self.cb, self.ob, self.n, p(self.uv), None, p(self.op),
                                          p(self.feat), self.C, 0, None, p(self.ranges),
+                                         p(self.order),
                                          p(self.list), p(self.out), p(self.tf), p(self.nc),
                                          p(self.state), p(self.ws), self.ws.numel(), self.stream),
                   "blend_forward")
@@ -113,7 +116,8 @@ class Step:
         p, lib = self.p, self.lib
         self._chk(lib.inpc_blend_backward(self.cb, self.ob, self.n, p(self.uv), p(self.op),
                                           p(self.feat), self.C, 0, None, p(self.ntiles),
-                                          p(self.ranges), p(self.list), p(self.tf), p(self.state),
+                                          p(self.ranges), p(self.order), p(self.list), p(self.tf),
+                                          p(self.state),
                                           p(self.grad), None, p(self.gf), p(self.go), p(self.guv),
                                           None, p(self.scratch), self.scratch.numel(), p(self.ws),
                                           self.ws.numel(), self.stream),

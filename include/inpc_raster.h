@@ -87,8 +87,11 @@ typedef struct {
  * max_radius.  Returns 0 for invalid arguments. */
 size_t inpc_workspace_bytes(int64_t n, const inpc_camera_t* cam, const inpc_opts_t* opts);
 
-/* Bytes of the per-pixel forward state the backward pass reads (12 per pixel). */
-size_t inpc_state_bytes(const inpc_camera_t* cam);
+/* Bytes of the forward state the backward pass reads: 12 per pixel (how far
+ * down its tile list the pixel blended, and the transmittance in front of
+ * its last blended fragment with nonzero transmittance) plus 4 per tile.
+ * 0 if invalid. */
+size_t inpc_state_bytes(const inpc_camera_t* cam, const inpc_opts_t* opts);
 
 /* Number of tiles, ceil(W/T) * ceil(H/T); tile t covers columns
  * [T (t mod ntx), ...) and rows [T (t div ntx), ...).  0 if invalid. */
@@ -118,11 +121,14 @@ inpc_status_t inpc_project(const inpc_camera_t* cam, const inpc_opts_t* opts, in
  *   uv, radius, depth_key, ntiles: outputs of inpc_project
  *   tile_ranges [num_tiles + 1] u32 out: tile t owns list[tile_ranges[t] ..
  *               tile_ranges[t+1]); tile_ranges[num_tiles] = total copies M
+ *   tile_order  [num_tiles] u32 out, or NULL: a permutation of the tiles by
+ *               decreasing copy count, for the blend passes (results do not
+ *               depend on it; it only schedules long lists first)
  */
 inpc_status_t inpc_bin(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
                        const float* uv, const float* radius, const uint32_t* depth_key,
-                       const uint32_t* ntiles, uint32_t* tile_ranges, void* ws,
-                       size_t ws_bytes, void* stream);
+                       const uint32_t* ntiles, uint32_t* tile_ranges, uint32_t* tile_order,
+                       void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Step 3 -- depth sort per tile (Sec. 3.2: depth-sorted per-tile lists).
@@ -151,6 +157,8 @@ int64_t inpc_copy_capacity(int64_t n, const inpc_camera_t* cam, const inpc_opts_
  *   feat       [n][C] features, dtype INPC_F32 / INPC_F16 / INPC_BF16
  *              (blending and accumulation are FP32 for every dtype)
  *   bg         [C] f32 constant background features, or NULL (zero)
+ *   tile_ranges, list: outputs of inpc_bin / inpc_sort
+ *   tile_order [num_tiles] from inpc_bin, or NULL (tile-index order)
  *   out        [C][H][W] f32 out: feature image
  *   t_final    [H][W] f32 out: transmittance behind the last blended fragment
  *   n_contrib  [H][W] u32 out: number of blended fragments
@@ -160,9 +168,10 @@ int64_t inpc_copy_capacity(int64_t n, const inpc_camera_t* cam, const inpc_opts_
 inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
                                  const float* uv, const float* radius, const float* opacity,
                                  const void* feat, int32_t C, int32_t dtype, const float* bg,
-                                 const uint32_t* tile_ranges, const uint32_t* list, float* out,
-                                 float* t_final, uint32_t* n_contrib, void* state,
-                                 void* ws, size_t ws_bytes, void* stream);
+                                 const uint32_t* tile_ranges, const uint32_t* tile_order,
+                                 const uint32_t* list, float* out, float* t_final,
+                                 uint32_t* n_contrib, void* state, void* ws, size_t ws_bytes,
+                                 void* stream);
 
 /*
  * Step 5 -- blend backward (Appendix A, Eq. (2), with the sign of the
@@ -191,7 +200,8 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
                                   const float* uv, const float* opacity, const void* feat,
                                   int32_t C, int32_t dtype, const float* bg,
                                   const uint32_t* ntiles, const uint32_t* tile_ranges,
-                                  const uint32_t* list, const float* t_final, const void* state,
+                                  const uint32_t* tile_order, const uint32_t* list,
+                                  const float* t_final, const void* state,
                                   const float* grad_out, const float* grad_t, float* grad_feat,
                                   float* grad_opacity, float* grad_uv, float* grad_bg,
                                   void* scratch, size_t scratch_bytes, void* ws, size_t ws_bytes,

@@ -68,16 +68,16 @@ def lib():
     CP, OP = ctypes.POINTER(Camera), ctypes.POINTER(Opts)
     sig = {
         "inpc_workspace_bytes": (SZ, [I64, CP, OP]),
-        "inpc_state_bytes": (SZ, [CP]),
+        "inpc_state_bytes": (SZ, [CP, OP]),
         "inpc_num_tiles": (I64, [CP, OP]),
         "inpc_copy_capacity": (I64, [I64, CP, OP]),
         "inpc_project": (I32, [CP, OP, I64, P, P, P, P, P, P, SZ, P]),
-        "inpc_bin": (I32, [CP, OP, I64, P, P, P, P, P, P, SZ, P]),
+        "inpc_bin": (I32, [CP, OP, I64, P, P, P, P, P, P, P, SZ, P]),
         "inpc_sort": (I32, [CP, OP, I64, P, P, P, SZ, P]),
         "inpc_blend_forward": (I32, [CP, OP, I64, P, P, P, P, I32, I32, P, P, P, P, P, P, P,
-                                     P, SZ, P]),
+                                     P, P, SZ, P]),
         "inpc_blend_backward": (I32, [CP, OP, I64, P, P, P, I32, I32, P, P, P, P, P, P, P, P,
-                                      P, P, P, P, P, SZ, P, SZ, P]),
+                                      P, P, P, P, P, P, SZ, P, SZ, P]),
         "inpc_backward_scratch_bytes": (SZ, [I64, I32, CP, OP]),
         "inpc_project_backward": (I32, [CP, I64, P, P, P, P, P]),
         "inpc_check_sync": (I32, [P, SZ, P]),

@@ -117,11 +117,21 @@ Ws make_ws(void* ws, int64_t n, const inpc_camera_t* c, const inpc_opts_t* o) {
   return w;
 }
 
-// Backward scratch: per-(point, tile slot) partial gradients, then the
-// per-tile background shares.
+// Backward scratch: visited flags (one word per point), per-(point, tile
+// slot) partial gradients, per-tile background shares.
+size_t scratch_visited_bytes(int64_t n) { return align_up((size_t)n * 4); }
+size_t scratch_partial_bytes(int64_t n, int C) {
+  return align_up((size_t)n * 4 * partial_stride(C) * 4);
+}
 size_t scratch_bytes(int64_t n, int C, const inpc_camera_t* c, const inpc_opts_t* o) {
-  return align_up((size_t)n * 4 * partial_stride(C) * 4) +
+  return scratch_visited_bytes(n) + scratch_partial_bytes(n, C) +
          align_up((size_t)num_tiles(c, o) * C * 4);
+}
+
+// Per-pixel forward state (last position, anchor position, anchor
+// transmittance) and the per-tile largest last position.
+size_t state_bytes(const inpc_camera_t* c, const inpc_opts_t* o) {
+  return (size_t)c->width * c->height * 12 + (size_t)num_tiles(c, o) * 4;
 }
 
 Cam to_cam(const inpc_camera_t* c) {
@@ -184,9 +194,9 @@ size_t inpc_backward_scratch_bytes(int64_t n, int32_t C, const inpc_camera_t* ca
   return scratch_bytes(n, C, cam, opts);
 }
 
-size_t inpc_state_bytes(const inpc_camera_t* cam) {
-  if (!valid_cam(cam)) return 0;
-  return (size_t)cam->width * cam->height * 12;
+size_t inpc_state_bytes(const inpc_camera_t* cam, const inpc_opts_t* opts) {
+  if (!valid_cam(cam) || !valid_opts(opts)) return 0;
+  return state_bytes(cam, opts);
 }
 
 int64_t inpc_num_tiles(const inpc_camera_t* cam, const inpc_opts_t* opts) {
@@ -221,8 +231,8 @@ inpc_status_t inpc_project(const inpc_camera_t* cam, const inpc_opts_t* opts, in
 
 inpc_status_t inpc_bin(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
                        const float* uv, const float* radius, const uint32_t* depth_key,
-                       const uint32_t* ntiles, uint32_t* tile_ranges, void* ws,
-                       size_t ws_bytes, void* stream) {
+                       const uint32_t* ntiles, uint32_t* tile_ranges, uint32_t* tile_order,
+                       void* ws, size_t ws_bytes, void* stream) {
   inpc_status_t st = check_common(cam, opts, n, ws, ws_bytes);
   if (st != INPC_OK) return st;
   REQUIRE(tile_ranges, "tile_ranges");
@@ -235,7 +245,7 @@ inpc_status_t inpc_bin(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_
   const Ws w = make_ws(ws, n, cam, opts);
   hipError_t e = launch_bin(to_cam(cam), to_opts(cam, opts), n, uv,
                             opts->splat == INPC_SPLAT_GAUSSIAN ? radius : nullptr, depth_key,
-                            ntiles, tile_ranges, w, (hipStream_t)stream);
+                            ntiles, tile_ranges, tile_order, w, (hipStream_t)stream);
   return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_bin");
 }
 
@@ -266,9 +276,10 @@ static inpc_status_t blend_checks(const inpc_camera_t* cam, const inpc_opts_t* o
 inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
                                  const float* uv, const float* radius, const float* opacity,
                                  const void* feat, int32_t C, int32_t dtype, const float* bg,
-                                 const uint32_t* tile_ranges, const uint32_t* list, float* out,
-                                 float* t_final, uint32_t* n_contrib, void* state, void* ws,
-                                 size_t ws_bytes, void* stream) {
+                                 const uint32_t* tile_ranges, const uint32_t* tile_order,
+                                 const uint32_t* list, float* out, float* t_final,
+                                 uint32_t* n_contrib, void* state, void* ws, size_t ws_bytes,
+                                 void* stream) {
   inpc_status_t st = blend_checks(cam, opts, n, C, dtype, ws, ws_bytes);
   if (st != INPC_OK) return st;
   REQUIRE(tile_ranges, "tile_ranges");
@@ -296,6 +307,7 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
   a.dtype = dtype;
   a.bg = bg;
   a.ranges = tile_ranges;
+  a.order = tile_order;
   a.list = list;
   a.out = out;
   a.t_final = t_final;
@@ -305,6 +317,7 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
     a.st_last = static_cast<uint32_t*>(state);
     a.st_anchor = a.st_last + P;
     a.st_tanchor = reinterpret_cast<float*>(a.st_anchor + P);
+    a.st_tile = a.st_last + 3 * P;
   }
   a.flags = w.flags;
   hipError_t e = launch_blend_forward(a, (hipStream_t)stream);
@@ -315,7 +328,8 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
                                   const float* uv, const float* opacity, const void* feat,
                                   int32_t C, int32_t dtype, const float* bg,
                                   const uint32_t* ntiles, const uint32_t* tile_ranges,
-                                  const uint32_t* list, const float* t_final, const void* state,
+                                  const uint32_t* tile_order, const uint32_t* list,
+                                  const float* t_final, const void* state,
                                   const float* grad_out, const float* grad_t, float* grad_feat,
                                   float* grad_opacity, float* grad_uv, float* grad_bg,
                                   void* scratch, size_t scratch_size, void* ws, size_t ws_bytes,
@@ -354,12 +368,14 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
   a.dtype = dtype;
   a.bg = bg;
   a.ranges = tile_ranges;
+  a.order = tile_order;
   a.list = list;
   a.t_final = const_cast<float*>(t_final);
   const size_t P = (size_t)cam->width * cam->height;
   a.st_last = static_cast<uint32_t*>(const_cast<void*>(state));
   a.st_anchor = a.st_last + P;
   a.st_tanchor = reinterpret_cast<float*>(a.st_anchor + P);
+  a.st_tile = a.st_last + 3 * P;
   a.ntiles = ntiles;
   a.grad_out = grad_out;
   a.grad_t = grad_t;
@@ -368,10 +384,11 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
   a.grad_uv = grad_uv;
   a.grad_bg = grad_bg;
   a.pstride = partial_stride(C);
-  a.partial = static_cast<float*>(scratch);
-  a.bg_partial = grad_bg ? reinterpret_cast<float*>(
-                               static_cast<char*>(scratch) +
-                               align_up((size_t)n * 4 * partial_stride(C) * 4))
+  char* sb = static_cast<char*>(scratch);
+  a.visited = reinterpret_cast<uint32_t*>(sb);
+  a.partial = reinterpret_cast<float*>(sb + scratch_visited_bytes(n));
+  a.bg_partial = grad_bg ? reinterpret_cast<float*>(sb + scratch_visited_bytes(n) +
+                                                    scratch_partial_bytes(n, C))
                          : nullptr;
   a.flags = w.flags;
   hipError_t e = launch_blend_backward(a, (hipStream_t)stream);

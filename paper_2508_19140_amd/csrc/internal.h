@@ -20,6 +20,7 @@ struct BlendArgs {
   int dtype;
   const float* bg;
   const uint32_t* ranges;
+  const uint32_t* order;  // [nt] tile processing order, or NULL for tile-index order
   const uint32_t* list;
   // forward outputs
   float* out;
@@ -28,6 +29,8 @@ struct BlendArgs {
   uint32_t* st_last;    // [P] one past the tile-list position of the last blended fragment
   uint32_t* st_anchor;  // [P] one past the position of the last blended fragment with T > 0
   float* st_tanchor;    // [P] transmittance in front of that fragment
+  uint32_t* st_tile;    // [nt] largest st_last over the tile's pixels
+  uint32_t* visited;    // [n] backward: byte k set when tile slot k wrote the point's gradient
   // backward
   const uint32_t* ntiles;
   const float* grad_out;
@@ -58,7 +61,7 @@ hipError_t launch_project(const Cam& cam, const Opts& o, int64_t n, const float*
                           const Ws& ws, hipStream_t s);
 hipError_t launch_bin(const Cam& cam, const Opts& o, int64_t n, const float* uv,
                       const float* radius, const uint32_t* key, const uint32_t* ntiles,
-                      uint32_t* ranges, const Ws& ws, hipStream_t s);
+                      uint32_t* ranges, uint32_t* order, const Ws& ws, hipStream_t s);
 hipError_t launch_sort(const Ws& ws, uint32_t* list, int64_t nt, hipStream_t s);
 hipError_t launch_blend_forward(const BlendArgs& a, hipStream_t s);
 hipError_t launch_blend_backward(const BlendArgs& a, hipStream_t s);

@@ -153,7 +153,8 @@ __device__ uint64_t block_incl_scan_u64(uint64_t v, uint64_t* s_wave, uint64_t& 
 // per thread).  Flags an overflow when the copies exceed the capacity.
 __global__ __launch_bounds__(1024) void k_scan(int64_t nt, const uint32_t* __restrict__ count,
                                                uint32_t* __restrict__ ranges,
-                                               uint32_t* __restrict__ cursor, Ws ws) {
+                                               uint32_t* __restrict__ cursor,
+                                               uint32_t* __restrict__ order, Ws ws) {
   __shared__ uint64_t s_wave[16];
   constexpr int PER = 8;
   uint64_t base = 0;                       // copies before this chunk
@@ -196,6 +197,30 @@ __global__ __launch_bounds__(1024) void k_scan(int64_t nt, const uint32_t* __res
     ws.flags[kFlagCountB0] = cb[2];
     ws.flags[kFlagCountX] = cb[3];
     if (base > (uint64_t)ws.cap) ws.flags[kFlagOverflow] = 1u;
+  }
+  if (!order) return;
+  // Blend order: tiles by decreasing copy count (power-of-two classes), so
+  // the longest tiles start first and do not form a tail.
+  __shared__ uint32_t s_h[33];
+  if (threadIdx.x < 33) s_h[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < nt; t += 1024) {
+    const uint32_t c = count[t];
+    atomicAdd(&s_h[c ? 32 - __clz(c) : 0], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int b = 32; b >= 0; --b) {
+      const uint32_t h = s_h[b];
+      s_h[b] = acc;
+      acc += h;
+    }
+  }
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < nt; t += 1024) {
+    const uint32_t c = count[t];
+    order[atomicAdd(&s_h[c ? 32 - __clz(c) : 0], 1u)] = (uint32_t)t;
   }
 }
 
@@ -338,9 +363,10 @@ hipError_t launch_project(const Cam& cam, const Opts& o, int64_t n, const float*
 
 hipError_t launch_bin(const Cam& cam, const Opts& o, int64_t n, const float* uv,
                       const float* radius, const uint32_t* key, const uint32_t* ntiles,
-                      uint32_t* ranges, const Ws& ws, hipStream_t s) {
+                      uint32_t* ranges, uint32_t* order, const Ws& ws, hipStream_t s) {
   const int64_t nt = (int64_t)o.ntx * o.nty;
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, nt, ws.tile_count, ranges, ws.cursor, ws);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, nt, ws.tile_count, ranges, ws.cursor,
+                     order, ws);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || n == 0) return e;
   if (nt <= kLdsBins) {

@@ -38,7 +38,7 @@ def test_workspace_and_sizes():
     c, o = cam(), L.make_opts(tile=8)
     assert lib.inpc_num_tiles(ctypes.byref(c), ctypes.byref(o)) == 8 * 6
     assert lib.inpc_copy_capacity(1000, ctypes.byref(c), ctypes.byref(o)) == 4000
-    assert lib.inpc_state_bytes(ctypes.byref(c)) == 64 * 48 * 12
+    assert lib.inpc_state_bytes(ctypes.byref(c), ctypes.byref(o)) == 64 * 48 * 12 + 48 * 4
     ws = lib.inpc_workspace_bytes(1000, ctypes.byref(c), ctypes.byref(o))
     assert ws >= 4 * 4000 * 4
     assert lib.inpc_workspace_bytes(2000, ctypes.byref(c), ctypes.byref(o)) > ws
@@ -92,7 +92,7 @@ def test_blend_rejects_bad_channels_and_dtype():
     n = 10
     wsb = lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(o))
     base = [ctypes.byref(c), ctypes.byref(o), n, FAKE, None, FAKE, FAKE]
-    tail = [None, FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, wsb, None]
+    tail = [None, FAKE, None, FAKE, FAKE, FAKE, FAKE, None, FAKE, wsb, None]
     assert lib.inpc_blend_forward(*base, 0, L.DTYPE_F32, *tail) == L.INPC_ERR_INVALID
     assert lib.inpc_blend_forward(*base, 65, L.DTYPE_F32, *tail) == L.INPC_ERR_INVALID
     assert lib.inpc_blend_forward(*base, 4, 7, *tail) == L.INPC_ERR_INVALID
@@ -106,8 +106,8 @@ def test_backward_rejects_gaussians():
     n = 10
     wsb = lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(g))
     st = lib.inpc_blend_backward(ctypes.byref(c), ctypes.byref(g), n, FAKE, FAKE, FAKE, 4,
-                                 L.DTYPE_F32, None, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None,
-                                 FAKE, FAKE, FAKE, None, FAKE, 1 << 20, FAKE, wsb, None)
+                                 L.DTYPE_F32, None, FAKE, FAKE, None, FAKE, FAKE, FAKE, FAKE,
+                                 None, FAKE, FAKE, FAKE, None, FAKE, 1 << 20, FAKE, wsb, None)
     assert st == L.INPC_ERR_UNSUPPORTED
 
 
@@ -119,7 +119,7 @@ def test_backward_rejects_small_scratch():
     need = lib.inpc_backward_scratch_bytes(n, C, ctypes.byref(c), ctypes.byref(o))
     assert need >= n * 4 * 8 * 4
     args = [ctypes.byref(c), ctypes.byref(o), n, FAKE, FAKE, FAKE, C, L.DTYPE_F32, None, FAKE,
-            FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, FAKE, None]
+            FAKE, None, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, FAKE, None]
     assert lib.inpc_blend_backward(*args, FAKE, need - 1, FAKE, wsb, None) == L.INPC_ERR_INVALID
     assert lib.inpc_blend_backward(*args, None, need, FAKE, wsb, None) == L.INPC_ERR_INVALID
 
