@@ -134,16 +134,27 @@ inpc_status_t inpc_bin(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_
  * Step 3 -- depth sort per tile (Sec. 3.2: depth-sorted per-tile lists).
  * Sorts every tile's bucket by (depth key ascending, point index
  * ascending) -- the same order the paper's split sort (stable depth sort,
- * then stable tile sort) produces -- and writes the point indices.
+ * then stable tile sort) produces -- and writes the point indices.  For
+ * bilinear splats it also writes, per list entry, where the point's 2x2
+ * footprint sits inside the tile, which the blend passes read instead of
+ * the point positions to find which pixels a copy covers.
  *   n           the point count the workspace was prepared for by
  *               inpc_project / inpc_bin
+ *   uv          [n][2] f32, output of inpc_project (bilinear splats only;
+ *               may be NULL for Gaussians)
  *   tile_ranges output of inpc_bin
+ *   tile_order  output of inpc_bin, or NULL
  *   list        [inpc_copy_capacity(n, cam, opts)] u32 out; the first
  *               tile_ranges[num_tiles] entries are written
+ *   lpos        [inpc_copy_capacity(n, cam, opts)] u16 out (bilinear splats;
+ *               ignored and may be NULL for Gaussians): entry q of tile
+ *               (tx, ty) holds (x0 - T tx + 1) | (y0 - T ty + 1) << 8, with
+ *               (x0, y0) the top-left pixel of the point's 2x2 splat
  */
 inpc_status_t inpc_sort(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
-                        const uint32_t* tile_ranges, uint32_t* list, void* ws, size_t ws_bytes,
-                        void* stream);
+                        const float* uv, const uint32_t* tile_ranges,
+                        const uint32_t* tile_order, uint32_t* list, uint16_t* lpos, void* ws,
+                        size_t ws_bytes, void* stream);
 
 /* Copy capacity (list entries) of a workspace sized for n points. */
 int64_t inpc_copy_capacity(int64_t n, const inpc_camera_t* cam, const inpc_opts_t* opts);
@@ -159,6 +170,7 @@ int64_t inpc_copy_capacity(int64_t n, const inpc_camera_t* cam, const inpc_opts_
  *   bg         [C] f32 constant background features, or NULL (zero)
  *   tile_ranges, list: outputs of inpc_bin / inpc_sort
  *   tile_order [num_tiles] from inpc_bin, or NULL (tile-index order)
+ *   lpos       output of inpc_sort (bilinear splats; NULL for Gaussians)
  *   out        [C][H][W] f32 out: feature image
  *   t_final    [H][W] f32 out: transmittance behind the last blended fragment
  *   n_contrib  [H][W] u32 out: number of blended fragments
@@ -169,9 +181,9 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
                                  const float* uv, const float* radius, const float* opacity,
                                  const void* feat, int32_t C, int32_t dtype, const float* bg,
                                  const uint32_t* tile_ranges, const uint32_t* tile_order,
-                                 const uint32_t* list, float* out, float* t_final,
-                                 uint32_t* n_contrib, void* state, void* ws, size_t ws_bytes,
-                                 void* stream);
+                                 const uint32_t* list, const uint16_t* lpos, float* out,
+                                 float* t_final, uint32_t* n_contrib, void* state, void* ws,
+                                 size_t ws_bytes, void* stream);
 
 /*
  * Step 5 -- blend backward (Appendix A, Eq. (2), with the sign of the
@@ -182,7 +194,8 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
  * B_k the blend of everything behind fragment k including the background;
  * then dL/df, dL/do = w dL/dalpha, dL/d(u,v) = o dw/d(u,v) dL/dalpha.
  * Bilinear splats only (INPC_ERR_UNSUPPORTED for Gaussians).
- *   ntiles, tile_ranges, list: from steps 1-3 (recomputed or kept)
+ *   ntiles, tile_ranges, tile_order, list, lpos: from steps 1-3
+ *              (recomputed or kept)
  *   t_final, state: from inpc_blend_forward with the same inputs
  *   grad_out   [C][H][W] f32 dL/dF
  *   grad_t     [H][W] f32 dL/dT_final, or NULL
@@ -201,7 +214,7 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
                                   int32_t C, int32_t dtype, const float* bg,
                                   const uint32_t* ntiles, const uint32_t* tile_ranges,
                                   const uint32_t* tile_order, const uint32_t* list,
-                                  const float* t_final, const void* state,
+                                  const uint16_t* lpos, const float* t_final, const void* state,
                                   const float* grad_out, const float* grad_t, float* grad_feat,
                                   float* grad_opacity, float* grad_uv, float* grad_bg,
                                   void* scratch, size_t scratch_bytes, void* ws, size_t ws_bytes,

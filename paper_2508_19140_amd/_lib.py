@@ -73,11 +73,11 @@ def lib():
         "inpc_copy_capacity": (I64, [I64, CP, OP]),
         "inpc_project": (I32, [CP, OP, I64, P, P, P, P, P, P, SZ, P]),
         "inpc_bin": (I32, [CP, OP, I64, P, P, P, P, P, P, P, SZ, P]),
-        "inpc_sort": (I32, [CP, OP, I64, P, P, P, SZ, P]),
+        "inpc_sort": (I32, [CP, OP, I64, P, P, P, P, P, P, SZ, P]),
         "inpc_blend_forward": (I32, [CP, OP, I64, P, P, P, P, I32, I32, P, P, P, P, P, P, P,
-                                     P, P, SZ, P]),
+                                     P, P, P, SZ, P]),
         "inpc_blend_backward": (I32, [CP, OP, I64, P, P, P, I32, I32, P, P, P, P, P, P, P, P,
-                                      P, P, P, P, P, P, SZ, P, SZ, P]),
+                                      P, P, P, P, P, P, P, SZ, P, SZ, P]),
         "inpc_backward_scratch_bytes": (SZ, [I64, I32, CP, OP]),
         "inpc_project_backward": (I32, [CP, I64, P, P, P, P, P]),
         "inpc_check_sync": (I32, [P, SZ, P]),

@@ -114,6 +114,19 @@ Ws make_ws(void* ws, int64_t n, const inpc_camera_t* c, const inpc_opts_t* o) {
   w.bucket = reinterpret_cast<uint2*>(b + L.bucket);
   w.xbucket = reinterpret_cast<uint2*>(b + L.xbucket);
   w.cap = (uint32_t)std::min<int64_t>(copy_capacity(n, c, o), 0xffffffffLL);
+  // Pack the tile-local splat corner (codes 0..T per axis) below the point
+  // index when both fit one 32-bit word; otherwise inpc_sort computes it in
+  // a separate pass.
+  w.lbits = w.pb = 0;
+  if (o->splat == INPC_SPLAT_BILINEAR) {
+    const int pb = o->tile == 8 ? 4 : (o->tile == 16 ? 5 : 6);
+    int ibits = 1;
+    while (ibits < 32 && ((int64_t)1 << ibits) < n) ++ibits;
+    if (ibits + 2 * pb <= 32) {
+      w.pb = pb;
+      w.lbits = 2 * pb;
+    }
+  }
   return w;
 }
 
@@ -250,14 +263,23 @@ inpc_status_t inpc_bin(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_
 }
 
 inpc_status_t inpc_sort(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
-                        const uint32_t* tile_ranges, uint32_t* list, void* ws, size_t ws_bytes,
-                        void* stream) {
+                        const float* uv, const uint32_t* tile_ranges,
+                        const uint32_t* tile_order, uint32_t* list, uint16_t* lpos, void* ws,
+                        size_t ws_bytes, void* stream) {
   inpc_status_t st = check_common(cam, opts, n, ws, ws_bytes);
   if (st != INPC_OK) return st;
   REQUIRE(tile_ranges, "tile_ranges");
   REQUIRE(list, "list");
+  const bool bilinear = opts->splat == INPC_SPLAT_BILINEAR;
+  if (bilinear) {
+    REQUIRE(lpos, "lpos");
+    if (n > 0) REQUIRE(uv, "uv");
+  }
   const Ws w = make_ws(ws, n, cam, opts);
-  hipError_t e = launch_sort(w, list, num_tiles(cam, opts), (hipStream_t)stream);
+  hipError_t e = launch_sort(w, list, lpos, num_tiles(cam, opts), (hipStream_t)stream);
+  if (e == hipSuccess && bilinear && n > 0 && w.lbits == 0)
+    e = launch_lpos(to_cam(cam), to_opts(cam, opts), tile_ranges, tile_order, uv, list, lpos,
+                    w.flags, (hipStream_t)stream);
   return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_sort");
 }
 
@@ -277,9 +299,9 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
                                  const float* uv, const float* radius, const float* opacity,
                                  const void* feat, int32_t C, int32_t dtype, const float* bg,
                                  const uint32_t* tile_ranges, const uint32_t* tile_order,
-                                 const uint32_t* list, float* out, float* t_final,
-                                 uint32_t* n_contrib, void* state, void* ws, size_t ws_bytes,
-                                 void* stream) {
+                                 const uint32_t* list, const uint16_t* lpos, float* out,
+                                 float* t_final, uint32_t* n_contrib, void* state, void* ws,
+                                 size_t ws_bytes, void* stream) {
   inpc_status_t st = blend_checks(cam, opts, n, C, dtype, ws, ws_bytes);
   if (st != INPC_OK) return st;
   REQUIRE(tile_ranges, "tile_ranges");
@@ -287,6 +309,7 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
   REQUIRE(out, "out");
   REQUIRE(t_final, "t_final");
   REQUIRE(n_contrib, "n_contrib");
+  if (opts->splat == INPC_SPLAT_BILINEAR) REQUIRE(lpos, "lpos");
   if (n > 0) {
     REQUIRE(uv, "uv");
     REQUIRE(opacity, "opacity");
@@ -309,6 +332,7 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
   a.ranges = tile_ranges;
   a.order = tile_order;
   a.list = list;
+  a.lpos = lpos;
   a.out = out;
   a.t_final = t_final;
   a.n_contrib = n_contrib;
@@ -329,7 +353,7 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
                                   int32_t C, int32_t dtype, const float* bg,
                                   const uint32_t* ntiles, const uint32_t* tile_ranges,
                                   const uint32_t* tile_order, const uint32_t* list,
-                                  const float* t_final, const void* state,
+                                  const uint16_t* lpos, const float* t_final, const void* state,
                                   const float* grad_out, const float* grad_t, float* grad_feat,
                                   float* grad_opacity, float* grad_uv, float* grad_bg,
                                   void* scratch, size_t scratch_size, void* ws, size_t ws_bytes,
@@ -343,6 +367,7 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
     return fail(INPC_ERR_INVALID, "scratch smaller than inpc_backward_scratch_bytes()%s", "");
   REQUIRE(tile_ranges, "tile_ranges");
   REQUIRE(list, "list");
+  REQUIRE(lpos, "lpos");
   REQUIRE(t_final, "t_final");
   REQUIRE(state, "state");
   REQUIRE(grad_out, "grad_out");
@@ -370,6 +395,7 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
   a.ranges = tile_ranges;
   a.order = tile_order;
   a.list = list;
+  a.lpos = lpos;
   a.t_final = const_cast<float*>(t_final);
   const size_t P = (size_t)cam->width * cam->height;
   a.st_last = static_cast<uint32_t*>(const_cast<void*>(state));

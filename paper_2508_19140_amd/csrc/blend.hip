@@ -1,15 +1,19 @@
 // Per-tile alpha blending, forward and backward.
 //
 // One workgroup per tile, one thread per pixel (an 8x8 tile is exactly one
-// 64-wide wavefront).  The tile's depth-ordered list is consumed in chunks:
-// the chunk's points are staged in LDS, and for bilinear splats each point
-// sets its bit in the 64-bit "which points cover me" mask of the (at most
-// four) pixels it covers, so a pixel then visits only its own fragments, in
-// list order, by walking the set bits.  Gaussians cover most of a tile, so
-// there every pixel tests every staged point.  While a chunk is blended, the
-// point data of the next chunk is already being fetched into registers, so
-// long lists do not pay one memory latency per chunk.  Tiles are processed
-// in the order inpc_bin produced (longest lists first).
+// 64-wide wavefront).  The tile's depth-ordered list is consumed in chunks
+// of copies.  For bilinear splats every copy's tile-local 2x2 position comes
+// from a small per-copy array written after the sort (lpos), so coverage
+// is known without touching the point data: each copy sets its bit in the
+// 64-bit "which copies cover me" mask of the (at most four) pixels it
+// covers, and a pixel then visits only its own fragments, in list order, by
+// walking the set bits.  Only copies that cover a pixel still blending have
+// their point data (position, opacity, features) fetched, and that fetch
+// for the next chunk is in flight while the current chunk is blended
+// (double-buffered LDS).  Long lists whose pixels have mostly terminated
+// therefore cost little more than reading their indices.  Gaussians cover
+// most of a tile, so there every pixel tests every staged copy.  Tiles are
+// processed in the order inpc_bin produced (longest lists first).
 //
 // Forward (Eq. (1) of the paper, Appendix A, then the background): per pixel
 // T = 1; for each fragment in order: stop if T < t_min; alpha = o w;
@@ -25,13 +29,13 @@
 // T_k = T_{k+1} / (1 - alpha_k), starting from the transmittance the forward
 // pass recorded in front of the last blended fragment with T > 0 (so an
 // alpha = 1 fragment never divides by zero).  The per-fragment terms land in
-// per-(point, corner) LDS slots; one thread per point then sums its
-// corners.  A point that lies in this tile only gets its gradient written
-// directly; a point split over several tiles writes this tile's share into
-// its own slot of a partial buffer.  Every write also marks the (point,
-// slot) as visited; a gather pass then sums the shares of split points and
-// writes zeros for points no blended fragment reached.  No floating-point
-// atomics are used, so the backward pass is deterministic.
+// per-(copy, corner) LDS slots; one thread per copy then sums its corners.
+// A point that lies in this tile only gets its gradient written directly; a
+// point split over several tiles writes this tile's share into its own slot
+// of a partial buffer.  Every write marks the (point, slot) as visited; a
+// gather pass sums the shares of split points and writes zeros where no
+// blended fragment reached.  No floating-point atomics are used, so the
+// backward pass is deterministic.
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
@@ -72,6 +76,16 @@ __device__ __forceinline__ bool tile_any(bool p) {
     return __ballot(p) != 0ull;
   else
     return __syncthreads_count(p) != 0;
+}
+
+__device__ __forceinline__ unsigned long long wave_or64(unsigned long long v) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo |= (uint32_t)__shfl_xor((int)lo, o, 64);
+    hi |= (uint32_t)__shfl_xor((int)hi, o, 64);
+  }
+  return ((unsigned long long)hi << 32) | lo;
 }
 
 __device__ __forceinline__ uint32_t pack_xy(int x0, int y0) {
@@ -141,11 +155,6 @@ struct RowRegs {
     }
   }
 
-  __device__ __forceinline__ void zero() {
-#pragma unroll
-    for (int k = 0; k < WORDS; ++k) w[k] = 0u;
-  }
-
   __device__ __forceinline__ void store_f32(float* __restrict__ dst) const {
     float4* d4 = reinterpret_cast<float4*>(dst);
     if constexpr (sizeof(FT) == 4) {
@@ -178,8 +187,9 @@ __device__ __forceinline__ void store_row(float* __restrict__ dst, const float (
   }
 }
 
-// Register prefetch of one list entry's point data.  `i` must be a valid
-// point index even when `v` is false (the loads are not predicated).
+// Register prefetch of one copy's point data.  The loads are not
+// predicated: a copy that is not needed fetches point 0 instead (all such
+// lanes hit the same line), which keeps the prefetch free of branches.
 template <int CP, typename FT, bool FULL>
 struct Prefetch {
   bool valid;
@@ -190,18 +200,70 @@ struct Prefetch {
 
   __device__ __forceinline__ void fetch(const BlendArgs& a, bool v, uint32_t i) {
     valid = v;
-    idx = i;
-    uv = reinterpret_cast<const float2*>(a.uv)[i];
-    o = a.opacity[i];
-    f.load(reinterpret_cast<const FT*>(a.feat), i, a.C);
+    idx = v ? i : 0u;
+    uv = reinterpret_cast<const float2*>(a.uv)[idx];
+    o = a.opacity[idx];
+    f.load(reinterpret_cast<const FT*>(a.feat), idx, a.C);
   }
 };
 
-// List entry at position q, clamped to the tile's last entry (end > start,
-// q >= start), so that prefetches never need a branch.
-__device__ __forceinline__ uint32_t list_at(const uint32_t* __restrict__ list, uint32_t q,
-                                            uint32_t end) {
-  return list[q < end ? q : end - 1];
+// List entry (point index and tile-local 2x2 position) of a chunk slot.
+struct Entry {
+  bool valid;
+  uint32_t idx, lp;
+  __device__ __forceinline__ void load(const BlendArgs& a, bool stager, uint32_t q, uint32_t end) {
+    valid = stager && q < end;
+    const uint32_t qq = q < end ? q : end - 1;  // end > start
+    idx = a.list[qq];
+    lp = a.lpos[qq];
+  }
+};
+
+// Clear the coverage masks of this thread's pixel, then set the bits of
+// this thread's copy (tile-local splat corner (x0, y0) = lp - 1).
+template <int T>
+__device__ __forceinline__ void build_coverage(unsigned long long* __restrict__ mask,
+                                               const Entry& e) {
+  using G = TileGeom<T>;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int w = 0; w < G::MW; ++w) mask[tid * G::MW + w] = 0ull;
+  tile_sync<G::NW>();
+  if (e.valid) {
+    const int x0 = (int)(e.lp & 0xffu) - 1, y0 = (int)(e.lp >> 8) - 1;
+    const unsigned long long bit = 1ull << (tid & 63);
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        const int qx = x0 + dx, qy = y0 + dy;
+        if (qx >= 0 && qx < T && qy >= 0 && qy < T)
+          atomicOr(&mask[(qy * T + qx) * G::MW + (tid >> 6)], bit);
+      }
+  }
+  tile_sync<G::NW>();
+}
+
+// Copies of the chunk covering at least one pixel with `active` set: is this
+// thread's copy among them?
+template <int T>
+__device__ __forceinline__ bool copy_needed(const unsigned long long* __restrict__ mask,
+                                            bool active, unsigned long long* __restrict__ s_need) {
+  using G = TileGeom<T>;
+  const int tid = threadIdx.x;
+  unsigned long long nd[G::MW];
+#pragma unroll
+  for (int w = 0; w < G::MW; ++w) nd[w] = wave_or64(active ? mask[tid * G::MW + w] : 0ull);
+  if constexpr (G::NW == 1) {
+    return (nd[0] >> (tid & 63)) & 1ull;
+  } else {
+    if ((tid & 63) == 0)
+#pragma unroll
+      for (int w = 0; w < G::MW; ++w) atomicOr(&s_need[w], nd[w]);
+    __syncthreads();
+    const bool r = tid < G::CHUNK && ((s_need[tid >> 6] >> (tid & 63)) & 1ull);
+    return r;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -210,10 +272,11 @@ __device__ __forceinline__ uint32_t list_at(const uint32_t* __restrict__ list, u
 template <int T, int CP, typename FT, bool FULL>
 __global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear(BlendArgs a) {
   using G = TileGeom<T>;
-  constexpr int NW = G::NW;
-  __shared__ float4 s_geo[G::CHUNK];
-  __shared__ __align__(16) float s_feat[G::CHUNK * fpad(CP)];
-  __shared__ unsigned long long s_mask[G::NTH * G::MW];
+  constexpr int NW = G::NW, CH = G::CHUNK, MW = G::MW;
+  __shared__ float4 s_geo[CH];
+  __shared__ __align__(16) float s_feat[CH * fpad(CP)];
+  __shared__ unsigned long long s_mask[2][G::NTH * MW];
+  __shared__ unsigned long long s_need[MW];
   __shared__ uint32_t s_ml[NW];
   if (a.flags[kFlagOverflow]) return;
 
@@ -225,7 +288,7 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear(BlendArgs a) {
   const bool inside = px < a.cam.W && py < a.cam.H;
   const uint32_t start = a.ranges[tile], end = a.ranges[tile + 1];
   const float t_min = a.opts.t_min;
-  const bool stager = tid < G::CHUNK;
+  const bool stager = tid < CH;
 
   float F[CP];
 #pragma unroll
@@ -234,51 +297,42 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear(BlendArgs a) {
   uint32_t cnt = 0, last = 0, anchor = 0;
   bool done = !inside;
 
-  // chunk 0's data and chunk 1's list entry are fetched before the loop
-  Prefetch<CP, FT, FULL> pf;
+  Entry e;  // list entries of the chunk whose coverage is built next
+  e.valid = false;
+  e.idx = e.lp = 0;
+  Prefetch<CP, FT, FULL> pf;  // point data of the chunk staged next
   pf.valid = false;
-  bool nv = false;
-  uint32_t nidx = 0u;
   if (end > start) {
-    pf.fetch(a, stager && start + tid < end, list_at(a.list, start + tid, end));
-    nv = stager && start + G::CHUNK + tid < end;
-    nidx = list_at(a.list, start + G::CHUNK + tid, end);
+    e.load(a, stager, start + tid, end);
+    if constexpr (NW > 1) {
+      if (tid < MW) s_need[tid] = 0ull;
+    }
+    build_coverage<T>(s_mask[0], e);
+    const bool nd = copy_needed<T>(s_mask[0], !done, s_need);  // every lane takes part
+    pf.fetch(a, e.valid && nd, e.idx);
+    e.load(a, stager, start + CH + tid, end);
   }
 
-  for (uint32_t base = start; base < end; base += G::CHUNK) {
+  int b = 0;
+  for (uint32_t base = start; base < end; base += CH, b ^= 1) {
     if (!tile_any<NW>(!done)) break;
-    // stage the prefetched copy of this chunk
-    int x0 = 0, y0 = 0;
-    const bool cur = pf.valid;
-    if (cur) {
+    // stage the fetched copies of this chunk
+    if (pf.valid) {
       const Footprint f = bilinear_footprint(pf.uv.x, pf.uv.y, a.cam.W, a.cam.H);
-      x0 = f.x0 - tx * T;
-      y0 = f.y0 - ty * T;
       s_geo[tid] = make_float4(f.a, f.b, pf.o, __uint_as_float(pack_xy(f.x0, f.y0)));
-      pf.f.store_f32(s_feat + tid * fpad(CP));
+      pf.f.store_f32(&s_feat[tid * fpad(CP)]);
     }
-#pragma unroll
-    for (int w = 0; w < G::MW; ++w) s_mask[tid * G::MW + w] = 0ull;
-    tile_sync<NW>();
-    if (cur) {
-      const unsigned long long bit = 1ull << (tid & 63);
-#pragma unroll
-      for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 2; ++dx) {
-          const int qx = x0 + dx, qy = y0 + dy;
-          if (qx >= 0 && qx < T && qy >= 0 && qy < T)
-            atomicOr(&s_mask[(qy * T + qx) * G::MW + (tid >> 6)], bit);
-        }
+    // coverage of the next chunk; fetch the copies it needs while this one blends
+    if constexpr (NW > 1) {
+      if (tid < MW) s_need[tid] = 0ull;
     }
-    // fetch the next chunk while this one is blended
-    pf.fetch(a, nv, nidx);
-    nv = stager && base + 2 * G::CHUNK + tid < end;
-    nidx = list_at(a.list, base + 2 * G::CHUNK + tid, end);
-    tile_sync<NW>();
+    build_coverage<T>(s_mask[b ^ 1], e);
+    const bool nd = copy_needed<T>(s_mask[b ^ 1], !done, s_need);
+    pf.fetch(a, e.valid && nd, e.idx);
+    e.load(a, stager, base + 2 * CH + tid, end);
     if (!done) {
-      for (int w = 0; w < G::MW && !done; ++w) {
-        unsigned long long m = s_mask[tid * G::MW + w];
+      for (int w = 0; w < MW && !done; ++w) {
+        unsigned long long m = s_mask[b][tid * MW + w];
         while (m) {
           const int j = __ffsll(m) - 1;
           m &= m - 1;
@@ -294,7 +348,7 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear(BlendArgs a) {
             break;
           }
           const float wt = Tr * al;
-          const float4* fr = reinterpret_cast<const float4*>(s_feat + kk * fpad(CP));
+          const float4* fr = reinterpret_cast<const float4*>(&s_feat[kk * fpad(CP)]);
 #pragma unroll
           for (int q = 0; q < CP / 4; ++q) {
             const float4 f4 = fr[q];
@@ -380,11 +434,12 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_gauss(BlendArgs a) {
   float prad = 0.f;
   bool nv = false;
   uint32_t nidx = 0u;
+  auto list_at = [&](uint32_t q) { return a.list[q < end ? q : end - 1]; };
   if (end > start) {
-    pf.fetch(a, stager && start + tid < end, list_at(a.list, start + tid, end));
+    pf.fetch(a, stager && start + tid < end, list_at(start + tid));
     prad = a.radius[pf.idx];
     nv = stager && start + G::CHUNK + tid < end;
-    nidx = list_at(a.list, start + G::CHUNK + tid, end);
+    nidx = list_at(start + G::CHUNK + tid);
   }
 
   for (uint32_t base = start; base < end; base += G::CHUNK) {
@@ -399,9 +454,9 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_gauss(BlendArgs a) {
       pf.f.store_f32(s_feat + tid * fpad(CP));
     }
     pf.fetch(a, nv, nidx);
-    prad = a.radius[nidx];
+    prad = a.radius[pf.idx];
     nv = stager && base + 2 * G::CHUNK + tid < end;
-    nidx = list_at(a.list, base + 2 * G::CHUNK + tid, end);
+    nidx = list_at(base + 2 * G::CHUNK + tid);
     tile_sync<NW>();
     if (!done) {
       for (uint32_t kk = 0; kk < nh; ++kk) {
@@ -450,11 +505,12 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_gauss(BlendArgs a) {
 template <int T, int CP, typename FT, bool FULL>
 __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
   using G = TileGeom<T>;
-  constexpr int NW = G::NW;
-  __shared__ float4 s_geo[G::CHUNK];
-  __shared__ __align__(16) float s_feat[G::CHUNK * fpad(CP)];
-  __shared__ unsigned long long s_mask[G::NTH * G::MW];
-  __shared__ float2 s_acc[G::CHUNK * 4];                  // per (point, corner): (T alpha, dL/dalpha)
+  constexpr int NW = G::NW, CH = G::CHUNK, MW = G::MW;
+  __shared__ float4 s_geo[CH];
+  __shared__ __align__(16) float s_feat[CH * fpad(CP)];
+  __shared__ unsigned long long s_mask[2][G::NTH * MW];
+  __shared__ unsigned long long s_need[MW];
+  __shared__ float2 s_acc[CH * 4];                        // per (copy, corner): (T alpha, dL/dalpha)
   __shared__ __align__(16) float s_G[G::NTH * fpad(CP)];  // dL/dF of every pixel of the tile
   __shared__ float s_red[NW][CP];
   if (a.flags[kFlagOverflow]) return;
@@ -469,7 +525,7 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
   const int64_t P = (int64_t)a.cam.W * a.cam.H;
   const int64_t p = (int64_t)py * a.cam.W + px;
   const int C = a.C;
-  const bool stager = tid < G::CHUNK;
+  const bool stager = tid < CH;
 
   float Gv[CP];
   float gB = 0.f, GT = 0.f, Tf = 0.f, t_anchor = 0.f;
@@ -488,7 +544,8 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
   {
     float4* d4 = reinterpret_cast<float4*>(s_G + tid * fpad(CP));
 #pragma unroll
-    for (int q = 0; q < CP / 4; ++q) d4[q] = make_float4(Gv[4 * q], Gv[4 * q + 1], Gv[4 * q + 2], Gv[4 * q + 3]);
+    for (int q = 0; q < CP / 4; ++q)
+      d4[q] = make_float4(Gv[4 * q], Gv[4 * q + 1], Gv[4 * q + 2], Gv[4 * q + 3]);
   }
 
   // background: this tile's share of sum_p T_final G
@@ -510,26 +567,33 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
   }
 
   // the forward pass blended nothing beyond list position st_tile[tile]
-  const uint32_t maxlast = a.st_tile[tile];
-  const int nchunks = (int)((maxlast + G::CHUNK - 1) / G::CHUNK);
+  const uint32_t maxlast = min(a.st_tile[tile], end - start);
+  const int nchunks = (int)((maxlast + CH - 1) / CH);
 
-  Prefetch<CP, FT, FULL> pf;
+  Entry e;  // list entries of the chunk whose coverage is built next
+  e.valid = false;
+  e.idx = e.lp = 0;
+  Prefetch<CP, FT, FULL> pf;  // point data of the chunk staged next
   pf.valid = false;
-  uint32_t pnt = 0;
+  uint32_t pnt = 0;            // its tile count
   if (nchunks > 0) {
-    const uint32_t q = start + (uint32_t)(nchunks - 1) * G::CHUNK + tid;
-    pf.fetch(a, stager && q < end, list_at(a.list, q, end));
+    const int c0 = nchunks - 1;
+    e.load(a, stager, start + (uint32_t)c0 * CH + tid, end);
+    if constexpr (NW > 1) {
+      if (tid < MW) s_need[tid] = 0ull;
+    }
+    build_coverage<T>(s_mask[c0 & 1], e);
+    const bool nd = copy_needed<T>(s_mask[c0 & 1], last > (uint32_t)c0 * CH, s_need);
+    pf.fetch(a, e.valid && nd, e.idx);
     pnt = a.ntiles[pf.idx];
+    if (nchunks >= 2) e.load(a, stager, start + (uint32_t)(c0 - 1) * CH + tid, end);
   }
-  bool nv = stager && nchunks >= 2;
-  uint32_t nidx = 0u;
-  if (nchunks >= 2) nidx = list_at(a.list, start + (uint32_t)(nchunks - 2) * G::CHUNK + tid, end);
-  tile_sync<NW>();
 
   float Pi = 1.f, Tcur = 0.f;
   for (int ci = nchunks - 1; ci >= 0; --ci) {
-    const uint32_t rb = (uint32_t)ci * G::CHUNK;  // relative base of the chunk
-    // stage this chunk's copy from the prefetch registers
+    const int b = ci & 1;
+    const uint32_t rb = (uint32_t)ci * CH;  // relative base of the chunk
+    // stage this chunk's fetched copies
     const bool cur = pf.valid;
     const uint32_t cur_idx = pf.idx, cur_nt = pnt;
     float ca = 0.f, cb = 0.f, co = 0.f;
@@ -538,35 +602,25 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
       const Footprint f = bilinear_footprint(pf.uv.x, pf.uv.y, a.cam.W, a.cam.H);
       ca = f.a; cb = f.b; co = pf.o; X0 = f.x0; Y0 = f.y0;
       s_geo[tid] = make_float4(f.a, f.b, pf.o, __uint_as_float(pack_xy(f.x0, f.y0)));
-      pf.f.store_f32(s_feat + tid * fpad(CP));
+      pf.f.store_f32(&s_feat[tid * fpad(CP)]);
 #pragma unroll
       for (int k = 0; k < 4; ++k) s_acc[tid * 4 + k] = make_float2(0.f, 0.f);
     }
-#pragma unroll
-    for (int w = 0; w < G::MW; ++w) s_mask[tid * G::MW + w] = 0ull;
     tile_sync<NW>();
-    if (cur) {
-      const int x0 = X0 - tx * T, y0 = Y0 - ty * T;
-      const unsigned long long bit = 1ull << (tid & 63);
-#pragma unroll
-      for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 2; ++dx) {
-          const int qx = x0 + dx, qy = y0 + dy;
-          if (qx >= 0 && qx < T && qy >= 0 && qy < T)
-            atomicOr(&s_mask[(qy * T + qx) * G::MW + (tid >> 6)], bit);
-        }
+    // coverage of the previous chunk; fetch what it needs while this one is replayed
+    if (ci >= 1) {
+      if constexpr (NW > 1) {
+        if (tid < MW) s_need[tid] = 0ull;
+      }
+      build_coverage<T>(s_mask[b ^ 1], e);
+      const bool nd = copy_needed<T>(s_mask[b ^ 1], last > rb - CH, s_need);
+      pf.fetch(a, e.valid && nd, e.idx);
+      pnt = a.ntiles[pf.idx];
+      if (ci >= 2) e.load(a, stager, start + rb - 2 * CH + tid, end);
     }
-    // fetch the previous chunk while this one is processed (point 0 stands
-    // in when there is none; its data is fetched and ignored)
-    pf.fetch(a, nv, nidx);
-    pnt = a.ntiles[nidx];
-    nv = stager && ci >= 2;
-    if (ci >= 2) nidx = list_at(a.list, start + (uint32_t)(ci - 2) * G::CHUNK + tid, end);
-    tile_sync<NW>();
     if (last > rb) {
-      for (int w = G::MW - 1; w >= 0; --w) {
-        unsigned long long m = s_mask[tid * G::MW + w];
+      for (int w = MW - 1; w >= 0; --w) {
+        unsigned long long m = s_mask[b][tid * MW + w];
         const uint32_t wb = rb + (uint32_t)w * 64;  // relative position of bit 0
         if (last <= wb) continue;
         const uint32_t lim = last - wb;             // positions < last are blended
@@ -590,7 +644,7 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
             Tk = t_anchor;
           else
             Tk = __fdividef(Tcur, om);
-          const float4* fr = reinterpret_cast<const float4*>(s_feat + kk * fpad(CP));
+          const float4* fr = reinterpret_cast<const float4*>(&s_feat[kk * fpad(CP)]);
           float gf = 0.f;
 #pragma unroll
           for (int q = 0; q < CP / 4; ++q) {
@@ -647,8 +701,9 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
       } else {
         // this tile's slot among the (at most 2 x 2) tiles of the point
         const int tx0 = max(X0, 0) >> G::SH, ty0 = max(Y0, 0) >> G::SH;
-        const int slot = (tx - tx0) + 2 * (ty - ty0);
-        float* dst = a.partial + ((size_t)cur_idx * 4 + slot) * a.pstride;
+        const int sx = tx - tx0, sy = ty - ty0;
+        const int slot = (sx | sy) & ~1 ? 0 : sx + 2 * sy;  // always 0..3 for consistent inputs
+        float* dst = a.partial + ((size_t)slot * a.n + cur_idx) * a.pstride;
         float4* d4 = reinterpret_cast<float4*>(dst);
 #pragma unroll
         for (int q = 0; q < CP / 4; ++q)
@@ -682,7 +737,7 @@ __global__ __launch_bounds__(256) void k_grad_gather(BlendArgs a) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         if (!((v >> (8 * k)) & 0xffu)) continue;
-        const float* src = a.partial + ((size_t)i * 4 + k) * a.pstride;
+        const float* src = a.partial + ((size_t)k * a.n + i) * a.pstride;
         const float4* s4 = reinterpret_cast<const float4*>(src);
 #pragma unroll
         for (int q = 0; q < CP / 4; ++q) {
@@ -789,7 +844,59 @@ hipError_t dispatch(const BlendArgs& a, hipStream_t s) {
   }
 }
 
+// Tile-local position of every copy's 2x2 splat, (x0 - tile x + 1) |
+// (y0 - tile y + 1) << 8, for workspaces whose bucket entries could not
+// carry it.  One wavefront per tile (longest first), four copies per lane
+// and round so that the position gathers of a long list overlap.
+__global__ __launch_bounds__(256) void k_lpos(Cam cam, Opts o, const uint32_t* __restrict__ ranges,
+                                              const uint32_t* __restrict__ order,
+                                              const float2* __restrict__ uv,
+                                              const uint32_t* __restrict__ list,
+                                              uint16_t* __restrict__ lpos,
+                                              const uint32_t* __restrict__ flags) {
+  if (flags[kFlagOverflow]) return;
+  const int64_t nt = (int64_t)o.ntx * o.nty;
+  const uint32_t lane = threadIdx.x & 63u;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < nt;
+       i += (int64_t)gridDim.x * 4) {
+    const uint32_t t = order ? order[i] : (uint32_t)i;
+    const uint32_t s = ranges[t], e = ranges[t + 1];
+    if (s == e) continue;
+    const int tx0 = (int)(t % (uint32_t)o.ntx) * o.T, ty0 = (int)(t / (uint32_t)o.ntx) * o.T;
+    for (uint32_t q0 = s + lane; q0 < e; q0 += 4 * 64) {
+      uint32_t idx[4];
+      float2 p[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t q = q0 + k * 64;
+        idx[k] = list[q < e ? q : e - 1];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) p[k] = uv[idx[k]];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t q = q0 + k * 64;
+        if (q < e) {
+          const Footprint f = bilinear_footprint(p[k].x, p[k].y, cam.W, cam.H);
+          lpos[q] = (uint16_t)((uint32_t)(f.x0 - tx0 + 1) | ((uint32_t)(f.y0 - ty0 + 1) << 8));
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_lpos(const Cam& cam, const Opts& o, const uint32_t* ranges,
+                       const uint32_t* order, const float* uv, const uint32_t* list,
+                       uint16_t* lpos, const uint32_t* flags, hipStream_t s) {
+  const int64_t nt = (int64_t)o.ntx * o.nty;
+  if (nt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lpos, dim3((unsigned)std::min<int64_t>((nt + 3) / 4, 16384)), dim3(256), 0, s,
+                     cam, o,
+                     ranges, order, reinterpret_cast<const float2*>(uv), list, lpos, flags);
+  return hipGetLastError();
+}
 
 hipError_t launch_blend_forward(const BlendArgs& a, hipStream_t s) {
   if (a.opts.ntx == 0 || a.opts.nty == 0) return hipSuccess;

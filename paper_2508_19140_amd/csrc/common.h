@@ -68,6 +68,29 @@ struct Ws {
   uint2* bucket;         // [cap]  (depth key, point index) copies, bucketed by tile
   uint2* xbucket;        // [cap]  ping-pong scratch for segments beyond the LDS capacity
   uint32_t cap;          // copy capacity
+  // Bilinear splats with few enough points: the index word of a bucket entry
+  // is (point index << lbits) | (y code << pb) | x code, where the codes are
+  // the tile-local corner of the copy's 2x2 splat plus one.  The index stays
+  // in the high bits, so ordering by the packed word orders by index.
+  int lbits;             // 0: plain point index
+  int pb;                // bits per axis code
+};
+
+// Where a sorted copy goes: its point index into list[q] and, for packed
+// entries, its tile-local splat corner into lpos[q] (x code | y code << 8).
+struct ListOut {
+  uint32_t* list;
+  uint16_t* lpos;
+  int lbits, pb;
+  __device__ __forceinline__ void put(uint32_t q, uint32_t v) const {
+    if (lbits) {
+      const uint32_t m = (1u << pb) - 1u;
+      list[q] = v >> lbits;
+      lpos[q] = (uint16_t)((v & m) | (((v >> pb) & m) << 8));
+    } else {
+      list[q] = v;
+    }
+  }
 };
 
 __device__ __forceinline__ float fmul(float a, float b) { return __fmul_rn(a, b); }

@@ -22,6 +22,7 @@ struct BlendArgs {
   const uint32_t* ranges;
   const uint32_t* order;  // [nt] tile processing order, or NULL for tile-index order
   const uint32_t* list;
+  const uint16_t* lpos;  // per list entry: tile-local 2x2 splat corner, +1 per axis (bilinear)
   // forward outputs
   float* out;
   float* t_final;
@@ -39,7 +40,7 @@ struct BlendArgs {
   float* grad_opacity;
   float* grad_uv;
   float* grad_bg;
-  float* partial;     // [n][4][pstride] per-(point, tile slot) gradients of multi-tile points
+  float* partial;     // [4][n][pstride] per-(tile slot, point) gradients of multi-tile points
   float* bg_partial;  // [num_tiles][C] per-tile background gradients
   int pstride;        // floats per partial record (C + 3 rounded up to 4)
   const uint32_t* flags;
@@ -62,7 +63,10 @@ hipError_t launch_project(const Cam& cam, const Opts& o, int64_t n, const float*
 hipError_t launch_bin(const Cam& cam, const Opts& o, int64_t n, const float* uv,
                       const float* radius, const uint32_t* key, const uint32_t* ntiles,
                       uint32_t* ranges, uint32_t* order, const Ws& ws, hipStream_t s);
-hipError_t launch_sort(const Ws& ws, uint32_t* list, int64_t nt, hipStream_t s);
+hipError_t launch_sort(const Ws& ws, uint32_t* list, uint16_t* lpos, int64_t nt, hipStream_t s);
+hipError_t launch_lpos(const Cam& cam, const Opts& o, const uint32_t* ranges,
+                       const uint32_t* order, const float* uv, const uint32_t* list,
+                       uint16_t* lpos, const uint32_t* flags, hipStream_t s);
 hipError_t launch_blend_forward(const BlendArgs& a, hipStream_t s);
 hipError_t launch_blend_backward(const BlendArgs& a, hipStream_t s);
 hipError_t launch_project_backward(const Cam& cam, int64_t n, const float* pos,

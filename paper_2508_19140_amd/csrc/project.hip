@@ -199,29 +199,74 @@ __global__ __launch_bounds__(1024) void k_scan(int64_t nt, const uint32_t* __res
     if (base > (uint64_t)ws.cap) ws.flags[kFlagOverflow] = 1u;
   }
   if (!order) return;
-  // Blend order: tiles by decreasing copy count (power-of-two classes), so
-  // the longest tiles start first and do not form a tail.
-  __shared__ uint32_t s_h[33];
-  if (threadIdx.x < 33) s_h[threadIdx.x] = 0;
-  __syncthreads();
-  for (int64_t t = threadIdx.x; t < nt; t += 1024) {
+  // Blend order: tiles by decreasing copy count in power-of-two classes (so
+  // the longest lists start first and do not form a tail), ascending tile
+  // index inside a class.  A stable counting sort over 33 classes; lanes of
+  // a wavefront with the same class are matched with ballots so that one
+  // lane per class and wavefront touches the shared counters.
+  __shared__ uint32_t s_h[34];
+  __shared__ uint32_t s_wc[16][34];
+  const uint32_t lane = __lane_id(), w = threadIdx.x >> 6;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  auto klass = [&](int64_t t) -> uint32_t {  // 0 = longest ... 32 = empty, 33 = no tile
+    if (t >= nt) return 33u;
     const uint32_t c = count[t];
-    atomicAdd(&s_h[c ? 32 - __clz(c) : 0], 1u);
+    return c ? (uint32_t)__clz(c) : 32u;
+  };
+  auto match6 = [&](uint32_t k) {
+    uint64_t m = ~0ull;
+#pragma unroll
+    for (int bit = 0; bit < 6; ++bit) {
+      const uint64_t bb = __ballot((k >> bit) & 1u);
+      m &= ((k >> bit) & 1u) ? bb : ~bb;
+    }
+    return m;
+  };
+  if (threadIdx.x < 34) s_h[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t t0 = 0; t0 < nt; t0 += 1024) {
+    const uint32_t k = klass(t0 + threadIdx.x);
+    const uint64_t m = match6(k);
+    if ((m & lt) == 0ull && k < 33u) atomicAdd(&s_h[k], (uint32_t)__popcll(m));
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t acc = 0;
-    for (int b = 32; b >= 0; --b) {
+    for (int b = 0; b < 34; ++b) {
       const uint32_t h = s_h[b];
       s_h[b] = acc;
       acc += h;
     }
   }
-  __syncthreads();
-  for (int64_t t = threadIdx.x; t < nt; t += 1024) {
-    const uint32_t c = count[t];
-    order[atomicAdd(&s_h[c ? 32 - __clz(c) : 0], 1u)] = (uint32_t)t;
+  for (int64_t t0 = 0; t0 < nt; t0 += 1024) {
+    for (int i = threadIdx.x; i < 16 * 34; i += 1024) (&s_wc[0][0])[i] = 0u;
+    __syncthreads();
+    const int64_t t = t0 + threadIdx.x;
+    const uint32_t k = klass(t);
+    const uint64_t m = match6(k);
+    if ((m & lt) == 0ull) s_wc[w][k] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (k < 33u) {
+      uint32_t pos = s_h[k] + (uint32_t)__popcll(m & lt);
+      for (uint32_t v = 0; v < w; ++v) pos += s_wc[v][k];
+      order[pos] = (uint32_t)t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 33) {
+      uint32_t add = 0;
+      for (int v = 0; v < 16; ++v) add += s_wc[v][threadIdx.x];
+      s_h[threadIdx.x] += add;
+    }
+    __syncthreads();
   }
+}
+
+// Index word of a bucket entry (see Ws::lbits).
+__device__ __forceinline__ uint32_t entry_word(const Footprint& f, int64_t i, int tx, int ty,
+                                               int T, int lbits, int pb) {
+  if (!lbits) return (uint32_t)i;
+  const uint32_t cx = (uint32_t)(f.x0 - tx * T + 1), cy = (uint32_t)(f.y0 - ty * T + 1);
+  return ((uint32_t)i << lbits) | (cy << pb) | cx;
 }
 
 // Step 2 with per-workgroup slot reservation: histogram the chunk's tiles in
@@ -234,6 +279,7 @@ __global__ __launch_bounds__(kBinBlock) void k_scatter(Cam cam, Opts o, int64_t 
                                                        const uint32_t* __restrict__ ntiles,
                                                        uint32_t* __restrict__ cursor,
                                                        uint2* __restrict__ bucket, uint32_t cap,
+                                                       int lbits, int pb,
                                                        const uint32_t* __restrict__ flags) {
   __shared__ uint32_t bins[kLdsBins];
   if (flags[kFlagOverflow]) return;
@@ -258,12 +304,14 @@ __global__ __launch_bounds__(kBinBlock) void k_scatter(Cam cam, Opts o, int64_t 
   for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBinBlock) {
     if (ntiles[i] == 0) continue;
     const float2 p = uv[i];
-    const TileRect r = tile_rect(footprint(o, cam, p.x, p.y, radius ? radius[i] : 0.f), sh);
-    const uint2 e = make_uint2(key[i], (uint32_t)i);
+    const Footprint f = footprint(o, cam, p.x, p.y, radius ? radius[i] : 0.f);
+    const TileRect r = tile_rect(f, sh);
+    const uint32_t k = key[i];
     for (int ty = r.ty0; ty <= r.ty1; ++ty)
       for (int tx = r.tx0; tx <= r.tx1; ++tx) {
         const uint32_t slot = atomicAdd(&bins[ty * o.ntx + tx], 1u);
-        if (slot < cap) bucket[slot] = e;  // always true when the counts of step 1 hold
+        // always in range when the counts of step 1 hold
+        if (slot < cap) bucket[slot] = make_uint2(k, entry_word(f, i, tx, ty, o.T, lbits, pb));
       }
   }
 }
@@ -272,7 +320,7 @@ __global__ __launch_bounds__(kBinBlock) void k_scatter(Cam cam, Opts o, int64_t 
 __global__ __launch_bounds__(kBlock) void k_scatter_global(
     Cam cam, Opts o, int64_t n, const float2* __restrict__ uv, const float* __restrict__ radius,
     const uint32_t* __restrict__ key, const uint32_t* __restrict__ ntiles,
-    uint32_t* __restrict__ cursor, uint2* __restrict__ bucket, uint32_t cap,
+    uint32_t* __restrict__ cursor, uint2* __restrict__ bucket, uint32_t cap, int lbits, int pb,
     const uint32_t* __restrict__ flags) {
   if (flags[kFlagOverflow]) return;
   const int sh = tile_shift(o.T);
@@ -280,12 +328,13 @@ __global__ __launch_bounds__(kBlock) void k_scatter_global(
        i += (int64_t)gridDim.x * blockDim.x) {
     if (ntiles[i] == 0) continue;
     const float2 p = uv[i];
-    const TileRect r = tile_rect(footprint(o, cam, p.x, p.y, radius ? radius[i] : 0.f), sh);
-    const uint2 e = make_uint2(key[i], (uint32_t)i);
+    const Footprint f = footprint(o, cam, p.x, p.y, radius ? radius[i] : 0.f);
+    const TileRect r = tile_rect(f, sh);
+    const uint32_t k = key[i];
     for (int ty = r.ty0; ty <= r.ty1; ++ty)
       for (int tx = r.tx0; tx <= r.tx1; ++tx) {
         const uint32_t slot = atomicAdd(&cursor[ty * o.ntx + tx], 1u);
-        if (slot < cap) bucket[slot] = e;
+        if (slot < cap) bucket[slot] = make_uint2(k, entry_word(f, i, tx, ty, o.T, lbits, pb));
       }
   }
 }
@@ -373,11 +422,11 @@ hipError_t launch_bin(const Cam& cam, const Opts& o, int64_t n, const float* uv,
     const int64_t chunk = bin_chunk(n);
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)((n + chunk - 1) / chunk)), dim3(kBinBlock), 0, s,
                        cam, o, n, chunk, reinterpret_cast<const float2*>(uv), radius, key, ntiles,
-                       ws.cursor, ws.bucket, ws.cap, ws.flags);
+                       ws.cursor, ws.bucket, ws.cap, ws.lbits, ws.pb, ws.flags);
   } else {
     hipLaunchKernelGGL(k_scatter_global, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, cam, o, n,
                        reinterpret_cast<const float2*>(uv), radius, key, ntiles, ws.cursor,
-                       ws.bucket, ws.cap, ws.flags);
+                       ws.bucket, ws.cap, ws.lbits, ws.pb, ws.flags);
   }
   return hipGetLastError();
 }

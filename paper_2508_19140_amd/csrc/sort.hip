@@ -180,8 +180,8 @@ __device__ __forceinline__ void block_rank(const uint32_t (&d)[ITEMS], const boo
 // Sort n <= NW*ITEMS*64 (key, idx) pairs of one segment entirely in LDS and
 // write the point indices in (key, idx) order to out[0..n).
 template <int NW, int ITEMS, bool WAVE_ONLY>
-__device__ void sort_segment_lds(const uint2* __restrict__ seg, uint32_t n,
-                                 uint32_t* __restrict__ out, const SortSmem& sm) {
+__device__ void sort_segment_lds(const uint2* __restrict__ seg, uint32_t n, const ListOut& out,
+                                 uint32_t base, const SortSmem& sm) {
   constexpr int PER_WAVE = ITEMS * 64;
   const uint32_t lane = __lane_id();
   const uint32_t w = WAVE_ONLY ? 0u : (threadIdx.x >> 6);
@@ -313,13 +313,13 @@ __device__ void sort_segment_lds(const uint2* __restrict__ seg, uint32_t n,
     if (!long_run) break;
     bsync<WAVE_ONLY>();
   }
-  for (uint32_t e = tid; e < n; e += nth) out[e] = sm.idx[e];
+  for (uint32_t e = tid; e < n; e += nth) out.put(base + e, sm.idx[e]);
   bsync<WAVE_ONLY>();
 }
 
 // n <= 64: every lane counts the (key, index) pairs smaller than its own.
-__device__ void rank_sort_wave(const uint2* __restrict__ seg, uint32_t n,
-                               uint32_t* __restrict__ out, uint2* __restrict__ s) {
+__device__ void rank_sort_wave(const uint2* __restrict__ seg, uint32_t n, const ListOut& out,
+                               uint32_t base, uint2* __restrict__ s) {
   const uint32_t lane = __lane_id();
   const bool valid = lane < n;
   const uint2 v = valid ? seg[lane] : make_uint2(0u, 0u);
@@ -330,7 +330,7 @@ __device__ void rank_sort_wave(const uint2* __restrict__ seg, uint32_t n,
     const uint2 o = s[m];
     r += (o.x < v.x) || (o.x == v.x && o.y < v.y);
   }
-  if (valid) out[r] = v.y;
+  if (valid) out.put(base + r, v.y);
   bsync<true>();
 }
 
@@ -341,7 +341,7 @@ constexpr int kW_CAP = kW_ITEMS * 64;
 __global__ __launch_bounds__(256) void k_sort_w(const uint2* __restrict__ segs,
                                                 const uint32_t* __restrict__ flags,
                                                 const uint2* __restrict__ bucket,
-                                                uint32_t* __restrict__ list) {
+                                                ListOut out) {
   __shared__ uint32_t s_key[4][kW_CAP];
   __shared__ uint32_t s_idx[4][kW_CAP];
   __shared__ uint32_t s_hist[4][256];
@@ -354,9 +354,9 @@ __global__ __launch_bounds__(256) void k_sort_w(const uint2* __restrict__ segs,
   for (uint32_t i = blockIdx.x * 4 + w; i < count; i += gridDim.x * 4) {
     const uint2 sg = segs[i];
     if (sg.y <= 64)
-      rank_sort_wave(bucket + sg.x, sg.y, list + sg.x, reinterpret_cast<uint2*>(s_key[w]));
+      rank_sort_wave(bucket + sg.x, sg.y, out, sg.x, reinterpret_cast<uint2*>(s_key[w]));
     else
-      sort_segment_lds<1, kW_ITEMS, true>(bucket + sg.x, sg.y, list + sg.x, sm);
+      sort_segment_lds<1, kW_ITEMS, true>(bucket + sg.x, sg.y, out, sg.x, sm);
   }
 }
 
@@ -365,7 +365,7 @@ template <int NW, int ITEMS, int FLAG>
 __global__ __launch_bounds__(NW * 64) void k_sort_block(const uint2* __restrict__ segs,
                                                         const uint32_t* __restrict__ flags,
                                                         const uint2* __restrict__ bucket,
-                                                        uint32_t* __restrict__ list) {
+                                                        ListOut out) {
   constexpr int CAP = NW * ITEMS * 64;
   __shared__ uint32_t s_key[CAP];
   __shared__ uint32_t s_idx[CAP];
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(NW * 64) void k_sort_block(const uint2* __restrict_
   const uint32_t count = flags[FLAG];
   for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
     const uint2 sg = segs[i];
-    sort_segment_lds<NW, ITEMS, false>(bucket + sg.x, sg.y, list + sg.x, sm);
+    sort_segment_lds<NW, ITEMS, false>(bucket + sg.x, sg.y, out, sg.x, sm);
   }
 }
 
@@ -475,7 +475,7 @@ __global__ __launch_bounds__(1024) void k_split(int round, Ws ws) {
 // elements; each pass first histograms the whole segment so that every round
 // knows where each digit's run starts.
 template <int NW, int ITEMS>
-__global__ __launch_bounds__(NW * 64) void k_sort_x(Ws ws, uint32_t* __restrict__ list) {
+__global__ __launch_bounds__(NW * 64) void k_sort_x(Ws ws, ListOut out) {
   constexpr int ROUND = NW * ITEMS * 64;
   __shared__ uint32_t s_hist[NW * 256];
   __shared__ uint32_t s_off[256];
@@ -548,7 +548,7 @@ __global__ __launch_bounds__(NW * 64) void k_sort_x(Ws ws, uint32_t* __restrict_
         for (int j = 0; j < ITEMS; ++j) {
           if (valid[j]) {
             if (last)
-              list[s + rank[j]] = v[j].y;
+              out.put(s + rank[j], v[j].y);
             else
               dst[rank[j]] = v[j];
           }
@@ -560,7 +560,7 @@ __global__ __launch_bounds__(NW * 64) void k_sort_x(Ws ws, uint32_t* __restrict_
       dst = t;
     }
     if (np == 0) {
-      for (uint32_t e = threadIdx.x; e < n; e += NW * 64) list[s + e] = ws.bucket[s + e].y;
+      for (uint32_t e = threadIdx.x; e < n; e += NW * 64) out.put(s + e, ws.bucket[s + e].y);
     }
     __syncthreads();
   }
@@ -568,20 +568,22 @@ __global__ __launch_bounds__(NW * 64) void k_sort_x(Ws ws, uint32_t* __restrict_
 
 }  // namespace
 
-hipError_t launch_sort(const Ws& ws, uint32_t* list, int64_t nt, hipStream_t stream) {
+hipError_t launch_sort(const Ws& ws, uint32_t* list, uint16_t* lpos, int64_t nt,
+                       hipStream_t stream) {
+  const ListOut out{list, lpos, ws.lbits, ws.pb};
   const int64_t big_max = std::max<int64_t>(1, (int64_t)ws.cap / (int64_t)(kSortCapM + 1));
   const int grid_split = (int)std::min<int64_t>(big_max, 1024);
   hipLaunchKernelGGL(k_split, dim3(grid_split), dim3(1024), 0, stream, 0, ws);
   hipLaunchKernelGGL(k_split, dim3(grid_split), dim3(1024), 0, stream, 1, ws);
   const int grid_w = (int)std::min<int64_t>((nt + 3) / 4 + (int64_t)ws.cap / 256, 8192);
   hipLaunchKernelGGL(k_sort_w, dim3(std::max(grid_w, 1)), dim3(256), 0, stream, ws.seg_w, ws.flags,
-                     ws.bucket, list);
+                     ws.bucket, out);
   const int grid_m = (int)std::min<int64_t>(nt + (int64_t)ws.cap / 2048, 4096);
   hipLaunchKernelGGL((k_sort_block<4, 8, kFlagCountM>), dim3(std::max(grid_m, 1)), dim3(256), 0,
-                     stream, ws.seg_m, ws.flags, ws.bucket, list);
+                     stream, ws.seg_m, ws.flags, ws.bucket, out);
   hipLaunchKernelGGL((k_sort_block<16, 16, kFlagCountL>), dim3(grid_split), dim3(1024), 0, stream,
-                     ws.seg_l, ws.flags, ws.bucket, list);
-  hipLaunchKernelGGL((k_sort_x<16, 16>), dim3(256), dim3(1024), 0, stream, ws, list);
+                     ws.seg_l, ws.flags, ws.bucket, out);
+  hipLaunchKernelGGL((k_sort_x<16, 16>), dim3(256), dim3(1024), 0, stream, ws, out);
   return hipGetLastError();
 }
 

@@ -91,6 +91,8 @@ class Binning(NamedTuple):
     ranges: torch.Tensor    # [num_tiles + 1] (int32 storage of u32)
     list: torch.Tensor      # [copy capacity] point indices (int32 storage of u32)
     order: torch.Tensor     # [num_tiles] blend order, longest tiles first
+    lpos: torch.Tensor      # [copy capacity] tile-local splat corner per list entry (int16
+                            # storage of u16; bilinear splats)
 
 
 def project_bin_sort(pos: torch.Tensor, cam: L.Camera, opts: L.Opts, ws: torch.Tensor,
@@ -107,6 +109,7 @@ def project_bin_sort(pos: torch.Tensor, cam: L.Camera, opts: L.Opts, ws: torch.T
     ranges = torch.empty(nt + 1, dtype=torch.int32, device=dev)
     order = torch.empty(max(nt, 1), dtype=torch.int32, device=dev)
     lst = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    lpos = torch.empty(max(cap, 1), dtype=torch.int16, device=dev)
     s = _stream(dev)
     cb, ob = ctypes.byref(cam), ctypes.byref(opts)
     wsb = ws.numel()
@@ -114,8 +117,9 @@ def project_bin_sort(pos: torch.Tensor, cam: L.Camera, opts: L.Opts, ws: torch.T
            wsb, s)
     L.call("inpc_bin", cb, ob, n, _p(uv), _p(radius), _p(key), _p(ntiles), _p(ranges),
            _p(order), _p(ws), wsb, s)
-    L.call("inpc_sort", cb, ob, n, _p(ranges), _p(lst), _p(ws), wsb, s)
-    return Binning(uv, key, ntiles, ranges, lst, order)
+    L.call("inpc_sort", cb, ob, n, _p(uv), _p(ranges), _p(order), _p(lst), _p(lpos), _p(ws),
+           wsb, s)
+    return Binning(uv, key, ntiles, ranges, lst, order, lpos)
 
 
 def blend_forward(b: Binning, opacity, feat, cam: L.Camera, opts: L.Opts, ws: torch.Tensor,
@@ -133,8 +137,8 @@ def blend_forward(b: Binning, opacity, feat, cam: L.Camera, opts: L.Opts, ws: to
                             dtype=torch.uint8, device=dev)
     L.call("inpc_blend_forward", ctypes.byref(cam), ctypes.byref(opts), n, _p(b.uv), _p(radius),
            _p(opacity), _p(feat), C, _DTYPES[feat.dtype], _p(bg), _p(b.ranges), _p(b.order),
-           _p(b.list), _p(out), _p(t_final), _p(n_contrib), _p(state), _p(ws), ws.numel(),
-           _stream(dev))
+           _p(b.list), _p(b.lpos if opts.splat == L.SPLAT_BILINEAR else None), _p(out),
+           _p(t_final), _p(n_contrib), _p(state), _p(ws), ws.numel(), _stream(dev))
     return out, t_final, n_contrib, state
 
 
@@ -156,9 +160,8 @@ def blend_backward(b: Binning, opacity, feat, cam: L.Camera, opts: L.Opts, ws: t
                               device=dev)
     L.call("inpc_blend_backward", ctypes.byref(cam), ctypes.byref(opts), n, _p(b.uv),
            _p(opacity), _p(feat), C, _DTYPES[feat.dtype], _p(bg), _p(b.ntiles), _p(b.ranges),
-           _p(b.order), _p(b.list), _p(t_final), _p(state), _p(grad_out), _p(grad_t),
-           _p(grad_feat),
-           _p(grad_opacity), _p(grad_uv), _p(grad_bg), _p(scratch), scratch.numel(), _p(ws),
+           _p(b.order), _p(b.list), _p(b.lpos), _p(t_final), _p(state), _p(grad_out),
+           _p(grad_t), _p(grad_feat), _p(grad_opacity), _p(grad_uv), _p(grad_bg), _p(scratch), scratch.numel(), _p(ws),
            ws.numel(), _stream(dev))
     return grad_feat, grad_opacity, grad_uv, grad_bg
 

@@ -31,7 +31,10 @@ def run_gpu(scene, settings, bg=None, feat_dtype=torch.float32, backward=True, f
     r = dict(uv=b.uv.cpu().numpy(), key=b.key.cpu().numpy().view(np.uint32),
              ntiles=b.ntiles.cpu().numpy().view(np.uint32),
              ranges=b.ranges.cpu().numpy().view(np.uint32), list=b.list.cpu().numpy().view(np.uint32),
-             out=out.cpu().numpy(), t_final=tf.cpu().numpy(), n_contrib=nc.cpu().numpy().view(np.uint32))
+             out=out.cpu().numpy(), t_final=tf.cpu().numpy(), n_contrib=nc.cpu().numpy().view(np.uint32),
+             order=b.order.cpu().numpy().view(np.uint32), tile=settings.tile,
+             W=cam.width, H=cam.height,
+             lpos=b.lpos.cpu().numpy().view(np.uint16) if settings.splat == "bilinear" else None)
     if backward and scene.grad is not None and settings.splat == "bilinear":
         g = torch.from_numpy(scene.grad).to(DEV)
         gt = None if scene.grad_t is None else torch.from_numpy(scene.grad_t).to(DEV)
@@ -65,6 +68,34 @@ def assert_binning_exact(g, proj, tl):
     np.testing.assert_array_equal(g["ranges"].astype(np.int64), tl["ranges"])
     M = int(tl["ranges"][-1])
     np.testing.assert_array_equal(g["list"][:M], tl["list"])
+    # blend order: decreasing power-of-two class of the copy count, then tile index
+    counts = np.diff(tl["ranges"])
+    klass = np.array([32 - int(c).bit_length() for c in counts], np.int64)
+    np.testing.assert_array_equal(g["order"][:len(counts)], np.lexsort((np.arange(len(counts)), klass)))
+    if g.get("lpos") is not None:
+        assert_lpos(g, proj, tl)
+
+
+def assert_lpos(g, proj, tl):
+    """Every list entry's tile-local 2x2 position covers exactly the in-image
+    pixels of its tile that the oracle's candidate rect covers."""
+    T, ntx = g["tile"], tl["ntx"]
+    counts = np.diff(tl["ranges"])
+    M = int(tl["ranges"][-1])
+    if M == 0:
+        return
+    tile = np.repeat(np.arange(len(counts)), counts)
+    tx0, ty0 = (tile % ntx) * T, (tile // ntx) * T
+    lp = g["lpos"][:M].astype(np.int64)
+    rect = proj["rect"][tl["list"]].astype(np.int64)
+    for ax, (base, lo, size) in enumerate(((tx0, lp & 0xff, g["W"]), (ty0, lp >> 8, g["H"]))):
+        a = base + lo - 1
+        got_lo = np.maximum(np.maximum(a, base), 0)
+        got_hi = np.minimum(np.minimum(a + 1, base + T - 1), size - 1)
+        ref_lo = np.maximum(rect[:, ax], base)
+        ref_hi = np.minimum(rect[:, ax + 2], base + T - 1)
+        np.testing.assert_array_equal(got_lo, ref_lo)
+        np.testing.assert_array_equal(got_hi, ref_hi)
 
 
 def assert_close(name, gpu, ref, ref_abs, rel=1e-5, abs_=1e-6, mask=None):

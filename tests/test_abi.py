@@ -92,7 +92,7 @@ def test_blend_rejects_bad_channels_and_dtype():
     n = 10
     wsb = lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(o))
     base = [ctypes.byref(c), ctypes.byref(o), n, FAKE, None, FAKE, FAKE]
-    tail = [None, FAKE, None, FAKE, FAKE, FAKE, FAKE, None, FAKE, wsb, None]
+    tail = [None, FAKE, None, FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, wsb, None]
     assert lib.inpc_blend_forward(*base, 0, L.DTYPE_F32, *tail) == L.INPC_ERR_INVALID
     assert lib.inpc_blend_forward(*base, 65, L.DTYPE_F32, *tail) == L.INPC_ERR_INVALID
     assert lib.inpc_blend_forward(*base, 4, 7, *tail) == L.INPC_ERR_INVALID
@@ -107,7 +107,8 @@ def test_backward_rejects_gaussians():
     wsb = lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(g))
     st = lib.inpc_blend_backward(ctypes.byref(c), ctypes.byref(g), n, FAKE, FAKE, FAKE, 4,
                                  L.DTYPE_F32, None, FAKE, FAKE, None, FAKE, FAKE, FAKE, FAKE,
-                                 None, FAKE, FAKE, FAKE, None, FAKE, 1 << 20, FAKE, wsb, None)
+                                 FAKE, None, FAKE, FAKE, FAKE, None, FAKE, 1 << 20, FAKE, wsb,
+                                 None)
     assert st == L.INPC_ERR_UNSUPPORTED
 
 
@@ -119,9 +120,23 @@ def test_backward_rejects_small_scratch():
     need = lib.inpc_backward_scratch_bytes(n, C, ctypes.byref(c), ctypes.byref(o))
     assert need >= n * 4 * 8 * 4
     args = [ctypes.byref(c), ctypes.byref(o), n, FAKE, FAKE, FAKE, C, L.DTYPE_F32, None, FAKE,
-            FAKE, None, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, FAKE, None]
+            FAKE, None, FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, FAKE, None]
     assert lib.inpc_blend_backward(*args, FAKE, need - 1, FAKE, wsb, None) == L.INPC_ERR_INVALID
     assert lib.inpc_blend_backward(*args, None, need, FAKE, wsb, None) == L.INPC_ERR_INVALID
+
+
+def test_sort_and_blend_require_lpos_for_bilinear():
+    lib = L.lib()
+    c, o = cam(), L.make_opts(tile=8)
+    n = 10
+    wsb = lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(o))
+    st = lib.inpc_sort(ctypes.byref(c), ctypes.byref(o), n, FAKE, FAKE, None, FAKE, None, FAKE,
+                       wsb, None)
+    assert st == L.INPC_ERR_INVALID and b"lpos" in lib.inpc_last_error()
+    st = lib.inpc_blend_forward(ctypes.byref(c), ctypes.byref(o), n, FAKE, None, FAKE, FAKE, 4,
+                                L.DTYPE_F32, None, FAKE, None, FAKE, None, FAKE, FAKE, FAKE,
+                                None, FAKE, wsb, None)
+    assert st == L.INPC_ERR_INVALID and b"lpos" in lib.inpc_last_error()
 
 
 def test_status_strings():

@@ -173,3 +173,16 @@ def test_forward_deterministic():
     b = run_gpu(sc, st, backward=False)
     for k in ("list", "ranges", "out", "t_final", "n_contrib"):
         np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_unpacked_splat_positions():
+    """More than 2^22 points with 16x16 tiles: the point index and the
+    tile-local splat corner no longer share one 32-bit word, so the sort
+    writes the corners in a separate pass.  Forward and backward parity."""
+    sc = small_c2(n=(1 << 22) + 5, W=256, H=144, channels=4)
+    st = settings_opts(tile=16)
+    g = run_gpu(sc, st)
+    proj, tl, rr = run_oracle(sc, st)
+    assert_binning_exact(g, proj, tl)
+    assert_forward(g, rr)
+    assert_backward(g, rr, sc.grad)
