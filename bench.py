@@ -38,7 +38,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="H", choices=["H", "C2", "C3", "C5"])
+    ap.add_argument("--config", default="H", choices=["H", "C2", "C3", "C5", "C4"],
+                    help="C4: 8 views of uneven size in one autotuned graph launch")
     ap.add_argument("--tile", type=int, default=8, choices=[8, 16])
     ap.add_argument("--dtype", default=None, choices=["f32", "bf16", "f16"],
                     help="feature storage type (default: bf16 for C5, f32 otherwise)")
@@ -50,124 +51,53 @@ def parse():
                          "the stored features and on the original FP32 features")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many untimed steps (for rocprofv3) and exit")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="with --profile-steps: also run one plain device-to-device copy of "
+                         "this many MiB (the reference for scaling HBM byte counters)")
     return ap.parse_args()
 
 
-class Step:
-    """Preallocated buffers and the ABI calls of one pass."""
+def make_step(sc, tile, keep_lists, dtype, dev):
+    """The preallocated pipeline of one view (every buffer allocated here)."""
+    import torch
+    import paper_2508_19140_amd as inpc
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[dtype]
+    gauss = sc.radius is not None
+    v = inpc.ViewInputs(pos=torch.from_numpy(sc.pos).to(dev),
+                        opacity=torch.from_numpy(sc.opacity).to(dev),
+                        feat=torch.from_numpy(sc.feat).to(dev).to(tdt).contiguous(),
+                        camera=sc.camera,
+                        grad_out=None if gauss else torch.from_numpy(sc.grad).to(dev),
+                        radius=torch.from_numpy(sc.radius).to(dev) if gauss else None)
+    st = inpc.RasterSettings(splat="gaussian" if gauss else "bilinear", tile=tile,
+                             keep_lists=keep_lists,
+                             max_radius=float(sc.radius.max()) if gauss else 0.0)
+    step = inpc.ViewPipeline(v, st)
+    step.bf = 4 if dtype == "f32" else 2
+    step.P = sc.camera.width * sc.camera.height
+    return step
 
-    def __init__(self, sc, tile, keep_lists, dtype, dev):
-        import torch
-        import paper_2508_19140_amd as inpc
-        from paper_2508_19140_amd import _lib as L
-        self.torch, self.L = torch, L
-        self.gauss = sc.radius is not None
-        self.cam = inpc.camera_struct(sc.camera)
-        self.opts = inpc.RasterSettings(splat="gaussian" if self.gauss else "bilinear", tile=tile,
-                                        max_radius=float(sc.radius.max()) if self.gauss
-                                        else 0.0).opts()
-        self.keep_lists = keep_lists
-        n, C = sc.feat.shape
-        self.n, self.C = n, C
-        tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[dtype]
-        self.dtype_code = {"f32": L.DTYPE_F32, "bf16": L.DTYPE_BF16, "f16": L.DTYPE_F16}[dtype]
-        self.bf = 4 if dtype == "f32" else 2
-        self.pos = torch.from_numpy(sc.pos).to(dev)
-        self.op = torch.from_numpy(sc.opacity).to(dev)
-        self.feat = torch.from_numpy(sc.feat).to(dev).to(tdt).contiguous()
-        self.radius = torch.from_numpy(sc.radius).to(dev) if self.gauss else None
-        self.grad = None if self.gauss else torch.from_numpy(sc.grad).to(dev)
-        lib = L.lib()
-        cb, ob = ctypes.byref(self.cam), ctypes.byref(self.opts)
-        self.cb, self.ob = cb, ob
-        nt = int(lib.inpc_num_tiles(cb, ob))
-        cap = int(lib.inpc_copy_capacity(n, cb, ob))
-        self.nt = nt
-        wsb = int(lib.inpc_workspace_bytes(n, cb, ob))
-        self.ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
-        H, W = sc.camera.height, sc.camera.width
-        self.P = H * W
-        i32 = torch.int32
-        mk = lambda *s, dt=torch.float32: torch.empty(*s, dtype=dt, device=dev)
-        self.uv, self.key, self.ntiles = mk(n, 2), mk(n, dt=i32), mk(n, dt=i32)
-        self.ranges, self.list = mk(nt + 1, dt=i32), mk(cap, dt=i32)
-        self.order = mk(nt, dt=i32)
-        self.lpos = mk(cap, dt=torch.int16)
-        self.out, self.tf, self.nc = mk(C, H, W), mk(H, W), mk(H, W, dt=i32)
-        self.state = None
-        if not self.gauss:
-            self.state = mk(int(lib.inpc_state_bytes(cb, ob)), dt=torch.uint8)
-            self.gf, self.go, self.guv, self.gpos = mk(n, C), mk(n), mk(n, 2), mk(n, 3)
-            self.scratch = mk(int(lib.inpc_backward_scratch_bytes(n, C, cb, ob)),
-                              dt=torch.uint8)
-        self.lib = lib
-        self.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
-    @staticmethod
-    def p(t):
-        return None if t is None else ctypes.c_void_p(t.data_ptr())
-
-    def _chk(self, st, name):
-        if st != 0:
-            raise RuntimeError(f"{name}: {self.lib.inpc_last_error().decode()}")
-
-    def project(self):
-        p, lib = self.p, self.lib
-        self._chk(lib.inpc_project(self.cb, self.ob, self.n, p(self.pos), p(self.radius),
-                                   p(self.uv), p(self.key), p(self.ntiles), p(self.ws),
-                                   self.ws.numel(), self.stream), "project")
-
-    def bin(self):
-        p, lib = self.p, self.lib
-        self._chk(lib.inpc_bin(self.cb, self.ob, self.n, p(self.uv), p(self.radius), p(self.key),
-                               p(self.ntiles), p(self.ranges), p(self.order), p(self.ws),
-                               self.ws.numel(), self.stream), "bin")
-
-    def sort(self):
-        p, lib = self.p, self.lib
-        self._chk(lib.inpc_sort(self.cb, self.ob, self.n, p(self.uv), p(self.ranges),
-                                p(self.order), p(self.list), p(self.lpos), p(self.ws),
-                                self.ws.numel(), self.stream), "sort")
-
-    def blend_fwd(self):
-        p, lib = self.p, self.lib
-        self._chk(lib.inpc_blend_forward(self.cb, self.ob, self.n, p(self.uv), p(self.radius),
-                                         p(self.op), p(self.feat), self.C, self.dtype_code, None,
-                                         p(self.ranges), p(self.order), p(self.list),
-                                         None if self.gauss else p(self.lpos), p(self.out),
-                                         p(self.tf), p(self.nc), p(self.state), p(self.ws),
-                                         self.ws.numel(), self.stream), "blend_forward")
-
-    def blend_bwd(self):
-        p, lib = self.p, self.lib
-        self._chk(lib.inpc_blend_backward(self.cb, self.ob, self.n, p(self.uv), p(self.op),
-                                          p(self.feat), self.C, self.dtype_code, None,
-                                          p(self.ntiles), p(self.ranges), p(self.order),
-                                          p(self.list), p(self.lpos), p(self.tf), p(self.state),
-                                          p(self.grad), None, p(self.gf), p(self.go),
-                                          p(self.guv), None, p(self.scratch),
-                                          self.scratch.numel(), p(self.ws), self.ws.numel(),
-                                          self.stream), "blend_backward")
-
-    def project_bwd(self):
-        p, lib = self.p, self.lib
-        self._chk(lib.inpc_project_backward(self.cb, self.n, p(self.pos), p(self.ntiles),
-                                            p(self.guv), p(self.gpos), self.stream),
-                  "project_backward")
-
-    def phases(self):
-        fwd = [("project", self.project), ("bin", self.bin), ("sort", self.sort),
-               ("blend_fwd", self.blend_fwd)]
-        if self.gauss:
-            return fwd
-        bwd = [] if self.keep_lists else [("project", self.project), ("bin", self.bin),
-                                          ("sort", self.sort)]
-        bwd += [("blend_bwd", self.blend_bwd), ("project_bwd", self.project_bwd)]
-        return fwd + bwd
-
-    def run(self):
-        for _, f in self.phases():
-            f()
+def measured_traffic(entry, config):
+    """HBM bytes per launch of an entry point from a committed counter
+    summary (profiles/pmc_<entry>_<config>.txt: FETCH_SIZE + WRITE_SIZE summed
+    over the entry point's kernels, scaled by a plain copy's counters), or
+    None when there is none or a kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"pmc_{entry}_{config}.txt")
+    if not os.path.exists(path):
+        return None
+    traffic, ok = None, True
+    for line in open(path):
+        f = line.split()
+        if len(f) == 3 and f[0] == "sha256":
+            src = os.path.join(ROOT, f[1])
+            if not os.path.exists(src) or \
+                    hashlib.sha256(open(src, "rb").read()).hexdigest() != f[2]:
+                ok = False
+        elif len(f) == 2 and f[0] == "traffic_bytes_per_launch":
+            traffic = float(f[1])
+    return traffic if ok else None
 
 
 def byte_models(n, V, M, P, C, nt, bf=4, gauss=False, keep_lists=False):
@@ -175,23 +105,23 @@ def byte_models(n, V, M, P, C, nt, bf=4, gauss=False, keep_lists=False):
     the per-entry-point minima (each input read once, each output written once)."""
     D = M / max(V, 1)
     per_kernel = {
-        # read positions (and radii), write uv + key + ntiles
-        "project": 12 * n + 16 * n + (4 * n if gauss else 0),
-        # read ntiles, uv and key of visible points; write one (key, index) copy per tile
-        "bin": 4 * n + 12 * V + 8 * M + 8 * nt,
+        # read positions, opacity (and radii); write the projection record, key, ntiles
+        "project": 12 * n + 4 * n + 16 * n + 8 * n + (4 * n if gauss else 0),
+        # read ntiles, and record and key of visible points; write one copy per tile
+        "bin": 4 * n + 20 * V + 8 * M + 8 * nt,
         # read the bucket, write the list (and the 2-byte splat positions)
-        "sort": 8 * M + 4 * M + 4 * nt + (0 if gauss else 2 * M + 8 * V),
+        "sort": 8 * M + 4 * M + 4 * nt + (0 if gauss else 2 * M),
     }
     if gauss:
-        # list + point data (uv, radius, opacity, features) once + image, t_final, n_contrib
+        # list + point data (record, features) once + image, t_final, n_contrib
         per_kernel["blend_fwd"] = 4 * M + 4 * nt + V * (16 + C * bf) + P * (4 * C + 8)
         b_min = n * (16 + 4 + C * bf) + 4 * D * V + 4 * P * (C + 2)
         return b_min, b_min + 64 * V + 24 * D * V, per_kernel
     per_kernel.update({
-        # list + positions + point data once + image, t_final, n_contrib and state written
-        "blend_fwd": 6 * M + 4 * nt + V * (12 + C * bf) + P * (4 * C + 20),
-        # list + positions + point data + ntiles once + G, t_final, state read + gradients
-        "blend_bwd": 6 * M + 4 * nt + V * (16 + C * bf) + P * (4 * C + 16) + n * (4 * C + 12),
+        # list + splat positions + point data once + image, t_final, n_contrib, state written
+        "blend_fwd": 6 * M + 4 * nt + V * (16 + C * bf) + P * (4 * C + 20),
+        # list + positions + point data once + G, t_final, state read + ntiles and gradients
+        "blend_bwd": 6 * M + 4 * nt + V * (16 + C * bf) + P * (4 * C + 16) + n * (4 * C + 16),
         # positions, ntiles, grad_uv read; grad_pos written
         "project_bwd": 12 * n + 4 * n + 8 * n + 12 * n,
     })
@@ -221,13 +151,14 @@ def error_table(step, sc, tile):
     import numpy as np
     import oracle
     oracle.build(force=False)
-    step.run()
-    step.torch.cuda.synchronize()
+    import torch
+    step.step(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
     gpu = {"out": step.out.cpu().numpy(), "t_final": step.tf.cpu().numpy()}
     if not step.gauss:
         gpu.update(grad_feat=step.gf.cpu().numpy(), grad_opacity=step.go.cpu().numpy(),
                    grad_pos=step.gpos.cpu().numpy())
-    stored = step.feat.float().cpu().numpy()
+    stored = step.v.feat.float().cpu().numpy()
     table = {}
     for label, feat in (("vs_stored_features", stored), ("vs_fp32_features", sc.feat)):
         rr = oracle.render(sc.camera, sc.pos, sc.opacity, feat, radius=sc.radius,
@@ -248,12 +179,76 @@ def error_table(step, sc, tile):
     return table
 
 
+def run_multiview(args):
+    """8 views (n_v ~ U{0.5M..6M}, mixed resolutions) as one graph launch per
+    step, against the same views run one after another with default settings
+    and no graph (the plain single-view form)."""
+    import numpy as np
+    import torch
+    import paper_2508_19140_amd as inpc
+    from scenes import multi_view_scenes
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    scenes = multi_view_scenes(8)
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[args.dtype or "f32"]
+    views = [inpc.ViewInputs(pos=torch.from_numpy(s.pos).to(dev),
+                             opacity=torch.from_numpy(s.opacity).to(dev),
+                             feat=torch.from_numpy(s.feat).to(dev).to(tdt).contiguous(),
+                             camera=s.camera, grad_out=torch.from_numpy(s.grad).to(dev))
+             for s in scenes]
+    n_total = sum(s.pos.shape[0] for s in scenes)
+    plain = inpc.MultiViewRasterizer(views, autotune=False)
+
+    def timed(fn, k):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    for _ in range(args.warmup):
+        plain.run_eager()
+    ms_plain = timed(plain.run_eager, args.steps)
+    del plain
+    torch.cuda.empty_cache()
+    tuned = inpc.MultiViewRasterizer(views)
+    tuned.capture()
+    for _ in range(args.warmup):
+        tuned.replay()
+    ms = timed(tuned.replay, args.steps)
+    t_s = ms * 1e-3
+    res = {
+        "metric": "points rasterized/s fwd+bwd, 8 views of uneven size in one graph launch",
+        "value": n_total / t_s, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.dtype or "f32",
+        "data": "synthetic (8 views of one seeded scene, own point sample per view)",
+        "config": {"workload": f"C4: 8 views, {n_total} points in total, fwd+bwd, lists "
+                               "recomputed, one graph launch per step",
+                   "views": [{"points": int(s.pos.shape[0]), "width": s.camera.width,
+                              "height": s.camera.height, "tile": t, "bin_points": bp}
+                             for s, (t, bp) in zip(scenes, tuned.choice)]},
+        "plain_single_view_ms": ms_plain,
+        "speedup_vs_plain_single_view": ms_plain / ms,
+        "autotune_ms": [{f"{t}/{bp}": round(v, 4) for (t, bp), v in tt.items()}
+                        for tt in tuned.tuning],
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU: the rasterizer shards by view, one view per GPU, "
               "and this build measures the single-GPU path only (--gpus 1).", file=sys.stderr)
         sys.exit(2)
+    if args.config == "C4":
+        run_multiview(args)
+        return
     import numpy as np
     import torch
     from scenes import CONFIGS, make_scene
@@ -263,17 +258,24 @@ def main():
     sc = make_scene(spec)
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    step = Step(sc, args.tile, args.keep_lists, dtype, dev)
+    step = make_step(sc, args.tile, args.keep_lists, dtype, dev)
+    h = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
     if args.profile_steps:
         for _ in range(args.profile_steps):
-            step.run()
+            step.step(h)
+        if args.copy_probe_mib:
+            src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_steps": args.profile_steps}), flush=True)
+        print(json.dumps({"profile_steps": args.profile_steps,
+                          "copy_probe_bytes": args.copy_probe_mib << 20}), flush=True)
         return
 
     for _ in range(args.warmup):
-        step.run()
+        step.step(h)
     torch.cuda.synchronize()
 
     # Timed region: K steps, every entry point bracketed by HIP events on the
@@ -285,7 +287,7 @@ def main():
     for s in range(args.steps):
         evs[s][0].record()
         for i, (_, f) in enumerate(step.phases()):
-            f()
+            f(h)
             evs[s][i + 1].record()
     torch.cuda.synchronize()
     ms = evs[0][0].elapsed_time(evs[-1][-1]) / args.steps
@@ -340,7 +342,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": f"inpc_{dominant}", "achieved": dom_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS,
                      "bytes_per_launch": dom_bytes, "ms_per_launch": per_launch_ms[dominant],
-                     "traffic": None},
+                     "traffic": measured_traffic(dominant, args.config)},
     }
     if args.errors:
         res["errors"] = error_table(step, sc, args.tile)

@@ -34,8 +34,8 @@
  *  - Discrete decisions (culling, footprints, tile membership, sort keys)
  *    use IEEE FP32 with one rounding per operation and no fused
  *    multiply-add, so they are reproducible bit for bit.
- *  - Layouts: positions [n][3], uv [n][2], features [n][C] (row per
- *    point), images planar [C][H][W], per-pixel planes [H][W].
+ *  - Layouts: positions [n][3], projection records [n][4], features [n][C]
+ *    (row per point), images planar [C][H][W], per-pixel planes [H][W].
  */
 #ifndef INPC_RASTER_H
 #define INPC_RASTER_H
@@ -79,6 +79,10 @@ typedef struct {
     float dilation;     /* Gaussian: variance added to r^2 (paper: 0.16) */
     float cutoff;       /* Gaussian: truncation in standard deviations (paper: 3) */
     float max_radius;   /* Gaussian: largest radius_px any point may have; sizes the workspace */
+    int32_t bin_points; /* points per workgroup of the counting and scatter passes of steps 1-2:
+                           0 = automatic (8192, or n/256 when larger), else a multiple of
+                           1024; never fewer than n/256 (a tuning knob: results do not
+                           depend on it; the workspace size does) */
 } inpc_opts_t;
 
 /* Bytes of workspace needed for n points with this camera and options.
@@ -101,24 +105,28 @@ int64_t inpc_num_tiles(const inpc_camera_t* cam, const inpc_opts_t* opts);
  * Step 1 -- project, cull, key (Sec. 2: points rasterized into a calibrated
  * camera; Sec. 3.2: 32-bit depth keys).
  *   pos      [n][3] f32 world positions
+ *   opacity  [n] f32 in [0, 1]
  *   radius   [n] f32 Gaussian standard deviation in pixels (before
  *            dilation), NULL for bilinear splats
- *   uv       [n][2] f32 out: image coordinates
+ *   proj     [n][4] f32 out, 16-byte aligned: per point (u, v, opacity,
+ *            radius or 0), the image coordinates next to what the blend
+ *            passes read with them, so that one 16-byte load fetches all of
+ *            a point's footprint data
  *   depth_key[n] u32 out: bit pattern of camera-space Z (monotone in Z > 0)
  *   ntiles   [n] u32 out: tiles the footprint meets, 0 for culled points
  * Also counts copies per tile into the workspace for step 2.
  */
 inpc_status_t inpc_project(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
-                           const float* pos, const float* radius, float* uv,
-                           uint32_t* depth_key, uint32_t* ntiles, void* ws, size_t ws_bytes,
-                           void* stream);
+                           const float* pos, const float* opacity, const float* radius,
+                           float* proj, uint32_t* depth_key, uint32_t* ntiles, void* ws,
+                           size_t ws_bytes, void* stream);
 
 /*
  * Step 2 -- bin (Sec. 3.2 "Tiled Rendering": one copy of a point per tile
  * its footprint meets).  Exclusive scan of the per-tile counts gathered by
  * inpc_project into tile_ranges, then one (depth key, point index) copy per
  * touched tile into the workspace buckets.
- *   uv, radius, depth_key, ntiles: outputs of inpc_project
+ *   proj, depth_key, ntiles: outputs of inpc_project
  *   tile_ranges [num_tiles + 1] u32 out: tile t owns list[tile_ranges[t] ..
  *               tile_ranges[t+1]); tile_ranges[num_tiles] = total copies M
  *   tile_order  [num_tiles] u32 out, or NULL: a permutation of the tiles by
@@ -126,9 +134,9 @@ inpc_status_t inpc_project(const inpc_camera_t* cam, const inpc_opts_t* opts, in
  *               depend on it; it only schedules long lists first)
  */
 inpc_status_t inpc_bin(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
-                       const float* uv, const float* radius, const uint32_t* depth_key,
-                       const uint32_t* ntiles, uint32_t* tile_ranges, uint32_t* tile_order,
-                       void* ws, size_t ws_bytes, void* stream);
+                       const float* proj, const uint32_t* depth_key, const uint32_t* ntiles,
+                       uint32_t* tile_ranges, uint32_t* tile_order, void* ws, size_t ws_bytes,
+                       void* stream);
 
 /*
  * Step 3 -- depth sort per tile (Sec. 3.2: depth-sorted per-tile lists).
@@ -140,8 +148,8 @@ inpc_status_t inpc_bin(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_
  * the point positions to find which pixels a copy covers.
  *   n           the point count the workspace was prepared for by
  *               inpc_project / inpc_bin
- *   uv          [n][2] f32, output of inpc_project (bilinear splats only;
- *               may be NULL for Gaussians)
+ *   proj        output of inpc_project (bilinear splats only; may be NULL
+ *               for Gaussians)
  *   tile_ranges output of inpc_bin
  *   tile_order  output of inpc_bin, or NULL
  *   list        [inpc_copy_capacity(n, cam, opts)] u32 out; the first
@@ -152,7 +160,7 @@ inpc_status_t inpc_bin(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_
  *               (x0, y0) the top-left pixel of the point's 2x2 splat
  */
 inpc_status_t inpc_sort(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
-                        const float* uv, const uint32_t* tile_ranges,
+                        const float* proj, const uint32_t* tile_ranges,
                         const uint32_t* tile_order, uint32_t* list, uint16_t* lpos, void* ws,
                         size_t ws_bytes, void* stream);
 
@@ -164,7 +172,7 @@ int64_t inpc_copy_capacity(int64_t n, const inpc_camera_t* cam, const inpc_opts_
  * For every pixel, the fragments of its tile's list in order: alpha = o w
  * (w bilinear weight or Gaussian value), F += T alpha f, T *= 1 - alpha;
  * stops before the first fragment whose T < t_min; finally F += T f_bg.
- *   opacity    [n] f32 in [0, 1]
+ *   proj       output of inpc_project (position, opacity, radius)
  *   feat       [n][C] features, dtype INPC_F32 / INPC_F16 / INPC_BF16
  *              (blending and accumulation are FP32 for every dtype)
  *   bg         [C] f32 constant background features, or NULL (zero)
@@ -178,8 +186,8 @@ int64_t inpc_copy_capacity(int64_t n, const inpc_camera_t* cam, const inpc_opts_
  *              may be NULL when no backward pass follows
  */
 inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
-                                 const float* uv, const float* radius, const float* opacity,
-                                 const void* feat, int32_t C, int32_t dtype, const float* bg,
+                                 const float* proj, const void* feat, int32_t C, int32_t dtype,
+                                 const float* bg,
                                  const uint32_t* tile_ranges, const uint32_t* tile_order,
                                  const uint32_t* list, const uint16_t* lpos, float* out,
                                  float* t_final, uint32_t* n_contrib, void* state, void* ws,
@@ -194,7 +202,7 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
  * B_k the blend of everything behind fragment k including the background;
  * then dL/df, dL/do = w dL/dalpha, dL/d(u,v) = o dw/d(u,v) dL/dalpha.
  * Bilinear splats only (INPC_ERR_UNSUPPORTED for Gaussians).
- *   ntiles, tile_ranges, tile_order, list, lpos: from steps 1-3
+ *   proj, ntiles, tile_ranges, tile_order, list, lpos: from steps 1-3
  *              (recomputed or kept)
  *   t_final, state: from inpc_blend_forward with the same inputs
  *   grad_out   [C][H][W] f32 dL/dF
@@ -210,8 +218,8 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
  * Every output element is written (zero for culled points).
  */
 inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
-                                  const float* uv, const float* opacity, const void* feat,
-                                  int32_t C, int32_t dtype, const float* bg,
+                                  const float* proj, const void* feat, int32_t C, int32_t dtype,
+                                  const float* bg,
                                   const uint32_t* ntiles, const uint32_t* tile_ranges,
                                   const uint32_t* tile_order, const uint32_t* list,
                                   const uint16_t* lpos, const float* t_final, const void* state,

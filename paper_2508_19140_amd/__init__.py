@@ -4,6 +4,7 @@ Neural Point Clouds": project, bin, per-tile depth sort, alpha blend (bilinear
 behind a C ABI (include/inpc_raster.h).
 """
 from . import _lib  # noqa: F401
+from .batched import MultiViewRasterizer, ViewInputs, ViewPipeline  # noqa: F401
 from .raster import (  # noqa: F401
     Binning,
     RasterSettings,
@@ -18,6 +19,6 @@ from .raster import (  # noqa: F401
 )
 
 __all__ = [
-    "Binning", "RasterSettings", "Workspace", "blend_backward", "blend_forward",
+    "MultiViewRasterizer", "ViewInputs", "ViewPipeline", "Binning", "RasterSettings", "Workspace", "blend_backward", "blend_forward",
     "camera_struct", "check_capacity", "project_backward", "project_bin_sort", "rasterize",
 ]

@@ -43,7 +43,8 @@ class Camera(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("splat", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("t_min", ctypes.c_float), ("dilation", ctypes.c_float),
-                ("cutoff", ctypes.c_float), ("max_radius", ctypes.c_float)]
+                ("cutoff", ctypes.c_float), ("max_radius", ctypes.c_float),
+                ("bin_points", ctypes.c_int32)]
 
 
 class InpcError(RuntimeError):
@@ -71,13 +72,13 @@ def lib():
         "inpc_state_bytes": (SZ, [CP, OP]),
         "inpc_num_tiles": (I64, [CP, OP]),
         "inpc_copy_capacity": (I64, [I64, CP, OP]),
-        "inpc_project": (I32, [CP, OP, I64, P, P, P, P, P, P, SZ, P]),
-        "inpc_bin": (I32, [CP, OP, I64, P, P, P, P, P, P, P, SZ, P]),
+        "inpc_project": (I32, [CP, OP, I64, P, P, P, P, P, P, P, SZ, P]),
+        "inpc_bin": (I32, [CP, OP, I64, P, P, P, P, P, P, SZ, P]),
         "inpc_sort": (I32, [CP, OP, I64, P, P, P, P, P, P, SZ, P]),
-        "inpc_blend_forward": (I32, [CP, OP, I64, P, P, P, P, I32, I32, P, P, P, P, P, P, P,
-                                     P, P, P, SZ, P]),
-        "inpc_blend_backward": (I32, [CP, OP, I64, P, P, P, I32, I32, P, P, P, P, P, P, P, P,
-                                      P, P, P, P, P, P, P, SZ, P, SZ, P]),
+        "inpc_blend_forward": (I32, [CP, OP, I64, P, P, I32, I32, P, P, P, P, P, P, P, P, P,
+                                     P, SZ, P]),
+        "inpc_blend_backward": (I32, [CP, OP, I64, P, P, I32, I32, P, P, P, P, P, P, P, P, P,
+                                      P, P, P, P, P, P, SZ, P, SZ, P]),
         "inpc_backward_scratch_bytes": (SZ, [I64, I32, CP, OP]),
         "inpc_project_backward": (I32, [CP, I64, P, P, P, P, P]),
         "inpc_check_sync": (I32, [P, SZ, P]),
@@ -119,8 +120,9 @@ def make_camera(width, height, fx, fy, cx, cy, R, t, z_near=0.2) -> Camera:
 
 
 def make_opts(splat=SPLAT_BILINEAR, tile=8, t_min=1e-4, dilation=0.16, cutoff=3.0,
-              max_radius=0.0) -> Opts:
+              max_radius=0.0, bin_points=0) -> Opts:
     o = Opts()
+    o.bin_points = int(bin_points)
     o.splat, o.tile = int(splat), int(tile)
     o.t_min, o.dilation, o.cutoff, o.max_radius = float(t_min), float(dilation), float(cutoff), \
         float(max_radius)

@@ -30,7 +30,8 @@ bool valid_cam(const inpc_camera_t* c) {
 }
 
 bool valid_opts(const inpc_opts_t* o) {
-  return o && (o->tile == 8 || o->tile == 16 || o->tile == 32) &&
+  return o && (o->tile == 8 || o->tile == 16 || o->tile == 32) && o->bin_points >= 0 &&
+         o->bin_points % 1024 == 0 &&
          (o->splat == INPC_SPLAT_BILINEAR || o->splat == INPC_SPLAT_GAUSSIAN) &&
          o->t_min >= 0.f && o->t_min <= 1.f &&
          (o->splat == INPC_SPLAT_BILINEAR ||
@@ -62,7 +63,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t flags, tile_count, cursor, seg_w, seg_m, seg_l, seg_x, seg_b0, seg_b1, bucket, xbucket,
+  size_t flags, tile_count, gsum, gcls, gord, coltot, blk, cursor, seg_w, seg_m, seg_l, seg_x, seg_b0, seg_b1, bucket, xbucket,
       total;
 };
 
@@ -85,6 +86,12 @@ Layout layout(int64_t n, const inpc_camera_t* c, const inpc_opts_t* o) {
   };
   L.flags = take(kFlagSlots * 4);
   L.tile_count = take(nt * 4);
+  const size_t groups = (nt + 63) / 64;
+  L.gsum = take(groups * 8);
+  L.gcls = take(groups * 4 * 4);
+  L.gord = take(groups * kOrderClasses * 4);
+  L.coltot = take((1 + 4 + kOrderClasses) * 8);
+  L.blk = take(nt <= (size_t)kLdsBins ? (size_t)bin_rows(n, o->bin_points) * nt * 4 : 0);
   L.cursor = take(nt * 4);
   L.seg_w = take(small_segs * 8);
   L.seg_m = take(small_segs * 8);
@@ -104,6 +111,12 @@ Ws make_ws(void* ws, int64_t n, const inpc_camera_t* c, const inpc_opts_t* o) {
   Ws w;
   w.flags = reinterpret_cast<uint32_t*>(b + L.flags);
   w.tile_count = reinterpret_cast<uint32_t*>(b + L.tile_count);
+  w.gsum = reinterpret_cast<uint64_t*>(b + L.gsum);
+  w.gcls = reinterpret_cast<uint32_t*>(b + L.gcls);
+  w.gord = reinterpret_cast<uint32_t*>(b + L.gord);
+  w.coltot = reinterpret_cast<uint64_t*>(b + L.coltot);
+  w.groups = (num_tiles(c, o) + 63) / 64;
+  w.blk = reinterpret_cast<uint32_t*>(b + L.blk);
   w.cursor = reinterpret_cast<uint32_t*>(b + L.cursor);
   w.seg_w = reinterpret_cast<uint2*>(b + L.seg_w);
   w.seg_m = reinterpret_cast<uint2*>(b + L.seg_m);
@@ -114,6 +127,8 @@ Ws make_ws(void* ws, int64_t n, const inpc_camera_t* c, const inpc_opts_t* o) {
   w.bucket = reinterpret_cast<uint2*>(b + L.bucket);
   w.xbucket = reinterpret_cast<uint2*>(b + L.xbucket);
   w.cap = (uint32_t)std::min<int64_t>(copy_capacity(n, c, o), 0xffffffffLL);
+  w.chunk = bin_chunk(n, o->bin_points);
+  w.rows = bin_rows(n, o->bin_points);
   // Pack the tile-local splat corner (codes 0..T per axis) below the point
   // index when both fit one 32-bit word; otherwise inpc_sort computes it in
   // a separate pass.
@@ -189,6 +204,14 @@ inpc_status_t check_common(const inpc_camera_t* cam, const inpc_opts_t* opts, in
 #define REQUIRE(ptr, name) \
   if (!(ptr)) return fail(INPC_ERR_INVALID, "null %s", name)
 
+// Projection records are read as 16-byte vectors.
+#define REQUIRE_PROJ(ptr)                                  \
+  do {                                                     \
+    REQUIRE(ptr, "proj");                                  \
+    if (reinterpret_cast<uintptr_t>(ptr) % 16)             \
+      return fail(INPC_ERR_INVALID, "%s not 16-byte aligned", "proj"); \
+  } while (0)
+
 }  // namespace
 }  // namespace inpc
 
@@ -223,47 +246,46 @@ int64_t inpc_copy_capacity(int64_t n, const inpc_camera_t* cam, const inpc_opts_
 }
 
 inpc_status_t inpc_project(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
-                           const float* pos, const float* radius, float* uv,
-                           uint32_t* depth_key, uint32_t* ntiles, void* ws, size_t ws_bytes,
-                           void* stream) {
+                           const float* pos, const float* opacity, const float* radius,
+                           float* proj, uint32_t* depth_key, uint32_t* ntiles, void* ws,
+                           size_t ws_bytes, void* stream) {
   inpc_status_t st = check_common(cam, opts, n, ws, ws_bytes);
   if (st != INPC_OK) return st;
   if (n > 0) {
     REQUIRE(pos, "pos");
-    REQUIRE(uv, "uv");
+    REQUIRE(opacity, "opacity");
+    REQUIRE_PROJ(proj);
     REQUIRE(depth_key, "depth_key");
     REQUIRE(ntiles, "ntiles");
     if (opts->splat == INPC_SPLAT_GAUSSIAN) REQUIRE(radius, "radius");
   }
   const Ws w = make_ws(ws, n, cam, opts);
-  hipError_t e = launch_project(to_cam(cam), to_opts(cam, opts), n, pos,
-                                opts->splat == INPC_SPLAT_GAUSSIAN ? radius : nullptr, uv,
+  hipError_t e = launch_project(to_cam(cam), to_opts(cam, opts), n, pos, opacity,
+                                opts->splat == INPC_SPLAT_GAUSSIAN ? radius : nullptr, proj,
                                 depth_key, ntiles, w, (hipStream_t)stream);
   return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_project");
 }
 
 inpc_status_t inpc_bin(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
-                       const float* uv, const float* radius, const uint32_t* depth_key,
-                       const uint32_t* ntiles, uint32_t* tile_ranges, uint32_t* tile_order,
-                       void* ws, size_t ws_bytes, void* stream) {
+                       const float* proj, const uint32_t* depth_key, const uint32_t* ntiles,
+                       uint32_t* tile_ranges, uint32_t* tile_order, void* ws, size_t ws_bytes,
+                       void* stream) {
   inpc_status_t st = check_common(cam, opts, n, ws, ws_bytes);
   if (st != INPC_OK) return st;
   REQUIRE(tile_ranges, "tile_ranges");
   if (n > 0) {
-    REQUIRE(uv, "uv");
+    REQUIRE_PROJ(proj);
     REQUIRE(depth_key, "depth_key");
     REQUIRE(ntiles, "ntiles");
-    if (opts->splat == INPC_SPLAT_GAUSSIAN) REQUIRE(radius, "radius");
   }
   const Ws w = make_ws(ws, n, cam, opts);
-  hipError_t e = launch_bin(to_cam(cam), to_opts(cam, opts), n, uv,
-                            opts->splat == INPC_SPLAT_GAUSSIAN ? radius : nullptr, depth_key,
-                            ntiles, tile_ranges, tile_order, w, (hipStream_t)stream);
+  hipError_t e = launch_bin(to_cam(cam), to_opts(cam, opts), n, proj, depth_key, ntiles,
+                            tile_ranges, tile_order, w, (hipStream_t)stream);
   return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_bin");
 }
 
 inpc_status_t inpc_sort(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
-                        const float* uv, const uint32_t* tile_ranges,
+                        const float* proj, const uint32_t* tile_ranges,
                         const uint32_t* tile_order, uint32_t* list, uint16_t* lpos, void* ws,
                         size_t ws_bytes, void* stream) {
   inpc_status_t st = check_common(cam, opts, n, ws, ws_bytes);
@@ -273,12 +295,12 @@ inpc_status_t inpc_sort(const inpc_camera_t* cam, const inpc_opts_t* opts, int64
   const bool bilinear = opts->splat == INPC_SPLAT_BILINEAR;
   if (bilinear) {
     REQUIRE(lpos, "lpos");
-    if (n > 0) REQUIRE(uv, "uv");
+    if (n > 0) REQUIRE_PROJ(proj);
   }
   const Ws w = make_ws(ws, n, cam, opts);
   hipError_t e = launch_sort(w, list, lpos, num_tiles(cam, opts), (hipStream_t)stream);
   if (e == hipSuccess && bilinear && n > 0 && w.lbits == 0)
-    e = launch_lpos(to_cam(cam), to_opts(cam, opts), tile_ranges, tile_order, uv, list, lpos,
+    e = launch_lpos(to_cam(cam), to_opts(cam, opts), tile_ranges, tile_order, proj, list, lpos,
                     w.flags, (hipStream_t)stream);
   return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_sort");
 }
@@ -296,8 +318,8 @@ static inpc_status_t blend_checks(const inpc_camera_t* cam, const inpc_opts_t* o
 }
 
 inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
-                                 const float* uv, const float* radius, const float* opacity,
-                                 const void* feat, int32_t C, int32_t dtype, const float* bg,
+                                 const float* proj, const void* feat, int32_t C, int32_t dtype,
+                                 const float* bg,
                                  const uint32_t* tile_ranges, const uint32_t* tile_order,
                                  const uint32_t* list, const uint16_t* lpos, float* out,
                                  float* t_final, uint32_t* n_contrib, void* state, void* ws,
@@ -311,10 +333,8 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
   REQUIRE(n_contrib, "n_contrib");
   if (opts->splat == INPC_SPLAT_BILINEAR) REQUIRE(lpos, "lpos");
   if (n > 0) {
-    REQUIRE(uv, "uv");
-    REQUIRE(opacity, "opacity");
+    REQUIRE_PROJ(proj);
     REQUIRE(feat, "feat");
-    if (opts->splat == INPC_SPLAT_GAUSSIAN) REQUIRE(radius, "radius");
   }
   const Ws w = make_ws(ws, n, cam, opts);
   BlendArgs a;
@@ -322,9 +342,7 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
   a.cam = to_cam(cam);
   a.opts = to_opts(cam, opts);
   a.n = n;
-  a.uv = uv;
-  a.radius = radius;
-  a.opacity = opacity;
+  a.proj = proj;
   a.feat = feat;
   a.C = C;
   a.dtype = dtype;
@@ -349,8 +367,8 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
 }
 
 inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
-                                  const float* uv, const float* opacity, const void* feat,
-                                  int32_t C, int32_t dtype, const float* bg,
+                                  const float* proj, const void* feat, int32_t C, int32_t dtype,
+                                  const float* bg,
                                   const uint32_t* ntiles, const uint32_t* tile_ranges,
                                   const uint32_t* tile_order, const uint32_t* list,
                                   const uint16_t* lpos, const float* t_final, const void* state,
@@ -372,8 +390,7 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
   REQUIRE(state, "state");
   REQUIRE(grad_out, "grad_out");
   if (n > 0) {
-    REQUIRE(uv, "uv");
-    REQUIRE(opacity, "opacity");
+    REQUIRE_PROJ(proj);
     REQUIRE(feat, "feat");
     REQUIRE(ntiles, "ntiles");
     REQUIRE(grad_feat, "grad_feat");
@@ -386,8 +403,7 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
   a.cam = to_cam(cam);
   a.opts = to_opts(cam, opts);
   a.n = n;
-  a.uv = uv;
-  a.opacity = opacity;
+  a.proj = proj;
   a.feat = feat;
   a.C = C;
   a.dtype = dtype;

@@ -194,15 +194,13 @@ template <int CP, typename FT, bool FULL>
 struct Prefetch {
   bool valid;
   uint32_t idx;
-  float2 uv;
-  float o;
+  float4 p;  // u, v, opacity, radius
   RowRegs<CP, FT, FULL> f;
 
   __device__ __forceinline__ void fetch(const BlendArgs& a, bool v, uint32_t i) {
     valid = v;
     idx = v ? i : 0u;
-    uv = reinterpret_cast<const float2*>(a.uv)[idx];
-    o = a.opacity[idx];
+    p = reinterpret_cast<const float4*>(a.proj)[idx];
     f.load(reinterpret_cast<const FT*>(a.feat), idx, a.C);
   }
 };
@@ -218,6 +216,19 @@ struct Entry {
     lp = a.lpos[qq];
   }
 };
+
+// Whether a copy's point meets this tile only, from its tile-local corner
+// code c = x0 - T tx + 1 (and likewise in y): both columns x0, x0 + 1 fall in
+// this tile (1 <= c <= T - 1), or the other one lies outside the image (c = 0
+// in the first tile column, c = T in the last).  Equals ntiles == 1 of the
+// projection, whose tile rectangle is that of the clipped 2x2 footprint.
+template <int T>
+__device__ __forceinline__ bool single_tile(uint32_t lp, int tx, int ty, int W, int H) {
+  const int cx = (int)(lp & 0xffu), cy = (int)(lp >> 8);
+  const bool sx = (cx >= 1 && cx <= T - 1) || (cx == 0 && tx == 0) || (cx == T && (tx + 1) * T >= W);
+  const bool sy = (cy >= 1 && cy <= T - 1) || (cy == 0 && ty == 0) || (cy == T && (ty + 1) * T >= H);
+  return sx && sy;
+}
 
 // Clear the coverage masks of this thread's pixel, then set the bits of
 // this thread's copy (tile-local splat corner (x0, y0) = lp - 1).
@@ -318,8 +329,8 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear(BlendArgs a) {
     if (!tile_any<NW>(!done)) break;
     // stage the fetched copies of this chunk
     if (pf.valid) {
-      const Footprint f = bilinear_footprint(pf.uv.x, pf.uv.y, a.cam.W, a.cam.H);
-      s_geo[tid] = make_float4(f.a, f.b, pf.o, __uint_as_float(pack_xy(f.x0, f.y0)));
+      const Footprint f = bilinear_footprint(pf.p.x, pf.p.y, a.cam.W, a.cam.H);
+      s_geo[tid] = make_float4(f.a, f.b, pf.p.z, __uint_as_float(pack_xy(f.x0, f.y0)));
       pf.f.store_f32(&s_feat[tid * fpad(CP)]);
     }
     // coverage of the next chunk; fetch the copies it needs while this one blends
@@ -431,13 +442,11 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_gauss(BlendArgs a) {
 
   Prefetch<CP, FT, FULL> pf;
   pf.valid = false;
-  float prad = 0.f;
   bool nv = false;
   uint32_t nidx = 0u;
   auto list_at = [&](uint32_t q) { return a.list[q < end ? q : end - 1]; };
   if (end > start) {
     pf.fetch(a, stager && start + tid < end, list_at(start + tid));
-    prad = a.radius[pf.idx];
     nv = stager && start + G::CHUNK + tid < end;
     nidx = list_at(start + G::CHUNK + tid);
   }
@@ -446,15 +455,14 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_gauss(BlendArgs a) {
     if (!tile_any<NW>(!done)) break;
     const uint32_t nh = min((uint32_t)G::CHUNK, end - base);
     if (pf.valid) {
-      const Footprint f = gaussian_footprint(pf.uv.x, pf.uv.y, prad, a.cam.W, a.cam.H,
+      const Footprint f = gaussian_footprint(pf.p.x, pf.p.y, pf.p.w, a.cam.W, a.cam.H,
                                              a.opts.dilation, a.opts.cutoff);
-      s_g0[tid] = make_float4(pf.uv.x, pf.uv.y, pf.o, f.s2);
+      s_g0[tid] = make_float4(pf.p.x, pf.p.y, pf.p.z, f.s2);
       s_g1[tid] = make_float4(f.thr, __uint_as_float(pack_xy(f.px0, f.py0)),
                               __uint_as_float(pack_xy(f.px1, f.py1)), 0.f);
       pf.f.store_f32(s_feat + tid * fpad(CP));
     }
     pf.fetch(a, nv, nidx);
-    prad = a.radius[pf.idx];
     nv = stager && base + 2 * G::CHUNK + tid < end;
     nidx = list_at(base + 2 * G::CHUNK + tid);
     tile_sync<NW>();
@@ -575,7 +583,7 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
   e.idx = e.lp = 0;
   Prefetch<CP, FT, FULL> pf;  // point data of the chunk staged next
   pf.valid = false;
-  uint32_t pnt = 0;            // its tile count
+  bool psingle = false;        // whether that point lies in this tile only
   if (nchunks > 0) {
     const int c0 = nchunks - 1;
     e.load(a, stager, start + (uint32_t)c0 * CH + tid, end);
@@ -585,7 +593,7 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
     build_coverage<T>(s_mask[c0 & 1], e);
     const bool nd = copy_needed<T>(s_mask[c0 & 1], last > (uint32_t)c0 * CH, s_need);
     pf.fetch(a, e.valid && nd, e.idx);
-    pnt = a.ntiles[pf.idx];
+    psingle = single_tile<T>(e.lp, tx, ty, a.cam.W, a.cam.H);
     if (nchunks >= 2) e.load(a, stager, start + (uint32_t)(c0 - 1) * CH + tid, end);
   }
 
@@ -595,13 +603,14 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
     const uint32_t rb = (uint32_t)ci * CH;  // relative base of the chunk
     // stage this chunk's fetched copies
     const bool cur = pf.valid;
-    const uint32_t cur_idx = pf.idx, cur_nt = pnt;
+    const uint32_t cur_idx = pf.idx;
+    const bool cur_single = psingle;
     float ca = 0.f, cb = 0.f, co = 0.f;
     int X0 = 0, Y0 = 0;
     if (cur) {
-      const Footprint f = bilinear_footprint(pf.uv.x, pf.uv.y, a.cam.W, a.cam.H);
-      ca = f.a; cb = f.b; co = pf.o; X0 = f.x0; Y0 = f.y0;
-      s_geo[tid] = make_float4(f.a, f.b, pf.o, __uint_as_float(pack_xy(f.x0, f.y0)));
+      const Footprint f = bilinear_footprint(pf.p.x, pf.p.y, a.cam.W, a.cam.H);
+      ca = f.a; cb = f.b; co = pf.p.z; X0 = f.x0; Y0 = f.y0;
+      s_geo[tid] = make_float4(f.a, f.b, pf.p.z, __uint_as_float(pack_xy(f.x0, f.y0)));
       pf.f.store_f32(&s_feat[tid * fpad(CP)]);
 #pragma unroll
       for (int k = 0; k < 4; ++k) s_acc[tid * 4 + k] = make_float2(0.f, 0.f);
@@ -615,7 +624,7 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
       build_coverage<T>(s_mask[b ^ 1], e);
       const bool nd = copy_needed<T>(s_mask[b ^ 1], last > rb - CH, s_need);
       pf.fetch(a, e.valid && nd, e.idx);
-      pnt = a.ntiles[pf.idx];
+      psingle = single_tile<T>(e.lp, tx, ty, a.cam.W, a.cam.H);
       if (ci >= 2) e.load(a, stager, start + rb - 2 * CH + tid, end);
     }
     if (last > rb) {
@@ -663,7 +672,7 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
       }
     }
     tile_sync<NW>();
-    if (cur && cur_nt > 0) {
+    if (cur) {
       float gfeat[CP];
 #pragma unroll
       for (int c = 0; c < CP; ++c) gfeat[c] = 0.f;
@@ -693,7 +702,7 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
       gu *= co;
       gv *= co;
       uint8_t* vis = reinterpret_cast<uint8_t*>(a.visited);
-      if (cur_nt == 1) {
+      if (cur_single) {
         store_row<CP>(a.grad_feat + (size_t)cur_idx * C, gfeat, C);
         a.grad_opacity[cur_idx] = go;
         reinterpret_cast<float2*>(a.grad_uv)[cur_idx] = make_float2(gu, gv);
@@ -850,7 +859,7 @@ hipError_t dispatch(const BlendArgs& a, hipStream_t s) {
 // and round so that the position gathers of a long list overlap.
 __global__ __launch_bounds__(256) void k_lpos(Cam cam, Opts o, const uint32_t* __restrict__ ranges,
                                               const uint32_t* __restrict__ order,
-                                              const float2* __restrict__ uv,
+                                              const float4* __restrict__ proj,
                                               const uint32_t* __restrict__ list,
                                               uint16_t* __restrict__ lpos,
                                               const uint32_t* __restrict__ flags) {
@@ -865,14 +874,14 @@ __global__ __launch_bounds__(256) void k_lpos(Cam cam, Opts o, const uint32_t* _
     const int tx0 = (int)(t % (uint32_t)o.ntx) * o.T, ty0 = (int)(t / (uint32_t)o.ntx) * o.T;
     for (uint32_t q0 = s + lane; q0 < e; q0 += 4 * 64) {
       uint32_t idx[4];
-      float2 p[4];
+      float4 p[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const uint32_t q = q0 + k * 64;
         idx[k] = list[q < e ? q : e - 1];
       }
 #pragma unroll
-      for (int k = 0; k < 4; ++k) p[k] = uv[idx[k]];
+      for (int k = 0; k < 4; ++k) p[k] = proj[idx[k]];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const uint32_t q = q0 + k * 64;
@@ -888,13 +897,13 @@ __global__ __launch_bounds__(256) void k_lpos(Cam cam, Opts o, const uint32_t* _
 }  // namespace
 
 hipError_t launch_lpos(const Cam& cam, const Opts& o, const uint32_t* ranges,
-                       const uint32_t* order, const float* uv, const uint32_t* list,
+                       const uint32_t* order, const float* proj, const uint32_t* list,
                        uint16_t* lpos, const uint32_t* flags, hipStream_t s) {
   const int64_t nt = (int64_t)o.ntx * o.nty;
   if (nt == 0) return hipSuccess;
   hipLaunchKernelGGL(k_lpos, dim3((unsigned)std::min<int64_t>((nt + 3) / 4, 16384)), dim3(256), 0, s,
                      cam, o,
-                     ranges, order, reinterpret_cast<const float2*>(uv), list, lpos, flags);
+                     ranges, order, reinterpret_cast<const float4*>(proj), list, lpos, flags);
   return hipGetLastError();
 }
 

@@ -20,10 +20,26 @@ constexpr int kWave = 64;
 // Sort size classes (segment copy counts).
 constexpr uint32_t kSortCapW = 256;
 constexpr uint32_t kSortCapM = 2048;
-constexpr uint32_t kSortCapL = 16384;
+constexpr uint32_t kSortCapL = 16384;   // largest segment the MSD split takes
+constexpr uint32_t kSortCapLB = 8192;   // largest segment LSD-sorted by one block (L class)
 
 // Largest tile count whose per-workgroup histogram fits in LDS (144 KiB).
 constexpr int kLdsBins = 36864;
+constexpr int kOrderClasses = 34;  // blend-order classes 0..32 and "no tile"
+
+// Points per workgroup of the counting / scatter passes (tile counts up to
+// kLdsBins): at least 8192 and at most 256 workgroups, in whole rounds of
+// the 1024-thread block.
+// `want` = 0 picks 8192.
+inline int64_t bin_chunk(int64_t n, int64_t want) {
+  const int64_t per = (n + 255) / 256;
+  const int64_t w = want > 0 ? want : 8192;
+  const int64_t c = per > w ? per : w;
+  return (c + 1023) / 1024 * 1024;
+}
+inline int64_t bin_rows(int64_t n, int64_t want) {
+  return n > 0 ? (n + bin_chunk(n, want) - 1) / bin_chunk(n, want) : 0;
+}
 
 // Camera in kernel-argument form (by value).
 struct Cam {
@@ -46,7 +62,7 @@ enum : int {
   kFlagOverflow = 0,
   kFlagCountW = 1,   // segments sorted by one wavefront (n <= 256)
   kFlagCountM = 2,   // segments sorted by a 256-thread block (n <= 2048)
-  kFlagCountL = 3,   // segments LSD-sorted by a 1024-thread block (n <= 16384)
+  kFlagCountL = 3,   // segments LSD-sorted by a 1024-thread block (n <= kSortCapLB)
   kFlagCountX = 4,   // larger segments, sorted through global memory
   kFlagCountB0 = 5,  // tiles to split (2048 < n <= 16384)
   kFlagCountB1 = 6,  // sub-segments to split a second time
@@ -58,6 +74,15 @@ enum : int {
 struct Ws {
   uint32_t* flags;       // [kFlagSlots]
   uint32_t* tile_count;  // [nt]   copies per tile (filled by project)
+  // per group of 64 tiles: copies, tiles per sort class, tiles per blend-order
+  // class (then their exclusive prefix over the groups), and the totals
+  uint64_t* gsum;        // [groups]
+  uint32_t* gcls;        // [groups][4]
+  uint32_t* gord;        // [groups][kOrderClasses]
+  uint64_t* coltot;      // [1 + 4 + kOrderClasses] column totals over the groups
+  int64_t groups;
+  uint32_t* blk;         // [rows][nt] per-workgroup tile counts, then their exclusive
+                         //        prefix over workgroups (nt <= kLdsBins)
   uint32_t* cursor;      // [nt]   scatter cursors
   uint2* seg_w;          // segment lists per sort class
   uint2* seg_m;
@@ -68,6 +93,7 @@ struct Ws {
   uint2* bucket;         // [cap]  (depth key, point index) copies, bucketed by tile
   uint2* xbucket;        // [cap]  ping-pong scratch for segments beyond the LDS capacity
   uint32_t cap;          // copy capacity
+  int64_t chunk, rows;   // points per workgroup of the counting / scatter passes, workgroups
   // Bilinear splats with few enough points: the index word of a bucket entry
   // is (point index << lbits) | (y code << pb) | x code, where the codes are
   // the tile-local corner of the copy's 2x2 splat plus one.  The index stays

@@ -12,9 +12,7 @@ struct BlendArgs {
   Cam cam;
   Opts opts;
   int64_t n;
-  const float* uv;
-  const float* radius;
-  const float* opacity;
+  const float* proj;  // [n][4] (u, v, opacity, radius)
   const void* feat;
   int C;
   int dtype;
@@ -58,14 +56,14 @@ inline int partial_stride(int C) {
 
 hipError_t launch_clear(uint32_t* p, size_t n, hipStream_t s);
 hipError_t launch_project(const Cam& cam, const Opts& o, int64_t n, const float* pos,
-                          const float* radius, float* uv, uint32_t* key, uint32_t* ntiles,
-                          const Ws& ws, hipStream_t s);
-hipError_t launch_bin(const Cam& cam, const Opts& o, int64_t n, const float* uv,
-                      const float* radius, const uint32_t* key, const uint32_t* ntiles,
-                      uint32_t* ranges, uint32_t* order, const Ws& ws, hipStream_t s);
+                          const float* opacity, const float* radius, float* proj, uint32_t* key,
+                          uint32_t* ntiles, const Ws& ws, hipStream_t s);
+hipError_t launch_bin(const Cam& cam, const Opts& o, int64_t n, const float* proj,
+                      const uint32_t* key, const uint32_t* ntiles, uint32_t* ranges,
+                      uint32_t* order, const Ws& ws, hipStream_t s);
 hipError_t launch_sort(const Ws& ws, uint32_t* list, uint16_t* lpos, int64_t nt, hipStream_t s);
 hipError_t launch_lpos(const Cam& cam, const Opts& o, const uint32_t* ranges,
-                       const uint32_t* order, const float* uv, const uint32_t* list,
+                       const uint32_t* order, const float* proj, const uint32_t* list,
                        uint16_t* lpos, const uint32_t* flags, hipStream_t s);
 hipError_t launch_blend_forward(const BlendArgs& a, hipStream_t s);
 hipError_t launch_blend_backward(const BlendArgs& a, hipStream_t s);

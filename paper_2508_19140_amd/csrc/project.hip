@@ -22,6 +22,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kBinBlock = 1024;  // threads of the privatised counting / scatter blocks
+constexpr int kUnroll = 4;       // points per thread and round in those blocks
 
 __device__ __forceinline__ int tile_shift(int T) { return T == 8 ? 3 : (T == 16 ? 4 : 5); }
 
@@ -51,18 +52,16 @@ __device__ __forceinline__ TileRect tile_rect(const Footprint& f, int sh) {
   return r;
 }
 
-__device__ __forceinline__ TileRect project_one(const Cam& cam, const Opts& o, int sh,
-                                                const float* __restrict__ pos,
-                                                const float* __restrict__ radius, int64_t i,
-                                                float2* __restrict__ uv,
+__device__ __forceinline__ TileRect project_one(const Cam& cam, const Opts& o, int sh, float x,
+                                                float y, float z, float rad, int64_t i, float op,
+                                                float4* __restrict__ proj,
                                                 uint32_t* __restrict__ key,
                                                 uint32_t* __restrict__ ntiles) {
-  const float x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
   const Proj p = project_point(cam, x, y, z);
   Footprint f;
   f.visible = false;
-  if (p.in_front) f = footprint(o, cam, p.u, p.v, radius ? radius[i] : 0.f);
-  uv[i] = make_float2(p.u, p.v);
+  if (p.in_front) f = footprint(o, cam, p.u, p.v, rad);
+  proj[i] = make_float4(p.u, p.v, op, rad);
   key[i] = __float_as_uint(p.Z);
   const TileRect r = tile_rect(f, sh);
   ntiles[i] = r.count();
@@ -84,180 +83,265 @@ __device__ __forceinline__ Chunk chunk_of(int64_t n, int64_t chunk) {
 __global__ __launch_bounds__(kBinBlock) void k_project_count(Cam cam, Opts o, int64_t n,
                                                              int64_t chunk,
                                                              const float* __restrict__ pos,
+                                                             const float* __restrict__ opacity,
                                                              const float* __restrict__ radius,
-                                                             float2* __restrict__ uv,
+                                                             float4* __restrict__ proj,
                                                              uint32_t* __restrict__ key,
                                                              uint32_t* __restrict__ ntiles,
-                                                             uint32_t* __restrict__ tile_count) {
+                                                             uint32_t* __restrict__ blk) {
   __shared__ uint32_t bins[kLdsBins];
   const int nt = o.ntx * o.nty;
   for (int t = threadIdx.x; t < nt; t += kBinBlock) bins[t] = 0u;
   __syncthreads();
   const int sh = tile_shift(o.T);
   const Chunk c = chunk_of(n, chunk);
-  for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBinBlock) {
-    const TileRect r = project_one(cam, o, sh, pos, radius, i, uv, key, ntiles);
-    for (int ty = r.ty0; ty <= r.ty1; ++ty)
-      for (int tx = r.tx0; tx <= r.tx1; ++tx) atomicAdd(&bins[ty * o.ntx + tx], 1u);
+  // kUnroll points per thread and round: their loads are all in flight
+  // before the first is used
+  for (int64_t i0 = c.begin + threadIdx.x; i0 < c.end; i0 += kUnroll * kBinBlock) {
+    float x[kUnroll], y[kUnroll], z[kUnroll], rad[kUnroll], op[kUnroll];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) {
+      const int64_t i = i0 + (int64_t)k * kBinBlock;
+      const int64_t j = i < c.end ? i : c.begin;
+      x[k] = pos[3 * j]; y[k] = pos[3 * j + 1]; z[k] = pos[3 * j + 2];
+      rad[k] = radius ? radius[j] : 0.f;
+      op[k] = opacity[j];
+    }
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) {
+      const int64_t i = i0 + (int64_t)k * kBinBlock;
+      if (i >= c.end) break;
+      const TileRect r =
+          project_one(cam, o, sh, x[k], y[k], z[k], rad[k], i, op[k], proj, key, ntiles);
+      for (int ty = r.ty0; ty <= r.ty1; ++ty)
+        for (int tx = r.tx0; tx <= r.tx1; ++tx) atomicAdd(&bins[ty * o.ntx + tx], 1u);
+    }
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < nt; t += kBinBlock) {
-    const uint32_t v = bins[t];
-    if (v) atomicAdd(&tile_count[t], v);
-  }
-}
-
-// Step 1 for very large tile counts: one global atomic per copy.
-__global__ __launch_bounds__(kBlock) void k_project_count_global(
-    Cam cam, Opts o, int64_t n, const float* __restrict__ pos, const float* __restrict__ radius,
-    float2* __restrict__ uv, uint32_t* __restrict__ key, uint32_t* __restrict__ ntiles,
-    uint32_t* __restrict__ tile_count) {
-  const int sh = tile_shift(o.T);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const TileRect r = project_one(cam, o, sh, pos, radius, i, uv, key, ntiles);
-    for (int ty = r.ty0; ty <= r.ty1; ++ty)
-      for (int tx = r.tx0; tx <= r.tx1; ++tx) atomicAdd(&tile_count[ty * o.ntx + tx], 1u);
-  }
+  uint32_t* row = blk + (size_t)blockIdx.x * nt;
+  for (int t = threadIdx.x; t < nt; t += kBinBlock) row[t] = bins[t];
 }
 
 __device__ __forceinline__ int sort_class(uint32_t c) {
   return c == 0 ? -1 : (c <= kSortCapW ? 0 : (c <= kSortCapM ? 1 : (c <= kSortCapL ? 2 : 3)));
 }
 
-// Inclusive scan of one 64-bit value per thread over a 1024-thread block;
-// also returns the block total.
-__device__ uint64_t block_incl_scan_u64(uint64_t v, uint64_t* s_wave, uint64_t& total) {
-  const uint32_t lane = __lane_id(), w = threadIdx.x >> 6;
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v, uint32_t lane) {
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     const uint64_t t = __shfl_up(v, o, 64);
     if (lane >= (uint32_t)o) v += t;
   }
-  if (lane == 63) s_wave[w] = v;
-  __syncthreads();
-  uint64_t pre = 0;
-  total = 0;
-  for (uint32_t k = 0; k < 16; ++k) {
-    const uint64_t x = s_wave[k];
-    if (k < w) pre += x;
-    total += x;
-  }
-  __syncthreads();
-  return v + pre;
+  return v;
 }
 
-// Single 1024-thread block: ranges = exclusive scan of the tile counts,
-// scatter cursors, and the initial sort segments (one per non-empty tile, in
-// tile order, per size class), in chunks of 8192 tiles (8 consecutive tiles
-// per thread).  Flags an overflow when the copies exceed the capacity.
-__global__ __launch_bounds__(1024) void k_scan(int64_t nt, const uint32_t* __restrict__ count,
-                                               uint32_t* __restrict__ ranges,
-                                               uint32_t* __restrict__ cursor,
-                                               uint32_t* __restrict__ order, Ws ws) {
-  __shared__ uint64_t s_wave[16];
-  constexpr int PER = 8;
-  uint64_t base = 0;                       // copies before this chunk
-  uint32_t cb[4] = {0u, 0u, 0u, 0u};       // class list sizes before this chunk
-  uint2* lists[4] = {ws.seg_w, ws.seg_m, ws.seg_b0, ws.seg_x};
-  for (int64_t c0 = 0; c0 < nt; c0 += 1024 * PER) {
-    const int64_t b = c0 + (int64_t)threadIdx.x * PER;
-    uint32_t v[PER];
-    uint64_t tot = 0, cls = 0;  // class counts packed 16 bits each (<= 8192 per chunk)
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      v[k] = b + k < nt ? count[b + k] : 0u;
-      tot += v[k];
-      const int c = sort_class(v[k]);
-      if (c >= 0) cls += 1ull << (16 * c);
-    }
-    uint64_t tot_all, cls_all;
-    uint64_t off = block_incl_scan_u64(tot, s_wave, tot_all) - tot + base;
-    uint64_t coff = block_incl_scan_u64(cls, s_wave, cls_all) - cls;
-    uint32_t pos[4];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Lanes of the wavefront whose 6-bit value equals this lane's.
+__device__ __forceinline__ uint64_t match6(uint32_t k) {
+  uint64_t m = ~0ull;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) pos[c] = cb[c] + (uint32_t)((coff >> (16 * c)) & 0xffffu);
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      if (b + k >= nt) break;
-      ranges[b + k] = (uint32_t)off;
-      cursor[b + k] = (uint32_t)off;
-      const int c = sort_class(v[k]);
-      if (c >= 0) lists[c][pos[c]++] = make_uint2((uint32_t)off, v[k]);
-      off += v[k];
-    }
-    base += tot_all;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) cb[c] += (uint32_t)((cls_all >> (16 * c)) & 0xffffu);
+  for (int bit = 0; bit < 6; ++bit) {
+    const uint64_t bb = __ballot((k >> bit) & 1u);
+    m &= ((k >> bit) & 1u) ? bb : ~bb;
   }
-  if (threadIdx.x == 0) {
-    ranges[nt] = (uint32_t)base;
-    ws.flags[kFlagCountW] = cb[0];
-    ws.flags[kFlagCountM] = cb[1];
-    ws.flags[kFlagCountB0] = cb[2];
-    ws.flags[kFlagCountX] = cb[3];
-    if (base > (uint64_t)ws.cap) ws.flags[kFlagOverflow] = 1u;
+  return m;
+}
+
+// Blend-order class of a tile: 0 = longest lists ... 31 = one copy, 32 =
+// empty; 33 marks a lane without a tile.
+__device__ __forceinline__ uint32_t order_class(uint32_t c) { return c ? (uint32_t)__clz(c) : 32u; }
+
+// Tiles are handled in groups of 64 (one wavefront, lane = tile).  Per
+// group the count pass leaves its copies, its tiles per sort class and its
+// tiles per blend-order class; one small block scans these columns over the
+// groups, and one wavefront per group then writes the ranges, the sort
+// segments and the blend order of its tiles.  No step walks all tiles in
+// sequence.
+//
+// Blend order: tiles by decreasing power-of-two class of their copy count (so
+// that the longest lists start first and do not form a tail), ascending tile
+// index inside a class.  Lanes with the same class are matched with ballots.
+__device__ __forceinline__ void group_table(int64_t g, bool valid, uint32_t c, const Ws& ws,
+                                            uint32_t* __restrict__ s_hist) {
+  const uint32_t lane = __lane_id();
+  const uint64_t sum = wave_sum_u64(valid ? c : 0u);
+  const int sc = valid ? sort_class(c) : -1;
+  uint32_t cls[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) cls[q] = (uint32_t)__popcll(__ballot(sc == q));
+  const uint32_t k = valid ? order_class(c) : 33u;
+  const uint64_t m = match6(k);
+  if (lane < kOrderClasses) s_hist[lane] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if ((m & ((1ull << lane) - 1ull)) == 0ull) s_hist[k] = (uint32_t)__popcll(m);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (lane < kOrderClasses) ws.gord[(size_t)g * kOrderClasses + lane] = s_hist[lane];
+  if (lane == 0) {
+    ws.gsum[g] = sum;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ws.gcls[(size_t)g * 4 + q] = cls[q];
   }
-  if (!order) return;
-  // Blend order: tiles by decreasing copy count in power-of-two classes (so
-  // the longest lists start first and do not form a tail), ascending tile
-  // index inside a class.  A stable counting sort over 33 classes; lanes of
-  // a wavefront with the same class are matched with ballots so that one
-  // lane per class and wavefront touches the shared counters.
-  __shared__ uint32_t s_h[34];
-  __shared__ uint32_t s_wc[16][34];
-  const uint32_t lane = __lane_id(), w = threadIdx.x >> 6;
+}
+
+// Per tile: exclusive prefix of the workgroup counts over the workgroups (in
+// place) and the tile's total.  64 tiles per block (one tile group, see
+// group_table), the rows split over 16 sets of threads.
+__global__ __launch_bounds__(1024) void k_colscan(int64_t nt, int rows, uint32_t* __restrict__ blk,
+                                                  uint32_t* __restrict__ tile_count, Ws ws) {
+  __shared__ uint32_t s_sum[16][64];
+  __shared__ uint32_t s_hist[kOrderClasses];
+  const int tl = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t t = (int64_t)blockIdx.x * 64 + tl;
+  const int per = (rows + 15) / 16;
+  const int r0 = g * per, r1 = min(rows, r0 + per);
+  uint32_t v[16];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int r = r0 + k;
+    v[k] = (t < nt && r < r1) ? blk[(size_t)r * nt + t] : 0u;
+    sum += v[k];
+  }
+  s_sum[g][tl] = sum;
+  __syncthreads();
+  uint32_t run = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const uint32_t x = s_sum[k][tl];
+    run += k < g ? x : 0u;
+    tot += x;
+  }
+  if (t < nt) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int r = r0 + k;
+      if (r < r1) blk[(size_t)r * nt + t] = run;
+      run += v[k];
+    }
+    if (g == 0) tile_count[t] = tot;
+  }
+  if (g == 0) group_table(blockIdx.x, t < nt, t < nt ? tot : 0u, ws, s_hist);
+}
+
+// Step 1 for very large tile counts: one global atomic per copy.
+__global__ __launch_bounds__(kBlock) void k_project_count_global(
+    Cam cam, Opts o, int64_t n, const float* __restrict__ pos, const float* __restrict__ opacity,
+    const float* __restrict__ radius, float4* __restrict__ proj, uint32_t* __restrict__ key,
+    uint32_t* __restrict__ ntiles,
+    uint32_t* __restrict__ tile_count) {
+  const int sh = tile_shift(o.T);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const TileRect r = project_one(cam, o, sh, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2],
+                                   radius ? radius[i] : 0.f, i, opacity[i], proj, key, ntiles);
+    for (int ty = r.ty0; ty <= r.ty1; ++ty)
+      for (int tx = r.tx0; tx <= r.tx1; ++tx) atomicAdd(&tile_count[ty * o.ntx + tx], 1u);
+  }
+}
+
+
+// Group tables straight from the tile counts (the global counting path, or
+// no points at all).
+__global__ __launch_bounds__(64) void k_groups(int64_t nt, const uint32_t* __restrict__ tile_count,
+                                               Ws ws) {
+  __shared__ uint32_t s_hist[kOrderClasses];
+  const int64_t t = (int64_t)blockIdx.x * 64 + __lane_id();
+  const bool valid = t < nt;
+  group_table(blockIdx.x, valid, valid ? tile_count[t] : 0u, ws, s_hist);
+}
+
+// Exclusive scan of every group column over the groups (in place), one
+// wavefront per column; the column totals (copies, sort segments per class,
+// tiles per blend-order class) go to ws.coltot.  Each lane holds up to 16
+// rounds of the column in registers so that their loads overlap.
+__global__ __launch_bounds__(64) void k_group_scan(int64_t groups, Ws ws) {
+  constexpr int kRounds = 16;
+  const uint32_t lane = __lane_id();
+  const int col = blockIdx.x;
+  auto at = [&](int64_t g) -> size_t {
+    return col < 5 ? (size_t)g * 4 + (col - 1) : (size_t)g * kOrderClasses + (col - 5);
+  };
+  uint32_t* colp = col == 0 ? nullptr : (col < 5 ? ws.gcls : ws.gord);
+  uint64_t carry = 0;
+  for (int64_t g0 = 0; g0 < groups; g0 += 64 * kRounds) {
+    uint64_t v[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const int64_t g = g0 + r * 64 + lane;
+      v[r] = g < groups ? (col == 0 ? ws.gsum[g] : (uint64_t)colp[at(g)]) : 0ull;
+    }
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const int64_t g = g0 + r * 64 + lane;
+      const uint64_t incl = wave_incl_scan_u64(v[r], lane);
+      if (g < groups) {
+        const uint64_t ex = carry + incl - v[r];
+        if (col == 0)
+          ws.gsum[g] = ex;
+        else
+          colp[at(g)] = (uint32_t)ex;
+      }
+      carry += __shfl(incl, 63, 64);
+    }
+  }
+  if (lane == 0) ws.coltot[col] = carry;
+}
+
+// One wavefront per group of 64 tiles: tile ranges (and scatter cursors for
+// the global scatter), the initial sort segments (one per non-empty tile,
+// per size class) and the tiles' places in the blend order.
+__global__ __launch_bounds__(64) void k_place(int64_t nt, const uint32_t* __restrict__ count,
+                                              uint32_t* __restrict__ ranges,
+                                              uint32_t* __restrict__ cursor,
+                                              uint32_t* __restrict__ order, Ws ws) {
+  const uint32_t lane = __lane_id();
   const uint64_t lt = (1ull << lane) - 1ull;
-  auto klass = [&](int64_t t) -> uint32_t {  // 0 = longest ... 32 = empty, 33 = no tile
-    if (t >= nt) return 33u;
-    const uint32_t c = count[t];
-    return c ? (uint32_t)__clz(c) : 32u;
-  };
-  auto match6 = [&](uint32_t k) {
-    uint64_t m = ~0ull;
+  const int64_t g = blockIdx.x;
+  const int64_t t = g * 64 + lane;
+  const bool valid = t < nt;
+  const uint32_t c = valid ? count[t] : 0u;
+  const uint64_t incl = wave_incl_scan_u64(c, lane);
+  const uint32_t off = (uint32_t)(ws.gsum[g] + incl - c);
+  if (valid) {
+    ranges[t] = off;
+    if (cursor) cursor[t] = off;
+  }
+  const int sc = valid ? sort_class(c) : -1;
+  uint2* lists[4] = {ws.seg_w, ws.seg_m, ws.seg_b0, ws.seg_x};
 #pragma unroll
-    for (int bit = 0; bit < 6; ++bit) {
-      const uint64_t bb = __ballot((k >> bit) & 1u);
-      m &= ((k >> bit) & 1u) ? bb : ~bb;
-    }
-    return m;
-  };
-  if (threadIdx.x < 34) s_h[threadIdx.x] = 0;
-  __syncthreads();
-  for (int64_t t0 = 0; t0 < nt; t0 += 1024) {
-    const uint32_t k = klass(t0 + threadIdx.x);
-    const uint64_t m = match6(k);
-    if ((m & lt) == 0ull && k < 33u) atomicAdd(&s_h[k], (uint32_t)__popcll(m));
+  for (int q = 0; q < 4; ++q) {
+    const uint64_t mq = __ballot(sc == q);
+    if (sc == q)
+      lists[q][ws.gcls[(size_t)g * 4 + q] + (uint32_t)__popcll(mq & lt)] = make_uint2(off, c);
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (int b = 0; b < 34; ++b) {
-      const uint32_t h = s_h[b];
-      s_h[b] = acc;
-      acc += h;
-    }
+  if (g == 0 && lane == 0) {
+    const uint64_t total = ws.coltot[0];
+    ranges[nt] = (uint32_t)total;
+    ws.flags[kFlagCountW] = (uint32_t)ws.coltot[1];
+    ws.flags[kFlagCountM] = (uint32_t)ws.coltot[2];
+    ws.flags[kFlagCountB0] = (uint32_t)ws.coltot[3];
+    ws.flags[kFlagCountX] = (uint32_t)ws.coltot[4];
+    if (total > (uint64_t)ws.cap) ws.flags[kFlagOverflow] = 1u;
   }
-  for (int64_t t0 = 0; t0 < nt; t0 += 1024) {
-    for (int i = threadIdx.x; i < 16 * 34; i += 1024) (&s_wc[0][0])[i] = 0u;
-    __syncthreads();
-    const int64_t t = t0 + threadIdx.x;
-    const uint32_t k = klass(t);
+  if (order) {
+    // first order position of each class: exclusive scan of the class totals
+    const uint32_t tk = lane < 33u ? (uint32_t)ws.coltot[5 + lane] : 0u;
+    const uint32_t kbase = (uint32_t)wave_incl_scan_u64(tk, lane) - tk;
+    const uint32_t k = valid ? order_class(c) : 33u;
     const uint64_t m = match6(k);
-    if ((m & lt) == 0ull) s_wc[w][k] = (uint32_t)__popcll(m);
-    __syncthreads();
-    if (k < 33u) {
-      uint32_t pos = s_h[k] + (uint32_t)__popcll(m & lt);
-      for (uint32_t v = 0; v < w; ++v) pos += s_wc[v][k];
-      order[pos] = (uint32_t)t;
-    }
-    __syncthreads();
-    if (threadIdx.x < 33) {
-      uint32_t add = 0;
-      for (int v = 0; v < 16; ++v) add += s_wc[v][threadIdx.x];
-      s_h[threadIdx.x] += add;
-    }
-    __syncthreads();
+    const uint32_t cb = (uint32_t)__shfl((int)kbase, (int)(k < 33u ? k : 0u), 64);
+    if (k < 33u)
+      order[cb + ws.gord[(size_t)g * kOrderClasses + k] + (uint32_t)__popcll(m & lt)] =
+          (uint32_t)t;
   }
 }
 
@@ -269,56 +353,59 @@ __device__ __forceinline__ uint32_t entry_word(const Footprint& f, int64_t i, in
   return ((uint32_t)i << lbits) | (cy << pb) | cx;
 }
 
-// Step 2 with per-workgroup slot reservation: histogram the chunk's tiles in
-// LDS, reserve one contiguous run per non-empty tile with a single global
-// atomic, then hand out slots inside the run with LDS atomics.
+// Step 2 with per-workgroup slot ranges: workgroup b owns, in every tile's
+// bucket, the run that starts at the tile's range start plus the counts of
+// workgroups 0..b-1 (from the count pass); slots inside the run come from
+// LDS atomics.  No global atomics.
 __global__ __launch_bounds__(kBinBlock) void k_scatter(Cam cam, Opts o, int64_t n, int64_t chunk,
-                                                       const float2* __restrict__ uv,
-                                                       const float* __restrict__ radius,
+                                                       const float4* __restrict__ proj,
                                                        const uint32_t* __restrict__ key,
                                                        const uint32_t* __restrict__ ntiles,
-                                                       uint32_t* __restrict__ cursor,
+                                                       const uint32_t* __restrict__ ranges,
+                                                       const uint32_t* __restrict__ blk,
                                                        uint2* __restrict__ bucket, uint32_t cap,
                                                        int lbits, int pb,
                                                        const uint32_t* __restrict__ flags) {
   __shared__ uint32_t bins[kLdsBins];
   if (flags[kFlagOverflow]) return;
   const int nt = o.ntx * o.nty;
-  for (int t = threadIdx.x; t < nt; t += kBinBlock) bins[t] = 0u;
+  const uint32_t* row = blk + (size_t)blockIdx.x * nt;
+  for (int t = threadIdx.x; t < nt; t += kBinBlock) bins[t] = ranges[t] + row[t];
   __syncthreads();
   const int sh = tile_shift(o.T);
   const Chunk c = chunk_of(n, chunk);
-  for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBinBlock) {
-    if (ntiles[i] == 0) continue;
-    const float2 p = uv[i];
-    const TileRect r = tile_rect(footprint(o, cam, p.x, p.y, radius ? radius[i] : 0.f), sh);
-    for (int ty = r.ty0; ty <= r.ty1; ++ty)
-      for (int tx = r.tx0; tx <= r.tx1; ++tx) atomicAdd(&bins[ty * o.ntx + tx], 1u);
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < nt; t += kBinBlock) {
-    const uint32_t v = bins[t];
-    if (v) bins[t] = atomicAdd(&cursor[t], v);
-  }
-  __syncthreads();
-  for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBinBlock) {
-    if (ntiles[i] == 0) continue;
-    const float2 p = uv[i];
-    const Footprint f = footprint(o, cam, p.x, p.y, radius ? radius[i] : 0.f);
-    const TileRect r = tile_rect(f, sh);
-    const uint32_t k = key[i];
-    for (int ty = r.ty0; ty <= r.ty1; ++ty)
-      for (int tx = r.tx0; tx <= r.tx1; ++tx) {
-        const uint32_t slot = atomicAdd(&bins[ty * o.ntx + tx], 1u);
-        // always in range when the counts of step 1 hold
-        if (slot < cap) bucket[slot] = make_uint2(k, entry_word(f, i, tx, ty, o.T, lbits, pb));
-      }
+  for (int64_t i0 = c.begin + threadIdx.x; i0 < c.end; i0 += kUnroll * kBinBlock) {
+    uint32_t nts[kUnroll], ks[kUnroll];
+    float4 ps[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {  // all loads first, culled points included
+      const int64_t i = i0 + (int64_t)q * kBinBlock;
+      const int64_t j = i < c.end ? i : c.begin;
+      nts[q] = ntiles[j];
+      ps[q] = proj[j];
+      ks[q] = key[j];
+    }
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      const int64_t i = i0 + (int64_t)q * kBinBlock;
+      if (i >= c.end) break;
+      if (nts[q] == 0) continue;
+      const Footprint f = footprint(o, cam, ps[q].x, ps[q].y, ps[q].w);
+      const TileRect r = tile_rect(f, sh);
+      for (int ty = r.ty0; ty <= r.ty1; ++ty)
+        for (int tx = r.tx0; tx <= r.tx1; ++tx) {
+          const uint32_t slot = atomicAdd(&bins[ty * o.ntx + tx], 1u);
+          // always in range when the counts of step 1 hold
+          if (slot < cap)
+            bucket[slot] = make_uint2(ks[q], entry_word(f, i, tx, ty, o.T, lbits, pb));
+        }
+    }
   }
 }
 
 // Step 2 for very large tile counts: one global atomic per copy.
 __global__ __launch_bounds__(kBlock) void k_scatter_global(
-    Cam cam, Opts o, int64_t n, const float2* __restrict__ uv, const float* __restrict__ radius,
+    Cam cam, Opts o, int64_t n, const float4* __restrict__ proj,
     const uint32_t* __restrict__ key, const uint32_t* __restrict__ ntiles,
     uint32_t* __restrict__ cursor, uint2* __restrict__ bucket, uint32_t cap, int lbits, int pb,
     const uint32_t* __restrict__ flags) {
@@ -327,8 +414,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter_global(
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     if (ntiles[i] == 0) continue;
-    const float2 p = uv[i];
-    const Footprint f = footprint(o, cam, p.x, p.y, radius ? radius[i] : 0.f);
+    const float4 p = proj[i];
+    const Footprint f = footprint(o, cam, p.x, p.y, p.w);
     const TileRect r = tile_rect(f, sh);
     const uint32_t k = key[i];
     for (int ty = r.ty0; ty <= r.ty1; ++ty)
@@ -373,11 +460,6 @@ int grid_for(int64_t n, int block) {
 // Points per privatised block: one wave of blocks over the whole GPU for
 // large clouds, at least 8192 points per block so the per-block flush of the
 // tile histogram stays small next to the copies it replaces.
-int64_t bin_chunk(int64_t n) {
-  const int64_t per = (n + 255) / 256;
-  const int64_t c = std::max<int64_t>(8192, per);
-  return (c + kBinBlock - 1) / kBinBlock * kBinBlock;
-}
 
 }  // namespace
 
@@ -389,43 +471,58 @@ hipError_t launch_clear(uint32_t* p, size_t n, hipStream_t s) {
 }
 
 hipError_t launch_project(const Cam& cam, const Opts& o, int64_t n, const float* pos,
-                          const float* radius, float* uv, uint32_t* key, uint32_t* ntiles,
+                          const float* opacity, const float* radius, float* proj, uint32_t* key,
+                          uint32_t* ntiles,
                           const Ws& ws, hipStream_t s) {
   const int64_t nt = (int64_t)o.ntx * o.nty;
-  hipError_t e = launch_clear(ws.tile_count, (size_t)nt, s);
+  hipError_t e = launch_clear(ws.flags, kFlagSlots, s);
   if (e != hipSuccess) return e;
-  e = launch_clear(ws.flags, kFlagSlots, s);
-  if (e != hipSuccess) return e;
-  if (n == 0) return hipSuccess;
-  if (nt <= kLdsBins) {
-    const int64_t chunk = bin_chunk(n);
-    hipLaunchKernelGGL(k_project_count, dim3((unsigned)((n + chunk - 1) / chunk)), dim3(kBinBlock),
-                       0, s, cam, o, n, chunk, pos, radius, reinterpret_cast<float2*>(uv), key,
-                       ntiles, ws.tile_count);
-  } else {
-    hipLaunchKernelGGL(k_project_count_global, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, cam,
-                       o, n, pos, radius, reinterpret_cast<float2*>(uv), key, ntiles,
-                       ws.tile_count);
+  if (n == 0 || nt > kLdsBins) {
+    e = launch_clear(ws.tile_count, (size_t)nt, s);
+    if (e != hipSuccess) return e;
   }
+  if (n == 0) {
+    hipLaunchKernelGGL(k_groups, dim3((unsigned)ws.groups), dim3(64), 0, s, nt, ws.tile_count, ws);
+    return hipGetLastError();
+  }
+  if (nt <= kLdsBins) {
+    const int64_t chunk = ws.chunk, rows = ws.rows;
+    hipLaunchKernelGGL(k_project_count, dim3((unsigned)rows), dim3(kBinBlock), 0, s, cam, o, n,
+                       chunk, pos, opacity, radius, reinterpret_cast<float4*>(proj), key, ntiles,
+                       ws.blk);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_colscan, dim3((unsigned)ws.groups), dim3(1024), 0, s, nt, (int)rows,
+                       ws.blk, ws.tile_count, ws);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_project_count_global, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, cam, o,
+                     n, pos, opacity, radius, reinterpret_cast<float4*>(proj), key, ntiles,
+                     ws.tile_count);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_groups, dim3((unsigned)ws.groups), dim3(64), 0, s, nt, ws.tile_count, ws);
   return hipGetLastError();
 }
 
-hipError_t launch_bin(const Cam& cam, const Opts& o, int64_t n, const float* uv,
-                      const float* radius, const uint32_t* key, const uint32_t* ntiles,
+hipError_t launch_bin(const Cam& cam, const Opts& o, int64_t n, const float* proj,
+                      const uint32_t* key, const uint32_t* ntiles,
                       uint32_t* ranges, uint32_t* order, const Ws& ws, hipStream_t s) {
   const int64_t nt = (int64_t)o.ntx * o.nty;
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, nt, ws.tile_count, ranges, ws.cursor,
-                     order, ws);
+  hipLaunchKernelGGL(k_group_scan, dim3(1 + 4 + kOrderClasses), dim3(64), 0, s, ws.groups, ws);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_place, dim3((unsigned)ws.groups), dim3(64), 0, s, nt, ws.tile_count, ranges,
+                     nt <= kLdsBins ? nullptr : ws.cursor, order, ws);
+  e = hipGetLastError();
   if (e != hipSuccess || n == 0) return e;
   if (nt <= kLdsBins) {
-    const int64_t chunk = bin_chunk(n);
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)((n + chunk - 1) / chunk)), dim3(kBinBlock), 0, s,
-                       cam, o, n, chunk, reinterpret_cast<const float2*>(uv), radius, key, ntiles,
-                       ws.cursor, ws.bucket, ws.cap, ws.lbits, ws.pb, ws.flags);
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)ws.rows), dim3(kBinBlock), 0, s, cam, o, n,
+                       ws.chunk, reinterpret_cast<const float4*>(proj), key, ntiles,
+                       ranges, ws.blk, ws.bucket, ws.cap, ws.lbits, ws.pb, ws.flags);
   } else {
     hipLaunchKernelGGL(k_scatter_global, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, cam, o, n,
-                       reinterpret_cast<const float2*>(uv), radius, key, ntiles, ws.cursor,
+                       reinterpret_cast<const float4*>(proj), key, ntiles, ws.cursor,
                        ws.bucket, ws.cap, ws.lbits, ws.pb, ws.flags);
   }
   return hipGetLastError();

@@ -19,7 +19,8 @@
 //               queues the sub-segments (which are then sorted on their own;
 //               concatenated in digit order they give the sorted segment).
 //               Two split rounds; what is still larger is LSD-sorted by a
-//               1024-thread block.
+//               1024-thread block (up to 8192 copies) or through global
+//               memory.
 //   larger      LSD radix sort through global memory by a 1024-thread block.
 //
 // The LSD sorts rank elements inside a wavefront with 8 ballots per element
@@ -318,17 +319,29 @@ __device__ void sort_segment_lds(const uint2* __restrict__ seg, uint32_t n, cons
 }
 
 // n <= 64: every lane counts the (key, index) pairs smaller than its own.
+// Lanes without an element publish an all-ones pair, which no element
+// (key bit 31 is clear) counts as smaller, so the count runs over whole
+// groups of eight with 16-byte LDS reads.
 __device__ void rank_sort_wave(const uint2* __restrict__ seg, uint32_t n, const ListOut& out,
                                uint32_t base, uint2* __restrict__ s) {
   const uint32_t lane = __lane_id();
   const bool valid = lane < n;
-  const uint2 v = valid ? seg[lane] : make_uint2(0u, 0u);
+  const uint2 v = valid ? seg[lane] : make_uint2(0xffffffffu, 0xffffffffu);
   s[lane] = v;
   bsync<true>();
+  const uint64_t me = ((uint64_t)v.x << 32) | v.y;
+  const uint4* s4 = reinterpret_cast<const uint4*>(s);
+  const uint32_t groups = (n + 7u) >> 3;
   uint32_t r = 0;
-  for (uint32_t m = 0; m < n; ++m) {
-    const uint2 o = s[m];
-    r += (o.x < v.x) || (o.x == v.x && o.y < v.y);
+  for (uint32_t g = 0; g < groups; ++g) {
+    uint4 q[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = s4[4 * g + k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      r += (((uint64_t)q[k].x << 32) | q[k].y) < me;
+      r += (((uint64_t)q[k].z << 32) | q[k].w) < me;
+    }
   }
   if (valid) out.put(base + r, v.y);
   bsync<true>();
@@ -342,7 +355,7 @@ __global__ __launch_bounds__(256) void k_sort_w(const uint2* __restrict__ segs,
                                                 const uint32_t* __restrict__ flags,
                                                 const uint2* __restrict__ bucket,
                                                 ListOut out) {
-  __shared__ uint32_t s_key[4][kW_CAP];
+  __shared__ __align__(16) uint32_t s_key[4][kW_CAP];
   __shared__ uint32_t s_idx[4][kW_CAP];
   __shared__ uint32_t s_hist[4][256];
   __shared__ uint32_t s_off[4][256];
@@ -385,22 +398,29 @@ __global__ __launch_bounds__(NW * 64) void k_sort_block(const uint2* __restrict_
 // to the class lists: one global atomic per (block, class).
 __device__ void push_segments(uint2 sg, bool split_again, const Ws& ws, uint32_t* s_cnt,
                               uint32_t* s_base) {
-  int c = 3;  // 0: W, 1: M, 2: split again / L, 3: none
-  if (sg.y > 0) c = sg.y <= kSortCapW ? 0 : (sg.y <= kSortCapM ? 1 : 2);
-  if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+  // 0: W, 1: M, 2: split again (first round) or L, 3: X (global sort), 4: none
+  int c = 4;
+  if (sg.y > 0)
+    c = sg.y <= kSortCapW ? 0
+                          : (sg.y <= kSortCapM ? 1 : (split_again || sg.y <= kSortCapLB ? 2 : 3));
+  if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0;
   __syncthreads();
   uint32_t my = 0;
-  if (c < 3) my = atomicAdd(&s_cnt[c], 1u);
+  if (c < 4) my = atomicAdd(&s_cnt[c], 1u);
   __syncthreads();
-  if (threadIdx.x < 3 && s_cnt[threadIdx.x]) {
+  if (threadIdx.x < 4 && s_cnt[threadIdx.x]) {
     const int cc = (int)threadIdx.x;
     const int slot = cc == 0 ? kFlagCountW
-                             : (cc == 1 ? kFlagCountM : (split_again ? kFlagCountB1 : kFlagCountL));
+                             : (cc == 1 ? kFlagCountM
+                                        : (cc == 3 ? kFlagCountX
+                                                   : (split_again ? kFlagCountB1 : kFlagCountL)));
     s_base[cc] = atomicAdd(&ws.flags[slot], s_cnt[cc]);
   }
   __syncthreads();
-  if (c < 3) {
-    uint2* dst = c == 0 ? ws.seg_w : (c == 1 ? ws.seg_m : (split_again ? ws.seg_b1 : ws.seg_l));
+  if (c < 4) {
+    uint2* dst = c == 0 ? ws.seg_w
+                        : (c == 1 ? ws.seg_m
+                                  : (c == 3 ? ws.seg_x : (split_again ? ws.seg_b1 : ws.seg_l)));
     dst[s_base[c] + my] = sg;
   }
   __syncthreads();
@@ -411,7 +431,7 @@ __global__ __launch_bounds__(1024) void k_split(int round, Ws ws) {
   __shared__ uint2 s_e[kSortCapL];
   __shared__ uint32_t s_cnt[256], s_off[256];
   __shared__ uint32_t s_red[64];
-  __shared__ uint32_t s_pc[3], s_pb[3];
+  __shared__ uint32_t s_pc[4], s_pb[4];
   if (ws.flags[kFlagOverflow]) return;
   const uint2* segs = round == 0 ? ws.seg_b0 : ws.seg_b1;
   const uint32_t count = ws.flags[round == 0 ? kFlagCountB0 : kFlagCountB1];
@@ -581,7 +601,8 @@ hipError_t launch_sort(const Ws& ws, uint32_t* list, uint16_t* lpos, int64_t nt,
   const int grid_m = (int)std::min<int64_t>(nt + (int64_t)ws.cap / 2048, 4096);
   hipLaunchKernelGGL((k_sort_block<4, 8, kFlagCountM>), dim3(std::max(grid_m, 1)), dim3(256), 0,
                      stream, ws.seg_m, ws.flags, ws.bucket, out);
-  hipLaunchKernelGGL((k_sort_block<16, 16, kFlagCountL>), dim3(grid_split), dim3(1024), 0, stream,
+  hipLaunchKernelGGL((k_sort_block<16, kSortCapLB / 1024, kFlagCountL>), dim3(grid_split),
+                     dim3(1024), 0, stream,
                      ws.seg_l, ws.flags, ws.bucket, out);
   hipLaunchKernelGGL((k_sort_x<16, 16>), dim3(256), dim3(1024), 0, stream, ws, out);
   return hipGetLastError();

@@ -32,11 +32,12 @@ class RasterSettings:
     cutoff: float = 3.0         # Gaussian truncation in standard deviations
     max_radius: float = 3.0     # largest Gaussian radius (px); sizes the workspace
     keep_lists: bool = False    # keep tile lists for the backward instead of recomputing
+    bin_points: int = 0         # points per workgroup of the binning passes (0 = automatic)
 
     def opts(self) -> L.Opts:
         splat = {"bilinear": L.SPLAT_BILINEAR, "gaussian": L.SPLAT_GAUSSIAN}[self.splat]
         return L.make_opts(splat, self.tile, self.t_min, self.dilation, self.cutoff,
-                           self.max_radius)
+                           self.max_radius, self.bin_points)
 
 
 def camera_struct(cam) -> L.Camera:
@@ -85,7 +86,7 @@ def default_workspace(device) -> Workspace:
 
 
 class Binning(NamedTuple):
-    uv: torch.Tensor        # [n, 2] f32
+    proj: torch.Tensor      # [n, 4] f32 (u, v, opacity, radius)
     key: torch.Tensor       # [n] depth keys (int32 storage of u32)
     ntiles: torch.Tensor    # [n] tiles touched (int32 storage of u32), 0 = culled
     ranges: torch.Tensor    # [num_tiles + 1] (int32 storage of u32)
@@ -95,15 +96,15 @@ class Binning(NamedTuple):
                             # storage of u16; bilinear splats)
 
 
-def project_bin_sort(pos: torch.Tensor, cam: L.Camera, opts: L.Opts, ws: torch.Tensor,
-                     radius: Optional[torch.Tensor] = None) -> Binning:
+def project_bin_sort(pos: torch.Tensor, opacity: torch.Tensor, cam: L.Camera, opts: L.Opts,
+                     ws: torch.Tensor, radius: Optional[torch.Tensor] = None) -> Binning:
     """Steps 1-3: project, bin into tiles, sort every tile by (depth, index)."""
     dev = pos.device
     n = pos.shape[0]
     lib = L.lib()
     nt = int(lib.inpc_num_tiles(ctypes.byref(cam), ctypes.byref(opts)))
     cap = int(lib.inpc_copy_capacity(n, ctypes.byref(cam), ctypes.byref(opts)))
-    uv = torch.empty(n, 2, dtype=torch.float32, device=dev)
+    proj = torch.empty(n, 4, dtype=torch.float32, device=dev)
     key = torch.empty(n, dtype=torch.int32, device=dev)
     ntiles = torch.empty(n, dtype=torch.int32, device=dev)
     ranges = torch.empty(nt + 1, dtype=torch.int32, device=dev)
@@ -113,19 +114,19 @@ def project_bin_sort(pos: torch.Tensor, cam: L.Camera, opts: L.Opts, ws: torch.T
     s = _stream(dev)
     cb, ob = ctypes.byref(cam), ctypes.byref(opts)
     wsb = ws.numel()
-    L.call("inpc_project", cb, ob, n, _p(pos), _p(radius), _p(uv), _p(key), _p(ntiles), _p(ws),
+    L.call("inpc_project", cb, ob, n, _p(pos), _p(opacity), _p(radius), _p(proj), _p(key),
+           _p(ntiles), _p(ws), wsb, s)
+    L.call("inpc_bin", cb, ob, n, _p(proj), _p(key), _p(ntiles), _p(ranges), _p(order), _p(ws),
            wsb, s)
-    L.call("inpc_bin", cb, ob, n, _p(uv), _p(radius), _p(key), _p(ntiles), _p(ranges),
-           _p(order), _p(ws), wsb, s)
-    L.call("inpc_sort", cb, ob, n, _p(uv), _p(ranges), _p(order), _p(lst), _p(lpos), _p(ws),
+    L.call("inpc_sort", cb, ob, n, _p(proj), _p(ranges), _p(order), _p(lst), _p(lpos), _p(ws),
            wsb, s)
-    return Binning(uv, key, ntiles, ranges, lst, order, lpos)
+    return Binning(proj, key, ntiles, ranges, lst, order, lpos)
 
 
-def blend_forward(b: Binning, opacity, feat, cam: L.Camera, opts: L.Opts, ws: torch.Tensor,
-                  bg=None, radius=None, with_state=True):
+def blend_forward(b: Binning, feat, cam: L.Camera, opts: L.Opts, ws: torch.Tensor, bg=None,
+                  with_state=True):
     """Step 4.  Returns out [C,H,W], t_final [H,W], n_contrib [H,W], state."""
-    dev = opacity.device
+    dev = feat.device
     n, C = feat.shape
     H, W = cam.height, cam.width
     out = torch.empty(C, H, W, dtype=torch.float32, device=dev)
@@ -135,10 +136,10 @@ def blend_forward(b: Binning, opacity, feat, cam: L.Camera, opts: L.Opts, ws: to
     if with_state:
         state = torch.empty(int(L.lib().inpc_state_bytes(ctypes.byref(cam), ctypes.byref(opts))),
                             dtype=torch.uint8, device=dev)
-    L.call("inpc_blend_forward", ctypes.byref(cam), ctypes.byref(opts), n, _p(b.uv), _p(radius),
-           _p(opacity), _p(feat), C, _DTYPES[feat.dtype], _p(bg), _p(b.ranges), _p(b.order),
-           _p(b.list), _p(b.lpos if opts.splat == L.SPLAT_BILINEAR else None), _p(out),
-           _p(t_final), _p(n_contrib), _p(state), _p(ws), ws.numel(), _stream(dev))
+    L.call("inpc_blend_forward", ctypes.byref(cam), ctypes.byref(opts), n, _p(b.proj), _p(feat),
+           C, _DTYPES[feat.dtype], _p(bg), _p(b.ranges), _p(b.order), _p(b.list),
+           _p(b.lpos if opts.splat == L.SPLAT_BILINEAR else None), _p(out), _p(t_final),
+           _p(n_contrib), _p(state), _p(ws), ws.numel(), _stream(dev))
     return out, t_final, n_contrib, state
 
 
@@ -146,10 +147,10 @@ def backward_scratch_bytes(n: int, C: int, cam: L.Camera, opts: L.Opts) -> int:
     return int(L.lib().inpc_backward_scratch_bytes(n, C, ctypes.byref(cam), ctypes.byref(opts)))
 
 
-def blend_backward(b: Binning, opacity, feat, cam: L.Camera, opts: L.Opts, ws: torch.Tensor,
-                   t_final, state, grad_out, grad_t=None, bg=None, scratch=None):
+def blend_backward(b: Binning, feat, cam: L.Camera, opts: L.Opts, ws: torch.Tensor, t_final,
+                   state, grad_out, grad_t=None, bg=None, scratch=None):
     """Step 5.  Returns grad_feat [n,C] f32, grad_opacity [n], grad_uv [n,2], grad_bg [C]|None."""
-    dev = opacity.device
+    dev = feat.device
     n, C = feat.shape
     grad_feat = torch.empty(n, C, dtype=torch.float32, device=dev)
     grad_opacity = torch.empty(n, dtype=torch.float32, device=dev)
@@ -158,10 +159,10 @@ def blend_backward(b: Binning, opacity, feat, cam: L.Camera, opts: L.Opts, ws: t
     if scratch is None:
         scratch = torch.empty(backward_scratch_bytes(n, C, cam, opts), dtype=torch.uint8,
                               device=dev)
-    L.call("inpc_blend_backward", ctypes.byref(cam), ctypes.byref(opts), n, _p(b.uv),
-           _p(opacity), _p(feat), C, _DTYPES[feat.dtype], _p(bg), _p(b.ntiles), _p(b.ranges),
-           _p(b.order), _p(b.list), _p(b.lpos), _p(t_final), _p(state), _p(grad_out),
-           _p(grad_t), _p(grad_feat), _p(grad_opacity), _p(grad_uv), _p(grad_bg), _p(scratch), scratch.numel(), _p(ws),
+    L.call("inpc_blend_backward", ctypes.byref(cam), ctypes.byref(opts), n, _p(b.proj), _p(feat),
+           C, _DTYPES[feat.dtype], _p(bg), _p(b.ntiles), _p(b.ranges), _p(b.order), _p(b.list),
+           _p(b.lpos), _p(t_final), _p(state), _p(grad_out), _p(grad_t), _p(grad_feat),
+           _p(grad_opacity), _p(grad_uv), _p(grad_bg), _p(scratch), scratch.numel(), _p(ws),
            ws.numel(), _stream(dev))
     return grad_feat, grad_opacity, grad_uv, grad_bg
 
@@ -201,10 +202,9 @@ class _RasterizeFn(torch.autograd.Function):
     def forward(ctx, pos, opacity, feat, bg, radius, cam, settings, workspace):
         opts = settings.opts()
         ws = workspace.get(pos.shape[0], cam, opts, pos.device)
-        b = project_bin_sort(pos, cam, opts, ws, radius)
+        b = project_bin_sort(pos, opacity, cam, opts, ws, radius)
         out, t_final, n_contrib, state = blend_forward(
-            b, opacity, feat, cam, opts, ws, bg, radius,
-            with_state=settings.splat == "bilinear")
+            b, feat, cam, opts, ws, bg, with_state=settings.splat == "bilinear")
         ctx.cam, ctx.settings, ctx.workspace = cam, settings, workspace
         ctx.has_bg = bg is not None
         saved = [pos, opacity, feat, bg if bg is not None else torch.empty(0, device=pos.device),
@@ -227,11 +227,11 @@ class _RasterizeFn(torch.autograd.Function):
         if ctx.settings.keep_lists:
             b = Binning(*saved[6:])
         else:
-            b = project_bin_sort(pos, cam, opts, ws)
+            b = project_bin_sort(pos, opacity, cam, opts, ws)
         g_out = g_out.contiguous() if g_out is not None else torch.zeros(
             feat.shape[1], cam.height, cam.width, device=pos.device)
         g_t = g_t.contiguous() if g_t is not None else None
-        gf, go, guv, gbg = blend_backward(b, opacity, feat, cam, opts, ws, t_final, state, g_out,
+        gf, go, guv, gbg = blend_backward(b, feat, cam, opts, ws, t_final, state, g_out,
                                           g_t, bg)
         gpos = project_backward(pos, b, cam, guv)
         if feat.dtype != torch.float32:

@@ -12,6 +12,8 @@ from .generator import (  # noqa: F401
     CONFIGS,
     make_scene,
     make_camera,
+    multi_view_scenes,
+    multi_view_specs,
     ring_camera,
     tiny_scene,
 )

@@ -127,16 +127,16 @@ def _plane_basis(nrm: np.ndarray):
     return e1, e2
 
 
-def draw_points(rng: np.random.Generator, n: int, s: float, z_lo: float,
-                z_hi: float) -> np.ndarray:
-    """Steps 1-3: four surfaces (planes k=0,2; spheres k=1,3) plus uniform points."""
+def draw_surfaces(rng: np.random.Generator, s: float, z_lo: float, z_hi: float):
+    """Step 1: four surfaces (planes k=0,2; spheres k=1,3) with centres in the
+    box shrunk 25% toward its centre."""
     lo = np.array([-s, -s, z_lo])
     hi = np.array([s, s, z_hi])
     mid = 0.5 * (lo + hi)
     half = 0.5 * (hi - lo)
     s_lo, s_hi = mid - 0.75 * half, mid + 0.75 * half
     surfaces = []
-    for k in range(4):  # step 1
+    for k in range(4):
         centre = rng.uniform(s_lo, s_hi)
         if k % 2 == 0:
             nrm = rng.normal(size=3)
@@ -144,6 +144,16 @@ def draw_points(rng: np.random.Generator, n: int, s: float, z_lo: float,
             surfaces.append(("plane", centre, nrm))
         else:
             surfaces.append(("sphere", centre, rng.uniform(0.1, 0.25) * s))
+    return surfaces
+
+
+def draw_points(rng: np.random.Generator, n: int, s: float, z_lo: float,
+                z_hi: float, surfaces=None) -> np.ndarray:
+    """Steps 1-3: four surfaces (drawn here unless given) plus uniform points."""
+    lo = np.array([-s, -s, z_lo])
+    hi = np.array([s, s, z_hi])
+    if surfaces is None:
+        surfaces = draw_surfaces(rng, s, z_lo, z_hi)
     n_surf = int(0.7 * n)
     counts = [n_surf // 4] * 4
     counts[3] += n_surf - sum(counts)
@@ -163,9 +173,10 @@ def draw_points(rng: np.random.Generator, n: int, s: float, z_lo: float,
     return np.concatenate(parts, axis=0)
 
 
-def make_scene(spec: SceneSpec, camera: Optional[Camera] = None) -> Scene:
-    rng = np.random.default_rng(spec.seed)
-    pos = draw_points(rng, spec.n, spec.s, spec.z_lo, spec.z_hi)
+def make_scene(spec: SceneSpec, camera: Optional[Camera] = None, rng=None,
+               surfaces=None) -> Scene:
+    rng = np.random.default_rng(spec.seed) if rng is None else rng
+    pos = draw_points(rng, spec.n, spec.s, spec.z_lo, spec.z_hi, surfaces)
     lo, hi = spec.opacity_range
     opacity = rng.uniform(lo, hi, size=spec.n)  # step 4
     if spec.feat_dist == "uniform01":  # step 5
@@ -241,3 +252,34 @@ CONFIGS = {
                     channels=32, feat_dist="normal", opacity_range=(0.05, 0.95),
                     with_grad=True, seed=0),
 }
+
+
+# Multi-view batch: 8 views of one scene (the four surfaces of seed 0 in the
+# box [-4, 4]^2 x [2, 20]), each with its own point sample of n_v ~ U{500,000
+# .. 6,000,000} points (seed (0, v)) and a resolution drawn from {960x540,
+# 1280x720, 1920x1080}; cameras on a ring of radius 8 around the box centre.
+MULTI_VIEW_RESOLUTIONS = ((960, 540), (1280, 720), (1920, 1080))
+
+
+def multi_view_specs(n_views: int = 8, seed: int = 0, n_lo: int = 500_000,
+                     n_hi: int = 6_000_000, channels: int = 16, resolutions=None):
+    """Per-view (SceneSpec, Camera) pairs of the multi-view batch."""
+    res = MULTI_VIEW_RESOLUTIONS if resolutions is None else tuple(resolutions)
+    cfg = np.random.default_rng(seed)
+    counts = cfg.integers(n_lo, n_hi + 1, size=n_views)
+    picks = cfg.integers(0, len(res), size=n_views)
+    out = []
+    for v in range(n_views):
+        W, H = res[int(picks[v])]
+        spec = SceneSpec(n=int(counts[v]), s=4.0, z_lo=2.0, z_hi=20.0, width=W, height=H,
+                         channels=channels, feat_dist="normal", opacity_range=(0.05, 0.95),
+                         with_grad=True, seed=seed)
+        out.append((spec, ring_camera(v, n_views, W, H)))
+    return out
+
+
+def multi_view_scenes(n_views: int = 8, seed: int = 0, **kw):
+    """The scenes of the multi-view batch (see multi_view_specs)."""
+    surfaces = draw_surfaces(np.random.default_rng(seed), 4.0, 2.0, 20.0)
+    return [make_scene(spec, camera=cam, rng=np.random.default_rng([seed, v]), surfaces=surfaces)
+            for v, (spec, cam) in enumerate(multi_view_specs(n_views, seed, **kw))]

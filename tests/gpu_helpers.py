@@ -24,21 +24,23 @@ def run_gpu(scene, settings, bg=None, feat_dtype=torch.float32, backward=True, f
     rad = None if scene.radius is None else torch.from_numpy(scene.radius).to(DEV)
     bgt = None if bg is None else torch.as_tensor(bg, dtype=torch.float32, device=DEV)
     ws = inpc.Workspace().get(pos.shape[0], cam, opts, DEV)
-    b = inpc.project_bin_sort(pos, cam, opts, ws, rad if settings.splat == "gaussian" else None)
-    out, tf, nc, state = inpc.blend_forward(b, op, ft, cam, opts, ws, bgt, rad,
+    b = inpc.project_bin_sort(pos, op, cam, opts, ws, rad if settings.splat == "gaussian" else None)
+    out, tf, nc, state = inpc.blend_forward(b, ft, cam, opts, ws, bgt,
                                             with_state=settings.splat == "bilinear")
     inpc.check_capacity(ws)
-    r = dict(uv=b.uv.cpu().numpy(), key=b.key.cpu().numpy().view(np.uint32),
+    proj = b.proj.cpu().numpy()
+    r = dict(uv=np.ascontiguousarray(proj[:, :2]), proj=proj, key=b.key.cpu().numpy().view(np.uint32),
              ntiles=b.ntiles.cpu().numpy().view(np.uint32),
              ranges=b.ranges.cpu().numpy().view(np.uint32), list=b.list.cpu().numpy().view(np.uint32),
              out=out.cpu().numpy(), t_final=tf.cpu().numpy(), n_contrib=nc.cpu().numpy().view(np.uint32),
              order=b.order.cpu().numpy().view(np.uint32), tile=settings.tile,
-             W=cam.width, H=cam.height,
+             W=cam.width, H=cam.height, opacity=scene.opacity,
+             radius=scene.radius if settings.splat == "gaussian" else np.zeros_like(scene.opacity),
              lpos=b.lpos.cpu().numpy().view(np.uint16) if settings.splat == "bilinear" else None)
     if backward and scene.grad is not None and settings.splat == "bilinear":
         g = torch.from_numpy(scene.grad).to(DEV)
         gt = None if scene.grad_t is None else torch.from_numpy(scene.grad_t).to(DEV)
-        gf, go, guv, gbg = inpc.blend_backward(b, op, ft, cam, opts, ws, tf, state, g, gt, bgt)
+        gf, go, guv, gbg = inpc.blend_backward(b, ft, cam, opts, ws, tf, state, g, gt, bgt)
         gpos = inpc.project_backward(pos, b, cam, guv)
         torch.cuda.synchronize()
         r.update(grad_feat=gf.cpu().numpy(), grad_opacity=go.cpu().numpy(),
@@ -64,6 +66,9 @@ def assert_binning_exact(g, proj, tl):
     np.testing.assert_array_equal(g["ntiles"] > 0, vis)
     np.testing.assert_array_equal(g["ntiles"], proj["ntiles"])
     np.testing.assert_array_equal(g["uv"][vis].view(np.uint32), proj["uv"][vis].view(np.uint32))
+    if g.get("opacity") is not None:  # the projection record carries opacity and radius
+        np.testing.assert_array_equal(g["proj"][:, 2], g["opacity"])
+        np.testing.assert_array_equal(g["proj"][:, 3], g["radius"])
     np.testing.assert_array_equal(g["key"][vis], proj["key"][vis])
     np.testing.assert_array_equal(g["ranges"].astype(np.int64), tl["ranges"])
     M = int(tl["ranges"][-1])

@@ -47,6 +47,13 @@ def test_workspace_and_sizes():
     g3 = L.make_opts(splat=L.SPLAT_GAUSSIAN, tile=8, max_radius=3.0)
     assert lib.inpc_copy_capacity(10, ctypes.byref(c), ctypes.byref(g3)) > \
         lib.inpc_copy_capacity(10, ctypes.byref(c), ctypes.byref(g1))
+    # the binning workgroup size is a tuning knob: multiples of 1024 only; fewer
+    # points per workgroup means more per-workgroup count rows
+    o_small = L.make_opts(tile=8, bin_points=1024)
+    big_n = 100_000
+    assert lib.inpc_workspace_bytes(big_n, ctypes.byref(c), ctypes.byref(o_small)) > \
+        lib.inpc_workspace_bytes(big_n, ctypes.byref(c), ctypes.byref(o))
+    assert lib.inpc_workspace_bytes(10, ctypes.byref(c), ctypes.byref(L.make_opts(bin_points=1000))) == 0
     # invalid settings give 0
     assert lib.inpc_workspace_bytes(10, ctypes.byref(c), ctypes.byref(L.make_opts(tile=12))) == 0
     assert lib.inpc_workspace_bytes(-1, ctypes.byref(c), ctypes.byref(o)) == 0
@@ -57,14 +64,15 @@ FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: the calls fail before any 
 
 
 @pytest.mark.parametrize("case", ["null_cam", "bad_tile", "neg_n", "null_ws", "small_ws",
-                                  "null_pos", "gauss_no_radius"])
+                                  "null_pos", "null_opacity", "gauss_no_radius",
+                                  "misaligned_proj"])
 def test_project_rejects_bad_arguments(case):
     lib = L.lib()
     c, o = cam(), L.make_opts(tile=8)
     n = 100
     ws_bytes = lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(o))
-    args = dict(cam=ctypes.byref(c), opts=ctypes.byref(o), n=n, pos=FAKE, radius=None, uv=FAKE,
-                key=FAKE, ntiles=FAKE, ws=FAKE, ws_bytes=ws_bytes)
+    args = dict(cam=ctypes.byref(c), opts=ctypes.byref(o), n=n, pos=FAKE, opacity=FAKE,
+                radius=None, proj=FAKE, key=FAKE, ntiles=FAKE, ws=FAKE, ws_bytes=ws_bytes)
     if case == "null_cam":
         args["cam"] = None
     elif case == "bad_tile":
@@ -77,6 +85,10 @@ def test_project_rejects_bad_arguments(case):
         args["ws_bytes"] = ws_bytes - 1
     elif case == "null_pos":
         args["pos"] = None
+    elif case == "null_opacity":
+        args["opacity"] = None
+    elif case == "misaligned_proj":
+        args["proj"] = ctypes.c_void_p(0x1008)
     elif case == "gauss_no_radius":
         g = L.make_opts(splat=L.SPLAT_GAUSSIAN, max_radius=3.0)
         args["opts"] = ctypes.byref(g)
@@ -91,7 +103,7 @@ def test_blend_rejects_bad_channels_and_dtype():
     c, o = cam(), L.make_opts(tile=8)
     n = 10
     wsb = lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(o))
-    base = [ctypes.byref(c), ctypes.byref(o), n, FAKE, None, FAKE, FAKE]
+    base = [ctypes.byref(c), ctypes.byref(o), n, FAKE, FAKE]
     tail = [None, FAKE, None, FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, wsb, None]
     assert lib.inpc_blend_forward(*base, 0, L.DTYPE_F32, *tail) == L.INPC_ERR_INVALID
     assert lib.inpc_blend_forward(*base, 65, L.DTYPE_F32, *tail) == L.INPC_ERR_INVALID
@@ -105,7 +117,7 @@ def test_backward_rejects_gaussians():
     g = L.make_opts(splat=L.SPLAT_GAUSSIAN, max_radius=2.0)
     n = 10
     wsb = lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(g))
-    st = lib.inpc_blend_backward(ctypes.byref(c), ctypes.byref(g), n, FAKE, FAKE, FAKE, 4,
+    st = lib.inpc_blend_backward(ctypes.byref(c), ctypes.byref(g), n, FAKE, FAKE, 4,
                                  L.DTYPE_F32, None, FAKE, FAKE, None, FAKE, FAKE, FAKE, FAKE,
                                  FAKE, None, FAKE, FAKE, FAKE, None, FAKE, 1 << 20, FAKE, wsb,
                                  None)
@@ -119,7 +131,7 @@ def test_backward_rejects_small_scratch():
     wsb = lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(o))
     need = lib.inpc_backward_scratch_bytes(n, C, ctypes.byref(c), ctypes.byref(o))
     assert need >= n * 4 * 8 * 4
-    args = [ctypes.byref(c), ctypes.byref(o), n, FAKE, FAKE, FAKE, C, L.DTYPE_F32, None, FAKE,
+    args = [ctypes.byref(c), ctypes.byref(o), n, FAKE, FAKE, C, L.DTYPE_F32, None, FAKE,
             FAKE, None, FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, FAKE, None]
     assert lib.inpc_blend_backward(*args, FAKE, need - 1, FAKE, wsb, None) == L.INPC_ERR_INVALID
     assert lib.inpc_blend_backward(*args, None, need, FAKE, wsb, None) == L.INPC_ERR_INVALID
@@ -133,7 +145,7 @@ def test_sort_and_blend_require_lpos_for_bilinear():
     st = lib.inpc_sort(ctypes.byref(c), ctypes.byref(o), n, FAKE, FAKE, None, FAKE, None, FAKE,
                        wsb, None)
     assert st == L.INPC_ERR_INVALID and b"lpos" in lib.inpc_last_error()
-    st = lib.inpc_blend_forward(ctypes.byref(c), ctypes.byref(o), n, FAKE, None, FAKE, FAKE, 4,
+    st = lib.inpc_blend_forward(ctypes.byref(c), ctypes.byref(o), n, FAKE, FAKE, 4,
                                 L.DTYPE_F32, None, FAKE, None, FAKE, None, FAKE, FAKE, FAKE,
                                 None, FAKE, wsb, None)
     assert st == L.INPC_ERR_INVALID and b"lpos" in lib.inpc_last_error()
