@@ -212,10 +212,11 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
  *   grad_uv    [n][2] f32 out (input of inpc_project_backward)
  *   grad_bg    [C] f32 out, or NULL
  *   scratch    device scratch of inpc_backward_scratch_bytes(n, C, ...) bytes
- *              (per-tile shares of the gradients of points split over
- *              several tiles; no floating-point atomics are used, so the
- *              result is deterministic)
- * Every output element is written (zero for culled points).
+ * Every output element is written (zero for culled points and for points no
+ * blended fragment reached).  A point whose footprint lies in one tile gets
+ * its gradient stored by that tile; a point split over several tiles (at
+ * most four) gets each tile's share added with float atomics, so the last
+ * bits of those gradients depend on the order the tiles finish in.
  */
 inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
                                   const float* proj, const void* feat, int32_t C, int32_t dtype,
@@ -228,8 +229,9 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
                                   void* scratch, size_t scratch_bytes, void* ws, size_t ws_bytes,
                                   void* stream);
 
-/* Bytes of the scratch inpc_blend_backward needs for n points and C channels
- * (16 C + 48 bytes or more per point, plus 4 C per tile).  0 if invalid. */
+/* Bytes of the scratch inpc_blend_backward needs for n points and C channels:
+ * 4 C per tile (the per-tile shares of the background gradient).  0 if
+ * invalid. */
 size_t inpc_backward_scratch_bytes(int64_t n, int32_t C, const inpc_camera_t* cam,
                                    const inpc_opts_t* opts);
 

@@ -145,15 +145,10 @@ Ws make_ws(void* ws, int64_t n, const inpc_camera_t* c, const inpc_opts_t* o) {
   return w;
 }
 
-// Backward scratch: visited flags (one word per point), per-(point, tile
-// slot) partial gradients, per-tile background shares.
-size_t scratch_visited_bytes(int64_t n) { return align_up((size_t)n * 4); }
-size_t scratch_partial_bytes(int64_t n, int C) {
-  return align_up((size_t)n * 4 * partial_stride(C) * 4);
-}
+// Backward scratch: the per-tile shares of the background gradient.
 size_t scratch_bytes(int64_t n, int C, const inpc_camera_t* c, const inpc_opts_t* o) {
-  return scratch_visited_bytes(n) + scratch_partial_bytes(n, C) +
-         align_up((size_t)num_tiles(c, o) * C * 4);
+  (void)n;
+  return align_up((size_t)num_tiles(c, o) * C * 4);
 }
 
 // Per-pixel forward state (last position, anchor position, anchor
@@ -425,13 +420,7 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
   a.grad_opacity = grad_opacity;
   a.grad_uv = grad_uv;
   a.grad_bg = grad_bg;
-  a.pstride = partial_stride(C);
-  char* sb = static_cast<char*>(scratch);
-  a.visited = reinterpret_cast<uint32_t*>(sb);
-  a.partial = reinterpret_cast<float*>(sb + scratch_visited_bytes(n));
-  a.bg_partial = grad_bg ? reinterpret_cast<float*>(sb + scratch_visited_bytes(n) +
-                                                    scratch_partial_bytes(n, C))
-                         : nullptr;
+  a.bg_partial = grad_bg ? static_cast<float*>(scratch) : nullptr;
   a.flags = w.flags;
   hipError_t e = launch_blend_backward(a, (hipStream_t)stream);
   return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_blend_backward");

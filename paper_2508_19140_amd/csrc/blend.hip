@@ -29,13 +29,14 @@
 // T_k = T_{k+1} / (1 - alpha_k), starting from the transmittance the forward
 // pass recorded in front of the last blended fragment with T > 0 (so an
 // alpha = 1 fragment never divides by zero).  The per-fragment terms land in
-// per-(copy, corner) LDS slots; one thread per copy then sums its corners.
-// A point that lies in this tile only gets its gradient written directly; a
-// point split over several tiles writes this tile's share into its own slot
-// of a partial buffer.  Every write marks the (point, slot) as visited; a
-// gather pass sums the shares of split points and writes zeros where no
-// blended fragment reached.  No floating-point atomics are used, so the
-// backward pass is deterministic.
+// per-(copy, corner) LDS slots; one thread per copy then sums its corners
+// (the features enter only through G . f at each covered pixel, which the
+// copy's thread forms from registers).  The gradients start at zero; a
+// point that lies in this tile only gets its gradient written directly, a
+// point split over several tiles (about a quarter of them with 8x8 tiles)
+// gets this tile's share added with float atomics, one whole point row per
+// group of lanes (the wavefront-level staging keeps the atomic count at one
+// per 64 / C point rows instead of one per element).
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
@@ -152,6 +153,16 @@ struct RowRegs {
           w[c >> 1] |= (c < C ? v : 0u) << (16 * (c & 1));
         }
       }
+    }
+  }
+
+  __device__ __forceinline__ void to_f32(float (&v)[CP]) const {
+    if constexpr (sizeof(FT) == 4) {
+#pragma unroll
+      for (int c = 0; c < CP; ++c) v[c] = __uint_as_float(w[c]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < CP; ++c) v[c] = half_bits_to_f32<FT>(w[c >> 1] >> (16 * (c & 1)));
     }
   }
 
@@ -292,7 +303,7 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear(BlendArgs a) {
   if (a.flags[kFlagOverflow]) return;
 
   const int tid = threadIdx.x;
-  const uint32_t tile = a.order ? a.order[blockIdx.x] : blockIdx.x;
+  const uint32_t tile = a.order ? a.order[xcd_pos(blockIdx.x, gridDim.x)] : blockIdx.x;
   const int tx = (int)(tile % (uint32_t)a.opts.ntx), ty = (int)(tile / (uint32_t)a.opts.ntx);
   const int lx = tid % T, ly = tid / T;
   const int px = tx * T + lx, py = ty * T + ly;
@@ -424,7 +435,7 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_gauss(BlendArgs a) {
   if (a.flags[kFlagOverflow]) return;
 
   const int tid = threadIdx.x;
-  const uint32_t tile = a.order ? a.order[blockIdx.x] : blockIdx.x;
+  const uint32_t tile = a.order ? a.order[xcd_pos(blockIdx.x, gridDim.x)] : blockIdx.x;
   const int tx = (int)(tile % (uint32_t)a.opts.ntx), ty = (int)(tile / (uint32_t)a.opts.ntx);
   const int px = tx * T + tid % T, py = ty * T + tid / T;
   const bool inside = px < a.cam.W && py < a.cam.H;
@@ -510,21 +521,74 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_gauss(BlendArgs a) {
 // ---------------------------------------------------------------------------
 // Backward, bilinear splats
 // ---------------------------------------------------------------------------
+
+// Adds this tile's gradient share of every copy of the wavefront with
+// `mine` set (points that lie in more than one tile) to the point's
+// gradient with float atomics.  The shares are first staged as rows of
+// CP + 4 floats (features, opacity, u, v, point index) in `tr`, 512 floats
+// owned by this wavefront; then each group of CP lanes adds one row, so
+// that one atomic instruction covers 64 / CP whole feature rows.
+template <int CP>
+__device__ __forceinline__ void add_split_shares(bool mine, uint32_t idx, const float (&g)[CP],
+                                                 float go, float gu, float gv,
+                                                 float* __restrict__ tr, const BlendArgs& a) {
+  constexpr uint32_t RS = CP + 4;
+  constexpr uint32_t ROWS = 512 / RS;
+  constexpr uint32_t PER = 64 / CP;
+  const uint64_t m = __ballot(mine);
+  if (m == 0ull) return;
+  const uint32_t lane = __lane_id();
+  const uint32_t total = (uint32_t)__popcll(m);
+  const uint32_t r = mbcnt64(m);
+  const uint32_t C = (uint32_t)a.C;
+  for (uint32_t b0 = 0; b0 < total; b0 += ROWS) {
+    const uint32_t nb = min(total - b0, ROWS);
+    if (mine && r >= b0 && r < b0 + nb) {
+      float4* d = reinterpret_cast<float4*>(tr + (r - b0) * RS);
+#pragma unroll
+      for (int q = 0; q < CP / 4; ++q)
+        d[q] = make_float4(g[4 * q], g[4 * q + 1], g[4 * q + 2], g[4 * q + 3]);
+      d[CP / 4] = make_float4(go, gu, gv, __uint_as_float(idx));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t c = lane % CP;
+    if (c < C) {
+      for (uint32_t row = lane / CP; row < nb; row += PER) {
+        const uint32_t pidx = __float_as_uint(tr[row * RS + CP + 3]);
+        atomicAdd(a.grad_feat + (size_t)pidx * C + c, tr[row * RS + c]);
+      }
+    }
+    for (uint32_t k = lane; k < 3 * nb; k += 64) {
+      const uint32_t row = k / 3, comp = k - 3 * row;
+      const float* rr = tr + row * RS;
+      const uint32_t pidx = __float_as_uint(rr[CP + 3]);
+      if (comp == 0)
+        atomicAdd(a.grad_opacity + pidx, rr[CP]);
+      else
+        atomicAdd(a.grad_uv + 2 * (size_t)pidx + (comp - 1), rr[CP + comp]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
 template <int T, int CP, typename FT, bool FULL>
 __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
   using G = TileGeom<T>;
   constexpr int NW = G::NW, CH = G::CHUNK, MW = G::MW;
   __shared__ float4 s_geo[CH];
-  __shared__ __align__(16) float s_feat[CH * fpad(CP)];
   __shared__ unsigned long long s_mask[2][G::NTH * MW];
   __shared__ unsigned long long s_need[MW];
-  __shared__ float2 s_acc[CH * 4];                        // per (copy, corner): (T alpha, dL/dalpha)
+  __shared__ float s_gf[CH * 4];                          // per (copy, corner): G . f
+  __shared__ __align__(16) float2 s_acc[CH * 4];  // per (copy, corner): (T alpha, dL/dalpha)
   __shared__ __align__(16) float s_G[G::NTH * fpad(CP)];  // dL/dF of every pixel of the tile
   __shared__ float s_red[NW][CP];
   if (a.flags[kFlagOverflow]) return;
 
   const int tid = threadIdx.x;
-  const uint32_t tile = a.order ? a.order[blockIdx.x] : blockIdx.x;
+  const uint32_t tile = a.order ? a.order[xcd_pos(blockIdx.x, gridDim.x)] : blockIdx.x;
   const int tx = (int)(tile % (uint32_t)a.opts.ntx), ty = (int)(tile / (uint32_t)a.opts.ntx);
   const int lx = tid % T, ly = tid / T;
   const int px = tx * T + lx, py = ty * T + ly;
@@ -555,6 +619,7 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
     for (int q = 0; q < CP / 4; ++q)
       d4[q] = make_float4(Gv[4 * q], Gv[4 * q + 1], Gv[4 * q + 2], Gv[4 * q + 3]);
   }
+  tile_sync<NW>();  // s_G is read by the copies' threads below
 
   // background: this tile's share of sum_p T_final G
   if (a.bg_partial) {
@@ -608,12 +673,33 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
     float ca = 0.f, cb = 0.f, co = 0.f;
     int X0 = 0, Y0 = 0;
     if (cur) {
+      // The replay needs G . f at each covered pixel; the copy's thread forms
+      // these four dot products from its features in registers, so the
+      // features themselves never pass through LDS.
       const Footprint f = bilinear_footprint(pf.p.x, pf.p.y, a.cam.W, a.cam.H);
       ca = f.a; cb = f.b; co = pf.p.z; X0 = f.x0; Y0 = f.y0;
       s_geo[tid] = make_float4(f.a, f.b, pf.p.z, __uint_as_float(pack_xy(f.x0, f.y0)));
-      pf.f.store_f32(&s_feat[tid * fpad(CP)]);
+      float fv[CP];
+      pf.f.to_f32(fv);
+      const int x0 = X0 - tx * T, y0 = Y0 - ty * T;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) s_acc[tid * 4 + k] = make_float2(0.f, 0.f);
+      for (int k = 0; k < 4; ++k) {
+        const int qx = x0 + (k & 1), qy = y0 + (k >> 1);
+        float d = 0.f;
+        if (qx >= 0 && qx < T && qy >= 0 && qy < T) {
+          const float4* gp = reinterpret_cast<const float4*>(s_G + (qy * T + qx) * fpad(CP));
+#pragma unroll
+          for (int q = 0; q < CP / 4; ++q) {
+            const float4 g4 = gp[q];
+            d = fmaf(g4.x, fv[4 * q], d);
+            d = fmaf(g4.y, fv[4 * q + 1], d);
+            d = fmaf(g4.z, fv[4 * q + 2], d);
+            d = fmaf(g4.w, fv[4 * q + 3], d);
+          }
+        }
+        s_gf[tid * 4 + k] = d;
+        s_acc[tid * 4 + k] = make_float2(0.f, 0.f);
+      }
     }
     tile_sync<NW>();
     // coverage of the previous chunk; fetch what it needs while this one is replayed
@@ -653,16 +739,7 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
             Tk = t_anchor;
           else
             Tk = __fdividef(Tcur, om);
-          const float4* fr = reinterpret_cast<const float4*>(&s_feat[kk * fpad(CP)]);
-          float gf = 0.f;
-#pragma unroll
-          for (int q = 0; q < CP / 4; ++q) {
-            const float4 f4 = fr[q];
-            gf = fmaf(Gv[4 * q], f4.x, gf);
-            gf = fmaf(Gv[4 * q + 1], f4.y, gf);
-            gf = fmaf(Gv[4 * q + 2], f4.z, gf);
-            gf = fmaf(Gv[4 * q + 3], f4.w, gf);
-          }
+          const float gf = s_gf[kk * 4 + dy * 2 + dx];
           const float da = Tk * (gf - gB) - GT * Tk * Pi;
           s_acc[kk * 4 + dy * 2 + dx] = make_float2(Tk * al, da);
           gB = fmaf(al, gf, om * gB);
@@ -672,11 +749,11 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
       }
     }
     tile_sync<NW>();
-    if (cur) {
-      float gfeat[CP];
+    float gfeat[CP];
 #pragma unroll
-      for (int c = 0; c < CP; ++c) gfeat[c] = 0.f;
-      float go = 0.f, gu = 0.f, gv = 0.f;
+    for (int c = 0; c < CP; ++c) gfeat[c] = 0.f;
+    float go = 0.f, gu = 0.f, gv = 0.f;
+    if (cur) {
       const int x0 = X0 - tx * T, y0 = Y0 - ty * T;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -701,70 +778,41 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
       }
       gu *= co;
       gv *= co;
-      uint8_t* vis = reinterpret_cast<uint8_t*>(a.visited);
-      if (cur_single) {
+      if (cur_single) {  // the only tile of this point: its whole gradient
         store_row<CP>(a.grad_feat + (size_t)cur_idx * C, gfeat, C);
         a.grad_opacity[cur_idx] = go;
         reinterpret_cast<float2*>(a.grad_uv)[cur_idx] = make_float2(gu, gv);
-        vis[(size_t)cur_idx * 4] = 1;
-      } else {
-        // this tile's slot among the (at most 2 x 2) tiles of the point
-        const int tx0 = max(X0, 0) >> G::SH, ty0 = max(Y0, 0) >> G::SH;
-        const int sx = tx - tx0, sy = ty - ty0;
-        const int slot = (sx | sy) & ~1 ? 0 : sx + 2 * sy;  // always 0..3 for consistent inputs
-        float* dst = a.partial + ((size_t)slot * a.n + cur_idx) * a.pstride;
-        float4* d4 = reinterpret_cast<float4*>(dst);
-#pragma unroll
-        for (int q = 0; q < CP / 4; ++q)
-          d4[q] = make_float4(gfeat[4 * q], gfeat[4 * q + 1], gfeat[4 * q + 2], gfeat[4 * q + 3]);
-        dst[C] = go;
-        dst[C + 1] = gu;
-        dst[C + 2] = gv;
-        vis[(size_t)cur_idx * 4 + slot] = 1;
       }
     }
+    // A point split over several tiles receives this tile's share by float
+    // atomics, staged in this wavefront's quarter of s_acc (whose reads by
+    // the corner sums above are done) so that each atomic instruction covers
+    // whole point rows.
+    add_split_shares<CP>(cur && !cur_single, cur_idx, gfeat, go, gu, gv,
+                         reinterpret_cast<float*>(s_acc) + (tid >> 6) * 512, a);
     tile_sync<NW>();
   }
 }
 
-// Gradients the tiles did not write directly: sums of the per-tile shares
-// of points split over several tiles, zeros for culled points and for
-// points no blended fragment reached.
-template <int CP>
-__global__ __launch_bounds__(256) void k_grad_gather(BlendArgs a) {
-  const int C = a.C;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t nt = a.ntiles[i];
-    const uint32_t v = a.visited[i];
-    if (nt == 1 && v != 0) continue;  // written by its tile
-    float gfeat[CP];
-#pragma unroll
-    for (int c = 0; c < CP; ++c) gfeat[c] = 0.f;
-    float go = 0.f, gu = 0.f, gv = 0.f;
-    if (nt > 1) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (!((v >> (8 * k)) & 0xffu)) continue;
-        const float* src = a.partial + ((size_t)k * a.n + i) * a.pstride;
-        const float4* s4 = reinterpret_cast<const float4*>(src);
-#pragma unroll
-        for (int q = 0; q < CP / 4; ++q) {
-          const float4 x = s4[q];
-          gfeat[4 * q] += x.x;
-          gfeat[4 * q + 1] += x.y;
-          gfeat[4 * q + 2] += x.z;
-          gfeat[4 * q + 3] += x.w;
-        }
-        go += src[C];
-        gu += src[C + 1];
-        gv += src[C + 2];
-      }
-    }
-    store_row<CP>(a.grad_feat + (size_t)i * C, gfeat, C);
-    a.grad_opacity[i] = go;
-    reinterpret_cast<float2*>(a.grad_uv)[i] = make_float2(gu, gv);
-  }
+// Zero n floats at p (4-byte aligned): 16-byte stores for the aligned body.
+__global__ __launch_bounds__(256) void k_zero(float* __restrict__ p, size_t n) {
+  const size_t mis = (size_t)(reinterpret_cast<uintptr_t>(p) & 15u);
+  const size_t head = min(n, ((16u - mis) & 15u) / 4u);
+  const size_t nv = (n - head) / 4u;
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  if (tid < head) p[tid] = 0.f;
+  uint4* v = reinterpret_cast<uint4*>(p + head);
+  for (size_t i = tid; i < nv; i += stride) v[i] = make_uint4(0u, 0u, 0u, 0u);
+  const size_t tail0 = head + nv * 4u;
+  if (tid < n - tail0) p[tail0 + tid] = 0.f;
+}
+
+hipError_t launch_zero(float* p, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t g = std::min<size_t>((n / 4 + 255) / 256 + 1, 2048);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)g), dim3(256), 0, s, p, n);
+  return hipGetLastError();
 }
 
 // grad_bg[c] = sum over tiles of the per-tile shares (one block per channel).
@@ -804,7 +852,11 @@ hipError_t fwd_launch(const BlendArgs& a, hipStream_t s) {
 template <int T, int CP, typename FT>
 hipError_t bwd_launch(const BlendArgs& a, hipStream_t s) {
   const int64_t nt = (int64_t)a.opts.ntx * a.opts.nty;
-  hipError_t e = launch_clear(a.visited, (size_t)a.n, s);
+  // Every gradient starts at zero: points no blended fragment reached keep
+  // it, single-tile points are overwritten, split points are added to.
+  hipError_t e = launch_zero(a.grad_feat, (size_t)a.n * a.C, s);
+  if (e == hipSuccess) e = launch_zero(a.grad_opacity, (size_t)a.n, s);
+  if (e == hipSuccess) e = launch_zero(a.grad_uv, (size_t)a.n * 2, s);
   if (e != hipSuccess) return e;
   if (a.C == CP)
     hipLaunchKernelGGL((k_blend_bwd_bilinear<T, CP, FT, true>), dim3((unsigned)nt), dim3(T * T), 0,
@@ -814,12 +866,6 @@ hipError_t bwd_launch(const BlendArgs& a, hipStream_t s) {
                        0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (a.n > 0) {
-    const int64_t g = std::min<int64_t>((a.n + 255) / 256, 1 << 16);
-    hipLaunchKernelGGL((k_grad_gather<CP>), dim3((unsigned)g), dim3(256), 0, s, a);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
   if (a.grad_bg)
     hipLaunchKernelGGL(k_bg_reduce, dim3((unsigned)a.C), dim3(256), 0, s, a.bg_partial, nt, a.C,
                        a.grad_bg);

@@ -212,6 +212,17 @@ __device__ __forceinline__ Footprint footprint(const Opts& o, const Cam& c, floa
                                                              o.cutoff);
 }
 
+// Position in a tile order handled by workgroup b of an nb-workgroup launch.
+// Workgroups go to the 8 XCDs round-robin (workgroup b to XCD b mod 8) and
+// every XCD has an L2 of its own; this mapping gives each XCD runs of four
+// consecutive order positions (within every 32 consecutive workgroups, so the
+// start of the order still starts first), a bijection on [0, nb).
+__device__ __forceinline__ uint32_t xcd_pos(uint32_t b, uint32_t nb) {
+  if (b >= (nb & ~31u)) return b;
+  const uint32_t r = b & 31u;
+  return (b & ~31u) | ((r & 7u) << 2) | (r >> 3);
+}
+
 // Wave-wide helpers (wave64).
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 

@@ -29,7 +29,6 @@ struct BlendArgs {
   uint32_t* st_anchor;  // [P] one past the position of the last blended fragment with T > 0
   float* st_tanchor;    // [P] transmittance in front of that fragment
   uint32_t* st_tile;    // [nt] largest st_last over the tile's pixels
-  uint32_t* visited;    // [n] backward: byte k set when tile slot k wrote the point's gradient
   // backward
   const uint32_t* ntiles;
   const float* grad_out;
@@ -38,21 +37,12 @@ struct BlendArgs {
   float* grad_opacity;
   float* grad_uv;
   float* grad_bg;
-  float* partial;     // [4][n][pstride] per-(tile slot, point) gradients of multi-tile points
   float* bg_partial;  // [num_tiles][C] per-tile background gradients
-  int pstride;        // floats per partial record (C + 3 rounded up to 4)
   const uint32_t* flags;
 };
 
 // Channel capacity of the kernel instantiation used for C channels.
 inline int channel_capacity(int C) { return C <= 4 ? 4 : (C <= 8 ? 8 : (C <= 16 ? 16 : 32)); }
-
-// Floats per partial gradient record: C features, opacity, u, v; at least
-// the channel capacity (records are written with 16-byte stores).
-inline int partial_stride(int C) {
-  const int s = (C + 3 + 3) / 4 * 4;
-  return s > channel_capacity(C) ? s : channel_capacity(C);
-}
 
 hipError_t launch_clear(uint32_t* p, size_t n, hipStream_t s);
 hipError_t launch_project(const Cam& cam, const Opts& o, int64_t n, const float* pos,

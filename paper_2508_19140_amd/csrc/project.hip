@@ -153,8 +153,18 @@ __device__ __forceinline__ uint64_t match6(uint32_t k) {
 }
 
 // Blend-order class of a tile: 0 = longest lists ... 31 = one copy, 32 =
-// empty; 33 marks a lane without a tile.
-__device__ __forceinline__ uint32_t order_class(uint32_t c) { return c ? (uint32_t)__clz(c) : 32u; }
+// empty; 33 marks a lane without a tile.  A tile takes the class of the
+// longest list among the four tiles of its aligned quad (tile indices 4k ..
+// 4k + 3, side by side in a row), so that the four are consecutive in the
+// blend order: they then run on one XCD together (see xcd_pos) and share
+// the L2 lines of the image rows they read and write.  Every lane of the
+// wavefront takes part (lane = tile index mod 64).
+__device__ __forceinline__ uint32_t order_class(bool valid, uint32_t c) {
+  uint32_t q = valid ? c : 0u;
+  q = max(q, (uint32_t)__shfl_xor((int)q, 1, 64));
+  q = max(q, (uint32_t)__shfl_xor((int)q, 2, 64));
+  return valid ? (q ? (uint32_t)__clz(q) : 32u) : 33u;
+}
 
 // Tiles are handled in groups of 64 (one wavefront, lane = tile).  Per
 // group the count pass leaves its copies, its tiles per sort class and its
@@ -174,7 +184,7 @@ __device__ __forceinline__ void group_table(int64_t g, bool valid, uint32_t c, c
   uint32_t cls[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) cls[q] = (uint32_t)__popcll(__ballot(sc == q));
-  const uint32_t k = valid ? order_class(c) : 33u;
+  const uint32_t k = order_class(valid, c);
   const uint64_t m = match6(k);
   if (lane < kOrderClasses) s_hist[lane] = 0u;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -336,7 +346,7 @@ __global__ __launch_bounds__(64) void k_place(int64_t nt, const uint32_t* __rest
     // first order position of each class: exclusive scan of the class totals
     const uint32_t tk = lane < 33u ? (uint32_t)ws.coltot[5 + lane] : 0u;
     const uint32_t kbase = (uint32_t)wave_incl_scan_u64(tk, lane) - tk;
-    const uint32_t k = valid ? order_class(c) : 33u;
+    const uint32_t k = order_class(valid, c);
     const uint64_t m = match6(k);
     const uint32_t cb = (uint32_t)__shfl((int)kbase, (int)(k < 33u ? k : 0u), 64);
     if (k < 33u)
@@ -384,6 +394,34 @@ __global__ __launch_bounds__(kBinBlock) void k_scatter(Cam cam, Opts o, int64_t 
       nts[q] = ntiles[j];
       ps[q] = proj[j];
       ks[q] = key[j];
+    }
+    if (o.splat == INPC_SPLAT_BILINEAR) {
+      // At most 2 x 2 tiles per point: every slot of the round is reserved
+      // (independent LDS atomics, all in flight together) before the first
+      // copy is stored.
+      uint32_t slot[kUnroll][4], word[kUnroll][4];
+      bool put[kUnroll][4];
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) {
+        const int64_t i = i0 + (int64_t)q * kBinBlock;
+        const bool live = i < c.end && nts[q] != 0;
+        const Footprint f = bilinear_footprint(ps[q].x, ps[q].y, cam.W, cam.H);
+        const TileRect r = tile_rect(f, sh);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int tx = r.tx0 + (k & 1), ty = r.ty0 + (k >> 1);
+          put[q][k] = live && tx <= r.tx1 && ty <= r.ty1;
+          slot[q][k] = put[q][k] ? atomicAdd(&bins[ty * o.ntx + tx], 1u) : 0u;
+          word[q][k] = entry_word(f, i, tx, ty, o.T, lbits, pb);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          // always in range when the counts of step 1 hold
+          if (put[q][k] && slot[q][k] < cap) bucket[slot[q][k]] = make_uint2(ks[q], word[q][k]);
+      continue;
     }
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) {

@@ -23,8 +23,8 @@
 //               memory.
 //   larger      LSD radix sort through global memory by a 1024-thread block.
 //
-// The LSD sorts rank elements inside a wavefront with 8 ballots per element
-// (the lanes sharing a digit), so no order is decided by an atomic.  They
+// The LSD sorts rank elements inside a wavefront with one ballot per digit
+// bit (the lanes sharing a digit), so no order is decided by an atomic.  They
 // run on the depth key minus the segment's smallest key; equal keys are then
 // put in index order, and a segment with a long run of equal keys is re-sorted
 // on the full (key, index) pair.  Element placement by LDS atomics happens only
@@ -48,14 +48,17 @@ __device__ __forceinline__ void bsync() {
   }
 }
 
-// Lanes of the wave whose 8-bit digit equals this lane's.
-__device__ __forceinline__ uint64_t match8(uint32_t d) {
+// Lanes of the wave whose digit (the low `width` <= 8 bits of d, the rest
+// zero) equals this lane's.  `width` is the same for every lane.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, int width) {
   uint64_t m = ~0ull;
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t bal = __ballot(bit);
-    m &= bit ? bal : ~bal;
+    if (b < width) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
+      m &= bit ? bal : ~bal;
+    }
   }
   return m;
 }
@@ -89,12 +92,27 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 
 __device__ __forceinline__ uint32_t nbits(uint32_t range) { return range ? 32u - __clz(range) : 0u; }
 
+// LSD digits of one segment: first the passes over (idx - imin), then over
+// (key - kmin).  A field of B bits takes ceil(B / 8) passes of equal width
+// (at most 8 bits), so a 25-bit key range costs 25 ballots, not 32.
 struct Digits {
-  int nidx;        // passes over (idx - imin) digits, run first
-  int nkey;        // passes over (key - kmin) digits
+  int nidx, nkey;  // passes over the index and the key fields
+  int widx, wkey;  // bits per pass of each field
   uint32_t imin, kmin;
+  __device__ __forceinline__ void set_key(uint32_t range) {
+    const uint32_t b = nbits(range);
+    nkey = (int)((b + 7) / 8);
+    wkey = nkey ? (int)((b + nkey - 1) / nkey) : 0;
+  }
+  __device__ __forceinline__ void set_idx(uint32_t range) {
+    const uint32_t b = nbits(range);
+    nidx = (int)((b + 7) / 8);
+    widx = nidx ? (int)((b + nidx - 1) / nidx) : 0;
+  }
+  __device__ __forceinline__ int width(int p) const { return p < nidx ? widx : wkey; }
   __device__ __forceinline__ uint32_t get(uint32_t key, uint32_t idx, int p) const {
-    return p < nidx ? ((idx - imin) >> (8 * p)) & 255u : ((key - kmin) >> (8 * (p - nidx))) & 255u;
+    if (p < nidx) return ((idx - imin) >> (widx * p)) & ((1u << widx) - 1u);
+    return ((key - kmin) >> (wkey * (p - nidx))) & ((1u << wkey) - 1u);
   }
   __device__ __forceinline__ int passes() const { return nidx + nkey; }
 };
@@ -108,14 +126,16 @@ struct SortSmem {
   uint32_t* red;   // [64] reduction scratch
 };
 
-// Rank every element among the NW*ITEMS*64 striped elements by digit,
-// stably.  Element (w, j, lane) has position w*ITEMS*64 + j*64 + lane.
-// With `running`, digit bases come from sm.off (and are advanced by this
-// round's totals); otherwise they are the exclusive scan of the totals.
+// Rank every element among the NW*ni*64 striped elements by its digit of
+// `width` bits, stably.  Element (w, j, lane) has position w*ni*64 + j*64 +
+// lane; items j >= ni (ni <= ITEMS, the same for the whole block) hold no
+// element and are skipped.  With `running`, digit bases come from sm.off
+// (and are advanced by this round's totals); otherwise they are the
+// exclusive scan of the totals.
 template <int NW, int ITEMS, bool WAVE_ONLY>
 __device__ __forceinline__ void block_rank(const uint32_t (&d)[ITEMS], const bool (&valid)[ITEMS],
                                            uint32_t (&rank)[ITEMS], const SortSmem& sm,
-                                           bool running) {
+                                           bool running, int ni, int width) {
   const uint32_t lane = __lane_id();
   const uint32_t w = WAVE_ONLY ? 0u : (threadIdx.x >> 6);
   uint32_t* hist = sm.hist + w * 256;
@@ -123,7 +143,8 @@ __device__ __forceinline__ void block_rank(const uint32_t (&d)[ITEMS], const boo
   bsync<true>();
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
-    const uint64_t m = match8(d[j]) & __ballot(valid[j]);
+    if (j >= ni) break;
+    const uint64_t m = match_digit(d[j], width) & __ballot(valid[j]);
     const uint32_t pre = valid[j] ? hist[d[j]] : 0u;
     rank[j] = pre + mbcnt64(m);
     const bool leader = valid[j] && (mbcnt64(m) == 0);
@@ -179,14 +200,16 @@ __device__ __forceinline__ void block_rank(const uint32_t (&d)[ITEMS], const boo
 }
 
 // Sort n <= NW*ITEMS*64 (key, idx) pairs of one segment entirely in LDS and
-// write the point indices in (key, idx) order to out[0..n).
+// write the point indices in (key, idx) order to out[0..n).  Each wave holds
+// ni = ceil(n / (64 NW)) items per lane, so the ranking work follows the
+// segment's size rather than the block's capacity.
 template <int NW, int ITEMS, bool WAVE_ONLY>
 __device__ void sort_segment_lds(const uint2* __restrict__ seg, uint32_t n, const ListOut& out,
                                  uint32_t base, const SortSmem& sm) {
-  constexpr int PER_WAVE = ITEMS * 64;
   const uint32_t lane = __lane_id();
   const uint32_t w = WAVE_ONLY ? 0u : (threadIdx.x >> 6);
-  const uint32_t base_e = w * PER_WAVE;
+  const int ni = (int)((n + NW * 64 - 1) / (NW * 64));  // <= ITEMS as n <= NW*ITEMS*64
+  const uint32_t base_e = w * (uint32_t)ni * 64u;
   const int nth = WAVE_ONLY ? 64 : NW * 64;
   const int tid = WAVE_ONLY ? (int)lane : (int)threadIdx.x;
 
@@ -196,7 +219,7 @@ __device__ void sort_segment_lds(const uint2* __restrict__ seg, uint32_t n, cons
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     const uint32_t e = base_e + j * 64 + lane;
-    valid[j] = e < n;
+    valid[j] = j < ni && e < n;
     const uint2 v = valid[j] ? seg[e] : make_uint2(0u, 0u);
     key[j] = v.x;
     idx[j] = v.y;
@@ -224,8 +247,8 @@ __device__ void sort_segment_lds(const uint2* __restrict__ seg, uint32_t n, cons
   Digits dp;
   dp.kmin = kmin;
   dp.imin = imin;
-  dp.nkey = (int)((nbits(kmax - kmin) + 7) / 8);
-  dp.nidx = 0;
+  dp.set_key(kmax - kmin);
+  dp.nidx = dp.widx = 0;
 
   for (int attempt = 0; attempt < 2; ++attempt) {
     if (attempt == 1) {
@@ -238,13 +261,13 @@ __device__ void sort_segment_lds(const uint2* __restrict__ seg, uint32_t n, cons
         key[j] = v.x;
         idx[j] = v.y;
       }
-      dp.nidx = (int)((nbits(imax - imin) + 7) / 8);
+      dp.set_idx(imax - imin);
     }
     const int np = dp.passes();
     for (int p = 0; p < np; ++p) {
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j) dg[j] = dp.get(key[j], idx[j], p);
-      block_rank<NW, ITEMS, WAVE_ONLY>(dg, valid, rank, sm, false);
+      block_rank<NW, ITEMS, WAVE_ONLY>(dg, valid, rank, sm, false, ni, dp.width(p));
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j) {
         if (valid[j]) {
@@ -531,8 +554,8 @@ __global__ __launch_bounds__(NW * 64) void k_sort_x(Ws ws, ListOut out) {
     Digits dp;
     dp.kmin = kmin;
     dp.imin = imin;
-    dp.nkey = (int)((nbits(kmax - kmin) + 7) / 8);
-    dp.nidx = (int)((nbits(imax - imin) + 7) / 8);
+    dp.set_key(kmax - kmin);
+    dp.set_idx(imax - imin);
     const int np = dp.passes();
     uint2* src = ws.bucket + s;
     uint2* dst = ws.xbucket + s;
@@ -563,7 +586,7 @@ __global__ __launch_bounds__(NW * 64) void k_sort_x(Ws ws, ListOut out) {
           v[j] = valid[j] ? src[e] : make_uint2(0u, 0u);
           dg[j] = dp.get(v[j].x, v[j].y, p);
         }
-        block_rank<NW, ITEMS, false>(dg, valid, rank, sm, true);
+        block_rank<NW, ITEMS, false>(dg, valid, rank, sm, true, ITEMS, dp.width(p));
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
           if (valid[j]) {

@@ -73,9 +73,14 @@ def assert_binning_exact(g, proj, tl):
     np.testing.assert_array_equal(g["ranges"].astype(np.int64), tl["ranges"])
     M = int(tl["ranges"][-1])
     np.testing.assert_array_equal(g["list"][:M], tl["list"])
-    # blend order: decreasing power-of-two class of the copy count, then tile index
+    # blend order: decreasing power-of-two class of the longest copy count in
+    # the tile's aligned quad (tile indices 4k .. 4k+3), then tile index
     counts = np.diff(tl["ranges"])
-    klass = np.array([32 - int(c).bit_length() for c in counts], np.int64)
+    nq = (len(counts) + 3) // 4
+    quad = np.zeros(nq * 4, np.int64)
+    quad[:len(counts)] = counts
+    qmax = np.repeat(quad.reshape(nq, 4).max(axis=1), 4)[:len(counts)]
+    klass = np.array([32 - int(c).bit_length() for c in qmax], np.int64)
     np.testing.assert_array_equal(g["order"][:len(counts)], np.lexsort((np.arange(len(counts)), klass)))
     if g.get("lpos") is not None:
         assert_lpos(g, proj, tl)

@@ -1,6 +1,8 @@
 """Many views in one graph launch: the autotuned, graph-captured batch gives
-the same bits as every view run on its own (all kernels are deterministic),
-on every replay, and matches the oracle per view."""
+the same result as every view run on its own, on every replay, and matches
+the oracle per view.  Forward outputs are deterministic and compared bit for
+bit; gradients of points split over several tiles are summed with float
+atomics in arrival order, so they are compared to rounding."""
 import numpy as np
 import pytest
 import torch
@@ -46,7 +48,13 @@ def test_graph_batch_matches_single_views_and_oracle():
         got = _snapshot(mv)
         for v, (g, r) in enumerate(zip(got, ref)):
             for k in r:
-                np.testing.assert_array_equal(g[k], r[k], err_msg=f"replay {rep} view {v} {k}")
+                if k.startswith("grad"):
+                    # at most four shares per element, added in any order
+                    tol = 1e-6 * float(np.abs(r[k]).max(initial=0.0)) + 1e-7
+                    np.testing.assert_allclose(g[k], r[k], rtol=1e-5, atol=tol,
+                                               err_msg=f"replay {rep} view {v} {k}")
+                else:
+                    np.testing.assert_array_equal(g[k], r[k], err_msg=f"replay {rep} view {v} {k}")
         # eager work between replays
         torch.ones(1 << 20, device=DEV).sum().item()
     # per-view parity with the oracle
