@@ -423,6 +423,223 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear(BlendArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Forward, bilinear splats, 8x8 tiles: sparse compaction of long lists
+// ---------------------------------------------------------------------------
+//
+// In the longest lists most pixels terminate early while a few (pixels the
+// tile's surface barely covers) stay open to the last copy, so the chunk
+// loop above walks thousands of copies for a handful of fragments, paying a
+// memory round trip per 64 copies.  Here the list is read in super-chunks
+// of 512 positions (index and 2x2 position only, prefetched one super-chunk
+// ahead); from each copy's position alone the wavefront knows which copies
+// cover a pixel still blending, compacts those in list order into virtual
+// chunks of 64, and fetches and blends only them.  A super-chunk whose
+// pixels are all open is eight full virtual chunks (the point data of the
+// next is fetched while the current one blends); in the sparse tail a
+// super-chunk is one short virtual chunk.
+
+constexpr int kSubs = 8;  // chunks of 64 list positions per super-chunk
+
+// Pixels (bit ly * 8 + lx) of an 8x8 tile covered by the 2x2 splat whose
+// tile-local corner code is lp (x0 + 1 | (y0 + 1) << 8, x0, y0 in [-1, 7]).
+__device__ __forceinline__ uint64_t splat_pixels8(uint32_t lp) {
+  const int x0 = (int)(lp & 0xffu) - 1, y0 = (int)(lp >> 8) - 1;
+  const uint64_t r = (uint64_t)(((3u << (x0 + 1)) >> 1) & 0xffu);
+  uint64_t m = 0;
+  if (y0 >= 0) m |= r << (8 * y0);
+  if (y0 <= 6) m |= r << (8 * (y0 + 1));
+  return m;
+}
+
+// List entries (point index, 2x2 position) of a super-chunk: position
+// base + j * 64 + lane for j < kSubs.
+struct SuperEntries {
+  uint32_t idx[kSubs], lp[kSubs];
+  __device__ __forceinline__ void load(const BlendArgs& a, uint32_t base, uint32_t end) {
+    const uint32_t lane = __lane_id();
+#pragma unroll
+    for (int j = 0; j < kSubs; ++j) {
+      const uint32_t q = base + (uint32_t)j * 64u + lane;
+      const uint32_t qq = q < end ? q : end - 1;  // end > base
+      idx[j] = a.list[qq];
+      lp[j] = a.lpos[qq];
+    }
+  }
+};
+
+// Copies of a super-chunk that cover a pixel in `act`, compacted in list
+// order: ballot per chunk and the running count before it.
+struct Compaction {
+  uint64_t need[kSubs];
+  uint32_t before[kSubs];
+  uint32_t total;
+  __device__ __forceinline__ void build(const SuperEntries& e, uint32_t base, uint32_t end,
+                                        const uint64_t (&act)[kSubs]) {
+    const uint32_t lane = __lane_id();
+    total = 0;
+#pragma unroll
+    for (int j = 0; j < kSubs; ++j) {
+      const bool valid = base + (uint32_t)j * 64u + lane < end;
+      need[j] = __ballot(valid && (splat_pixels8(e.lp[j]) & act[j]) != 0ull);
+      before[j] = total;
+      total += (uint32_t)__popcll(need[j]);
+    }
+  }
+  // Writes the selected copies with compacted rank in [vb, vb + 64) to
+  // sel[rank - vb] as (point index, lp | offset in the super-chunk << 16).
+  __device__ __forceinline__ void publish(const SuperEntries& e, uint32_t vb,
+                                          uint2* __restrict__ sel) const {
+    const uint32_t lane = __lane_id();
+#pragma unroll
+    for (int j = 0; j < kSubs; ++j) {
+      if ((need[j] >> lane) & 1ull) {
+        const uint32_t r = before[j] + mbcnt64(need[j]) - vb;
+        if (r < 64u) sel[r] = make_uint2(e.idx[j], e.lp[j] | (((uint32_t)j * 64u + lane) << 16));
+      }
+    }
+  }
+};
+
+template <int CP, typename FT, bool FULL>
+__global__ __launch_bounds__(64) void k_blend_fwd_bilinear8(BlendArgs a) {
+  constexpr int T = 8;
+  constexpr uint32_t SC = kSubs * 64;
+  __shared__ float4 s_geo[64];
+  __shared__ __align__(16) float s_feat[64 * fpad(CP)];
+  __shared__ unsigned long long s_mask[64];
+  __shared__ uint2 s_sel[64];
+  __shared__ uint32_t s_q1[64];  // one past the copy's position in the tile list
+  if (a.flags[kFlagOverflow]) return;
+
+  const uint32_t lane = threadIdx.x;
+  const uint32_t tile = a.order ? a.order[xcd_pos(blockIdx.x, gridDim.x)] : blockIdx.x;
+  const int tx = (int)(tile % (uint32_t)a.opts.ntx), ty = (int)(tile / (uint32_t)a.opts.ntx);
+  const int px = tx * T + (int)(lane % T), py = ty * T + (int)(lane / T);
+  const bool inside = px < a.cam.W && py < a.cam.H;
+  const uint32_t start = a.ranges[tile], end = a.ranges[tile + 1];
+  const float t_min = a.opts.t_min;
+
+  float F[CP];
+#pragma unroll
+  for (int c = 0; c < CP; ++c) F[c] = 0.f;
+  float Tr = 1.f, t_anchor = 1.f;
+  uint32_t cnt = 0, last = 0, anchor = 0;
+  bool done = !inside;
+
+  SuperEntries nxt;
+  if (end > start) nxt.load(a, start, end);
+  for (uint32_t base = start; base < end; base += SC) {
+    const uint64_t open = __ballot(!done);
+    if (open == 0ull) break;
+    const SuperEntries cur = nxt;
+    if (base + SC < end) nxt.load(a, base + SC, end);
+    uint64_t act[kSubs];
+#pragma unroll
+    for (int j = 0; j < kSubs; ++j) act[j] = open;
+    Compaction cp;
+    cp.build(cur, base, end, act);
+    const uint32_t nvc = (cp.total + 63u) / 64u;
+    Prefetch<CP, FT, FULL> pf;
+    uint32_t plp = 0, pq1 = 0;
+    if (nvc > 0) {
+      cp.publish(cur, 0, s_sel);
+      tile_sync<1>();
+      const bool has = lane < cp.total;
+      const uint2 sl = has ? s_sel[lane] : make_uint2(0u, 0u);
+      pf.fetch(a, has, sl.x);
+      plp = sl.y & 0xffffu;
+      pq1 = base - start + (sl.y >> 16) + 1u;
+      tile_sync<1>();
+    }
+    for (uint32_t v = 0; v < nvc; ++v) {
+      if (__ballot(!done) == 0ull) break;
+      // stage virtual chunk v and its coverage
+      s_mask[lane] = 0ull;
+      tile_sync<1>();
+      if (pf.valid) {
+        const Footprint f = bilinear_footprint(pf.p.x, pf.p.y, a.cam.W, a.cam.H);
+        s_geo[lane] = make_float4(f.a, f.b, pf.p.z, __uint_as_float(pack_xy(f.x0, f.y0)));
+        pf.f.store_f32(&s_feat[lane * fpad(CP)]);
+        s_q1[lane] = pq1;
+        uint64_t pm = splat_pixels8(plp);
+        const unsigned long long bit = 1ull << lane;
+        while (pm) {
+          const int b = __ffsll((unsigned long long)pm) - 1;
+          pm &= pm - 1ull;
+          atomicOr(&s_mask[b], bit);
+        }
+      }
+      tile_sync<1>();
+      // fetch virtual chunk v + 1 while v blends
+      if (v + 1 < nvc) {
+        cp.publish(cur, (v + 1) * 64u, s_sel);
+        tile_sync<1>();
+        const bool has = (v + 1) * 64u + lane < cp.total;
+        const uint2 sl = has ? s_sel[lane] : make_uint2(0u, 0u);
+        pf.fetch(a, has, sl.x);
+        plp = sl.y & 0xffffu;
+        pq1 = base - start + (sl.y >> 16) + 1u;
+      }
+      if (!done) {
+        unsigned long long m = s_mask[lane];
+        while (m) {
+          const int kk = __ffsll(m) - 1;
+          m &= m - 1;
+          const float4 g = s_geo[kk];
+          const uint32_t pk = __float_as_uint(g.w);
+          const int dx = px - unpack_x(pk), dy = py - unpack_y(pk);
+          const float wx = dx ? g.x : fsub(1.f, g.x);
+          const float wy = dy ? g.y : fsub(1.f, g.y);
+          const float al = fmul(g.z, fmul(wx, wy));
+          if (Tr < t_min) {
+            done = true;
+            break;
+          }
+          const float wt = Tr * al;
+          const float4* fr = reinterpret_cast<const float4*>(&s_feat[kk * fpad(CP)]);
+#pragma unroll
+          for (int q = 0; q < CP / 4; ++q) {
+            const float4 f4 = fr[q];
+            F[4 * q] = fmaf(wt, f4.x, F[4 * q]);
+            F[4 * q + 1] = fmaf(wt, f4.y, F[4 * q + 1]);
+            F[4 * q + 2] = fmaf(wt, f4.z, F[4 * q + 2]);
+            F[4 * q + 3] = fmaf(wt, f4.w, F[4 * q + 3]);
+          }
+          const uint32_t q1 = s_q1[kk];
+          if (Tr > 0.f) {
+            anchor = q1;
+            t_anchor = Tr;
+          }
+          Tr = fmul(Tr, fsub(1.f, al));
+          ++cnt;
+          last = q1;
+        }
+      }
+      tile_sync<1>();
+    }
+  }
+  if (a.st_tile) {
+    uint32_t ml = last;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) ml = max(ml, (uint32_t)__shfl_xor((int)ml, o, 64));
+    if (lane == 0) a.st_tile[tile] = ml;
+  }
+  if (!inside) return;
+  const int64_t P = (int64_t)a.cam.W * a.cam.H;
+  const int64_t p = (int64_t)py * a.cam.W + px;
+#pragma unroll
+  for (int c = 0; c < CP; ++c)
+    if (c < a.C) a.out[c * P + p] = a.bg ? fmaf(Tr, a.bg[c], F[c]) : F[c];
+  a.t_final[p] = Tr;
+  a.n_contrib[p] = cnt;
+  if (a.st_last) {
+    a.st_last[p] = last;
+    a.st_anchor[p] = anchor;
+    a.st_tanchor[p] = t_anchor;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Forward, screen-space Gaussians (inference)
 // ---------------------------------------------------------------------------
 template <int T, int CP, typename FT, bool FULL>
@@ -794,6 +1011,222 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
   }
 }
 
+// Backward for 8x8 tiles with the sparse compaction of the forward: the
+// part of the list the forward reached is read in super-chunks from the back;
+// the copies covering a pixel whose blended range reaches them are compacted
+// in list order and replayed in reverse, one virtual chunk of 64 at a time
+// (the previous virtual chunk's point data is fetched during the replay).
+template <int CP, typename FT, bool FULL>
+__global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
+  constexpr int T = 8;
+  constexpr uint32_t SC = kSubs * 64;
+  __shared__ float4 s_geo[64];
+  __shared__ unsigned long long s_mask[64];
+  __shared__ uint2 s_sel[64];
+  __shared__ uint32_t s_q1[64];
+  __shared__ float s_gf[64 * 4];                  // per (copy, corner): G . f
+  __shared__ __align__(16) float2 s_acc[64 * 4];  // per (copy, corner): (T alpha, dL/dalpha)
+  __shared__ __align__(16) float s_G[64 * fpad(CP)];
+  if (a.flags[kFlagOverflow]) return;
+
+  const uint32_t lane = threadIdx.x;
+  const uint32_t tile = a.order ? a.order[xcd_pos(blockIdx.x, gridDim.x)] : blockIdx.x;
+  const int tx = (int)(tile % (uint32_t)a.opts.ntx), ty = (int)(tile / (uint32_t)a.opts.ntx);
+  const int px = tx * T + (int)(lane % T), py = ty * T + (int)(lane / T);
+  const bool inside = px < a.cam.W && py < a.cam.H;
+  const uint32_t start = a.ranges[tile], end = a.ranges[tile + 1];
+  const int64_t P = (int64_t)a.cam.W * a.cam.H;
+  const int64_t p = (int64_t)py * a.cam.W + px;
+  const int C = a.C;
+
+  float gB = 0.f, GT = 0.f, Tf = 0.f, t_anchor = 0.f;
+  uint32_t last = 0, anchor = 0;
+  {
+    float Gv[CP];
+#pragma unroll
+    for (int c = 0; c < CP; ++c) Gv[c] = (inside && c < C) ? a.grad_out[c * P + p] : 0.f;
+    if (inside) {
+      GT = a.grad_t ? a.grad_t[p] : 0.f;
+      last = a.st_last[p];
+      anchor = a.st_anchor[p];
+      t_anchor = a.st_tanchor[p];
+      Tf = a.t_final[p];
+      if (a.bg)
+        for (int c = 0; c < C; ++c) gB = fmaf(Gv[c], a.bg[c], gB);
+    }
+    float4* d4 = reinterpret_cast<float4*>(s_G + lane * fpad(CP));
+#pragma unroll
+    for (int q = 0; q < CP / 4; ++q)
+      d4[q] = make_float4(Gv[4 * q], Gv[4 * q + 1], Gv[4 * q + 2], Gv[4 * q + 3]);
+    // background: this tile's share of sum_p T_final G
+    if (a.bg_partial) {
+#pragma unroll
+      for (int c = 0; c < CP; ++c) {
+        float v = Tf * Gv[c];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0 && c < C) a.bg_partial[(size_t)tile * C + c] = v;
+      }
+    }
+  }
+  tile_sync<1>();  // s_G is read by the copies' lanes below
+
+  // the forward pass blended nothing beyond list position st_tile[tile]
+  const uint32_t maxlast = min(a.st_tile[tile], end - start);
+  const uint32_t lend = start + maxlast;
+  float Pi = 1.f, Tcur = 0.f;
+  const int nsc = (int)((maxlast + SC - 1) / SC);
+  for (int k = nsc - 1; k >= 0; --k) {
+    const uint32_t base = start + (uint32_t)k * SC;
+    SuperEntries cur;
+    cur.load(a, base, lend);
+    // a pixel takes part in chunk j if its blended range reaches the chunk
+    uint64_t act[kSubs];
+#pragma unroll
+    for (int j = 0; j < kSubs; ++j) act[j] = __ballot(last > base - start + (uint32_t)j * 64u);
+    Compaction cp;
+    cp.build(cur, base, lend, act);
+    const int nvc = (int)((cp.total + 63u) / 64u);
+    Prefetch<CP, FT, FULL> pf;
+    uint32_t plp = 0, pq1 = 0;
+    if (nvc > 0) {
+      const uint32_t vb = (uint32_t)(nvc - 1) * 64u;
+      cp.publish(cur, vb, s_sel);
+      tile_sync<1>();
+      const bool has = vb + lane < cp.total;
+      const uint2 sl = has ? s_sel[lane] : make_uint2(0u, 0u);
+      pf.fetch(a, has, sl.x);
+      plp = sl.y & 0xffffu;
+      pq1 = base - start + (sl.y >> 16) + 1u;
+      tile_sync<1>();
+    }
+    for (int v = nvc - 1; v >= 0; --v) {
+      // stage virtual chunk v: geometry, G . f at the covered pixels, coverage
+      const bool cur_has = pf.valid;
+      const uint32_t cur_idx = pf.idx;
+      const uint32_t cur_lp = plp;
+      float ca = 0.f, cb = 0.f, co = 0.f;
+      int X0 = 0, Y0 = 0;
+      s_mask[lane] = 0ull;
+      tile_sync<1>();
+      if (cur_has) {
+        const Footprint f = bilinear_footprint(pf.p.x, pf.p.y, a.cam.W, a.cam.H);
+        ca = f.a; cb = f.b; co = pf.p.z; X0 = f.x0; Y0 = f.y0;
+        s_geo[lane] = make_float4(f.a, f.b, pf.p.z, __uint_as_float(pack_xy(f.x0, f.y0)));
+        s_q1[lane] = pq1;
+        float fv[CP];
+        pf.f.to_f32(fv);
+        const int x0 = X0 - tx * T, y0 = Y0 - ty * T;
+#pragma unroll
+        for (int c4 = 0; c4 < 4; ++c4) {
+          const int qx = x0 + (c4 & 1), qy = y0 + (c4 >> 1);
+          float d = 0.f;
+          if (qx >= 0 && qx < T && qy >= 0 && qy < T) {
+            const float4* gp = reinterpret_cast<const float4*>(s_G + (qy * T + qx) * fpad(CP));
+#pragma unroll
+            for (int q = 0; q < CP / 4; ++q) {
+              const float4 g4 = gp[q];
+              d = fmaf(g4.x, fv[4 * q], d);
+              d = fmaf(g4.y, fv[4 * q + 1], d);
+              d = fmaf(g4.z, fv[4 * q + 2], d);
+              d = fmaf(g4.w, fv[4 * q + 3], d);
+            }
+          }
+          s_gf[lane * 4 + c4] = d;
+          s_acc[lane * 4 + c4] = make_float2(0.f, 0.f);
+        }
+        uint64_t pm = splat_pixels8(cur_lp);
+        const unsigned long long bit = 1ull << lane;
+        while (pm) {
+          const int b = __ffsll((unsigned long long)pm) - 1;
+          pm &= pm - 1ull;
+          atomicOr(&s_mask[b], bit);
+        }
+      }
+      tile_sync<1>();
+      // fetch virtual chunk v - 1 while v is replayed
+      if (v >= 1) {
+        const uint32_t vb = (uint32_t)(v - 1) * 64u;
+        cp.publish(cur, vb, s_sel);
+        tile_sync<1>();
+        const uint2 sl = s_sel[lane];  // virtual chunks below the last are full
+        pf.fetch(a, true, sl.x);
+        plp = sl.y & 0xffffu;
+        pq1 = base - start + (sl.y >> 16) + 1u;
+      }
+      // reverse replay of this pixel's fragments in the chunk
+      unsigned long long m = s_mask[lane];
+      while (m) {
+        const int kk = 63 - __clzll(m);
+        m &= ~(1ull << kk);
+        const uint32_t q1 = s_q1[kk];
+        if (q1 > last) continue;  // behind this pixel's last blended fragment
+        const float4 g = s_geo[kk];
+        const uint32_t pk = __float_as_uint(g.w);
+        const int dx = px - unpack_x(pk), dy = py - unpack_y(pk);
+        const float wx = dx ? g.x : fsub(1.f, g.x);
+        const float wy = dy ? g.y : fsub(1.f, g.y);
+        const float al = fmul(g.z, fmul(wx, wy));
+        const float om = fsub(1.f, al);
+        float Tk;
+        if (q1 > anchor)
+          Tk = 0.f;
+        else if (q1 == anchor)
+          Tk = t_anchor;
+        else
+          Tk = __fdividef(Tcur, om);
+        const float gf = s_gf[kk * 4 + dy * 2 + dx];
+        const float da = Tk * (gf - gB) - GT * Tk * Pi;
+        s_acc[kk * 4 + dy * 2 + dx] = make_float2(Tk * al, da);
+        gB = fmaf(al, gf, om * gB);
+        Pi = Pi * om;
+        Tcur = Tk;
+      }
+      tile_sync<1>();
+      float gfeat[CP];
+#pragma unroll
+      for (int c = 0; c < CP; ++c) gfeat[c] = 0.f;
+      float go = 0.f, gu = 0.f, gv = 0.f;
+      bool single = false;
+      if (cur_has) {
+        const int x0 = X0 - tx * T, y0 = Y0 - ty * T;
+#pragma unroll
+        for (int c4 = 0; c4 < 4; ++c4) {
+          const int dx = c4 & 1, dy = c4 >> 1;
+          const int qx = x0 + dx, qy = y0 + dy;
+          if (qx < 0 || qx >= T || qy < 0 || qy >= T) continue;
+          const float2 acc = s_acc[lane * 4 + c4];
+          const float4* gp = reinterpret_cast<const float4*>(s_G + (qy * T + qx) * fpad(CP));
+#pragma unroll
+          for (int q = 0; q < CP / 4; ++q) {
+            const float4 g4 = gp[q];
+            gfeat[4 * q] = fmaf(acc.x, g4.x, gfeat[4 * q]);
+            gfeat[4 * q + 1] = fmaf(acc.x, g4.y, gfeat[4 * q + 1]);
+            gfeat[4 * q + 2] = fmaf(acc.x, g4.z, gfeat[4 * q + 2]);
+            gfeat[4 * q + 3] = fmaf(acc.x, g4.w, gfeat[4 * q + 3]);
+          }
+          const float wx = dx ? ca : 1.f - ca;
+          const float wy = dy ? cb : 1.f - cb;
+          go = fmaf(wx * wy, acc.y, go);
+          gu = fmaf((dx ? 1.f : -1.f) * wy, acc.y, gu);
+          gv = fmaf((dy ? 1.f : -1.f) * wx, acc.y, gv);
+        }
+        gu *= co;
+        gv *= co;
+        single = single_tile<T>(cur_lp, tx, ty, a.cam.W, a.cam.H);
+        if (single) {  // the only tile of this point: its whole gradient
+          store_row<CP>(a.grad_feat + (size_t)cur_idx * C, gfeat, C);
+          a.grad_opacity[cur_idx] = go;
+          reinterpret_cast<float2*>(a.grad_uv)[cur_idx] = make_float2(gu, gv);
+        }
+      }
+      add_split_shares<CP>(cur_has && !single, cur_idx, gfeat, go, gu, gv,
+                           reinterpret_cast<float*>(s_acc), a);
+      tile_sync<1>();
+    }
+  }
+}
+
 // Zero n floats at p (4-byte aligned): 16-byte stores for the aligned body.
 __global__ __launch_bounds__(256) void k_zero(float* __restrict__ p, size_t n) {
   const size_t mis = (size_t)(reinterpret_cast<uintptr_t>(p) & 15u);
@@ -835,7 +1268,12 @@ template <int T, int CP, typename FT>
 hipError_t fwd_launch(const BlendArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)((int64_t)a.opts.ntx * a.opts.nty)), block(T * T);
   const bool full = a.C == CP;
-  if (a.opts.splat == INPC_SPLAT_BILINEAR) {
+  if (a.opts.splat == INPC_SPLAT_BILINEAR && T == 8) {
+    if (full)
+      hipLaunchKernelGGL((k_blend_fwd_bilinear8<CP, FT, true>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_blend_fwd_bilinear8<CP, FT, false>), grid, block, 0, s, a);
+  } else if (a.opts.splat == INPC_SPLAT_BILINEAR) {
     if (full)
       hipLaunchKernelGGL((k_blend_fwd_bilinear<T, CP, FT, true>), grid, block, 0, s, a);
     else
@@ -858,7 +1296,13 @@ hipError_t bwd_launch(const BlendArgs& a, hipStream_t s) {
   if (e == hipSuccess) e = launch_zero(a.grad_opacity, (size_t)a.n, s);
   if (e == hipSuccess) e = launch_zero(a.grad_uv, (size_t)a.n * 2, s);
   if (e != hipSuccess) return e;
-  if (a.C == CP)
+  if (T == 8 && a.C == CP)
+    hipLaunchKernelGGL((k_blend_bwd_bilinear8<CP, FT, true>), dim3((unsigned)nt), dim3(64), 0, s,
+                       a);
+  else if (T == 8)
+    hipLaunchKernelGGL((k_blend_bwd_bilinear8<CP, FT, false>), dim3((unsigned)nt), dim3(64), 0, s,
+                       a);
+  else if (a.C == CP)
     hipLaunchKernelGGL((k_blend_bwd_bilinear<T, CP, FT, true>), dim3((unsigned)nt), dim3(T * T), 0,
                        s, a);
   else
