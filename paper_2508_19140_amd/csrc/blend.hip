@@ -216,6 +216,89 @@ struct Prefetch {
   }
 };
 
+// Point data of one copy per lane gathered straight into LDS (gfx950
+// global_load_lds_dwordx4, one 16-byte quad per lane and instruction, lane l
+// at slot l): the projection record to prj[l], feature quad q of the row to
+// fq[q][l].  Nothing passes through registers, so a fetch issued for the
+// next chunk stays in flight until the chunk is staged.  For rows that are
+// whole quads (C == CP and CP * sizeof(FT) a multiple of 16 bytes).
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+template <int CP, typename FT>
+struct DmaRow {
+  static constexpr int Q = CP * (int)sizeof(FT) / 16;  // quads per feature row
+  static constexpr bool OK = CP * (int)sizeof(FT) % 16 == 0;
+
+  __device__ __forceinline__ static void fetch(const BlendArgs& a, uint32_t idx, float4* prj,
+                                               uint4 (*fq)[64]) {
+    const float4* pp = reinterpret_cast<const float4*>(a.proj) + idx;
+    __builtin_amdgcn_global_load_lds((const void*)pp, (lds_void_t*)prj, 16, 0, 0);
+    const uint4* fr = reinterpret_cast<const uint4*>(reinterpret_cast<const FT*>(a.feat) +
+                                                     (size_t)idx * CP);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      __builtin_amdgcn_global_load_lds((const void*)(fr + q), (lds_void_t*)&fq[q][0], 16, 0, 0);
+  }
+
+  // Feature row of this lane's copy as FP32.
+  __device__ __forceinline__ static void row(const uint4 (*fq)[64], uint32_t lane,
+                                             float (&v)[CP]) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const uint4 w = fq[q][lane];
+      if constexpr (sizeof(FT) == 4) {
+        v[4 * q] = __uint_as_float(w.x); v[4 * q + 1] = __uint_as_float(w.y);
+        v[4 * q + 2] = __uint_as_float(w.z); v[4 * q + 3] = __uint_as_float(w.w);
+      } else {
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          v[8 * q + 2 * k] = half_bits_to_f32<FT>(ws[k]);
+          v[8 * q + 2 * k + 1] = half_bits_to_f32<FT>(ws[k] >> 16);
+        }
+      }
+    }
+  }
+};
+
+// The point data of the copy a lane stages next: gathered into LDS when the
+// rows are whole quads (DmaRow), else into registers (Prefetch).
+template <int CP, typename FT, bool FULL>
+struct PointFetch {
+  static constexpr bool DMA = FULL && DmaRow<CP, FT>::OK;
+  static constexpr int QS = DMA ? DmaRow<CP, FT>::Q : 1;  // LDS quads per row slot
+  bool valid;
+  uint32_t idx;
+  Prefetch<CP, FT, FULL> reg;
+
+  __device__ __forceinline__ void fetch(const BlendArgs& a, bool v, uint32_t i, float4* prj,
+                                        uint4 (*fq)[64]) {
+    if constexpr (DMA) {
+      valid = v;
+      idx = v ? i : 0u;
+      if (v) DmaRow<CP, FT>::fetch(a, idx, prj, fq);
+    } else {
+      reg.fetch(a, v, i);
+      valid = reg.valid;
+      idx = reg.idx;
+    }
+  }
+  // Before the staged copy is read: the compiler does not order LDS reads
+  // after the gather's LDS writes, so wait for every outstanding memory
+  // operation of this wavefront (each lane reads only its own slots).
+  __device__ __forceinline__ void wait() const {
+    if constexpr (DMA) __builtin_amdgcn_s_waitcnt(0);
+  }
+  __device__ __forceinline__ float4 proj(const float4* prj, uint32_t lane) const {
+    if constexpr (DMA) return prj[lane];
+    else return reg.p;
+  }
+  __device__ __forceinline__ void row(const uint4 (*fq)[64], uint32_t lane, float (&v)[CP]) const {
+    if constexpr (DMA) DmaRow<CP, FT>::row(fq, lane, v);
+    else reg.f.to_f32(v);
+  }
+};
+
 // List entry (point index and tile-local 2x2 position) of a chunk slot.
 struct Entry {
   bool valid;
@@ -1027,6 +1110,9 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
   __shared__ float s_gf[64 * 4];                  // per (copy, corner): G . f
   __shared__ __align__(16) float2 s_acc[64 * 4];  // per (copy, corner): (T alpha, dL/dalpha)
   __shared__ __align__(16) float s_G[64 * fpad(CP)];
+  using PF = PointFetch<CP, FT, FULL>;
+  __shared__ float4 s_prj[64];             // gathered projection records
+  __shared__ uint4 s_fq[PF::QS][64];       // gathered feature quads
   if (a.flags[kFlagOverflow]) return;
 
   const uint32_t lane = threadIdx.x;
@@ -1087,7 +1173,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
     Compaction cp;
     cp.build(cur, base, lend, act);
     const int nvc = (int)((cp.total + 63u) / 64u);
-    Prefetch<CP, FT, FULL> pf;
+    PF pf;
     uint32_t plp = 0, pq1 = 0;
     if (nvc > 0) {
       const uint32_t vb = (uint32_t)(nvc - 1) * 64u;
@@ -1095,7 +1181,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
       tile_sync<1>();
       const bool has = vb + lane < cp.total;
       const uint2 sl = has ? s_sel[lane] : make_uint2(0u, 0u);
-      pf.fetch(a, has, sl.x);
+      pf.fetch(a, has, sl.x, s_prj, s_fq);
       plp = sl.y & 0xffffu;
       pq1 = base - start + (sl.y >> 16) + 1u;
       tile_sync<1>();
@@ -1107,15 +1193,17 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
       const uint32_t cur_lp = plp;
       float ca = 0.f, cb = 0.f, co = 0.f;
       int X0 = 0, Y0 = 0;
+      pf.wait();
       s_mask[lane] = 0ull;
       tile_sync<1>();
       if (cur_has) {
-        const Footprint f = bilinear_footprint(pf.p.x, pf.p.y, a.cam.W, a.cam.H);
-        ca = f.a; cb = f.b; co = pf.p.z; X0 = f.x0; Y0 = f.y0;
-        s_geo[lane] = make_float4(f.a, f.b, pf.p.z, __uint_as_float(pack_xy(f.x0, f.y0)));
+        const float4 pp = pf.proj(s_prj, lane);
+        const Footprint f = bilinear_footprint(pp.x, pp.y, a.cam.W, a.cam.H);
+        ca = f.a; cb = f.b; co = pp.z; X0 = f.x0; Y0 = f.y0;
+        s_geo[lane] = make_float4(f.a, f.b, pp.z, __uint_as_float(pack_xy(f.x0, f.y0)));
         s_q1[lane] = pq1;
         float fv[CP];
-        pf.f.to_f32(fv);
+        pf.row(s_fq, lane, fv);
         const int x0 = X0 - tx * T, y0 = Y0 - ty * T;
 #pragma unroll
         for (int c4 = 0; c4 < 4; ++c4) {
@@ -1150,7 +1238,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
         cp.publish(cur, vb, s_sel);
         tile_sync<1>();
         const uint2 sl = s_sel[lane];  // virtual chunks below the last are full
-        pf.fetch(a, true, sl.x);
+        pf.fetch(a, true, sl.x, s_prj, s_fq);
         plp = sl.y & 0xffffu;
         pq1 = base - start + (sl.y >> 16) + 1u;
       }
