@@ -54,7 +54,123 @@ def parse():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="with --profile-steps: also run one plain device-to-device copy of "
                          "this many MiB (the reference for scaling HBM byte counters)")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="print a markdown table of a rocprofv3 --kernel-trace --stats run "
+                         "(DIR/run_kernel_stats.csv) of --profile-steps S and exit")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="HBM traffic per launch of --entry from two rocprofv3 --pmc runs "
+                         "(FETCH_SIZE, WRITE_SIZE) of --profile-steps S --copy-probe-mib M, "
+                         "scaled by the copy's counters; prints a profiles/pmc_*.txt record")
+    ap.add_argument("--entry", default="blend_bwd", help="entry point for --summarize-pmc")
+    ap.add_argument("--command", default="", help="command line recorded in a summary")
     return ap.parse_args()
+
+
+# Kernels launched by each C-ABI entry point (name prefixes) and how many
+# times a recomputing training step calls the entry point.
+ENTRY_KERNELS = {
+    "project": ("k_project_count", "k_colscan", "k_clear", "k_groups"),
+    "bin": ("k_group_scan", "k_place", "k_scatter"),
+    "sort": ("k_split", "k_sort_w", "k_sort_block", "k_sort_x", "k_lpos"),
+    "blend_fwd": ("k_blend_fwd",),
+    "blend_bwd": ("k_zero", "k_blend_bwd", "k_bg_reduce"),
+    "project_bwd": ("k_project_bwd",),
+}
+CALLS_PER_STEP = {"project": 2, "bin": 2, "sort": 2, "blend_fwd": 1, "blend_bwd": 1,
+                  "project_bwd": 1}
+SOURCES = ["include/inpc_raster.h"] + [f"paper_2508_19140_amd/csrc/{f}" for f in
+                                       ("api.hip", "project.hip", "sort.hip", "blend.hip",
+                                        "common.h", "internal.h")]
+
+
+def _kernel_short(name):
+    import re
+    n = re.sub(r"\(.*", "", name.replace("(anonymous namespace)::", "").replace("inpc::", ""))
+    return n.replace("void ", "").strip()
+
+
+def _entry_of(short):
+    for e, pre in ENTRY_KERNELS.items():
+        if any(short.startswith(p) for p in pre):
+            return e
+    return None
+
+
+def summarize_trace(d, steps, command):
+    import csv
+    rows = list(csv.DictReader(open(os.path.join(d, "run_kernel_stats.csv"))))
+    out = ["| kernel | entry point | calls | calls/step | avg us | total us/step | share |",
+           "|---|---|---:|---:|---:|---:|---:|"]
+    tot = sum(float(r["TotalDurationNs"]) for r in rows if _entry_of(_kernel_short(r["Name"])))
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        k = _kernel_short(r["Name"])
+        e = _entry_of(k)
+        if e is None:
+            continue
+        c = int(r["Calls"])
+        t = float(r["TotalDurationNs"])
+        out.append(f"| `{k}` | {e} | {c} | {c / steps:g} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{t / steps / 1e3:.1f} | {100 * t / tot:.1f}% |")
+    print(f"Command: `{command}`\n\nrocprofv3 `run_kernel_stats.csv`, {steps} steps, "
+          f"averages per launch.\n")
+    print("\n".join(out))
+    per_entry = {}
+    for r in rows:
+        e = _entry_of(_kernel_short(r["Name"]))
+        if e:
+            per_entry[e] = per_entry.get(e, 0.0) + float(r["TotalDurationNs"])
+    print("\n| entry point | kernel time per call, us |\n|---|---:|")
+    for e, t in sorted(per_entry.items(), key=lambda x: -x[1]):
+        print(f"| inpc_{e} | {t / steps / CALLS_PER_STEP[e] / 1e3:.1f} |")
+    print(f"\nsum of kernel time per step: {tot / steps / 1e3:.1f} us")
+
+
+def summarize_pmc(fetch_dir, write_dir, entry, steps, command):
+    import csv
+    import hashlib
+
+    def read(d, counter):
+        acc = {}
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            if r["Counter_Name"] != counter:
+                continue
+            k = _kernel_short(r["Kernel_Name"])
+            acc.setdefault(k, []).append(float(r["Counter_Value"]) * 1024.0)  # KiB -> bytes
+        return acc
+
+    fetch, write = read(fetch_dir, "FETCH_SIZE"), read(write_dir, "WRITE_SIZE")
+    copy = [k for k in fetch if "copyBuffer" in k]
+    if not copy:
+        raise SystemExit("no copy-probe kernel in the counter run (use --copy-probe-mib)")
+    # the probe copies the same number of bytes it reads: its WRITE_SIZE run
+    # is taken as exact (1 byte per byte) and FETCH_SIZE scaled to match
+    cw = sum(write[copy[0]]) / len(write[copy[0]])
+    cf = sum(fetch[copy[0]]) / len(fetch[copy[0]])
+    fetch_scale, write_scale = cw / cf, 1.0
+    lines = []
+    per_launch_f = per_launch_w = 0.0
+    calls = CALLS_PER_STEP[entry] * steps
+    for k in sorted(set(fetch) | set(write)):
+        if _entry_of(k) != entry:
+            continue
+        f = sum(fetch.get(k, [])) * fetch_scale / calls
+        w = sum(write.get(k, [])) * write_scale / calls
+        per_launch_f += f
+        per_launch_w += w
+        lines.append(f"kernel {k} fetch_bytes_per_entry_call {f:.0f} write_bytes_per_entry_call "
+                     f"{w:.0f}")
+    print(f"# HBM traffic of inpc_{entry} per call, from rocprofv3 FETCH_SIZE and WRITE_SIZE")
+    print(f"# command: {command}")
+    print(f"# copy probe: FETCH_SIZE scaled by {fetch_scale:.4f} (copy reads = copy writes), "
+          f"WRITE_SIZE by {write_scale:.4f}")
+    for ln in lines:
+        print(ln)
+    print(f"fetch_bytes_per_launch {per_launch_f:.0f}")
+    print(f"write_bytes_per_launch {per_launch_w:.0f}")
+    print(f"traffic_bytes_per_launch {per_launch_f + per_launch_w:.0f}")
+    for src in SOURCES:
+        h = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+        print(f"sha256 {src} {h}")
 
 
 def make_step(sc, tile, keep_lists, dtype, dev):
@@ -242,6 +358,12 @@ def run_multiview(args):
 
 def main():
     args = parse()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.profile_steps or 1, args.command)
+        return
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc, args.entry, args.profile_steps or 1, args.command)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU: the rasterizer shards by view, one view per GPU, "
               "and this build measures the single-GPU path only (--gpus 1).", file=sys.stderr)
