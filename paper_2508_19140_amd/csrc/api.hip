@@ -63,8 +63,8 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t flags, tile_count, gsum, gcls, gord, coltot, blk, cursor, seg_w, seg_m, seg_l, seg_x, seg_b0, seg_b1, bucket, xbucket,
-      total;
+  size_t flags, tile_count, gsum, gcls, gord, coltot, blk, cursor, seg_w, seg_m, seg_l, seg_x,
+      seg_g, seg_x2, seg_b0, seg_b1, bucket, xbucket, total;
 };
 
 // Segment-list capacities.  Every non-empty tile starts one segment; an MSD
@@ -75,7 +75,7 @@ Layout layout(int64_t n, const inpc_camera_t* c, const inpc_opts_t* o) {
   const size_t nt = (size_t)num_tiles(c, o);
   const size_t cap = (size_t)std::max<int64_t>(copy_capacity(n, c, o), 1);
   const size_t big = cap / (kSortCapM + 1) + 1;
-  const size_t small_segs = nt + 2 * 256 * big;
+  const size_t small_segs = nt + 4 * 256 * big;  // two LDS and two global split rounds
   const size_t big_segs = nt + big;
   Layout L;
   size_t off = 0;
@@ -97,6 +97,8 @@ Layout layout(int64_t n, const inpc_camera_t* c, const inpc_opts_t* o) {
   L.seg_m = take(small_segs * 8);
   L.seg_l = take(big_segs * 8);
   L.seg_x = take(big_segs * 8);
+  L.seg_g = take(big_segs * 8);
+  L.seg_x2 = take(big_segs * 8);
   L.seg_b0 = take(big_segs * 8);
   L.seg_b1 = take(big_segs * 8);
   L.bucket = take(cap * 8);
@@ -122,6 +124,8 @@ Ws make_ws(void* ws, int64_t n, const inpc_camera_t* c, const inpc_opts_t* o) {
   w.seg_m = reinterpret_cast<uint2*>(b + L.seg_m);
   w.seg_l = reinterpret_cast<uint2*>(b + L.seg_l);
   w.seg_x = reinterpret_cast<uint2*>(b + L.seg_x);
+  w.seg_g = reinterpret_cast<uint2*>(b + L.seg_g);
+  w.seg_x2 = reinterpret_cast<uint2*>(b + L.seg_x2);
   w.seg_b0 = reinterpret_cast<uint2*>(b + L.seg_b0);
   w.seg_b1 = reinterpret_cast<uint2*>(b + L.seg_b1);
   w.bucket = reinterpret_cast<uint2*>(b + L.bucket);

@@ -66,6 +66,8 @@ enum : int {
   kFlagCountX = 4,   // larger segments, sorted through global memory
   kFlagCountB0 = 5,  // tiles to split (2048 < n <= 16384)
   kFlagCountB1 = 6,  // sub-segments to split a second time
+  kFlagCountG = 7,   // sub-segments of more than 16384 copies to split through global memory again
+  kFlagCountX2 = 8,  // segments left for the global-memory LSD sort
   kFlagSlots = 16
 };
 
@@ -87,7 +89,9 @@ struct Ws {
   uint2* seg_w;          // segment lists per sort class
   uint2* seg_m;
   uint2* seg_l;
-  uint2* seg_x;
+  uint2* seg_x;          // tiles of more than 16384 copies (split through global memory)
+  uint2* seg_g;          // their sub-segments still above 16384 (second global split)
+  uint2* seg_x2;         // what is left for the global-memory LSD sort
   uint2* seg_b0;
   uint2* seg_b1;
   uint2* bucket;         // [cap]  (depth key, point index) copies, bucketed by tile

@@ -21,7 +21,12 @@
 //               Two split rounds; what is still larger is LSD-sorted by a
 //               1024-thread block (up to 8192 copies) or through global
 //               memory.
-//   larger      LSD radix sort through global memory by a 1024-thread block.
+//   larger      the same MSD split through global memory (the segment is
+//               scattered into the ping-pong buffer and copied back), two
+//               rounds, before the LDS splits; whatever is still larger
+//               than 16384 copies after them is LSD-sorted through global
+//               memory by a 1024-thread block.  (Large Gaussian footprints
+//               give tiles of tens of thousands of copies.)
 //
 // The LSD sorts rank elements inside a wavefront with one ballot per digit
 // bit (the lanes sharing a digit), so no order is decided by an atomic.  They
@@ -417,35 +422,49 @@ __global__ __launch_bounds__(NW * 64) void k_sort_block(const uint2* __restrict_
   }
 }
 
+// Where the sub-segments of a split go, by split round.
+enum SplitRound : int { kLdsRound0 = 0, kLdsRound1 = 1, kGlobalRound0 = 2, kGlobalRound1 = 3 };
+
 // Append one segment per thread (threads with an empty segment pass n = 0)
-// to the class lists: one global atomic per (block, class).
-__device__ void push_segments(uint2 sg, bool split_again, const Ws& ws, uint32_t* s_cnt,
+// to the class lists: one global atomic per (block, class).  Classes: 0 W
+// (<= 256), 1 M (<= 2048), 2 and 3 by round: after the first LDS split, split
+// again; after the second, LSD-sort in one block (<= 8192) or through global
+// memory; after a global split, the LDS split (<= 16384) or another global
+// split / the global LSD sort.
+__device__ void push_segments(uint2 sg, int round, const Ws& ws, uint32_t* s_cnt,
                               uint32_t* s_base) {
-  // 0: W, 1: M, 2: split again (first round) or L, 3: X (global sort), 4: none
-  int c = 4;
-  if (sg.y > 0)
-    c = sg.y <= kSortCapW ? 0
-                          : (sg.y <= kSortCapM ? 1 : (split_again || sg.y <= kSortCapLB ? 2 : 3));
+  int c = 4;  // none
+  if (sg.y > 0) {
+    if (sg.y <= kSortCapW) c = 0;
+    else if (sg.y <= kSortCapM) c = 1;
+    else if (round == kLdsRound0) c = 2;
+    else if (round == kLdsRound1) c = sg.y <= kSortCapLB ? 2 : 3;
+    else c = sg.y <= kSortCapL ? 2 : 3;
+  }
+  uint2* lists[4];
+  int slots[4];
+  lists[0] = ws.seg_w; slots[0] = kFlagCountW;
+  lists[1] = ws.seg_m; slots[1] = kFlagCountM;
+  if (round == kLdsRound0) {
+    lists[2] = ws.seg_b1; slots[2] = kFlagCountB1;
+    lists[3] = ws.seg_x2; slots[3] = kFlagCountX2;  // not reached: round-0 inputs are <= 16384
+  } else if (round == kLdsRound1) {
+    lists[2] = ws.seg_l; slots[2] = kFlagCountL;
+    lists[3] = ws.seg_x2; slots[3] = kFlagCountX2;
+  } else {
+    lists[2] = ws.seg_b0; slots[2] = kFlagCountB0;
+    lists[3] = round == kGlobalRound0 ? ws.seg_g : ws.seg_x2;
+    slots[3] = round == kGlobalRound0 ? kFlagCountG : kFlagCountX2;
+  }
   if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0;
   __syncthreads();
   uint32_t my = 0;
   if (c < 4) my = atomicAdd(&s_cnt[c], 1u);
   __syncthreads();
-  if (threadIdx.x < 4 && s_cnt[threadIdx.x]) {
-    const int cc = (int)threadIdx.x;
-    const int slot = cc == 0 ? kFlagCountW
-                             : (cc == 1 ? kFlagCountM
-                                        : (cc == 3 ? kFlagCountX
-                                                   : (split_again ? kFlagCountB1 : kFlagCountL)));
-    s_base[cc] = atomicAdd(&ws.flags[slot], s_cnt[cc]);
-  }
+  if (threadIdx.x < 4 && s_cnt[threadIdx.x])
+    s_base[threadIdx.x] = atomicAdd(&ws.flags[slots[threadIdx.x]], s_cnt[threadIdx.x]);
   __syncthreads();
-  if (c < 4) {
-    uint2* dst = c == 0 ? ws.seg_w
-                        : (c == 1 ? ws.seg_m
-                                  : (c == 3 ? ws.seg_x : (split_again ? ws.seg_b1 : ws.seg_l)));
-    dst[s_base[c] + my] = sg;
-  }
+  if (c < 4) lists[c][s_base[c] + my] = sg;
   __syncthreads();
 }
 
@@ -509,7 +528,74 @@ __global__ __launch_bounds__(1024) void k_split(int round, Ws ws) {
       const uint2 v = s_e[e];
       g[atomicAdd(&s_off[digit(v)], 1u)] = v;
     }
-    push_segments(sub, round == 0, ws, s_pc, s_pb);
+    push_segments(sub, round == 0 ? kLdsRound0 : kLdsRound1, ws, s_pc, s_pb);
+  }
+}
+
+// MSD split of segments of more than 16384 copies, through global memory:
+// the same digit as the LDS split, the segment scattered by digit into the
+// ping-pong buffer and copied back, its sub-segments queued by size.
+__global__ __launch_bounds__(1024) void k_split_global(int round, Ws ws) {
+  __shared__ uint32_t s_cnt[256], s_off[256];
+  __shared__ uint32_t s_red[64];
+  __shared__ uint32_t s_pc[4], s_pb[4];
+  if (ws.flags[kFlagOverflow]) return;
+  const uint2* segs = round == 0 ? ws.seg_x : ws.seg_g;
+  const uint32_t count = ws.flags[round == 0 ? kFlagCountX : kFlagCountG];
+  const uint32_t lane = __lane_id(), w = threadIdx.x >> 6;
+  for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+    const uint2 sg = segs[i];
+    const uint32_t n = sg.y;
+    uint2* g = ws.bucket + sg.x;
+    uint2* x = ws.xbucket + sg.x;
+    uint32_t kmin = 0xffffffffu, kmax = 0, imin = 0xffffffffu, imax = 0;
+    for (uint32_t e = threadIdx.x; e < n; e += 1024) {
+      const uint2 v = g[e];
+      kmin = min(kmin, v.x); kmax = max(kmax, v.x);
+      imin = min(imin, v.y); imax = max(imax, v.y);
+    }
+    if (threadIdx.x < 256) s_cnt[threadIdx.x] = 0;
+    kmin = wave_min(kmin); kmax = wave_max(kmax);
+    imin = wave_min(imin); imax = wave_max(imax);
+    if (lane == 0) {
+      s_red[w * 4 + 0] = kmin; s_red[w * 4 + 1] = kmax;
+      s_red[w * 4 + 2] = imin; s_red[w * 4 + 3] = imax;
+    }
+    __syncthreads();
+    kmin = 0xffffffffu; kmax = 0; imin = 0xffffffffu; imax = 0;
+    for (int ww = 0; ww < 16; ++ww) {
+      kmin = min(kmin, s_red[ww * 4 + 0]); kmax = max(kmax, s_red[ww * 4 + 1]);
+      imin = min(imin, s_red[ww * 4 + 2]); imax = max(imax, s_red[ww * 4 + 3]);
+    }
+    const uint32_t ib = nbits(imax - imin);
+    const uint32_t total = nbits(kmax - kmin) + ib;
+    const uint32_t sh = total > 8 ? total - 8 : 0;
+    const uint32_t k0 = kmin, i0 = imin;
+    auto digit = [=](uint2 v) -> uint32_t {
+      const uint64_t c = ((uint64_t)(v.x - k0) << ib) | (uint64_t)(v.y - i0);
+      return (uint32_t)(c >> sh);
+    };
+    for (uint32_t e = threadIdx.x; e < n; e += 1024) atomicAdd(&s_cnt[digit(g[e])], 1u);
+    __syncthreads();
+    if (w == 0) {
+      uint32_t t4[4], s = 0;
+      for (int q = 0; q < 4; ++q) { t4[q] = s_cnt[lane * 4 + q]; s += t4[q]; }
+      uint32_t ex = wave_incl_scan(s) - s;
+      for (int q = 0; q < 4; ++q) { s_off[lane * 4 + q] = ex; ex += t4[q]; }
+    }
+    __syncthreads();
+    uint2 sub = make_uint2(0u, 0u);
+    if (threadIdx.x < 256) sub = make_uint2(sg.x + s_off[threadIdx.x], s_cnt[threadIdx.x]);
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < n; e += 1024) {
+      const uint2 v = g[e];
+      x[atomicAdd(&s_off[digit(v)], 1u)] = v;
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < n; e += 1024) g[e] = x[e];
+    __threadfence_block();
+    push_segments(sub, round == 0 ? kGlobalRound0 : kGlobalRound1, ws, s_pc, s_pb);
   }
 }
 
@@ -528,9 +614,9 @@ __global__ __launch_bounds__(NW * 64) void k_sort_x(Ws ws, ListOut out) {
   SortSmem sm{nullptr, nullptr, s_hist, s_off, s_red};
   const uint32_t lane = __lane_id();
   const uint32_t w = threadIdx.x >> 6;
-  const uint32_t count = ws.flags[kFlagCountX];
+  const uint32_t count = ws.flags[kFlagCountX2];
   for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
-    const uint2 sg = ws.seg_x[i];
+    const uint2 sg = ws.seg_x2[i];
     const uint32_t s = sg.x, n = sg.y;
     uint32_t kmin = 0xffffffffu, kmax = 0, imin = 0xffffffffu, imax = 0;
     for (uint32_t e = threadIdx.x; e < n; e += NW * 64) {
@@ -616,6 +702,9 @@ hipError_t launch_sort(const Ws& ws, uint32_t* list, uint16_t* lpos, int64_t nt,
   const ListOut out{list, lpos, ws.lbits, ws.pb};
   const int64_t big_max = std::max<int64_t>(1, (int64_t)ws.cap / (int64_t)(kSortCapM + 1));
   const int grid_split = (int)std::min<int64_t>(big_max, 1024);
+  const int grid_huge = (int)std::min<int64_t>(std::max<int64_t>(1, (int64_t)ws.cap / (kSortCapL + 1)), 256);
+  hipLaunchKernelGGL(k_split_global, dim3(grid_huge), dim3(1024), 0, stream, 0, ws);
+  hipLaunchKernelGGL(k_split_global, dim3(grid_huge), dim3(1024), 0, stream, 1, ws);
   hipLaunchKernelGGL(k_split, dim3(grid_split), dim3(1024), 0, stream, 0, ws);
   hipLaunchKernelGGL(k_split, dim3(grid_split), dim3(1024), 0, stream, 1, ws);
   const int grid_w = (int)std::min<int64_t>((nt + 3) / 4 + (int64_t)ws.cap / 256, 8192);
