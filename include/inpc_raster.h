@@ -230,8 +230,9 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
                                   void* stream);
 
 /* Bytes of the scratch inpc_blend_backward needs for n points and C channels:
- * 4 C per tile (the per-tile shares of the background gradient).  0 if
- * invalid. */
+ * 16 per point (the opacity and position gradients as one row per point,
+ * which the atomics of points split over tiles add to) plus 4 C per tile
+ * (the per-tile shares of the background gradient).  0 if invalid. */
 size_t inpc_backward_scratch_bytes(int64_t n, int32_t C, const inpc_camera_t* cam,
                                    const inpc_opts_t* opts);
 

@@ -149,10 +149,11 @@ Ws make_ws(void* ws, int64_t n, const inpc_camera_t* c, const inpc_opts_t* o) {
   return w;
 }
 
-// Backward scratch: the per-tile shares of the background gradient.
+// Backward scratch: a 16-byte (dL/do, dL/du, dL/dv) row per point, then the
+// per-tile shares of the background gradient.
+size_t scratch_scalar_bytes(int64_t n) { return align_up((size_t)n * 16); }
 size_t scratch_bytes(int64_t n, int C, const inpc_camera_t* c, const inpc_opts_t* o) {
-  (void)n;
-  return align_up((size_t)num_tiles(c, o) * C * 4);
+  return scratch_scalar_bytes(n) + align_up((size_t)num_tiles(c, o) * C * 4);
 }
 
 // Per-pixel forward state (last position, anchor position, anchor
@@ -424,7 +425,10 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
   a.grad_opacity = grad_opacity;
   a.grad_uv = grad_uv;
   a.grad_bg = grad_bg;
-  a.bg_partial = grad_bg ? static_cast<float*>(scratch) : nullptr;
+  a.gsc = static_cast<float4*>(scratch);
+  a.bg_partial = grad_bg ? reinterpret_cast<float*>(static_cast<char*>(scratch) +
+                                                    scratch_scalar_bytes(n))
+                         : nullptr;
   a.flags = w.flags;
   hipError_t e = launch_blend_backward(a, (hipStream_t)stream);
   return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_blend_backward");

@@ -860,14 +860,12 @@ __device__ __forceinline__ void add_split_shares(bool mine, uint32_t idx, const 
         atomicAdd(a.grad_feat + (size_t)pidx * C + c, tr[row * RS + c]);
       }
     }
-    for (uint32_t k = lane; k < 3 * nb; k += 64) {
-      const uint32_t row = k / 3, comp = k - 3 * row;
+    // opacity and position: one 16-byte scalar row per point, 4 lanes each
+    for (uint32_t k = lane; k < 4 * nb; k += 64) {
+      const uint32_t row = k >> 2, comp = k & 3u;
       const float* rr = tr + row * RS;
       const uint32_t pidx = __float_as_uint(rr[CP + 3]);
-      if (comp == 0)
-        atomicAdd(a.grad_opacity + pidx, rr[CP]);
-      else
-        atomicAdd(a.grad_uv + 2 * (size_t)pidx + (comp - 1), rr[CP + comp]);
+      if (comp < 3) atomicAdd(reinterpret_cast<float*>(a.gsc + pidx) + comp, rr[CP + comp]);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1080,8 +1078,7 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
       gv *= co;
       if (cur_single) {  // the only tile of this point: its whole gradient
         store_row<CP>(a.grad_feat + (size_t)cur_idx * C, gfeat, C);
-        a.grad_opacity[cur_idx] = go;
-        reinterpret_cast<float2*>(a.grad_uv)[cur_idx] = make_float2(gu, gv);
+        a.gsc[cur_idx] = make_float4(go, gu, gv, 0.f);
       }
     }
     // A point split over several tiles receives this tile's share by float
@@ -1304,8 +1301,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
         single = single_tile<T>(cur_lp, tx, ty, a.cam.W, a.cam.H);
         if (single) {  // the only tile of this point: its whole gradient
           store_row<CP>(a.grad_feat + (size_t)cur_idx * C, gfeat, C);
-          a.grad_opacity[cur_idx] = go;
-          reinterpret_cast<float2*>(a.grad_uv)[cur_idx] = make_float2(gu, gv);
+          a.gsc[cur_idx] = make_float4(go, gu, gv, 0.f);
         }
       }
       add_split_shares<CP>(cur_has && !single, cur_idx, gfeat, go, gu, gv,
@@ -1327,6 +1323,18 @@ __global__ __launch_bounds__(256) void k_zero(float* __restrict__ p, size_t n) {
   for (size_t i = tid; i < nv; i += stride) v[i] = make_uint4(0u, 0u, 0u, 0u);
   const size_t tail0 = head + nv * 4u;
   if (tid < n - tail0) p[tail0 + tid] = 0.f;
+}
+
+// grad_opacity and grad_uv from the per-point scalar rows.
+__global__ __launch_bounds__(256) void k_unpack_scalars(const float4* __restrict__ gsc, int64_t n,
+                                                        float* __restrict__ go,
+                                                        float2* __restrict__ guv) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float4 v = gsc[i];
+    go[i] = v.x;
+    guv[i] = make_float2(v.y, v.z);
+  }
 }
 
 hipError_t launch_zero(float* p, size_t n, hipStream_t s) {
@@ -1381,8 +1389,7 @@ hipError_t bwd_launch(const BlendArgs& a, hipStream_t s) {
   // Every gradient starts at zero: points no blended fragment reached keep
   // it, single-tile points are overwritten, split points are added to.
   hipError_t e = launch_zero(a.grad_feat, (size_t)a.n * a.C, s);
-  if (e == hipSuccess) e = launch_zero(a.grad_opacity, (size_t)a.n, s);
-  if (e == hipSuccess) e = launch_zero(a.grad_uv, (size_t)a.n * 2, s);
+  if (e == hipSuccess) e = launch_zero(reinterpret_cast<float*>(a.gsc), (size_t)a.n * 4, s);
   if (e != hipSuccess) return e;
   if (T == 8 && a.C == CP)
     hipLaunchKernelGGL((k_blend_bwd_bilinear8<CP, FT, true>), dim3((unsigned)nt), dim3(64), 0, s,
@@ -1398,6 +1405,13 @@ hipError_t bwd_launch(const BlendArgs& a, hipStream_t s) {
                        0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (a.n > 0) {
+    const int64_t g = std::min<int64_t>((a.n + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(k_unpack_scalars, dim3((unsigned)g), dim3(256), 0, s, a.gsc, a.n,
+                       a.grad_opacity, reinterpret_cast<float2*>(a.grad_uv));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (a.grad_bg)
     hipLaunchKernelGGL(k_bg_reduce, dim3((unsigned)a.C), dim3(256), 0, s, a.bg_partial, nt, a.C,
                        a.grad_bg);

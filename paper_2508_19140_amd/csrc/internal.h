@@ -38,6 +38,8 @@ struct BlendArgs {
   float* grad_uv;
   float* grad_bg;
   float* bg_partial;  // [num_tiles][C] per-tile background gradients
+  float4* gsc;        // [n] (dL/do, dL/du, dL/dv, -) per point, unpacked into grad_opacity
+                      // and grad_uv at the end (one 16-byte row per point for the atomics)
   const uint32_t* flags;
 };
 

@@ -131,7 +131,7 @@ def test_backward_rejects_small_scratch():
     wsb = lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(o))
     need = lib.inpc_backward_scratch_bytes(n, C, ctypes.byref(c), ctypes.byref(o))
     nt = lib.inpc_num_tiles(ctypes.byref(c), ctypes.byref(o))
-    assert need >= nt * C * 4  # per-tile shares of the background gradient
+    assert need >= n * 16 + nt * C * 4  # scalar gradient rows, background shares
     args = [ctypes.byref(c), ctypes.byref(o), n, FAKE, FAKE, C, L.DTYPE_F32, None, FAKE,
             FAKE, None, FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, FAKE, None]
     assert lib.inpc_blend_backward(*args, FAKE, need - 1, FAKE, wsb, None) == L.INPC_ERR_INVALID
