@@ -375,31 +375,10 @@ __device__ void rank_sort_wave(const uint2* __restrict__ seg, uint32_t n, const 
   bsync<true>();
 }
 
-// Segments of at most 256 copies: one wavefront each, four per block.
+// Segments of at most 256 copies: one wavefront each, four per block (the W
+// role of k_sort_wm below).
 constexpr int kW_ITEMS = 4;
 constexpr int kW_CAP = kW_ITEMS * 64;
-
-__global__ __launch_bounds__(256) void k_sort_w(const uint2* __restrict__ segs,
-                                                const uint32_t* __restrict__ flags,
-                                                const uint2* __restrict__ bucket,
-                                                ListOut out) {
-  __shared__ __align__(16) uint32_t s_key[4][kW_CAP];
-  __shared__ uint32_t s_idx[4][kW_CAP];
-  __shared__ uint32_t s_hist[4][256];
-  __shared__ uint32_t s_off[4][256];
-  __shared__ uint32_t s_red[4][64];
-  if (flags[kFlagOverflow]) return;
-  const uint32_t w = threadIdx.x >> 6;
-  SortSmem sm{s_key[w], s_idx[w], s_hist[w], s_off[w], s_red[w]};
-  const uint32_t count = flags[kFlagCountW];
-  for (uint32_t i = blockIdx.x * 4 + w; i < count; i += gridDim.x * 4) {
-    const uint2 sg = segs[i];
-    if (sg.y <= 64)
-      rank_sort_wave(bucket + sg.x, sg.y, out, sg.x, reinterpret_cast<uint2*>(s_key[w]));
-    else
-      sort_segment_lds<1, kW_ITEMS, true>(bucket + sg.x, sg.y, out, sg.x, sm);
-  }
-}
 
 // Segments of at most NW*ITEMS*64 copies: one block each.
 template <int NW, int ITEMS, int FLAG>
@@ -419,6 +398,47 @@ __global__ __launch_bounds__(NW * 64) void k_sort_block(const uint2* __restrict_
   for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
     const uint2 sg = segs[i];
     sort_segment_lds<NW, ITEMS, false>(bucket + sg.x, sg.y, out, sg.x, sm);
+  }
+}
+
+// The W class (one wavefront per segment, four per block) and the M class
+// (one 256-thread block per segment) in one launch: workgroups [0, gm) take
+// M segments and are dispatched first (the larger sorts start first), the
+// rest take W segments, so that neither class leaves a tail of idle compute
+// units behind it.  Both roles carve their LDS from one arena.
+constexpr int kM_NW = 4, kM_ITEMS = 8, kM_CAP = kM_NW * kM_ITEMS * 64;
+constexpr int kM_WORDS = 2 * kM_CAP + kM_NW * 256 + 256 + 64;
+constexpr int kW_WORDS = 2 * kW_CAP + 256 + 256 + 64;  // per wavefront
+static_assert(kW_WORDS % 4 == 0, "wavefront arenas must stay 16-byte aligned");
+
+__global__ __launch_bounds__(256) void k_sort_wm(int gm, const uint2* __restrict__ seg_w,
+                                                 const uint2* __restrict__ seg_m,
+                                                 const uint32_t* __restrict__ flags,
+                                                 const uint2* __restrict__ bucket, ListOut out) {
+  __shared__ __align__(16) uint32_t s_lds[kM_WORDS > 4 * kW_WORDS ? kM_WORDS : 4 * kW_WORDS];
+  if (flags[kFlagOverflow]) return;
+  if ((int)blockIdx.x < gm) {
+    uint32_t* b = s_lds;
+    const SortSmem sm{b, b + kM_CAP, b + 2 * kM_CAP, b + 2 * kM_CAP + kM_NW * 256,
+                      b + 2 * kM_CAP + kM_NW * 256 + 256};
+    const uint32_t count = flags[kFlagCountM];
+    for (uint32_t i = blockIdx.x; i < count; i += (uint32_t)gm) {
+      const uint2 sg = seg_m[i];
+      sort_segment_lds<kM_NW, kM_ITEMS, false>(bucket + sg.x, sg.y, out, sg.x, sm);
+    }
+  } else {
+    const uint32_t w = threadIdx.x >> 6;
+    uint32_t* b = s_lds + w * kW_WORDS;  // 16-byte aligned: kW_WORDS is a multiple of 4
+    const SortSmem sm{b, b + kW_CAP, b + 2 * kW_CAP, b + 2 * kW_CAP + 256, b + 2 * kW_CAP + 512};
+    const uint32_t count = flags[kFlagCountW];
+    const uint32_t nb = gridDim.x - (uint32_t)gm;
+    for (uint32_t i = (blockIdx.x - (uint32_t)gm) * 4 + w; i < count; i += nb * 4) {
+      const uint2 sg = seg_w[i];
+      if (sg.y <= 64)
+        rank_sort_wave(bucket + sg.x, sg.y, out, sg.x, reinterpret_cast<uint2*>(b));
+      else
+        sort_segment_lds<1, kW_ITEMS, true>(bucket + sg.x, sg.y, out, sg.x, sm);
+    }
   }
 }
 
@@ -700,23 +720,27 @@ __global__ __launch_bounds__(NW * 64) void k_sort_x(Ws ws, ListOut out) {
 hipError_t launch_sort(const Ws& ws, uint32_t* list, uint16_t* lpos, int64_t nt,
                        hipStream_t stream) {
   const ListOut out{list, lpos, ws.lbits, ws.pb};
+  // Grids: the first split round takes one 1024-thread block per tile above
+  // 2048 copies (up to 1024 blocks); the later, rarely busy classes (huge
+  // tiles, second split round, L and X sorts) loop over their segments with
+  // at most 256 or 64 blocks, so that a class with no work costs little more
+  // than a launch.
   const int64_t big_max = std::max<int64_t>(1, (int64_t)ws.cap / (int64_t)(kSortCapM + 1));
   const int grid_split = (int)std::min<int64_t>(big_max, 1024);
-  const int grid_huge = (int)std::min<int64_t>(std::max<int64_t>(1, (int64_t)ws.cap / (kSortCapL + 1)), 256);
+  const int grid_rare = (int)std::min<int64_t>(big_max, 256);
+  const int grid_huge = (int)std::min<int64_t>(std::max<int64_t>(1, (int64_t)ws.cap / (kSortCapL + 1)), 64);
   hipLaunchKernelGGL(k_split_global, dim3(grid_huge), dim3(1024), 0, stream, 0, ws);
   hipLaunchKernelGGL(k_split_global, dim3(grid_huge), dim3(1024), 0, stream, 1, ws);
   hipLaunchKernelGGL(k_split, dim3(grid_split), dim3(1024), 0, stream, 0, ws);
-  hipLaunchKernelGGL(k_split, dim3(grid_split), dim3(1024), 0, stream, 1, ws);
+  hipLaunchKernelGGL(k_split, dim3(grid_rare), dim3(1024), 0, stream, 1, ws);
   const int grid_w = (int)std::min<int64_t>((nt + 3) / 4 + (int64_t)ws.cap / 256, 8192);
-  hipLaunchKernelGGL(k_sort_w, dim3(std::max(grid_w, 1)), dim3(256), 0, stream, ws.seg_w, ws.flags,
-                     ws.bucket, out);
   const int grid_m = (int)std::min<int64_t>(nt + (int64_t)ws.cap / 2048, 4096);
-  hipLaunchKernelGGL((k_sort_block<4, 8, kFlagCountM>), dim3(std::max(grid_m, 1)), dim3(256), 0,
-                     stream, ws.seg_m, ws.flags, ws.bucket, out);
-  hipLaunchKernelGGL((k_sort_block<16, kSortCapLB / 1024, kFlagCountL>), dim3(grid_split),
+  hipLaunchKernelGGL(k_sort_wm, dim3(std::max(grid_m, 1) + std::max(grid_w, 1)), dim3(256), 0,
+                     stream, std::max(grid_m, 1), ws.seg_w, ws.seg_m, ws.flags, ws.bucket, out);
+  hipLaunchKernelGGL((k_sort_block<16, kSortCapLB / 1024, kFlagCountL>), dim3(grid_rare),
                      dim3(1024), 0, stream,
                      ws.seg_l, ws.flags, ws.bucket, out);
-  hipLaunchKernelGGL((k_sort_x<16, 16>), dim3(256), dim3(1024), 0, stream, ws, out);
+  hipLaunchKernelGGL((k_sort_x<16, 16>), dim3(64), dim3(1024), 0, stream, ws, out);
   return hipGetLastError();
 }
 
