@@ -1312,17 +1312,25 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
 }
 
 // Zero n floats at p (4-byte aligned): 16-byte stores for the aligned body.
-__global__ __launch_bounds__(256) void k_zero(float* __restrict__ p, size_t n) {
+__device__ __forceinline__ void zero_range(float* __restrict__ p, size_t n, size_t tid,
+                                           size_t stride) {
   const size_t mis = (size_t)(reinterpret_cast<uintptr_t>(p) & 15u);
   const size_t head = min(n, ((16u - mis) & 15u) / 4u);
   const size_t nv = (n - head) / 4u;
-  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
   if (tid < head) p[tid] = 0.f;
   uint4* v = reinterpret_cast<uint4*>(p + head);
   for (size_t i = tid; i < nv; i += stride) v[i] = make_uint4(0u, 0u, 0u, 0u);
   const size_t tail0 = head + nv * 4u;
   if (tid < n - tail0) p[tail0 + tid] = 0.f;
+}
+
+// Zero two float ranges in one launch.
+__global__ __launch_bounds__(256) void k_zero(float* __restrict__ p0, size_t n0,
+                                              float* __restrict__ p1, size_t n1) {
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  zero_range(p0, n0, tid, stride);
+  if (p1) zero_range(p1, n1, tid, stride);
 }
 
 // grad_opacity and grad_uv from the per-point scalar rows.
@@ -1337,10 +1345,10 @@ __global__ __launch_bounds__(256) void k_unpack_scalars(const float4* __restrict
   }
 }
 
-hipError_t launch_zero(float* p, size_t n, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  const size_t g = std::min<size_t>((n / 4 + 255) / 256 + 1, 2048);
-  hipLaunchKernelGGL(k_zero, dim3((unsigned)g), dim3(256), 0, s, p, n);
+hipError_t launch_zero(float* p0, size_t n0, float* p1, size_t n1, hipStream_t s) {
+  if (n0 + n1 == 0) return hipSuccess;
+  const size_t g = std::min<size_t>((std::max(n0, n1) / 4 + 255) / 256 + 1, 2048);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)g), dim3(256), 0, s, p0, n0, p1, n1);
   return hipGetLastError();
 }
 
@@ -1388,8 +1396,8 @@ hipError_t bwd_launch(const BlendArgs& a, hipStream_t s) {
   const int64_t nt = (int64_t)a.opts.ntx * a.opts.nty;
   // Every gradient starts at zero: points no blended fragment reached keep
   // it, single-tile points are overwritten, split points are added to.
-  hipError_t e = launch_zero(a.grad_feat, (size_t)a.n * a.C, s);
-  if (e == hipSuccess) e = launch_zero(reinterpret_cast<float*>(a.gsc), (size_t)a.n * 4, s);
+  hipError_t e = launch_zero(a.grad_feat, (size_t)a.n * a.C, reinterpret_cast<float*>(a.gsc),
+                            (size_t)a.n * 4, s);
   if (e != hipSuccess) return e;
   if (T == 8 && a.C == CP)
     hipLaunchKernelGGL((k_blend_bwd_bilinear8<CP, FT, true>), dim3((unsigned)nt), dim3(64), 0, s,

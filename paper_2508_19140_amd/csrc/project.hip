@@ -88,9 +88,13 @@ __global__ __launch_bounds__(kBinBlock) void k_project_count(Cam cam, Opts o, in
                                                              float4* __restrict__ proj,
                                                              uint32_t* __restrict__ key,
                                                              uint32_t* __restrict__ ntiles,
-                                                             uint32_t* __restrict__ blk) {
+                                                             uint32_t* __restrict__ blk,
+                                                             uint32_t* __restrict__ flags) {
   __shared__ uint32_t bins[kLdsBins];
   const int nt = o.ntx * o.nty;
+  // the workspace flags of this pass start at zero (no other block of this
+  // kernel reads them)
+  if (blockIdx.x == 0 && threadIdx.x < kFlagSlots) flags[threadIdx.x] = 0u;
   for (int t = threadIdx.x; t < nt; t += kBinBlock) bins[t] = 0u;
   __syncthreads();
   const int sh = tile_shift(o.T);
@@ -513,9 +517,10 @@ hipError_t launch_project(const Cam& cam, const Opts& o, int64_t n, const float*
                           uint32_t* ntiles,
                           const Ws& ws, hipStream_t s) {
   const int64_t nt = (int64_t)o.ntx * o.nty;
-  hipError_t e = launch_clear(ws.flags, kFlagSlots, s);
-  if (e != hipSuccess) return e;
-  if (n == 0 || nt > kLdsBins) {
+  hipError_t e = hipSuccess;
+  if (n == 0 || nt > kLdsBins) {  // else k_project_count clears the flags
+    e = launch_clear(ws.flags, kFlagSlots, s);
+    if (e != hipSuccess) return e;
     e = launch_clear(ws.tile_count, (size_t)nt, s);
     if (e != hipSuccess) return e;
   }
@@ -527,7 +532,7 @@ hipError_t launch_project(const Cam& cam, const Opts& o, int64_t n, const float*
     const int64_t chunk = ws.chunk, rows = ws.rows;
     hipLaunchKernelGGL(k_project_count, dim3((unsigned)rows), dim3(kBinBlock), 0, s, cam, o, n,
                        chunk, pos, opacity, radius, reinterpret_cast<float4*>(proj), key, ntiles,
-                       ws.blk);
+                       ws.blk, ws.flags);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_colscan, dim3((unsigned)ws.groups), dim3(1024), 0, s, nt, (int)rows,

@@ -380,26 +380,6 @@ __device__ void rank_sort_wave(const uint2* __restrict__ seg, uint32_t n, const 
 constexpr int kW_ITEMS = 4;
 constexpr int kW_CAP = kW_ITEMS * 64;
 
-// Segments of at most NW*ITEMS*64 copies: one block each.
-template <int NW, int ITEMS, int FLAG>
-__global__ __launch_bounds__(NW * 64) void k_sort_block(const uint2* __restrict__ segs,
-                                                        const uint32_t* __restrict__ flags,
-                                                        const uint2* __restrict__ bucket,
-                                                        ListOut out) {
-  constexpr int CAP = NW * ITEMS * 64;
-  __shared__ uint32_t s_key[CAP];
-  __shared__ uint32_t s_idx[CAP];
-  __shared__ uint32_t s_hist[NW * 256];
-  __shared__ uint32_t s_off[256];
-  __shared__ uint32_t s_red[64];
-  if (flags[kFlagOverflow]) return;
-  SortSmem sm{s_key, s_idx, s_hist, s_off, s_red};
-  const uint32_t count = flags[FLAG];
-  for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
-    const uint2 sg = segs[i];
-    sort_segment_lds<NW, ITEMS, false>(bucket + sg.x, sg.y, out, sg.x, sm);
-  }
-}
 
 // The W class (one wavefront per segment, four per block) and the M class
 // (one 256-thread block per segment) in one launch: workgroups [0, gm) take
@@ -447,10 +427,10 @@ enum SplitRound : int { kLdsRound0 = 0, kLdsRound1 = 1, kGlobalRound0 = 2, kGlob
 
 // Append one segment per thread (threads with an empty segment pass n = 0)
 // to the class lists: one global atomic per (block, class).  Classes: 0 W
-// (<= 256), 1 M (<= 2048), 2 and 3 by round: after the first LDS split, split
-// again; after the second, LSD-sort in one block (<= 8192) or through global
-// memory; after a global split, the LDS split (<= 16384) or another global
-// split / the global LSD sort.
+// (<= 256), 1 M (<= 2048); after a first-round split, the second round (the
+// LDS split up to 16384 copies, the global split beyond); after a
+// second-round split, the LSD sort of one 1024-thread block (<= 8192) or
+// through global memory.
 __device__ void push_segments(uint2 sg, int round, const Ws& ws, uint32_t* s_cnt,
                               uint32_t* s_base) {
   int c = 4;  // none
@@ -458,23 +438,21 @@ __device__ void push_segments(uint2 sg, int round, const Ws& ws, uint32_t* s_cnt
     if (sg.y <= kSortCapW) c = 0;
     else if (sg.y <= kSortCapM) c = 1;
     else if (round == kLdsRound0) c = 2;
-    else if (round == kLdsRound1) c = sg.y <= kSortCapLB ? 2 : 3;
-    else c = sg.y <= kSortCapL ? 2 : 3;
+    else if (round == kGlobalRound0) c = sg.y <= kSortCapL ? 2 : 3;
+    else c = sg.y <= kSortCapLB ? 2 : 3;  // second rounds
   }
   uint2* lists[4];
   int slots[4];
   lists[0] = ws.seg_w; slots[0] = kFlagCountW;
   lists[1] = ws.seg_m; slots[1] = kFlagCountM;
-  if (round == kLdsRound0) {
+  if (round == kLdsRound0 || round == kGlobalRound0) {
+    // the second split round takes what is still above 2048 (the LDS split
+    // up to 16384, the global split beyond)
     lists[2] = ws.seg_b1; slots[2] = kFlagCountB1;
-    lists[3] = ws.seg_x2; slots[3] = kFlagCountX2;  // not reached: round-0 inputs are <= 16384
-  } else if (round == kLdsRound1) {
+    lists[3] = ws.seg_g; slots[3] = kFlagCountG;  // only from global splits
+  } else {
     lists[2] = ws.seg_l; slots[2] = kFlagCountL;
     lists[3] = ws.seg_x2; slots[3] = kFlagCountX2;
-  } else {
-    lists[2] = ws.seg_b0; slots[2] = kFlagCountB0;
-    lists[3] = round == kGlobalRound0 ? ws.seg_g : ws.seg_x2;
-    slots[3] = round == kGlobalRound0 ? kFlagCountG : kFlagCountX2;
   }
   if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -489,16 +467,28 @@ __device__ void push_segments(uint2 sg, int round, const Ws& ws, uint32_t* s_cnt
 }
 
 // MSD split of segments with 2048 < n <= 16384 copies (in place).
-__global__ __launch_bounds__(1024) void k_split(int round, Ws ws) {
+__device__ void split_global_blocks(int round, const Ws& ws, uint32_t b, uint32_t nb,
+                                    uint32_t* s_cnt, uint32_t* s_off, uint32_t* s_red,
+                                    uint32_t* s_pc, uint32_t* s_pb);
+
+// One split round: workgroups [0, gl) split the LDS-sized segments of the
+// round (2048 < n <= 16384) in LDS, the others split the larger ones through
+// global memory.
+__global__ __launch_bounds__(1024) void k_split(int round, int gl, Ws ws) {
   __shared__ uint2 s_e[kSortCapL];
   __shared__ uint32_t s_cnt[256], s_off[256];
   __shared__ uint32_t s_red[64];
   __shared__ uint32_t s_pc[4], s_pb[4];
   if (ws.flags[kFlagOverflow]) return;
+  if ((int)blockIdx.x >= gl) {
+    split_global_blocks(round, ws, blockIdx.x - (uint32_t)gl, gridDim.x - (uint32_t)gl, s_cnt,
+                        s_off, s_red, s_pc, s_pb);
+    return;
+  }
   const uint2* segs = round == 0 ? ws.seg_b0 : ws.seg_b1;
   const uint32_t count = ws.flags[round == 0 ? kFlagCountB0 : kFlagCountB1];
   const uint32_t lane = __lane_id(), w = threadIdx.x >> 6;
-  for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+  for (uint32_t i = blockIdx.x; i < count; i += (uint32_t)gl) {
     const uint2 sg = segs[i];
     const uint32_t n = sg.y;
     uint2* g = ws.bucket + sg.x;
@@ -555,15 +545,13 @@ __global__ __launch_bounds__(1024) void k_split(int round, Ws ws) {
 // MSD split of segments of more than 16384 copies, through global memory:
 // the same digit as the LDS split, the segment scattered by digit into the
 // ping-pong buffer and copied back, its sub-segments queued by size.
-__global__ __launch_bounds__(1024) void k_split_global(int round, Ws ws) {
-  __shared__ uint32_t s_cnt[256], s_off[256];
-  __shared__ uint32_t s_red[64];
-  __shared__ uint32_t s_pc[4], s_pb[4];
-  if (ws.flags[kFlagOverflow]) return;
+__device__ void split_global_blocks(int round, const Ws& ws, uint32_t b, uint32_t nb,
+                                    uint32_t* s_cnt, uint32_t* s_off, uint32_t* s_red,
+                                    uint32_t* s_pc, uint32_t* s_pb) {
   const uint2* segs = round == 0 ? ws.seg_x : ws.seg_g;
   const uint32_t count = ws.flags[round == 0 ? kFlagCountX : kFlagCountG];
   const uint32_t lane = __lane_id(), w = threadIdx.x >> 6;
-  for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+  for (uint32_t i = b; i < count; i += nb) {
     const uint2 sg = segs[i];
     const uint32_t n = sg.y;
     uint2* g = ws.bucket + sg.x;
@@ -624,18 +612,15 @@ __global__ __launch_bounds__(1024) void k_split_global(int round, Ws ws) {
 // elements; each pass first histograms the whole segment so that every round
 // knows where each digit's run starts.
 template <int NW, int ITEMS>
-__global__ __launch_bounds__(NW * 64) void k_sort_x(Ws ws, ListOut out) {
+__device__ void sort_x_blocks(const Ws& ws, const ListOut& out, uint32_t* s_hist,
+                              uint32_t* s_off, uint32_t* s_red, uint32_t* s_glob, uint32_t b,
+                              uint32_t nb) {
   constexpr int ROUND = NW * ITEMS * 64;
-  __shared__ uint32_t s_hist[NW * 256];
-  __shared__ uint32_t s_off[256];
-  __shared__ uint32_t s_red[64];
-  __shared__ uint32_t s_glob[256];
-  if (ws.flags[kFlagOverflow]) return;
   SortSmem sm{nullptr, nullptr, s_hist, s_off, s_red};
   const uint32_t lane = __lane_id();
   const uint32_t w = threadIdx.x >> 6;
   const uint32_t count = ws.flags[kFlagCountX2];
-  for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+  for (uint32_t i = b; i < count; i += nb) {
     const uint2 sg = ws.seg_x2[i];
     const uint32_t s = sg.x, n = sg.y;
     uint32_t kmin = 0xffffffffu, kmax = 0, imin = 0xffffffffu, imax = 0;
@@ -715,32 +700,50 @@ __global__ __launch_bounds__(NW * 64) void k_sort_x(Ws ws, ListOut out) {
   }
 }
 
+// The L class (one 1024-thread block per segment of at most 8192 copies,
+// LSD in LDS) on workgroups [0, gl) and the global-memory LSD sort of what
+// is larger on the rest, in one launch.
+constexpr int kL_NW = 16, kL_ITEMS = kSortCapLB / 1024, kL_CAP = kL_NW * kL_ITEMS * 64;
+
+__global__ __launch_bounds__(1024) void k_sort_lx(int gl, Ws ws, ListOut out) {
+  __shared__ uint32_t s_key[kL_CAP];
+  __shared__ uint32_t s_idx[kL_CAP];
+  __shared__ uint32_t s_hist[kL_NW * 256];
+  __shared__ uint32_t s_off[256];
+  __shared__ uint32_t s_red[64];
+  if (ws.flags[kFlagOverflow]) return;
+  if ((int)blockIdx.x >= gl) {
+    sort_x_blocks<kL_NW, 16>(ws, out, s_hist, s_off, s_red, s_key, blockIdx.x - (uint32_t)gl,
+                             gridDim.x - (uint32_t)gl);
+    return;
+  }
+  const SortSmem sm{s_key, s_idx, s_hist, s_off, s_red};
+  const uint32_t count = ws.flags[kFlagCountL];
+  for (uint32_t i = blockIdx.x; i < count; i += (uint32_t)gl) {
+    const uint2 sg = ws.seg_l[i];
+    sort_segment_lds<kL_NW, kL_ITEMS, false>(ws.bucket + sg.x, sg.y, out, sg.x, sm);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_sort(const Ws& ws, uint32_t* list, uint16_t* lpos, int64_t nt,
                        hipStream_t stream) {
   const ListOut out{list, lpos, ws.lbits, ws.pb};
-  // Grids: the first split round takes one 1024-thread block per tile above
-  // 2048 copies (up to 1024 blocks); the later, rarely busy classes (huge
-  // tiles, second split round, L and X sorts) loop over their segments with
-  // at most 256 or 64 blocks, so that a class with no work costs little more
-  // than a launch.
+  // Every launch costs a few microseconds even without work, so the rarely
+  // busy roles (global splits of huge tiles, the L and X sorts) share
+  // launches with the busy ones and get small grids.
   const int64_t big_max = std::max<int64_t>(1, (int64_t)ws.cap / (int64_t)(kSortCapM + 1));
   const int grid_split = (int)std::min<int64_t>(big_max, 1024);
   const int grid_rare = (int)std::min<int64_t>(big_max, 256);
   const int grid_huge = (int)std::min<int64_t>(std::max<int64_t>(1, (int64_t)ws.cap / (kSortCapL + 1)), 64);
-  hipLaunchKernelGGL(k_split_global, dim3(grid_huge), dim3(1024), 0, stream, 0, ws);
-  hipLaunchKernelGGL(k_split_global, dim3(grid_huge), dim3(1024), 0, stream, 1, ws);
-  hipLaunchKernelGGL(k_split, dim3(grid_split), dim3(1024), 0, stream, 0, ws);
-  hipLaunchKernelGGL(k_split, dim3(grid_rare), dim3(1024), 0, stream, 1, ws);
+  hipLaunchKernelGGL(k_split, dim3(grid_split + grid_huge), dim3(1024), 0, stream, 0, grid_split, ws);
+  hipLaunchKernelGGL(k_split, dim3(grid_rare + grid_huge), dim3(1024), 0, stream, 1, grid_rare, ws);
   const int grid_w = (int)std::min<int64_t>((nt + 3) / 4 + (int64_t)ws.cap / 256, 8192);
   const int grid_m = (int)std::min<int64_t>(nt + (int64_t)ws.cap / 2048, 4096);
   hipLaunchKernelGGL(k_sort_wm, dim3(std::max(grid_m, 1) + std::max(grid_w, 1)), dim3(256), 0,
                      stream, std::max(grid_m, 1), ws.seg_w, ws.seg_m, ws.flags, ws.bucket, out);
-  hipLaunchKernelGGL((k_sort_block<16, kSortCapLB / 1024, kFlagCountL>), dim3(grid_rare),
-                     dim3(1024), 0, stream,
-                     ws.seg_l, ws.flags, ws.bucket, out);
-  hipLaunchKernelGGL((k_sort_x<16, 16>), dim3(64), dim3(1024), 0, stream, ws, out);
+  hipLaunchKernelGGL(k_sort_lx, dim3(grid_rare + 64), dim3(1024), 0, stream, grid_rare, ws, out);
   return hipGetLastError();
 }
 
