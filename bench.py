@@ -71,9 +71,9 @@ def parse():
 ENTRY_KERNELS = {
     "project": ("k_project_count", "k_colscan", "k_clear", "k_groups"),
     "bin": ("k_group_scan", "k_place", "k_scatter"),
-    "sort": ("k_split", "k_sort_w", "k_sort_block", "k_sort_x", "k_lpos"),
+    "sort": ("k_split", "k_sort_w", "k_sort_block", "k_sort_lx", "k_sort_x", "k_lpos"),
     "blend_fwd": ("k_blend_fwd",),
-    "blend_bwd": ("k_zero", "k_blend_bwd", "k_bg_reduce"),
+    "blend_bwd": ("k_zero", "k_blend_bwd", "k_unpack_scalars", "k_bg_reduce"),
     "project_bwd": ("k_project_bwd",),
 }
 CALLS_PER_STEP = {"project": 2, "bin": 2, "sort": 2, "blend_fwd": 1, "blend_bwd": 1,
