@@ -217,11 +217,16 @@ struct Prefetch {
 };
 
 // Point data of one copy per lane gathered straight into LDS (gfx950
-// global_load_lds_dwordx4, one 16-byte quad per lane and instruction, lane l
-// at slot l): the projection record to prj[l], feature quad q of the row to
-// fq[q][l].  Nothing passes through registers, so a fetch issued for the
-// next chunk stays in flight until the chunk is staged.  For rows that are
-// whole quads (C == CP and CP * sizeof(FT) a multiple of 16 bytes).
+// global_load_lds_dwordx4: one 16-byte quad per lane and instruction, lane l
+// of an instruction writes slot l of the instruction's 1 KB block).  The
+// projection record of lane l's copy goes to prj[l].  The feature rows are
+// fetched row-major: flat quad f = 64 k + l of instruction k is quad f mod Q
+// of row f / Q, so Q neighbouring lanes read one row's contiguous bytes
+// (one cache line per Q lanes instead of one per lane), and the rows land in
+// LDS as fq[row * Q + quad].  Nothing passes through registers, so a fetch
+// issued for the next chunk stays in flight until the chunk is staged.  For
+// rows that are whole quads (C == CP and CP * sizeof(FT) a multiple of 16
+// bytes).  Called by the whole wavefront; lanes with v false fetch nothing.
 typedef __attribute__((address_space(3))) void lds_void_t;
 
 template <int CP, typename FT>
@@ -229,23 +234,31 @@ struct DmaRow {
   static constexpr int Q = CP * (int)sizeof(FT) / 16;  // quads per feature row
   static constexpr bool OK = CP * (int)sizeof(FT) % 16 == 0;
 
-  __device__ __forceinline__ static void fetch(const BlendArgs& a, uint32_t idx, float4* prj,
-                                               uint4 (*fq)[64]) {
-    const float4* pp = reinterpret_cast<const float4*>(a.proj) + idx;
-    __builtin_amdgcn_global_load_lds((const void*)pp, (lds_void_t*)prj, 16, 0, 0);
-    const uint4* fr = reinterpret_cast<const uint4*>(reinterpret_cast<const FT*>(a.feat) +
-                                                     (size_t)idx * CP);
+  __device__ __forceinline__ static void fetch(const BlendArgs& a, bool v, uint32_t idx,
+                                               float4* prj, uint4* fq) {
+    const uint32_t lane = __lane_id();
+    if (v) {
+      const float4* pp = reinterpret_cast<const float4*>(a.proj) + idx;
+      __builtin_amdgcn_global_load_lds((const void*)pp, (lds_void_t*)prj, 16, 0, 0);
+    }
+    const uint4* feat = reinterpret_cast<const uint4*>(a.feat);
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
-      __builtin_amdgcn_global_load_lds((const void*)(fr + q), (lds_void_t*)&fq[q][0], 16, 0, 0);
+    for (int k = 0; k < Q; ++k) {
+      const uint32_t f = (uint32_t)k * 64u + lane;
+      const int row = (int)(f / (uint32_t)Q);
+      const uint32_t ridx = (uint32_t)__shfl((int)idx, row, 64);
+      const bool rv = __shfl((int)v, row, 64) != 0;
+      if (rv)
+        __builtin_amdgcn_global_load_lds((const void*)(feat + (size_t)ridx * Q + f % (uint32_t)Q),
+                                         (lds_void_t*)(fq + k * 64), 16, 0, 0);
+    }
   }
 
   // Feature row of this lane's copy as FP32.
-  __device__ __forceinline__ static void row(const uint4 (*fq)[64], uint32_t lane,
-                                             float (&v)[CP]) {
+  __device__ __forceinline__ static void row(const uint4* fq, uint32_t lane, float (&v)[CP]) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const uint4 w = fq[q][lane];
+      const uint4 w = fq[lane * Q + q];
       if constexpr (sizeof(FT) == 4) {
         v[4 * q] = __uint_as_float(w.x); v[4 * q + 1] = __uint_as_float(w.y);
         v[4 * q + 2] = __uint_as_float(w.z); v[4 * q + 3] = __uint_as_float(w.w);
@@ -272,11 +285,11 @@ struct PointFetch {
   Prefetch<CP, FT, FULL> reg;
 
   __device__ __forceinline__ void fetch(const BlendArgs& a, bool v, uint32_t i, float4* prj,
-                                        uint4 (*fq)[64]) {
+                                        uint4* fq) {
     if constexpr (DMA) {
       valid = v;
       idx = v ? i : 0u;
-      if (v) DmaRow<CP, FT>::fetch(a, idx, prj, fq);
+      DmaRow<CP, FT>::fetch(a, v, idx, prj, fq);
     } else {
       reg.fetch(a, v, i);
       valid = reg.valid;
@@ -293,7 +306,7 @@ struct PointFetch {
     if constexpr (DMA) return prj[lane];
     else return reg.p;
   }
-  __device__ __forceinline__ void row(const uint4 (*fq)[64], uint32_t lane, float (&v)[CP]) const {
+  __device__ __forceinline__ void row(const uint4* fq, uint32_t lane, float (&v)[CP]) const {
     if constexpr (DMA) DmaRow<CP, FT>::row(fq, lane, v);
     else reg.f.to_f32(v);
   }
@@ -1109,7 +1122,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
   __shared__ __align__(16) float s_G[64 * fpad(CP)];
   using PF = PointFetch<CP, FT, FULL>;
   __shared__ float4 s_prj[64];             // gathered projection records
-  __shared__ uint4 s_fq[PF::QS][64];       // gathered feature quads
+  __shared__ uint4 s_fq[PF::QS * 64];      // gathered feature rows, row-major
   if (a.flags[kFlagOverflow]) return;
 
   const uint32_t lane = threadIdx.x;

@@ -148,13 +148,21 @@ def backward_scratch_bytes(n: int, C: int, cam: L.Camera, opts: L.Opts) -> int:
 
 
 def blend_backward(b: Binning, feat, cam: L.Camera, opts: L.Opts, ws: torch.Tensor, t_final,
-                   state, grad_out, grad_t=None, bg=None, scratch=None):
-    """Step 5.  Returns grad_feat [n,C] f32, grad_opacity [n], grad_uv [n,2], grad_bg [C]|None."""
+                   state, grad_out, grad_t=None, bg=None, scratch=None, outputs=None):
+    """Step 5.  Returns grad_feat [n,C] f32, grad_opacity [n], grad_uv [n,2], grad_bg [C]|None.
+    outputs: optional preallocated (grad_feat, grad_opacity, grad_uv); every element is
+    overwritten."""
     dev = feat.device
     n, C = feat.shape
-    grad_feat = torch.empty(n, C, dtype=torch.float32, device=dev)
-    grad_opacity = torch.empty(n, dtype=torch.float32, device=dev)
-    grad_uv = torch.empty(n, 2, dtype=torch.float32, device=dev)
+    if outputs is not None:
+        grad_feat, grad_opacity, grad_uv = outputs
+        if (grad_feat.shape != (n, C) or grad_opacity.shape != (n,) or grad_uv.shape != (n, 2)
+                or any(t.dtype != torch.float32 or not t.is_contiguous() for t in outputs)):
+            raise ValueError("outputs must be contiguous f32 [n,C], [n], [n,2]")
+    else:
+        grad_feat = torch.empty(n, C, dtype=torch.float32, device=dev)
+        grad_opacity = torch.empty(n, dtype=torch.float32, device=dev)
+        grad_uv = torch.empty(n, 2, dtype=torch.float32, device=dev)
     grad_bg = torch.empty(C, dtype=torch.float32, device=dev) if bg is not None else None
     if scratch is None:
         scratch = torch.empty(backward_scratch_bytes(n, C, cam, opts), dtype=torch.uint8,

@@ -6,6 +6,7 @@ import torch
 import oracle
 import paper_2508_19140_amd as inpc
 from paper_2508_19140_amd import _lib as L
+from paper_2508_19140_amd import raster
 
 DEV = "cuda:0"
 
@@ -40,7 +41,15 @@ def run_gpu(scene, settings, bg=None, feat_dtype=torch.float32, backward=True, f
     if backward and scene.grad is not None and settings.splat == "bilinear":
         g = torch.from_numpy(scene.grad).to(DEV)
         gt = None if scene.grad_t is None else torch.from_numpy(scene.grad_t).to(DEV)
-        gf, go, guv, gbg = inpc.blend_backward(b, ft, cam, opts, ws, tf, state, g, gt, bgt)
+        # outputs and scratch start as NaN: every element the backward does
+        # not write shows up against the oracle
+        n, C = ft.shape
+        nan = lambda *s: torch.full(s, float("nan"), dtype=torch.float32, device=DEV)
+        scratch = torch.full((raster.backward_scratch_bytes(n, C, cam, opts),), 0xFF,
+                             dtype=torch.uint8, device=DEV)
+        gf, go, guv, gbg = inpc.blend_backward(b, ft, cam, opts, ws, tf, state, g, gt, bgt,
+                                               scratch=scratch,
+                                               outputs=(nan(n, C), nan(n), nan(n, 2)))
         gpos = inpc.project_backward(pos, b, cam, guv)
         torch.cuda.synchronize()
         r.update(grad_feat=gf.cpu().numpy(), grad_opacity=go.cpu().numpy(),
