@@ -866,19 +866,36 @@ __device__ __forceinline__ void add_split_shares(bool mine, uint32_t idx, const 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // every LDS read of the batch is issued before its first atomic
+    constexpr uint32_t IT = (ROWS + PER - 1) / PER;  // feature rows per lane
+    constexpr uint32_t IS = (4 * ROWS + 63) / 64;    // scalar slots per lane
     const uint32_t c = lane % CP;
-    if (c < C) {
-      for (uint32_t row = lane / CP; row < nb; row += PER) {
-        const uint32_t pidx = __float_as_uint(tr[row * RS + CP + 3]);
-        atomicAdd(a.grad_feat + (size_t)pidx * C + c, tr[row * RS + c]);
-      }
+    uint32_t fp[IT], sp[IS];
+    float fv[IT], sv[IS];
+#pragma unroll
+    for (uint32_t it = 0; it < IT; ++it) {
+      const uint32_t row = lane / CP + it * PER;
+      const bool ok = c < (uint32_t)C && row < nb;
+      fp[it] = ok ? __float_as_uint(tr[row * RS + CP + 3]) : 0u;
+      fv[it] = ok ? tr[row * RS + c] : 0.f;
     }
     // opacity and position: one 16-byte scalar row per point, 4 lanes each
-    for (uint32_t k = lane; k < 4 * nb; k += 64) {
-      const uint32_t row = k >> 2, comp = k & 3u;
-      const float* rr = tr + row * RS;
-      const uint32_t pidx = __float_as_uint(rr[CP + 3]);
-      if (comp < 3) atomicAdd(reinterpret_cast<float*>(a.gsc + pidx) + comp, rr[CP + comp]);
+#pragma unroll
+    for (uint32_t is = 0; is < IS; ++is) {
+      const uint32_t k = lane + 64u * is, row = k >> 2, comp = k & 3u;
+      const bool ok = row < nb && comp < 3u;
+      sp[is] = ok ? __float_as_uint(tr[row * RS + CP + 3]) : 0u;
+      sv[is] = ok ? tr[row * RS + CP + comp] : 0.f;
+    }
+#pragma unroll
+    for (uint32_t it = 0; it < IT; ++it)
+      if (c < (uint32_t)C && lane / CP + it * PER < nb)
+        atomicAdd(a.grad_feat + (size_t)fp[it] * C + c, fv[it]);
+#pragma unroll
+    for (uint32_t is = 0; is < IS; ++is) {
+      const uint32_t k = lane + 64u * is;
+      if ((k >> 2) < nb && (k & 3u) < 3u)
+        atomicAdd(reinterpret_cast<float*>(a.gsc + sp[is]) + (k & 3u), sv[is]);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1172,10 +1189,14 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
   const uint32_t lend = start + maxlast;
   float Pi = 1.f, Tcur = 0.f;
   const int nsc = (int)((maxlast + SC - 1) / SC);
+  // the entries of the next super-chunk (towards the front) are loaded
+  // while this one is compacted and replayed
+  SuperEntries nxt;
+  if (nsc > 0) nxt.load(a, start + (uint32_t)(nsc - 1) * SC, lend);
   for (int k = nsc - 1; k >= 0; --k) {
     const uint32_t base = start + (uint32_t)k * SC;
-    SuperEntries cur;
-    cur.load(a, base, lend);
+    const SuperEntries cur = nxt;
+    if (k >= 1) nxt.load(a, base - SC, lend);
     // a pixel takes part in chunk j if its blended range reaches the chunk
     uint64_t act[kSubs];
 #pragma unroll
