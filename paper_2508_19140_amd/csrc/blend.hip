@@ -1345,15 +1345,18 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
   }
 }
 
-// Zero n floats at p (4-byte aligned): 16-byte stores for the aligned body.
+// Zero n floats at p (4-byte aligned): 16-byte non-temporal stores for the
+// aligned body (a streaming fill that nothing reads back soon).
 __device__ __forceinline__ void zero_range(float* __restrict__ p, size_t n, size_t tid,
                                            size_t stride) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
   const size_t mis = (size_t)(reinterpret_cast<uintptr_t>(p) & 15u);
   const size_t head = min(n, ((16u - mis) & 15u) / 4u);
   const size_t nv = (n - head) / 4u;
   if (tid < head) p[tid] = 0.f;
-  uint4* v = reinterpret_cast<uint4*>(p + head);
-  for (size_t i = tid; i < nv; i += stride) v[i] = make_uint4(0u, 0u, 0u, 0u);
+  u32x4* v = reinterpret_cast<u32x4*>(p + head);
+  const u32x4 z = {0u, 0u, 0u, 0u};
+  for (size_t i = tid; i < nv; i += stride) __builtin_nontemporal_store(z, v + i);
   const size_t tail0 = head + nv * 4u;
   if (tid < n - tail0) p[tail0 + tid] = 0.f;
 }
