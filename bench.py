@@ -61,6 +61,10 @@ def parse():
                     help="HBM traffic per launch of --entry from two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) of --profile-steps S --copy-probe-mib M, "
                          "scaled by the copy's counters; prints a profiles/pmc_*.txt record")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="print a markdown table of any rocprofv3 --pmc run "
+                         "(DIR/run_counter_collection.csv): every counter per kernel, "
+                         "averaged over its calls, and exit")
     ap.add_argument("--entry", default="blend_bwd", help="entry point for --summarize-pmc")
     ap.add_argument("--command", default="", help="command line recorded in a summary")
     return ap.parse_args()
@@ -123,6 +127,25 @@ def summarize_trace(d, steps, command):
     for e, t in sorted(per_entry.items(), key=lambda x: -x[1]):
         print(f"| inpc_{e} | {t / steps / CALLS_PER_STEP[e] / 1e3:.1f} |")
     print(f"\nsum of kernel time per step: {tot / steps / 1e3:.1f} us")
+
+
+def summarize_counters(d, command):
+    import csv
+    from collections import defaultdict
+    vals = defaultdict(lambda: defaultdict(list))
+    for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+        k = _kernel_short(r["Kernel_Name"])
+        if _entry_of(k):
+            vals[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    names = sorted({c for k in vals for c in vals[k]})
+    print(f"Command: `{command}`\n")
+    print("rocprofv3 counters per kernel launch (mean over the launches of the run).\n")
+    print("| kernel | entry point | " + " | ".join(names) + " |")
+    print("|---|---|" + "---:|" * len(names))
+    for k in sorted(vals):
+        row = [f"{sum(vals[k][c]) / len(vals[k][c]):.4g}" if vals[k].get(c) else "-"
+               for c in names]
+        print(f"| `{k}` | {_entry_of(k)} | " + " | ".join(row) + " |")
 
 
 def summarize_pmc(fetch_dir, write_dir, entry, steps, command):
@@ -364,6 +387,9 @@ def main():
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc, args.entry, args.profile_steps or 1, args.command)
         return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.command)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU: the rasterizer shards by view, one view per GPU, "
               "and this build measures the single-GPU path only (--gpus 1).", file=sys.stderr)
@@ -421,6 +447,7 @@ def main():
     for nm in phase_ms:
         per_launch_ms[nm] = phase_ms[nm] / count[nm]
 
+    copy_gbs = copy_bandwidth(dev)
     ntiles = step.ntiles.cpu().numpy()
     V = int((ntiles > 0).sum())
     M = int(step.ranges[-1].item())
@@ -460,9 +487,13 @@ def main():
         "B_method_GBps": b_method / t_s / 1e9,
         "B_min_frac": b_min / t_s / 1e9 / HBM_PEAK_GBS,
         "B_method_frac": b_method / t_s / 1e9 / HBM_PEAK_GBS,
+        "copy_bw_GBps": copy_gbs,
+        "B_min_frac_of_copy": b_min / t_s / 1e9 / copy_gbs,
+        "B_method_frac_of_copy": b_method / t_s / 1e9 / copy_gbs,
         "phase_ms": phase_ms,
         "roofline": {"bound": "hbm", "kernel": f"inpc_{dominant}", "achieved": dom_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS,
+                     "frac_of_copy": dom_gbs / copy_gbs,
                      "bytes_per_launch": dom_bytes, "ms_per_launch": per_launch_ms[dominant],
                      "traffic": measured_traffic(dominant, args.config)},
     }
@@ -471,6 +502,25 @@ def main():
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(sc)
     print(json.dumps(res), flush=True)
+
+
+def copy_bandwidth(dev, mib=512, reps=5):
+    """Bytes read plus written per second by a plain device-to-device copy of
+    `mib` MiB (torch's copy kernel), the practical HBM rate of this device."""
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return 2.0 * (mib << 20) / sec / 1e9
 
 
 if __name__ == "__main__":
