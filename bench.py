@@ -65,6 +65,9 @@ def parse():
                     help="print a markdown table of any rocprofv3 --pmc run "
                          "(DIR/run_counter_collection.csv): every counter per kernel, "
                          "averaged over its calls, and exit")
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="time the CPU oracle (fwd+bwd frames of C1, C2 and H) on one thread "
+                         "and on all threads of this host, print one JSON line per row and exit")
     ap.add_argument("--entry", default="blend_bwd", help="entry point for --summarize-pmc")
     ap.add_argument("--command", default="", help="command line recorded in a summary")
     return ap.parse_args()
@@ -284,6 +287,39 @@ def cpu_baseline(sc):
                       f"{dt:.1f} s wall"}
 
 
+def cpu_table():
+    """The oracle's wall time for one forward + backward frame, single-threaded
+    and on every host thread: median of 3 for C1 and C2, one run for H."""
+    import statistics
+    import oracle
+    from scenes import CONFIGS, make_scene
+    oracle.build(force=False)
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    all_threads = oracle.num_threads()
+    print(json.dumps({"cpu_model": model, "nproc": os.cpu_count(),
+                      "oracle_threads_all": all_threads}), flush=True)
+    for cfg, reps in (("C1", 3), ("C2", 3), ("H", 1)):
+        sc = make_scene(CONFIGS[cfg])
+        for thr in (all_threads, 1):
+            oracle.set_num_threads(thr)
+            times = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                oracle.render(sc.camera, sc.pos, sc.opacity, sc.feat, grad_out=sc.grad)
+                times.append(time.perf_counter() - t0)
+            med = statistics.median(times)
+            print(json.dumps({"config": cfg, "points": sc.n, "threads": thr, "runs": reps,
+                              "median_s": med, "points_per_s": sc.n / med}), flush=True)
+    oracle.set_num_threads(all_threads)
+
+
 def error_table(step, sc, tile):
     """max abs / max rel / RMS of every output against the oracle, on the
     stored (possibly rounded) features and on the original FP32 features."""
@@ -389,6 +425,9 @@ def main():
         return
     if args.summarize_counters:
         summarize_counters(args.summarize_counters, args.command)
+        return
+    if args.cpu_table:
+        cpu_table()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU: the rasterizer shards by view, one view per GPU, "

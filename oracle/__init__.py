@@ -71,6 +71,8 @@ def _load():
         lib.oracle_count_fragments.restype = ctypes.c_int64
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_num_threads.restype = None
         _lib = lib
     return _lib
 
@@ -113,6 +115,11 @@ def _f32(a, shape=None):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (timing only)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def project(camera, pos, radius=None, splat=SPLAT_BILINEAR, tile=8, dilation=0.16, cutoff=3.0):

@@ -559,3 +559,13 @@ int oracle_num_threads(void) {
     return 1;
 #endif
 }
+
+/* Threads of the following parallel loops (timing only; results do not
+   depend on it: every pixel is computed by one thread in a fixed order). */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
