@@ -15,6 +15,7 @@ pytestmark = [pytest.mark.gpu,
 
 from gpu_helpers import (  # noqa: E402
     assert_backward, assert_binning_exact, assert_forward, run_gpu, run_oracle, settings_opts)
+from paper_2508_19140_amd import _lib as L  # noqa: E402
 
 
 def small_c2(n=1 << 17, W=320, H=180, seed=0, channels=16):
@@ -129,6 +130,24 @@ def test_many_tiles_global_binning():
     ok = rrg["flags"] == 0  # FP64 T on the t_min threshold: excluded, as for every Gaussian test
     assert ok.mean() > 0.99
     assert_forward(gg, rrg, flags_ok=ok)
+
+
+def test_capacity_overflow_reported():
+    """Gaussians wider than opts.max_radius touch more tiles than the
+    workspace was sized for: the kernels stop at the overflow flag and
+    inpc_check_sync reports INPC_ERR_CAPACITY; the next call is exact again."""
+    sc = tiny_scene(3000, 96, 64, channels=4, seed=5, radius_range=(10.0, 12.0))
+    st = settings_opts(splat="gaussian", tile=8, max_radius=3.0)
+    with pytest.raises(L.InpcError) as ei:
+        run_gpu(sc, st, backward=False)
+    assert ei.value.status == L.INPC_ERR_CAPACITY
+    ok_sc = tiny_scene(800, 37, 23, channels=3, seed=60)
+    ok_st = settings_opts(tile=8)
+    g = run_gpu(ok_sc, ok_st)
+    proj, tl, rr = run_oracle(ok_sc, ok_st)
+    assert_binning_exact(g, proj, tl)
+    assert_forward(g, rr)
+    assert_backward(g, rr, ok_sc.grad)
 
 
 def test_empty_and_culled():
