@@ -431,7 +431,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU: the rasterizer shards by view, one view per GPU, "
-              "and this build measures the single-GPU path only (--gpus 1).", file=sys.stderr)
+              "and this benchmark measures the single-GPU path only (--gpus 1).", file=sys.stderr)
         sys.exit(2)
     if args.config == "C4":
         run_multiview(args)
