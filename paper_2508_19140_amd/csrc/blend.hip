@@ -1152,6 +1152,15 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
   const int64_t p = (int64_t)py * a.cam.W + px;
   const int C = a.C;
 
+  // the forward pass blended nothing beyond list position st_tile[tile];
+  // the entries of the last super-chunk it reached are loaded together with
+  // this tile's upstream gradient and blend state
+  const uint32_t maxlast = min(a.st_tile[tile], end - start);
+  const uint32_t lend = start + maxlast;
+  const int nsc = (int)((maxlast + SC - 1) / SC);
+  SuperEntries nxt;
+  if (nsc > 0) nxt.load(a, start + (uint32_t)(nsc - 1) * SC, lend);
+
   float gB = 0.f, GT = 0.f, Tf = 0.f, t_anchor = 0.f;
   uint32_t last = 0, anchor = 0;
   {
@@ -1184,15 +1193,9 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
   }
   tile_sync<1>();  // s_G is read by the copies' lanes below
 
-  // the forward pass blended nothing beyond list position st_tile[tile]
-  const uint32_t maxlast = min(a.st_tile[tile], end - start);
-  const uint32_t lend = start + maxlast;
   float Pi = 1.f, Tcur = 0.f;
-  const int nsc = (int)((maxlast + SC - 1) / SC);
   // the entries of the next super-chunk (towards the front) are loaded
   // while this one is compacted and replayed
-  SuperEntries nxt;
-  if (nsc > 0) nxt.load(a, start + (uint32_t)(nsc - 1) * SC, lend);
   for (int k = nsc - 1; k >= 0; --k) {
     const uint32_t base = start + (uint32_t)k * SC;
     const SuperEntries cur = nxt;
