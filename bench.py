@@ -543,13 +543,14 @@ def main():
     print(json.dumps(res), flush=True)
 
 
-def copy_bandwidth(dev, mib=512, reps=5):
+def copy_bandwidth(dev, mib=512, reps=20):
     """Bytes read plus written per second by a plain device-to-device copy of
     `mib` MiB (torch's copy kernel), the practical HBM rate of this device."""
     import torch
     src = torch.ones(mib << 18, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
-    dst.copy_(src)
+    for _ in range(3):
+        dst.copy_(src)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
