@@ -10,6 +10,19 @@ Two tiers, sharing nothing with the GPU path:
     FP32 decision arithmetic.  Wrapped here with ctypes.
   * ``brute.py``: an O(pixels x points) pure-Python brute force for tiny
     scenes, which pins the C tier.
+
+Pins (tests/test_oracle_pins.py, test_oracle_brute.py, test_oracle_grad.py,
+test_golden.py): projection and tile lists by closed-form tile counts per
+sub-tile position and their mean (1 + 1/T)^2, by the partition and order of
+the ranges, and by the brute force; the forward by closed forms for one,
+two and three splats, alpha = 1 occlusion, a single Gaussian's profile,
+telescoping, linearity and input-order invariance; the backward by torch
+float64 autograd of Eq. (1) and by central finite differences.  Every
+function here has a pin.  What the paper leaves open (pixel-centre
+convention, near plane, termination threshold, tie-break by index, Gaussian
+radius semantics, bounding-box tile membership) is a reading of this
+implementation, not a printed value: parity unpinned by the paper for those
+readings, which the pins exercise but cannot confirm.
 """
 from __future__ import annotations
 
