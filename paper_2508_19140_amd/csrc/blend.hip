@@ -902,6 +902,102 @@ __device__ __forceinline__ void add_split_shares(bool mine, uint32_t idx, const 
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
+// The 8x8 backward's gradient writes for one virtual chunk: every copy with
+// `has` set is staged in `tr` as a row of CP + 4 floats (features, opacity,
+// u, v, point index with bit 31 set for a single-tile point).  A single-tile
+// point's row is stored whole, Q = CP / 4 neighbouring lanes writing the
+// 16-byte quads of one row, so one store instruction covers 64 / Q rows; a
+// split point's share is added with float atomics, CP lanes per row.
+template <int CP>
+__device__ __forceinline__ void write_chunk_rows(bool has, bool single, uint32_t idx,
+                                                 const float (&g)[CP], float go, float gu,
+                                                 float gv, float* __restrict__ tr,
+                                                 const BlendArgs& a) {
+  constexpr uint32_t RS = CP + 4;
+  constexpr uint32_t ROWS = 512 / RS;
+  constexpr uint32_t PER = 64 / CP;
+  constexpr uint32_t Q = CP / 4;
+  constexpr uint32_t IT = (ROWS + PER - 1) / PER;  // feature slots per lane (atomics)
+  constexpr uint32_t IS = (4 * ROWS + 63) / 64;    // scalar slots per lane
+  constexpr uint32_t IQ = (ROWS * Q + 63) / 64;    // quad slots per lane (stores)
+  const uint64_t m = __ballot(has);
+  if (m == 0ull) return;
+  const uint32_t lane = __lane_id();
+  const uint32_t total = (uint32_t)__popcll(m);
+  const uint32_t r = mbcnt64(m);
+  const uint32_t C = (uint32_t)a.C;
+  const uint32_t kSingle = 0x80000000u;
+  for (uint32_t b0 = 0; b0 < total; b0 += ROWS) {
+    const uint32_t nb = min(total - b0, ROWS);
+    if (has && r >= b0 && r < b0 + nb) {
+      float4* d = reinterpret_cast<float4*>(tr + (r - b0) * RS);
+#pragma unroll
+      for (int q = 0; q < CP / 4; ++q)
+        d[q] = make_float4(g[4 * q], g[4 * q + 1], g[4 * q + 2], g[4 * q + 3]);
+      d[CP / 4] = make_float4(go, gu, gv, __uint_as_float(idx | (single ? kSingle : 0u)));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // single-tile rows: whole-row stores
+    if (C == CP) {
+#pragma unroll
+      for (uint32_t iq = 0; iq < IQ; ++iq) {
+        const uint32_t slot = lane + 64u * iq, row = slot / Q, qd = slot % Q;
+        if (row < nb) {
+          const uint32_t w = __float_as_uint(tr[row * RS + CP + 3]);
+          if (w & kSingle) {
+            const float4 v = *reinterpret_cast<const float4*>(tr + row * RS + 4 * qd);
+            reinterpret_cast<float4*>(a.grad_feat + (size_t)(w & ~kSingle) * C)[qd] = v;
+          }
+        }
+      }
+    } else {
+      for (uint32_t slot = lane; slot < nb * CP; slot += 64u) {
+        const uint32_t row = slot / CP, c = slot % CP;
+        const uint32_t w = __float_as_uint(tr[row * RS + CP + 3]);
+        if ((w & kSingle) && c < C) a.grad_feat[(size_t)(w & ~kSingle) * C + c] = tr[row * RS + c];
+      }
+    }
+    for (uint32_t row = lane; row < nb; row += 64u) {
+      const uint32_t w = __float_as_uint(tr[row * RS + CP + 3]);
+      if (w & kSingle)
+        a.gsc[w & ~kSingle] =
+            make_float4(tr[row * RS + CP], tr[row * RS + CP + 1], tr[row * RS + CP + 2], 0.f);
+    }
+    // split rows: every LDS read of the batch is issued before its first atomic
+    const uint32_t c = lane % CP;
+    uint32_t fp[IT], sp[IS];
+    float fv[IT], sv[IS];
+#pragma unroll
+    for (uint32_t it = 0; it < IT; ++it) {
+      const uint32_t row = lane / CP + it * PER;
+      const bool ok = c < C && row < nb;
+      fp[it] = ok ? __float_as_uint(tr[row * RS + CP + 3]) : kSingle;
+      fv[it] = ok ? tr[row * RS + c] : 0.f;
+    }
+#pragma unroll
+    for (uint32_t is = 0; is < IS; ++is) {
+      const uint32_t k = lane + 64u * is, row = k >> 2, comp = k & 3u;
+      const bool ok = row < nb && comp < 3u;
+      sp[is] = ok ? __float_as_uint(tr[row * RS + CP + 3]) : kSingle;
+      sv[is] = ok ? tr[row * RS + CP + comp] : 0.f;
+    }
+#pragma unroll
+    for (uint32_t it = 0; it < IT; ++it)
+      if (!(fp[it] & kSingle)) atomicAdd(a.grad_feat + (size_t)fp[it] * C + c, fv[it]);
+#pragma unroll
+    for (uint32_t is = 0; is < IS; ++is) {
+      const uint32_t k = lane + 64u * is;
+      if (!(sp[is] & kSingle))
+        atomicAdd(reinterpret_cast<float*>(a.gsc + sp[is]) + (k & 3u), sv[is]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 template <int T, int CP, typename FT, bool FULL>
 __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
   using G = TileGeom<T>;
@@ -1335,13 +1431,10 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
         }
         gu *= co;
         gv *= co;
+        // the only tile of a single-tile point writes its whole gradient
         single = single_tile<T>(cur_lp, tx, ty, a.cam.W, a.cam.H);
-        if (single) {  // the only tile of this point: its whole gradient
-          store_row<CP>(a.grad_feat + (size_t)cur_idx * C, gfeat, C);
-          a.gsc[cur_idx] = make_float4(go, gu, gv, 0.f);
-        }
       }
-      add_split_shares<CP>(cur_has && !single, cur_idx, gfeat, go, gu, gv,
+      write_chunk_rows<CP>(cur_has, single, cur_idx, gfeat, go, gu, gv,
                            reinterpret_cast<float*>(s_acc), a);
       tile_sync<1>();
     }
