@@ -30,7 +30,14 @@
  *  - Data-dependent capacity overflow (more tile copies than the workspace
  *    holds, e.g. Gaussians larger than opts.max_radius) cannot be seen on
  *    the host without a sync: the kernels set a flag in the workspace and
- *    skip their work; inpc_check_sync() reports it as INPC_ERR_CAPACITY.
+ *    skip their work, leaving every output undefined; inpc_check_sync()
+ *    reports it as INPC_ERR_CAPACITY.  The flag is sticky: later builds on
+ *    the same workspace skip their work too until inpc_check_sync() has
+ *    reported (and cleared) it.  A new workspace must therefore start
+ *    zeroed (at least its first 64 bytes).
+ *  - Alignment: the workspace, proj, feat, grad_feat and the backward
+ *    scratch are read or written as 16-byte vectors and must be 16-byte
+ *    aligned, grad_uv 8-byte aligned (INPC_ERR_INVALID otherwise).
  *  - Discrete decisions (culling, footprints, tile membership, sort keys)
  *    use IEEE FP32 with one rounding per operation and no fused
  *    multiply-add, so they are reproducible bit for bit.
@@ -247,8 +254,9 @@ inpc_status_t inpc_project_backward(const inpc_camera_t* cam, int64_t n, const f
                                     float* grad_pos, void* stream);
 
 /* The only synchronising call: waits for `stream`, then returns
- * INPC_ERR_CAPACITY if any kernel since the workspace was last reset (by
- * inpc_project) ran out of copy capacity, INPC_OK otherwise. */
+ * INPC_ERR_CAPACITY if any build on this workspace since the last
+ * inpc_check_sync() ran out of copy capacity (and clears the flag, so the
+ * next build runs), INPC_OK otherwise. */
 inpc_status_t inpc_check_sync(void* ws, size_t ws_bytes, void* stream);
 
 /* Static description of a status code. */

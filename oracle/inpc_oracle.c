@@ -256,8 +256,14 @@ static int cmp_frag(const void* pa, const void* pb) {
     return 0;
 }
 
+/* Fragments of every visible point; with a pixel mask, only those on
+ * masked pixels (a sampled subset of the image, for scenes whose full
+ * fragment set would not fit in memory: each kept pixel's list is still
+ * complete, so its blend is exact). */
+static int keep_pixel(const uint8_t* mask, int64_t pixel) { return !mask || mask[pixel]; }
+
 static void build_fragments(const ocam_t* cam, const oopts_t* o, int64_t n, const float* pos,
-                            const float* radius, oscene_t* s) {
+                            const float* radius, const uint8_t* mask, oscene_t* s) {
     const int W = cam->width, H = cam->height;
     const int64_t P = (int64_t)W * H;
     s->pts = (opoint_t*)malloc(sizeof(opoint_t) * (size_t)(n > 0 ? n : 1));
@@ -269,11 +275,14 @@ static void build_fragments(const ocam_t* cam, const oopts_t* o, int64_t n, cons
         s->pt_start[i] = cnt;
         if (!q->visible) continue;
         if (o->splat == 0) {
-            cnt += (int64_t)(q->px1 - q->px0 + 1) * (q->py1 - q->py0 + 1);
+            for (int py = q->py0; py <= q->py1; ++py)
+                for (int px = q->px0; px <= q->px1; ++px)
+                    cnt += keep_pixel(mask, (int64_t)py * W + px);
         } else {
             for (int py = q->py0; py <= q->py1; ++py)
                 for (int px = q->px0; px <= q->px1; ++px) {
                     float d2;
+                    if (!keep_pixel(mask, (int64_t)py * W + px)) continue;
                     cnt += gauss_frag(q, px, py, &d2);
                 }
         }
@@ -292,6 +301,7 @@ static void build_fragments(const ocam_t* cam, const oopts_t* o, int64_t n, cons
                 int dx = c & 1, dy = c >> 1;
                 int px = q->x0 + dx, py = q->y0 + dy;
                 if (px < 0 || px >= W || py < 0 || py >= H) continue;
+                if (!keep_pixel(mask, (int64_t)py * W + px)) continue;
                 ofrag_t* g = &s->frag[f++];
                 g->pixel = (int64_t)py * W + px;
                 g->key = q->key;
@@ -309,6 +319,7 @@ static void build_fragments(const ocam_t* cam, const oopts_t* o, int64_t n, cons
             for (int py = q->py0; py <= q->py1; ++py)
                 for (int px = q->px0; px <= q->px1; ++px) {
                     float d2;
+                    if (!keep_pixel(mask, (int64_t)py * W + px)) continue;
                     if (!gauss_frag(q, px, py, &d2)) continue;
                     ofrag_t* g = &s->frag[f++];
                     g->pixel = (int64_t)py * W + px;
@@ -361,6 +372,9 @@ static void free_scene(oscene_t* s) {
  * Backward outputs: grad_feat [n][C], grad_opacity [n], grad_uv [n][2],
  *                   grad_pos [n][3], grad_bg [C] (if bg), and the matching
  *                   *_abs magnitude bounds (same shapes).
+ * pixel_mask:       [H][W] or NULL: forward only, computes the masked pixels
+ *                   (the others are left as zero); -1 if combined with a
+ *                   backward pass.
  */
 int oracle_render(const ocam_t* cam, const oopts_t* o, int64_t n, const float* pos,
                   const float* radius, const float* opacity, const double* feat, int32_t C,
@@ -369,12 +383,13 @@ int oracle_render(const ocam_t* cam, const oopts_t* o, int64_t n, const float* p
                   const float* grad_t, double* grad_feat, double* grad_opacity,
                   double* grad_uv, double* grad_pos, double* grad_bg,
                   double* grad_feat_abs, double* grad_opacity_abs, double* grad_uv_abs,
-                  double* grad_pos_abs) {
+                  double* grad_pos_abs, const uint8_t* pixel_mask) {
     const int W = cam->width, H = cam->height;
     const int64_t P = (int64_t)W * H;
+    if (pixel_mask && grad_out) return -1;
     oscene_t s;
     memset(&s, 0, sizeof(s));
-    build_fragments(cam, o, n, pos, radius, &s);
+    build_fragments(cam, o, n, pos, radius, pixel_mask, &s);
     const float t_min = o->t_min;
     const int do_bwd = grad_out != NULL;
 
@@ -388,6 +403,7 @@ int oracle_render(const ocam_t* cam, const oopts_t* o, int64_t n, const float* p
         int64_t tk_cap = 0;
 #pragma omp for schedule(dynamic, 64)
         for (int64_t p = 0; p < P; ++p) {
+            if (!keep_pixel(pixel_mask, p)) continue;
             const int64_t s0 = s.pix_start[p], s1 = s.pix_start[p + 1];
             if (s1 - s0 > tk_cap) {
                 tk_cap = (s1 - s0) * 2;

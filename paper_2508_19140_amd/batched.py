@@ -69,7 +69,7 @@ class ViewPipeline:
         H, W = self.cam.height, self.cam.width
         mk = lambda *s, dt=torch.float32: torch.empty(*s, dtype=dt, device=dev)
         i32 = torch.int32
-        self.ws = mk(wsb, dt=torch.uint8)
+        self.ws = torch.zeros(wsb, dtype=torch.uint8, device=dev)  # overflow flag starts clear
         self.proj, self.key, self.ntiles = mk(n, 4), mk(n, dt=i32), mk(n, dt=i32)
         self.ranges, self.order = mk(nt + 1, dt=i32), mk(max(nt, 1), dt=i32)
         self.list, self.lpos = mk(max(cap, 1), dt=i32), mk(max(cap, 1), dt=torch.int16)

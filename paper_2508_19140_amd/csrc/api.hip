@@ -196,6 +196,8 @@ inpc_status_t check_common(const inpc_camera_t* cam, const inpc_opts_t* opts, in
   if (copy_capacity(n, cam, opts) > (int64_t)0xffffffffLL)
     return fail(INPC_ERR_INVALID, "copy capacity does not fit 32 bits%s", "");
   if (!ws) return fail(INPC_ERR_INVALID, "null %s", "workspace");
+  if (reinterpret_cast<uintptr_t>(ws) % 16)
+    return fail(INPC_ERR_INVALID, "%s not 16-byte aligned", "workspace");
   if (ws_bytes < layout(n, cam, opts).total)
     return fail(INPC_ERR_INVALID, "workspace smaller than inpc_workspace_bytes()%s", "");
   return INPC_OK;
@@ -203,6 +205,14 @@ inpc_status_t check_common(const inpc_camera_t* cam, const inpc_opts_t* opts, in
 
 #define REQUIRE(ptr, name) \
   if (!(ptr)) return fail(INPC_ERR_INVALID, "null %s", name)
+
+// Arrays the kernels read or write as 16-byte (or 8-byte) vectors.
+#define REQUIRE_ALIGNED(ptr, name, bytes)                              \
+  do {                                                                 \
+    REQUIRE(ptr, name);                                                \
+    if (reinterpret_cast<uintptr_t>(ptr) % (bytes))                    \
+      return fail(INPC_ERR_INVALID, "%s not " #bytes "-byte aligned", name); \
+  } while (0)
 
 // Projection records are read as 16-byte vectors.
 #define REQUIRE_PROJ(ptr)                                  \
@@ -334,7 +344,7 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
   if (opts->splat == INPC_SPLAT_BILINEAR) REQUIRE(lpos, "lpos");
   if (n > 0) {
     REQUIRE_PROJ(proj);
-    REQUIRE(feat, "feat");
+    REQUIRE_ALIGNED(feat, "feat", 16);
   }
   const Ws w = make_ws(ws, n, cam, opts);
   BlendArgs a;
@@ -389,13 +399,15 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
   REQUIRE(t_final, "t_final");
   REQUIRE(state, "state");
   REQUIRE(grad_out, "grad_out");
+  if (reinterpret_cast<uintptr_t>(scratch) % 16)
+    return fail(INPC_ERR_INVALID, "%s not 16-byte aligned", "scratch");
   if (n > 0) {
     REQUIRE_PROJ(proj);
-    REQUIRE(feat, "feat");
+    REQUIRE_ALIGNED(feat, "feat", 16);
     REQUIRE(ntiles, "ntiles");
-    REQUIRE(grad_feat, "grad_feat");
+    REQUIRE_ALIGNED(grad_feat, "grad_feat", 16);
     REQUIRE(grad_opacity, "grad_opacity");
-    REQUIRE(grad_uv, "grad_uv");
+    REQUIRE_ALIGNED(grad_uv, "grad_uv", 8);
   }
   const Ws w = make_ws(ws, n, cam, opts);
   BlendArgs a;
@@ -458,6 +470,10 @@ inpc_status_t inpc_check_sync(void* ws, size_t ws_bytes, void* stream) {
   if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "inpc_check_sync");
   if (flag) {
+    // reported once: the flag is cleared so that the next build runs again
+    e = hipMemsetAsync(ws, 0, sizeof(uint32_t), (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "inpc_check_sync");
     snprintf(g_err, sizeof(g_err), "tile copies exceeded the workspace capacity");
     return INPC_ERR_CAPACITY;
   }

@@ -127,6 +127,11 @@ __device__ __forceinline__ float fmul(float a, float b) { return __fmul_rn(a, b)
 __device__ __forceinline__ float fadd(float a, float b) { return __fadd_rn(a, b); }
 __device__ __forceinline__ float fsub(float a, float b) { return __fsub_rn(a, b); }
 __device__ __forceinline__ float fdiv(float a, float b) { return __fdiv_rn(a, b); }
+// Correctly rounded square root.  (HIP's __fsqrt_rn is the native
+// v_sqrt_f32, which is off by an ulp for some inputs; sqrtf is lowered to
+// the native root plus an FMA correction step, correctly rounded like the
+// divide, under HIP's default correctly-rounded divide/sqrt mode.)
+__device__ __forceinline__ float fsqrt(float a) { return sqrtf(a); }
 
 // Camera-space position and image coordinates of one point.
 struct Proj {
@@ -189,7 +194,7 @@ __device__ __forceinline__ Footprint gaussian_footprint(float u, float v, float 
   f.x0 = f.y0 = 0;
   f.a = f.b = 0.f;
   const float s2 = fadd(fmul(r, r), dilation);
-  const float Rc = fmul(cutoff, __fsqrt_rn(s2));
+  const float Rc = fmul(cutoff, fsqrt(s2));
   const float xs = fsub(u, 0.5f), ys = fsub(v, 0.5f);
   float lx = ceilf(fsub(xs, Rc)), hx = floorf(fadd(xs, Rc));
   float ly = ceilf(fsub(ys, Rc)), hy = floorf(fadd(ys, Rc));

@@ -92,9 +92,11 @@ __global__ __launch_bounds__(kBinBlock) void k_project_count(Cam cam, Opts o, in
                                                              uint32_t* __restrict__ flags) {
   __shared__ uint32_t bins[kLdsBins];
   const int nt = o.ntx * o.nty;
-  // the workspace flags of this pass start at zero (no other block of this
-  // kernel reads them)
-  if (blockIdx.x == 0 && threadIdx.x < kFlagSlots) flags[threadIdx.x] = 0u;
+  // the per-build counters of the workspace start at zero (no other block of
+  // this kernel reads them); the overflow flag is sticky: only
+  // inpc_check_sync, which reports it, clears it
+  if (blockIdx.x == 0 && threadIdx.x < kFlagSlots && threadIdx.x != kFlagOverflow)
+    flags[threadIdx.x] = 0u;
   for (int t = threadIdx.x; t < nt; t += kBinBlock) bins[t] = 0u;
   __syncthreads();
   const int sh = tile_shift(o.T);
@@ -518,8 +520,9 @@ hipError_t launch_project(const Cam& cam, const Opts& o, int64_t n, const float*
                           const Ws& ws, hipStream_t s) {
   const int64_t nt = (int64_t)o.ntx * o.nty;
   hipError_t e = hipSuccess;
-  if (n == 0 || nt > kLdsBins) {  // else k_project_count clears the flags
-    e = launch_clear(ws.flags, kFlagSlots, s);
+  if (n == 0 || nt > kLdsBins) {  // else k_project_count clears the counters
+    static_assert(kFlagOverflow == 0, "the sticky overflow flag is slot 0");
+    e = launch_clear(ws.flags + 1, kFlagSlots - 1, s);
     if (e != hipSuccess) return e;
     e = launch_clear(ws.tile_count, (size_t)nt, s);
     if (e != hipSuccess) return e;

@@ -60,7 +60,11 @@ def _stream(device) -> ctypes.c_void_p:
 
 
 class Workspace:
-    """Device scratch for one rasterizer: grown on demand, reused across calls."""
+    """Device scratch for one rasterizer: grown on demand, reused across calls.
+
+    A workspace holds the tile buckets, counters and the sticky overflow flag
+    of the calls made with it, so calls that may run concurrently (on
+    different streams) must not share one."""
 
     def __init__(self):
         self.buf: Optional[torch.Tensor] = None
@@ -71,7 +75,8 @@ class Workspace:
             raise ValueError("invalid camera or rasterizer settings")
         if self.buf is None or self.buf.numel() < size or self.buf.device != torch.device(device):
             self.buf = None
-            self.buf = torch.empty(size, dtype=torch.uint8, device=device)
+            # zeroed: the overflow flag at its start must begin cleared
+            self.buf = torch.zeros(size, dtype=torch.uint8, device=device)
         return self.buf
 
 
@@ -79,7 +84,10 @@ _default_ws = {}
 
 
 def default_workspace(device) -> Workspace:
-    key = str(torch.device(device))
+    """The workspace of the current stream on `device` (one per stream, so
+    that calls issued on different streams never share buckets or flags)."""
+    dev = torch.device(device)
+    key = (str(dev), torch.cuda.current_stream(dev).cuda_stream)
     if key not in _default_ws:
         _default_ws[key] = Workspace()
     return _default_ws[key]
@@ -159,6 +167,8 @@ def blend_backward(b: Binning, feat, cam: L.Camera, opts: L.Opts, ws: torch.Tens
         if (grad_feat.shape != (n, C) or grad_opacity.shape != (n,) or grad_uv.shape != (n, 2)
                 or any(t.dtype != torch.float32 or not t.is_contiguous() for t in outputs)):
             raise ValueError("outputs must be contiguous f32 [n,C], [n], [n,2]")
+        if n > 0 and (grad_feat.data_ptr() % 16 or grad_uv.data_ptr() % 8):
+            raise ValueError("grad_feat must be 16-byte and grad_uv 8-byte aligned")
     else:
         grad_feat = torch.empty(n, C, dtype=torch.float32, device=dev)
         grad_opacity = torch.empty(n, dtype=torch.float32, device=dev)
@@ -213,6 +223,12 @@ class _RasterizeFn(torch.autograd.Function):
         b = project_bin_sort(pos, opacity, cam, opts, ws, radius)
         out, t_final, n_contrib, state = blend_forward(
             b, feat, cam, opts, ws, bg, with_state=settings.splat == "bilinear")
+        if settings.splat != "bilinear":
+            # Gaussians wider than settings.max_radius can make more tile
+            # copies than the workspace holds; the kernels then skip their
+            # work, so the outputs must not be returned (one sync; bilinear
+            # splats make at most four copies per point and cannot overflow)
+            check_capacity(ws)
         ctx.cam, ctx.settings, ctx.workspace = cam, settings, workspace
         ctx.has_bg = bg is not None
         saved = [pos, opacity, feat, bg if bg is not None else torch.empty(0, device=pos.device),
@@ -260,6 +276,9 @@ def rasterize(pos: torch.Tensor, opacity: torch.Tensor, feat: torch.Tensor, came
     _check_inputs(pos, opacity, feat, bg, radius, settings)
     cam = camera_struct(camera)
     ws = workspace if workspace is not None else default_workspace(pos.device)
-    return _RasterizeFn.apply(pos.contiguous(), opacity.contiguous(), feat.contiguous(),
+    feat = feat.contiguous()
+    if feat.data_ptr() % 16:  # feature rows are read as 16-byte vectors
+        feat = feat.clone()
+    return _RasterizeFn.apply(pos.contiguous(), opacity.contiguous(), feat,
                               None if bg is None else bg.contiguous(),
                               None if radius is None else radius.contiguous(), cam, settings, ws)

@@ -118,12 +118,28 @@ def assert_lpos(g, proj, tl):
 
 
 def assert_close(name, gpu, ref, ref_abs, rel=1e-5, abs_=1e-6, mask=None):
-    gpu = np.asarray(gpu, np.float64)
-    ref = np.asarray(ref, np.float64)
-    ref_abs = np.asarray(ref_abs, np.float64)
+    """Element-wise tolerance check (oracle.within_tolerance), in chunks so
+    that full-size outputs (hundreds of millions of elements) stay within a
+    few GB of host memory.  Prints the statistics, including how many
+    elements would fail the plain test against |oracle| alone."""
+    gpu, ref, ref_abs = np.asarray(gpu), np.asarray(ref), np.asarray(ref_abs)
     if mask is not None:
         gpu, ref, ref_abs = gpu[..., mask], ref[..., mask], ref_abs[..., mask]
-    ok, st = oracle.within_tolerance(gpu, ref, ref_abs, rel=rel, abs_=abs_)
+    gpu, ref, ref_abs = gpu.reshape(-1), ref.reshape(-1), ref_abs.reshape(-1)
+    st = dict(max_abs=0.0, max_rel=0.0, sq=0.0, n_bad=0, n_plain_fail=0, max_plain_excess=0.0)
+    step = 1 << 23
+    for k in range(0, max(gpu.size, 1), step):
+        sl = slice(k, k + step)
+        _, s = oracle.within_tolerance(gpu[sl].astype(np.float64), ref[sl].astype(np.float64),
+                                       ref_abs[sl].astype(np.float64), rel=rel, abs_=abs_)
+        for key in ("max_abs", "max_rel", "max_plain_excess"):
+            st[key] = max(st[key], s[key])
+        for key in ("n_bad", "n_plain_fail"):
+            st[key] += s[key]
+        st["sq"] += s["rms"] ** 2 * gpu[sl].size
+    st["rms"] = float(np.sqrt(st.pop("sq") / max(gpu.size, 1)))
+    st["n"] = int(gpu.size)
+    print(f"  {name}: {st}", flush=True)
     assert st["n_bad"] == 0, f"{name}: {st}"
     return st
 

@@ -157,3 +157,127 @@ def test_uv_gradients_match_central_differences():
         if checked == 8:
             break
     assert checked == 8
+
+
+def torch_eq1_gauss(cam, pos, radius, opacity, feat, bg, G, Gt, n_contrib, dilation=0.16,
+                    cutoff=3.0):
+    """Eq. (1) per pixel with Gaussian fragment weights, in torch float64.
+
+    Fragment membership and order are the FP32 decisions of the screen-space
+    Gaussian footprint (bounding box, then d^2 <= cutoff^2 s2), taken here
+    with numpy float32 scalars; the weight exp(-d^2 / (2 s2)) is a torch
+    expression of the leaves u, v, so autograd differentiates it
+    independently of the oracle's hand-written dw/du, dw/dv."""
+    f32 = np.float32
+    pr = oracle.project(cam, pos, radius, splat=oracle.SPLAT_GAUSSIAN, dilation=dilation,
+                        cutoff=cutoff)
+    vis, uv32, key, rect = pr["visible"], pr["uv"], pr["key"], pr["rect"]
+    n, C = feat.shape
+    W, H = cam.width, cam.height
+    u = torch.tensor(uv32[:, 0].astype(np.float64), requires_grad=True)
+    v = torch.tensor(uv32[:, 1].astype(np.float64), requires_grad=True)
+    o = torch.tensor(opacity.astype(np.float64), requires_grad=True)
+    f = torch.tensor(feat.astype(np.float64), requires_grad=True)
+    bgt = torch.tensor(np.zeros(C) if bg is None else np.asarray(bg, np.float64))
+    frags = {}
+    for i in np.nonzero(vis)[0]:
+        r = f32(radius[i])
+        s2 = f32(r * r) + f32(dilation)
+        thr = f32(f32(cutoff) * f32(cutoff)) * s2
+        for py in range(rect[i, 1], rect[i, 3] + 1):
+            for px in range(rect[i, 0], rect[i, 2] + 1):
+                dx = f32(f32(px) + f32(0.5)) - uv32[i, 0]
+                dy = f32(f32(py) + f32(0.5)) - uv32[i, 1]
+                if f32(f32(dx * dx) + f32(dy * dy)) <= thr:
+                    frags.setdefault((px, py), []).append((int(key[i]), int(i), float(s2)))
+    loss = torch.zeros((), dtype=torch.float64)
+    for (px, py), lst in frags.items():
+        lst.sort()
+        lst = lst[:int(n_contrib[py, px])]
+        T = torch.ones((), dtype=torch.float64)
+        F = torch.zeros(C, dtype=torch.float64)
+        for _, i, s2 in lst:
+            d2 = ((px + 0.5) - u[i]) ** 2 + ((py + 0.5) - v[i]) ** 2
+            al = o[i] * torch.exp(-0.5 * d2 / s2)
+            F = F + T * al * f[i]
+            T = T * (1.0 - al)
+        F = F + T * bgt
+        loss = loss + (torch.tensor(G[:, py, px].astype(np.float64)) * F).sum() \
+            + float(Gt[py, px]) * T
+    loss.backward()
+    return dict(grad_u=u.grad.numpy(), grad_v=v.grad.numpy(), grad_o=o.grad.numpy(),
+                grad_f=f.grad.numpy())
+
+
+@pytest.mark.parametrize("t_min", [0.0, 1e-4, 0.3])
+def test_gaussian_backward_matches_torch_autograd_of_eq1(t_min):
+    """The oracle's Gaussian weight derivatives (dw/du = w dx / s2, dw/dv =
+    w dy / s2) and the rest of Eq. (2) for Gaussian fragments, against
+    autograd of the Gaussian-weighted Eq. (1) (Sec. 3.2 "Rendering Points as
+    Small Gaussians": dilation 0.16, cut at 3 sigma)."""
+    s = tiny_scene(40, 20, 14, channels=3, seed=31, with_grad_t=True, radius_range=(0.5, 2.0))
+    bg = np.array([0.25, -0.5, 1.0])
+    r = oracle.render(s.camera, s.pos, s.opacity, s.feat, radius=s.radius, bg=bg,
+                      splat=oracle.SPLAT_GAUSSIAN, t_min=t_min, grad_out=s.grad,
+                      grad_t=s.grad_t)
+    assert (r["flags"] == 0).all()
+    tt = torch_eq1_gauss(s.camera, s.pos, s.radius, s.opacity, s.feat, bg, s.grad, s.grad_t,
+                         r["n_contrib"])
+    assert np.abs(tt["grad_u"]).max() > 0.1  # the weights' slopes are exercised
+    np.testing.assert_allclose(r["grad_feat"], tt["grad_f"], rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(r["grad_opacity"], tt["grad_o"], rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(r["grad_uv"][:, 0], tt["grad_u"], rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(r["grad_uv"][:, 1], tt["grad_v"], rtol=1e-10, atol=1e-12)
+
+
+def test_gaussian_uv_gradients_match_central_differences():
+    """Moving a Gaussian without changing which pixels it covers changes the
+    loss smoothly: central differences over the actual FP32 shift of u,
+    with the fragment set checked unchanged at both ends."""
+    s = tiny_scene(60, 20, 14, channels=2, seed=32, radius_range=(0.7, 1.5))
+    kw = dict(radius=s.radius, splat=oracle.SPLAT_GAUSSIAN, t_min=0.0)
+    r = oracle.render(s.camera, s.pos, s.opacity, s.feat, grad_out=s.grad, **kw)
+    pr = oracle.project(s.camera, s.pos, s.radius, splat=oracle.SPLAT_GAUSSIAN)
+    nfrag = oracle.count_fragments(s.camera, s.pos, s.radius, splat=oracle.SPLAT_GAUSSIAN)
+    checked = 0
+    for i in np.nonzero(pr["visible"])[0]:
+        Z = float(pr["xyz"][i, 2])
+        dx = 2.0 ** -12 * Z / s.camera.fx
+        pp, pm = s.pos.copy(), s.pos.copy()
+        pp[i, 0] += np.float32(dx)
+        pm[i, 0] -= np.float32(dx)
+        cnt = [oracle.count_fragments(s.camera, q, s.radius, splat=oracle.SPLAT_GAUSSIAN)
+               for q in (pp, pm)]
+        rp = oracle.project(s.camera, pp, s.radius, splat=oracle.SPLAT_GAUSSIAN)
+        rm = oracle.project(s.camera, pm, s.radius, splat=oracle.SPLAT_GAUSSIAN)
+        if cnt != [nfrag, nfrag] or not (rp["rect"][i] == pr["rect"][i]).all() \
+                or not (rm["rect"][i] == pr["rect"][i]).all():
+            continue
+        up, um = float(rp["uv"][i, 0]), float(rm["uv"][i, 0])
+        fd = (_loss(oracle.render(s.camera, pp, s.opacity, s.feat, **kw), s.grad)
+              - _loss(oracle.render(s.camera, pm, s.opacity, s.feat, **kw), s.grad)) / (up - um)
+        assert r["grad_uv"][i, 0] == pytest.approx(fd, rel=1e-4, abs=1e-7)
+        checked += 1
+        if checked == 8:
+            break
+    assert checked == 8
+
+
+@pytest.mark.parametrize("splat", [oracle.SPLAT_BILINEAR, oracle.SPLAT_GAUSSIAN])
+def test_pixel_mask_computes_the_same_pixels(splat):
+    """The sampled-pixel forward (for scenes too large for the full fragment
+    set) equals the full forward on every masked pixel and leaves the rest."""
+    s = tiny_scene(300, 33, 21, channels=3, seed=33,
+                   radius_range=(0.5, 2.5) if splat else None)
+    rad = s.radius if splat else None
+    full = oracle.render(s.camera, s.pos, s.opacity, s.feat, radius=rad, splat=splat)
+    mask = np.random.default_rng(1).random((21, 33)) < 0.3
+    part = oracle.render(s.camera, s.pos, s.opacity, s.feat, radius=rad, splat=splat,
+                         pixel_mask=mask)
+    for k in ("out", "out_abs"):
+        np.testing.assert_array_equal(part[k][:, mask], full[k][:, mask])
+        assert (part[k][:, ~mask] == 0).all()
+    for k in ("t_final", "n_contrib", "flags"):
+        np.testing.assert_array_equal(part[k][mask], full[k][mask])
+    with pytest.raises(ValueError):
+        oracle.render(s.camera, s.pos, s.opacity, s.feat, grad_out=s.grad, pixel_mask=mask)

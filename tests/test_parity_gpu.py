@@ -16,6 +16,7 @@ pytestmark = [pytest.mark.gpu,
 from gpu_helpers import (  # noqa: E402
     assert_backward, assert_binning_exact, assert_forward, run_gpu, run_oracle, settings_opts)
 from paper_2508_19140_amd import _lib as L  # noqa: E402
+import oracle  # noqa: E402
 
 
 def small_c2(n=1 << 17, W=320, H=180, seed=0, channels=16):
@@ -148,6 +149,31 @@ def test_capacity_overflow_reported():
     assert_binning_exact(g, proj, tl)
     assert_forward(g, rr)
     assert_backward(g, rr, ok_sc.grad)
+
+
+def test_overflow_through_rasterize_raises():
+    """rasterize() with Gaussians wider than settings.max_radius: the copies
+    exceed the workspace, the forward raises INPC_ERR_CAPACITY instead of
+    returning undefined outputs, and the next call on the same (default)
+    workspace is exact again."""
+    import paper_2508_19140_amd as inpc
+    dev = "cuda:0"
+    sc = tiny_scene(3000, 96, 64, channels=4, seed=5, radius_range=(10.0, 12.0))
+    st = settings_opts(splat="gaussian", tile=8, max_radius=3.0)
+    t = lambda a: torch.from_numpy(a).to(dev)
+    with pytest.raises(L.InpcError) as ei:
+        inpc.rasterize(t(sc.pos), t(sc.opacity), t(sc.feat), sc.camera, radius=t(sc.radius),
+                       settings=st)
+    assert ei.value.status == L.INPC_ERR_CAPACITY
+    ok_sc = tiny_scene(2000, 96, 64, channels=4, seed=6, radius_range=(0.5, 3.0))
+    out, tf, nc = inpc.rasterize(t(ok_sc.pos), t(ok_sc.opacity), t(ok_sc.feat), ok_sc.camera,
+                                 radius=t(ok_sc.radius), settings=st)
+    rr = oracle.render(ok_sc.camera, ok_sc.pos, ok_sc.opacity, ok_sc.feat, radius=ok_sc.radius,
+                       splat=1, tile=8, t_min=st.t_min)
+    ok = rr["flags"] == 0
+    g = dict(out=out.cpu().numpy(), t_final=tf.cpu().numpy(),
+             n_contrib=nc.cpu().numpy().view(np.uint32))
+    assert_forward(g, rr, flags_ok=ok)
 
 
 def test_empty_and_culled():
