@@ -236,6 +236,29 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
                                   void* scratch, size_t scratch_bytes, void* ws, size_t ws_bytes,
                                   void* stream);
 
+/*
+ * Step 5 without allocation -- for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as
+ * inpc_blend_backward, minus `scratch`: the scratch comes from a static
+ * device array of INPC_STATIC_SCRATCH_BYTES (64 MiB) that the library holds
+ * on every GPU it runs on until the process ends.  Calls needing more than
+ * that (inpc_backward_scratch_bytes(n, C, ...) > INPC_STATIC_SCRATCH_BYTES,
+ * about 4 M points at C = 16 and 1080p) return INPC_ERR_INVALID.  The call
+ * itself allocates nothing.  The device is the current HIP device (the one
+ * `stream` belongs to).  Every call on a GPU shares that GPU's array, so
+ * calls that overlap on one GPU (concurrent streams, threads) race: the
+ * caller serialises them.
+ */
+#define INPC_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+inpc_status_t inpc_blend_backward_noalloc(
+    const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n, const float* proj,
+    const void* feat, int32_t C, int32_t dtype, const float* bg, const uint32_t* ntiles,
+    const uint32_t* tile_ranges, const uint32_t* tile_order, const uint32_t* list,
+    const uint16_t* lpos, const float* t_final, const void* state, const float* grad_out,
+    const float* grad_t, float* grad_feat, float* grad_opacity, float* grad_uv, float* grad_bg,
+    void* ws, size_t ws_bytes, void* stream);
+
 /* Bytes of the scratch inpc_blend_backward needs for n points and C channels:
  * 16 per point (the opacity and position gradients as one row per point,
  * which the atomics of points split over tiles add to) plus 4 C per tile

@@ -24,11 +24,13 @@ DTYPE_F32 = 0
 DTYPE_F16 = 1
 DTYPE_BF16 = 2
 
+STATIC_SCRATCH_BYTES = 64 << 20  # INPC_STATIC_SCRATCH_BYTES
+
 EXPORTS = (
     "inpc_workspace_bytes", "inpc_state_bytes", "inpc_num_tiles", "inpc_copy_capacity",
     "inpc_project", "inpc_bin", "inpc_sort", "inpc_blend_forward", "inpc_blend_backward",
     "inpc_project_backward", "inpc_check_sync", "inpc_status_string", "inpc_last_error",
-    "inpc_backward_scratch_bytes",
+    "inpc_backward_scratch_bytes", "inpc_blend_backward_noalloc",
 )
 
 
@@ -79,6 +81,8 @@ def lib():
                                      P, SZ, P]),
         "inpc_blend_backward": (I32, [CP, OP, I64, P, P, I32, I32, P, P, P, P, P, P, P, P, P,
                                       P, P, P, P, P, P, SZ, P, SZ, P]),
+        "inpc_blend_backward_noalloc": (I32, [CP, OP, I64, P, P, I32, I32, P, P, P, P, P, P, P,
+                                              P, P, P, P, P, P, P, P, SZ, P]),
         "inpc_backward_scratch_bytes": (SZ, [I64, I32, CP, OP]),
         "inpc_project_backward": (I32, [CP, I64, P, P, P, P, P]),
         "inpc_check_sync": (I32, [P, SZ, P]),

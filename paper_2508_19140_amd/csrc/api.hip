@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "common.h"
 #include "inpc_raster.h"
@@ -222,6 +223,119 @@ inpc_status_t check_common(const inpc_camera_t* cam, const inpc_opts_t* opts, in
       return fail(INPC_ERR_INVALID, "%s not 16-byte aligned", "proj"); \
   } while (0)
 
+static inpc_status_t blend_checks(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
+                                  int32_t C, int32_t dtype, const void* ws, size_t ws_bytes) {
+  inpc_status_t st = check_common(cam, opts, n, ws, ws_bytes);
+  if (st != INPC_OK) return st;
+  if (C < 1 || C > 64) return fail(INPC_ERR_INVALID, "channels must be in [1, 64]%s", "");
+  if (dtype != INPC_F32 && dtype != INPC_F16 && dtype != INPC_BF16)
+    return fail(INPC_ERR_INVALID, "unknown feature dtype%s", "");
+  if (C > 32) return fail(INPC_ERR_UNSUPPORTED, "more than 32 channels%s", "");
+  if (opts->tile == 32) return fail(INPC_ERR_UNSUPPORTED, "blending with 32x32 tiles%s", "");
+  return INPC_OK;
+}
+
+// Scratch of inpc_blend_backward_noalloc: a file-scope device array, one
+// copy per GPU, held until the process ends.  In host code `scratch` only
+// names the symbol; its device address comes from hipGetSymbolAddress,
+// once per device with that device current, and is kept per device.
+constexpr size_t kStaticScratchBytes = INPC_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+inpc_status_t static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "inpc_blend_backward_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(INPC_ERR_INVALID, "device index out of range%s", "");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                      "inpc_blend_backward_noalloc: hipGetSymbolAddress");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return INPC_OK;
+}
+
+static inpc_status_t blend_backward_impl(const char* who, const inpc_camera_t* cam,
+                                         const inpc_opts_t* opts, int64_t n,
+                                  const float* proj, const void* feat, int32_t C, int32_t dtype,
+                                  const float* bg,
+                                  const uint32_t* ntiles, const uint32_t* tile_ranges,
+                                  const uint32_t* tile_order, const uint32_t* list,
+                                  const uint16_t* lpos, const float* t_final, const void* state,
+                                  const float* grad_out, const float* grad_t, float* grad_feat,
+                                  float* grad_opacity, float* grad_uv, float* grad_bg,
+                                  void* scratch, size_t scratch_size, void* ws, size_t ws_bytes,
+                                  void* stream) {
+  inpc_status_t st = blend_checks(cam, opts, n, C, dtype, ws, ws_bytes);
+  if (st != INPC_OK) return st;
+  if (opts->splat != INPC_SPLAT_BILINEAR)
+    return fail(INPC_ERR_UNSUPPORTED, "backward of Gaussian splats%s", "");
+  REQUIRE(scratch, "scratch");
+  if (scratch_size < scratch_bytes(n, C, cam, opts))
+    return fail(INPC_ERR_INVALID, "scratch smaller than inpc_backward_scratch_bytes()%s", "");
+  REQUIRE(tile_ranges, "tile_ranges");
+  REQUIRE(list, "list");
+  REQUIRE(lpos, "lpos");
+  REQUIRE(t_final, "t_final");
+  REQUIRE(state, "state");
+  REQUIRE(grad_out, "grad_out");
+  if (reinterpret_cast<uintptr_t>(scratch) % 16)
+    return fail(INPC_ERR_INVALID, "%s not 16-byte aligned", "scratch");
+  if (n > 0) {
+    REQUIRE_PROJ(proj);
+    REQUIRE_ALIGNED(feat, "feat", 16);
+    REQUIRE(ntiles, "ntiles");
+    REQUIRE_ALIGNED(grad_feat, "grad_feat", 16);
+    REQUIRE(grad_opacity, "grad_opacity");
+    REQUIRE_ALIGNED(grad_uv, "grad_uv", 8);
+  }
+  const Ws w = make_ws(ws, n, cam, opts);
+  BlendArgs a;
+  memset(&a, 0, sizeof(a));
+  a.cam = to_cam(cam);
+  a.opts = to_opts(cam, opts);
+  a.n = n;
+  a.proj = proj;
+  a.feat = feat;
+  a.C = C;
+  a.dtype = dtype;
+  a.bg = bg;
+  a.ranges = tile_ranges;
+  a.order = tile_order;
+  a.list = list;
+  a.lpos = lpos;
+  a.t_final = const_cast<float*>(t_final);
+  const size_t P = (size_t)cam->width * cam->height;
+  a.st_last = static_cast<uint32_t*>(const_cast<void*>(state));
+  a.st_anchor = a.st_last + P;
+  a.st_tanchor = reinterpret_cast<float*>(a.st_anchor + P);
+  a.st_tile = a.st_last + 3 * P;
+  a.ntiles = ntiles;
+  a.grad_out = grad_out;
+  a.grad_t = grad_t;
+  a.grad_feat = grad_feat;
+  a.grad_opacity = grad_opacity;
+  a.grad_uv = grad_uv;
+  a.grad_bg = grad_bg;
+  a.gsc = static_cast<float4*>(scratch);
+  a.bg_partial = grad_bg ? reinterpret_cast<float*>(static_cast<char*>(scratch) +
+                                                    scratch_scalar_bytes(n))
+                         : nullptr;
+  a.flags = w.flags;
+  hipError_t e = launch_blend_backward(a, (hipStream_t)stream);
+  return e == hipSuccess ? INPC_OK : hip_fail(e, who);
+}
+
 }  // namespace
 }  // namespace inpc
 
@@ -315,17 +429,6 @@ inpc_status_t inpc_sort(const inpc_camera_t* cam, const inpc_opts_t* opts, int64
   return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_sort");
 }
 
-static inpc_status_t blend_checks(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
-                                  int32_t C, int32_t dtype, const void* ws, size_t ws_bytes) {
-  inpc_status_t st = check_common(cam, opts, n, ws, ws_bytes);
-  if (st != INPC_OK) return st;
-  if (C < 1 || C > 64) return fail(INPC_ERR_INVALID, "channels must be in [1, 64]%s", "");
-  if (dtype != INPC_F32 && dtype != INPC_F16 && dtype != INPC_BF16)
-    return fail(INPC_ERR_INVALID, "unknown feature dtype%s", "");
-  if (C > 32) return fail(INPC_ERR_UNSUPPORTED, "more than 32 channels%s", "");
-  if (opts->tile == 32) return fail(INPC_ERR_UNSUPPORTED, "blending with 32x32 tiles%s", "");
-  return INPC_OK;
-}
 
 inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
                                  const float* proj, const void* feat, int32_t C, int32_t dtype,
@@ -386,64 +489,40 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
                                   float* grad_opacity, float* grad_uv, float* grad_bg,
                                   void* scratch, size_t scratch_size, void* ws, size_t ws_bytes,
                                   void* stream) {
+  return blend_backward_impl("inpc_blend_backward", cam, opts, n, proj, feat, C, dtype, bg,
+                             ntiles, tile_ranges, tile_order, list, lpos, t_final, state,
+                             grad_out, grad_t, grad_feat, grad_opacity, grad_uv, grad_bg, scratch,
+                             scratch_size, ws, ws_bytes, stream);
+}
+
+inpc_status_t inpc_blend_backward_noalloc(
+    const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n, const float* proj,
+    const void* feat, int32_t C, int32_t dtype, const float* bg, const uint32_t* ntiles,
+    const uint32_t* tile_ranges, const uint32_t* tile_order, const uint32_t* list,
+    const uint16_t* lpos, const float* t_final, const void* state, const float* grad_out,
+    const float* grad_t, float* grad_feat, float* grad_opacity, float* grad_uv, float* grad_bg,
+    void* ws, size_t ws_bytes, void* stream) {
+  if (!valid_cam(cam)) return fail(INPC_ERR_INVALID, "invalid camera%s", "");
+  if (!valid_opts(opts)) return fail(INPC_ERR_INVALID, "invalid options%s", "");
+  if (n < 0 || n > (int64_t)0x7fffffff) return fail(INPC_ERR_INVALID, "n out of range%s", "");
+  if (C < 1 || C > 64) return fail(INPC_ERR_INVALID, "channels must be in [1, 64]%s", "");
+  const size_t need = scratch_bytes(n, C, cam, opts);
+  if (need > kStaticScratchBytes) {
+    snprintf(g_err, sizeof(g_err),
+             "inpc_blend_backward_noalloc: needs %zu bytes of scratch (16 per point + 4 C per "
+             "tile), more than the static %zu",
+             need, kStaticScratchBytes);
+    return INPC_ERR_INVALID;
+  }
   inpc_status_t st = blend_checks(cam, opts, n, C, dtype, ws, ws_bytes);
   if (st != INPC_OK) return st;
-  if (opts->splat != INPC_SPLAT_BILINEAR)
-    return fail(INPC_ERR_UNSUPPORTED, "backward of Gaussian splats%s", "");
-  REQUIRE(scratch, "scratch");
-  if (scratch_size < scratch_bytes(n, C, cam, opts))
-    return fail(INPC_ERR_INVALID, "scratch smaller than inpc_backward_scratch_bytes()%s", "");
-  REQUIRE(tile_ranges, "tile_ranges");
-  REQUIRE(list, "list");
-  REQUIRE(lpos, "lpos");
-  REQUIRE(t_final, "t_final");
-  REQUIRE(state, "state");
-  REQUIRE(grad_out, "grad_out");
-  if (reinterpret_cast<uintptr_t>(scratch) % 16)
-    return fail(INPC_ERR_INVALID, "%s not 16-byte aligned", "scratch");
-  if (n > 0) {
-    REQUIRE_PROJ(proj);
-    REQUIRE_ALIGNED(feat, "feat", 16);
-    REQUIRE(ntiles, "ntiles");
-    REQUIRE_ALIGNED(grad_feat, "grad_feat", 16);
-    REQUIRE(grad_opacity, "grad_opacity");
-    REQUIRE_ALIGNED(grad_uv, "grad_uv", 8);
-  }
-  const Ws w = make_ws(ws, n, cam, opts);
-  BlendArgs a;
-  memset(&a, 0, sizeof(a));
-  a.cam = to_cam(cam);
-  a.opts = to_opts(cam, opts);
-  a.n = n;
-  a.proj = proj;
-  a.feat = feat;
-  a.C = C;
-  a.dtype = dtype;
-  a.bg = bg;
-  a.ranges = tile_ranges;
-  a.order = tile_order;
-  a.list = list;
-  a.lpos = lpos;
-  a.t_final = const_cast<float*>(t_final);
-  const size_t P = (size_t)cam->width * cam->height;
-  a.st_last = static_cast<uint32_t*>(const_cast<void*>(state));
-  a.st_anchor = a.st_last + P;
-  a.st_tanchor = reinterpret_cast<float*>(a.st_anchor + P);
-  a.st_tile = a.st_last + 3 * P;
-  a.ntiles = ntiles;
-  a.grad_out = grad_out;
-  a.grad_t = grad_t;
-  a.grad_feat = grad_feat;
-  a.grad_opacity = grad_opacity;
-  a.grad_uv = grad_uv;
-  a.grad_bg = grad_bg;
-  a.gsc = static_cast<float4*>(scratch);
-  a.bg_partial = grad_bg ? reinterpret_cast<float*>(static_cast<char*>(scratch) +
-                                                    scratch_scalar_bytes(n))
-                         : nullptr;
-  a.flags = w.flags;
-  hipError_t e = launch_blend_backward(a, (hipStream_t)stream);
-  return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_blend_backward");
+  void* scr = nullptr;
+  st = static_scratch(&scr);
+  if (st != INPC_OK) return st;
+  return blend_backward_impl("inpc_blend_backward_noalloc", cam, opts, n, proj, feat, C, dtype,
+                             bg, ntiles, tile_ranges, tile_order, list, lpos, t_final, state,
+                             grad_out, grad_t, grad_feat, grad_opacity, grad_uv, grad_bg, scr,
+                             kStaticScratchBytes, ws, ws_bytes, stream);
 }
 
 inpc_status_t inpc_project_backward(const inpc_camera_t* cam, int64_t n, const float* pos,
