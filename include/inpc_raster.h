@@ -90,6 +90,9 @@ typedef struct {
                            0 = automatic (8192, or n/256 when larger), else a multiple of
                            1024; never fewer than n/256 (a tuning knob: results do not
                            depend on it; the workspace size does) */
+    int32_t bg_per_pixel; /* 0: the blend's background `bg` (and grad_bg) is one [C] vector;
+                             1: a per-pixel image [C][H][W] (e.g. from inpc_envmap_forward),
+                             and grad_bg is [C][H][W] as well */
 } inpc_opts_t;
 
 /* Bytes of workspace needed for n points with this camera and options.
@@ -182,7 +185,8 @@ int64_t inpc_copy_capacity(int64_t n, const inpc_camera_t* cam, const inpc_opts_
  *   proj       output of inpc_project (position, opacity, radius)
  *   feat       [n][C] features, dtype INPC_F32 / INPC_F16 / INPC_BF16
  *              (blending and accumulation are FP32 for every dtype)
- *   bg         [C] f32 constant background features, or NULL (zero)
+ *   bg         [C] f32 constant background features, [C][H][W] per-pixel
+ *              background when opts->bg_per_pixel, or NULL (zero)
  *   tile_ranges, list: outputs of inpc_bin / inpc_sort
  *   tile_order [num_tiles] from inpc_bin, or NULL (tile-index order)
  *   lpos       output of inpc_sort (bilinear splats; NULL for Gaussians)
@@ -217,7 +221,8 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
  *   grad_feat  [n][C] f32 out (FP32 for every feature dtype)
  *   grad_opacity [n] f32 out
  *   grad_uv    [n][2] f32 out (input of inpc_project_backward)
- *   grad_bg    [C] f32 out, or NULL
+ *   grad_bg    [C] f32 out (sum over pixels of T_final G), [C][H][W] (T_final G
+ *              per pixel) when opts->bg_per_pixel, or NULL
  *   scratch    device scratch of inpc_backward_scratch_bytes(n, C, ...) bytes
  * Every output element is written (zero for culled points and for points no
  * blended fragment reached).  A point whose footprint lies in one tile gets
@@ -275,6 +280,128 @@ size_t inpc_backward_scratch_bytes(int64_t n, int32_t C, const inpc_camera_t* ca
 inpc_status_t inpc_project_backward(const inpc_camera_t* cam, int64_t n, const float* pos,
                                     const uint32_t* ntiles, const float* grad_uv,
                                     float* grad_pos, void* stream);
+
+/*
+ * Background from a spherical environment map (Sec. 3.2 "Faster Background
+ * Model Evaluation": the background model is distilled into an
+ * equirectangular map sampled with bilinear interpolation along every
+ * pixel's view direction; the local view directions depend only on the
+ * intrinsics and are cached).  The sampled image is passed to the blend as
+ * a per-pixel background (opts->bg_per_pixel = 1), which composites it
+ * behind the points: F += T_final f_bg(pixel).
+ *
+ * inpc_view_dirs: dirs [H][W][3] f32 out, the unit camera-space direction
+ *   through every pixel centre, normalize((x + 0.5 - cx) / fx,
+ *   (y + 0.5 - cy) / fy, 1).  Computed once per set of intrinsics.
+ * inpc_envmap_forward: bg [C][H][W] f32 out, sampled from env [Hm][Wm][C]
+ *   f32 (texel-major) along w = R^T d: longitude phi = atan2(w_x, w_z),
+ *   polar angle theta = acos(-w_y / |w|) (OpenCV axes, so -y is up); column
+ *   coordinate (phi / (2 pi) + 1/2) Wm, row coordinate (theta / pi) Hm;
+ *   texel (i, j) centred at (i + 1/2, j + 1/2); bilinear between the four
+ *   surrounding centres, wrapping in longitude, clamping at the poles.
+ * inpc_envmap_backward: grad_env [Hm][Wm][C] f32 out (zeroed by the call,
+ *   then every pixel's grad_bg [C][H][W] is added onto its four texels with
+ *   the same weights, float atomics: the last bits depend on their order).
+ */
+inpc_status_t inpc_view_dirs(const inpc_camera_t* cam, float* dirs, void* stream);
+inpc_status_t inpc_envmap_forward(const inpc_camera_t* cam, const float* dirs, const float* env,
+                                  int32_t Hm, int32_t Wm, int32_t C, float* bg, void* stream);
+inpc_status_t inpc_envmap_backward(const inpc_camera_t* cam, const float* dirs,
+                                   const float* grad_bg, int32_t Hm, int32_t Wm, int32_t C,
+                                   float* grad_env, void* stream);
+
+/*
+ * Many views in one pass.  A training step or a frame renders several views
+ * (the paper samples one cloud per view and combines several clouds per
+ * frame, Sec. 3.1), with uneven point counts and resolutions.  The caller
+ * describes every view in an inpc_view_t: its camera and points, and the
+ * same per-view buffers the single-view calls take (sized by
+ * inpc_workspace_bytes, inpc_copy_capacity, inpc_num_tiles,
+ * inpc_state_bytes and inpc_backward_scratch_bytes for that view).  The
+ * table lives twice: `views_dev`, in device memory, is what the batched
+ * kernels read; `views_host`, the same records in host memory, sizes the
+ * launches.  All views share opts, the channel count C and the feature
+ * dtype.
+ *
+ * inpc_rasterize_batched(pass = INPC_PASS_FORWARD): every view's tile
+ *   lists are built (steps 1-3), then ONE persistent launch blends every
+ *   (view, tile) item: its workgroups take items from a device work queue
+ *   until it is empty, the views interleaved in proportion to their tile
+ *   counts, every view's tiles longest first.  Writes out, t_final,
+ *   n_contrib and state of every view, exactly as inpc_blend_forward would.
+ * inpc_rasterize_batched(pass = INPC_PASS_BACKWARD): the lists are built
+ *   again (bilinear splats only), ONE persistent launch replays every
+ *   (view, tile) item backwards, then every view's gradients are finished
+ *   and chained to positions: grad_feat, grad_opacity, grad_uv, grad_pos
+ *   and grad_bg as inpc_blend_backward + inpc_project_backward give them.
+ * batch_ws: device scratch of inpc_batch_workspace_bytes(views_host, ...)
+ *   bytes (per-view kernel arguments, the work queue and its counter).
+ * Everything is asynchronous on `stream` and allocates nothing, so a pass
+ * can be captured into a HIP graph.  Host-side checks as for the
+ * single-view calls; n_views must be in [1, 64].
+ */
+typedef struct {
+    inpc_camera_t cam;
+    int64_t n;
+    const float* pos;          /* [n][3] */
+    const float* opacity;      /* [n] */
+    const float* radius;       /* [n] Gaussian radii, or NULL (bilinear) */
+    const void* feat;          /* [n][C] of the batch's dtype */
+    const float* bg;           /* [C] or [C][H][W] (opts->bg_per_pixel), or NULL */
+    float* proj;               /* [n][4], 16-byte aligned */
+    uint32_t* depth_key;       /* [n] */
+    uint32_t* ntiles;          /* [n] */
+    uint32_t* tile_ranges;     /* [num_tiles + 1] */
+    uint32_t* tile_order;      /* [num_tiles] */
+    uint32_t* list;            /* [copy capacity] */
+    uint16_t* lpos;            /* [copy capacity] (bilinear) */
+    void* state;               /* inpc_state_bytes() (bilinear) */
+    void* ws;                  /* inpc_workspace_bytes(), zeroed when first allocated */
+    size_t ws_bytes;
+    void* scratch;             /* inpc_backward_scratch_bytes() (backward pass) */
+    size_t scratch_bytes;
+    float* out;                /* [C][H][W] */
+    float* t_final;            /* [H][W] */
+    uint32_t* n_contrib;       /* [H][W] */
+    const float* grad_out;     /* [C][H][W] (backward) */
+    const float* grad_t;       /* [H][W] or NULL */
+    float* grad_feat;          /* [n][C] f32 */
+    float* grad_opacity;       /* [n] */
+    float* grad_uv;            /* [n][2] */
+    float* grad_pos;           /* [n][3] */
+    float* grad_bg;            /* like bg, or NULL */
+} inpc_view_t;
+
+enum { INPC_PASS_FORWARD = 0, INPC_PASS_BACKWARD = 1 };
+
+size_t inpc_batch_workspace_bytes(const inpc_view_t* views_host, int32_t n_views,
+                                  const inpc_opts_t* opts);
+inpc_status_t inpc_rasterize_batched(const inpc_view_t* views_host, const inpc_view_t* views_dev,
+                                     int32_t n_views, const inpc_opts_t* opts, int32_t C,
+                                     int32_t dtype, int32_t pass, void* batch_ws,
+                                     size_t batch_ws_bytes, void* stream);
+
+/*
+ * View-dependent point features (Sec. 2 "Implicit Point Cloud": the
+ * appearance field gives every point spherical-harmonics coefficients up to
+ * degree two per feature channel, evaluated at the view direction).  The
+ * step before the rasterizer: its output is the `feat` of step 4.
+ *   view direction d = (p - c) / |p - c|, camera centre c = -R^T t;
+ *   real orthonormal SH of degrees 0-2 in graphics order (Condon-Shortley
+ *   phase): Y0 = k0, Y1 = -k1 y, Y2 = k1 z, Y3 = -k1 x, Y4 = k2 x y,
+ *   Y5 = -k2 y z, Y6 = k3 (2 z^2 - x^2 - y^2), Y7 = -k2 x z, Y8 = k4 (x^2 - y^2),
+ *   k0 = 1/(2 sqrt(pi)), k1 = sqrt(3/(4 pi)), k2 = sqrt(15/(4 pi)),
+ *   k3 = sqrt(5/(16 pi)), k4 = sqrt(15/(16 pi));  feat[i][c] = sum_j Y_j sh[i][c][j].
+ * inpc_sh_features: pos [n][3], sh [n][C][9] f32 -> feat [n][C] f32 (C in [1, 64]).
+ * inpc_sh_features_backward: grad_feat [n][C] -> grad_sh [n][C][9] (written)
+ *   and grad_pos [n][3] (written; the position gradient through the view
+ *   direction only, to be added to the rasterizer's; NULL skips it).
+ */
+inpc_status_t inpc_sh_features(const inpc_camera_t* cam, int64_t n, const float* pos,
+                               const float* sh, int32_t C, float* feat, void* stream);
+inpc_status_t inpc_sh_features_backward(const inpc_camera_t* cam, int64_t n, const float* pos,
+                                        const float* sh, int32_t C, const float* grad_feat,
+                                        float* grad_sh, float* grad_pos, void* stream);
 
 /* The only synchronising call: waits for `stream`, then returns
  * INPC_ERR_CAPACITY if any build on this workspace since the last

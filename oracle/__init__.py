@@ -78,7 +78,8 @@ def _load():
         lib.oracle_project.restype = ctypes.c_int
         lib.oracle_tile_lists.argtypes = [P, P, ctypes.c_int64, P, P, P, P]
         lib.oracle_tile_lists.restype = ctypes.c_int64
-        lib.oracle_render.argtypes = [P, P, ctypes.c_int64, P, P, P, P, ctypes.c_int32] + [P] * 18
+        lib.oracle_render.argtypes = [P, P, ctypes.c_int64, P, P, P, P, ctypes.c_int32] + [P] * 18 \
+            + [ctypes.c_int32]
         lib.oracle_render.restype = ctypes.c_int
         lib.oracle_count_fragments.argtypes = [P, P, ctypes.c_int64, P, P]
         lib.oracle_count_fragments.restype = ctypes.c_int64
@@ -181,6 +182,8 @@ def render(camera, pos, opacity, feat, radius=None, bg=None, splat=SPLAT_BILINEA
     """Forward (and, with grad_out, backward) render in FP64.
 
     feat is upcast exactly to float64 (FP16/BF16 values included).
+    bg: [C] constant background features, or a per-pixel background image
+    [C,H,W] (grad_bg then per pixel too).
     pixel_mask ([H,W] bool, forward only): compute only these pixels (each
     one exactly; the rest of the outputs stay zero), for scenes whose full
     fragment set would not fit in host memory.
@@ -195,9 +198,11 @@ def render(camera, pos, opacity, feat, radius=None, bg=None, splat=SPLAT_BILINEA
     feat = np.ascontiguousarray(np.asarray(feat).astype(np.float64)).reshape(n, -1)
     C = feat.shape[1]
     rad = None if radius is None else _f32(radius, (n,))
-    bgd = None if bg is None else np.ascontiguousarray(np.asarray(bg, np.float64).reshape(C))
     W, H = int(camera.width), int(camera.height)
     P = W * H
+    bg_image = bg is not None and np.ndim(bg) == 3
+    bgd = None if bg is None else np.ascontiguousarray(
+        np.asarray(bg, np.float64).reshape((C, H, W) if bg_image else (C,)))
     r = dict(out=np.zeros((C, H, W)), out_abs=np.zeros((C, H, W)), t_final=np.zeros((H, W)),
              n_contrib=np.zeros((H, W), np.uint32), flags=np.zeros((H, W), np.uint8))
     go = gt = None
@@ -208,7 +213,7 @@ def render(camera, pos, opacity, feat, radius=None, bg=None, splat=SPLAT_BILINEA
                        ("grad_pos", (n, 3))):
             r[k] = np.zeros(shp)
             r[k + "_abs"] = np.zeros(shp)
-        r["grad_bg"] = np.zeros(C) if bg is not None else None
+        r["grad_bg"] = (np.zeros((C, H, W) if bg_image else C) if bg is not None else None)
     if pixel_mask is not None:
         if grad_out is not None:
             raise ValueError("pixel_mask is for the forward pass only")
@@ -221,7 +226,7 @@ def render(camera, pos, opacity, feat, radius=None, bg=None, splat=SPLAT_BILINEA
                       _ptr(gt), _ptr(g("grad_feat")), _ptr(g("grad_opacity")), _ptr(g("grad_uv")),
                       _ptr(g("grad_pos")), _ptr(g("grad_bg")), _ptr(g("grad_feat_abs")),
                       _ptr(g("grad_opacity_abs")), _ptr(g("grad_uv_abs")),
-                      _ptr(g("grad_pos_abs")), _ptr(pixel_mask))
+                      _ptr(g("grad_pos_abs")), _ptr(pixel_mask), int(bg_image))
     return r
 
 

@@ -363,7 +363,9 @@ static void free_scene(oscene_t* s) {
  *
  * feat:    [n][C] double (features upcast exactly by the caller)
  * opacity: [n] float
- * bg:      [C] double or NULL (constant background features)
+ * bg:      [C] double or NULL (constant background features), or with
+ *          bg_image set a per-pixel background [C][H][W] (grad_bg then
+ *          [C][H][W] too: T_final G per pixel)
  * Forward outputs:  out [C][H][W], out_abs [C][H][W] (sum of |terms|),
  *                   t_final [H][W], n_contrib [H][W], flags [H][W]
  *                   (Gaussian: 1 where the FP64 transmittance at a
@@ -383,7 +385,7 @@ int oracle_render(const ocam_t* cam, const oopts_t* o, int64_t n, const float* p
                   const float* grad_t, double* grad_feat, double* grad_opacity,
                   double* grad_uv, double* grad_pos, double* grad_bg,
                   double* grad_feat_abs, double* grad_opacity_abs, double* grad_uv_abs,
-                  double* grad_pos_abs, const uint8_t* pixel_mask) {
+                  double* grad_pos_abs, const uint8_t* pixel_mask, int32_t bg_image) {
     const int W = cam->width, H = cam->height;
     const int64_t P = (int64_t)W * H;
     if (pixel_mask && grad_out) return -1;
@@ -439,7 +441,7 @@ int oracle_render(const ocam_t* cam, const oopts_t* o, int64_t n, const float* p
                 cnt++;
             }
             for (int c = 0; c < C; ++c) {
-                double bgc = bg ? bg[c] : 0.0;
+                double bgc = bg ? (bg_image ? bg[(int64_t)c * P + p] : bg[c]) : 0.0;
                 out[(int64_t)c * P + p] = F[c] + T * bgc;
                 out_abs[(int64_t)c * P + p] = Fa[c] + fabs(T * bgc);
             }
@@ -453,7 +455,7 @@ int oracle_render(const ocam_t* cam, const oopts_t* o, int64_t n, const float* p
             double G_T = grad_t ? (double)grad_t[p] : 0.0;
             double Pi = 1.0;
             for (int c = 0; c < C; ++c) {
-                B[c] = bg ? bg[c] : 0.0;
+                B[c] = bg ? (bg_image ? bg[(int64_t)c * P + p] : bg[c]) : 0.0;
                 Ba[c] = fabs(B[c]);
             }
             for (int64_t k = s0 + (int64_t)cnt - 1; k >= s0; --k) {
@@ -534,7 +536,12 @@ int oracle_render(const ocam_t* cam, const oopts_t* o, int64_t n, const float* p
                 grad_pos_abs[3 * i + j] = gpa[j];
             }
         }
-        if (grad_bg) {
+        if (grad_bg && bg_image) {
+            /* dL/df_bg(pixel) = T_final G (Eq. (1) with the background term) */
+            for (int c = 0; c < C; ++c)
+                for (int64_t p = 0; p < P; ++p)
+                    grad_bg[(int64_t)c * P + p] = t_final[p] * (double)grad_out[(int64_t)c * P + p];
+        } else if (grad_bg) {
             for (int c = 0; c < C; ++c) {
                 double acc = 0.0;
                 for (int64_t p = 0; p < P; ++p)

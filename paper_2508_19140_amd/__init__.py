@@ -4,7 +4,7 @@ Neural Point Clouds": project, bin, per-tile depth sort, alpha blend (bilinear
 behind a C ABI (include/inpc_raster.h).
 """
 from . import _lib  # noqa: F401
-from .batched import MultiViewRasterizer, ViewInputs, ViewPipeline  # noqa: F401
+from .batched import BatchedRasterizer, MultiViewRasterizer, ViewInputs, ViewPipeline  # noqa: F401
 from .raster import (  # noqa: F401
     Binning,
     RasterSettings,
@@ -13,12 +13,15 @@ from .raster import (  # noqa: F401
     blend_forward,
     camera_struct,
     check_capacity,
+    envmap_background,
     project_backward,
     project_bin_sort,
     rasterize,
+    sh_features,
+    view_directions,
 )
 
 __all__ = [
-    "MultiViewRasterizer", "ViewInputs", "ViewPipeline", "Binning", "RasterSettings", "Workspace", "blend_backward", "blend_forward",
-    "camera_struct", "check_capacity", "project_backward", "project_bin_sort", "rasterize",
+    "BatchedRasterizer", "MultiViewRasterizer", "ViewInputs", "ViewPipeline", "Binning", "RasterSettings", "Workspace", "blend_backward", "blend_forward",
+    "camera_struct", "check_capacity", "project_backward", "project_bin_sort", "rasterize", "envmap_background", "view_directions", "sh_features",
 ]

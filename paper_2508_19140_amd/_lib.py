@@ -31,7 +31,13 @@ EXPORTS = (
     "inpc_project", "inpc_bin", "inpc_sort", "inpc_blend_forward", "inpc_blend_backward",
     "inpc_project_backward", "inpc_check_sync", "inpc_status_string", "inpc_last_error",
     "inpc_backward_scratch_bytes", "inpc_blend_backward_noalloc",
+    "inpc_view_dirs", "inpc_envmap_forward", "inpc_envmap_backward",
+    "inpc_batch_workspace_bytes", "inpc_rasterize_batched",
+    "inpc_sh_features", "inpc_sh_features_backward",
 )
+
+PASS_FORWARD = 0
+PASS_BACKWARD = 1
 
 
 class Camera(ctypes.Structure):
@@ -46,7 +52,23 @@ class Opts(ctypes.Structure):
     _fields_ = [("splat", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("t_min", ctypes.c_float), ("dilation", ctypes.c_float),
                 ("cutoff", ctypes.c_float), ("max_radius", ctypes.c_float),
-                ("bin_points", ctypes.c_int32)]
+                ("bin_points", ctypes.c_int32), ("bg_per_pixel", ctypes.c_int32)]
+
+
+_VP = ctypes.c_void_p
+
+
+class ViewRecord(ctypes.Structure):
+    """inpc_view_t: one view of a batch (camera, points and its buffers)."""
+    _fields_ = [("cam", Camera), ("n", ctypes.c_int64),
+                ("pos", _VP), ("opacity", _VP), ("radius", _VP), ("feat", _VP), ("bg", _VP),
+                ("proj", _VP), ("depth_key", _VP), ("ntiles", _VP), ("tile_ranges", _VP),
+                ("tile_order", _VP), ("list", _VP), ("lpos", _VP), ("state", _VP),
+                ("ws", _VP), ("ws_bytes", ctypes.c_size_t),
+                ("scratch", _VP), ("scratch_bytes", ctypes.c_size_t),
+                ("out", _VP), ("t_final", _VP), ("n_contrib", _VP),
+                ("grad_out", _VP), ("grad_t", _VP), ("grad_feat", _VP), ("grad_opacity", _VP),
+                ("grad_uv", _VP), ("grad_pos", _VP), ("grad_bg", _VP)]
 
 
 class InpcError(RuntimeError):
@@ -84,6 +106,14 @@ def lib():
         "inpc_blend_backward_noalloc": (I32, [CP, OP, I64, P, P, I32, I32, P, P, P, P, P, P, P,
                                               P, P, P, P, P, P, P, P, SZ, P]),
         "inpc_backward_scratch_bytes": (SZ, [I64, I32, CP, OP]),
+        "inpc_view_dirs": (I32, [CP, P, P]),
+        "inpc_envmap_forward": (I32, [CP, P, P, I32, I32, I32, P, P]),
+        "inpc_envmap_backward": (I32, [CP, P, P, I32, I32, I32, P, P]),
+        "inpc_sh_features": (I32, [CP, I64, P, P, I32, P, P]),
+        "inpc_sh_features_backward": (I32, [CP, I64, P, P, I32, P, P, P, P]),
+        "inpc_batch_workspace_bytes": (SZ, [ctypes.POINTER(ViewRecord), I32, OP]),
+        "inpc_rasterize_batched": (I32, [ctypes.POINTER(ViewRecord), P, I32, OP, I32, I32, I32,
+                                         P, SZ, P]),
         "inpc_project_backward": (I32, [CP, I64, P, P, P, P, P]),
         "inpc_check_sync": (I32, [P, SZ, P]),
         "inpc_status_string": (ctypes.c_char_p, [I32]),
@@ -124,9 +154,10 @@ def make_camera(width, height, fx, fy, cx, cy, R, t, z_near=0.2) -> Camera:
 
 
 def make_opts(splat=SPLAT_BILINEAR, tile=8, t_min=1e-4, dilation=0.16, cutoff=3.0,
-              max_radius=0.0, bin_points=0) -> Opts:
+              max_radius=0.0, bin_points=0, bg_per_pixel=False) -> Opts:
     o = Opts()
     o.bin_points = int(bin_points)
+    o.bg_per_pixel = int(bool(bg_per_pixel))
     o.splat, o.tile = int(splat), int(tile)
     o.t_min, o.dilation, o.cutoff, o.max_radius = float(t_min), float(dilation), float(cutoff), \
         float(max_radius)

@@ -4,6 +4,12 @@
 the forward state, the gradients) and issues the C-ABI calls of one forward
 and one backward pass on a given stream, allocating nothing.
 
+`BatchedRasterizer` runs a batch of views with uneven point counts and
+resolutions through the batched entry point (inpc_rasterize_batched): per
+direction one call, whose blend is a single persistent launch over every
+(view, tile) item, autotuned over (tile size, points per binning
+workgroup) for the whole batch with the choice kept in a JSON cache.
+
 `MultiViewRasterizer` runs a batch of views with uneven point counts and
 resolutions as one training step: each view's forward + backward goes on a
 stream of its own, the streams fork from and join back to one capture
@@ -17,6 +23,8 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import json
+import os
 from typing import Dict, List, Optional, Sequence, Tuple
 
 import torch
@@ -82,6 +90,25 @@ class ViewPipeline:
             self.gf, self.go, self.guv, self.gpos = mk(n, C), mk(n), mk(n, 2), mk(n, 3)
             self.scratch = mk(int(lib.inpc_backward_scratch_bytes(n, C, self.cb, self.ob)),
                               dt=torch.uint8)
+
+    def fill_record(self, r: "L.ViewRecord") -> None:
+        """This view's camera, points and buffers as an inpc_view_t record."""
+        v = self.v
+        ptr = lambda t: None if t is None else t.data_ptr()
+        r.cam = self.cam
+        r.n = self.n
+        r.pos, r.opacity, r.radius, r.feat = ptr(v.pos), ptr(v.opacity), ptr(v.radius), ptr(v.feat)
+        r.bg = None
+        r.proj, r.depth_key, r.ntiles = ptr(self.proj), ptr(self.key), ptr(self.ntiles)
+        r.tile_ranges, r.tile_order = ptr(self.ranges), ptr(self.order)
+        r.list, r.lpos, r.state = ptr(self.list), ptr(self.lpos), ptr(self.state)
+        r.ws, r.ws_bytes = ptr(self.ws), self.ws.numel()
+        r.out, r.t_final, r.n_contrib = ptr(self.out), ptr(self.tf), ptr(self.nc)
+        r.grad_out, r.grad_t, r.grad_bg = ptr(v.grad_out), None, None
+        if self.backward_enabled:
+            r.scratch, r.scratch_bytes = ptr(self.scratch), self.scratch.numel()
+            r.grad_feat, r.grad_opacity = ptr(self.gf), ptr(self.go)
+            r.grad_uv, r.grad_pos = ptr(self.guv), ptr(self.gpos)
 
     def _call(self, name, *args):
         st = getattr(self.lib, name)(*args)
@@ -234,6 +261,157 @@ class MultiViewRasterizer:
                     p.step(_handle(st))
             for st in self.streams:
                 cs.wait_stream(st)
+        self.graph = g
+        return g
+
+    def replay(self):
+        if self.graph is None:
+            self.capture()
+        self.graph.replay()
+
+    def outputs(self) -> List[Dict[str, torch.Tensor]]:
+        return [p.outputs() for p in self.pipes]
+
+
+# ---------------------------------------------------------------------------
+# One batched pass over every view (inpc_rasterize_batched)
+# ---------------------------------------------------------------------------
+
+AUTOTUNE_CACHE_ENV = "INPC_AUTOTUNE_CACHE"
+
+
+def default_cache_path() -> str:
+    """JSON file of autotuned settings: $INPC_AUTOTUNE_CACHE, else
+    ~/.cache/inpc_raster/autotune.json."""
+    return os.environ.get(AUTOTUNE_CACHE_ENV) or os.path.join(
+        os.path.expanduser("~"), ".cache", "inpc_raster", "autotune.json")
+
+
+def batch_key(views: Sequence[ViewInputs], settings: RasterSettings) -> str:
+    """Cache key of a batch: every view's resolution and point count, the
+    channel count, the feature dtype and the splat kind."""
+    shapes = []
+    for v in views:
+        cam = camera_struct(v.camera)
+        shapes.append([cam.width, cam.height, int(v.feat.shape[0])])
+    return json.dumps({"views": shapes, "C": int(views[0].feat.shape[1]),
+                       "dtype": str(views[0].feat.dtype), "splat": settings.splat},
+                      sort_keys=True)
+
+
+def load_cache(path: str) -> dict:
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def store_cache(path: str, key: str, value) -> None:
+    d = load_cache(path)
+    d[key] = value
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+class BatchedRasterizer:
+    """Every view of a batch in one batched pass per direction.
+
+    The views (uneven point counts and resolutions) share one setting of
+    tile size and points per binning workgroup, chosen by timing the whole
+    batched step for every candidate (tiles x bin_points) and kept in a JSON
+    cache keyed by the batch's shapes (default_cache_path()).  Each step is
+    inpc_rasterize_batched(FORWARD) then (BACKWARD): the per-view list builds,
+    then one persistent launch over all (view, tile) items of the blend (and
+    of its replay).  The view table is built once from the per-view buffers
+    and kept in device memory; `capture()` records a step into a HIP graph.
+    """
+
+    def __init__(self, views: Sequence[ViewInputs], settings: RasterSettings = RasterSettings(),
+                 tiles: Sequence[int] = (8, 16), bin_points: Sequence[int] = (0, 2048, 4096),
+                 autotune: bool = True, cache_path: Optional[str] = None, reps: int = 3):
+        self.views = list(views)
+        if not self.views:
+            raise ValueError("a batch needs at least one view")
+        C, dt = self.views[0].feat.shape[1], self.views[0].feat.dtype
+        if any(v.feat.shape[1] != C or v.feat.dtype != dt for v in self.views):
+            raise ValueError("all views of a batch share the channel count and feature dtype")
+        self.base = settings
+        self.cache_path = cache_path or default_cache_path()
+        self.key = batch_key(self.views, settings)
+        self.tuning: Dict[Tuple[int, int], float] = {}
+        cached = load_cache(self.cache_path).get(self.key)
+        if cached is not None:
+            self.choice = (int(cached[0]), int(cached[1]))
+        elif autotune:
+            for t in tiles:
+                for bp in bin_points:
+                    self._build(dataclasses.replace(settings, tile=t, bin_points=bp))
+                    self.tuning[(t, bp)] = self._time(reps)
+            self.choice = min(self.tuning, key=self.tuning.get)
+            store_cache(self.cache_path, self.key, list(self.choice))
+        else:
+            self.choice = (settings.tile, settings.bin_points)
+        self._build(dataclasses.replace(settings, tile=self.choice[0],
+                                        bin_points=self.choice[1]))
+        self.graph = None
+
+    def _build(self, settings: RasterSettings):
+        self.settings = settings
+        self.pipes = [ViewPipeline(v, settings) for v in self.views]
+        self.opts = settings.opts()
+        recs = (L.ViewRecord * len(self.pipes))()
+        for r, p in zip(recs, self.pipes):
+            p.fill_record(r)
+        self.records = recs
+        dev = self.views[0].pos.device
+        raw = torch.frombuffer(bytearray(bytes(recs)), dtype=torch.uint8)
+        self.table = raw.to(dev)
+        lib = L.lib()
+        nb = int(lib.inpc_batch_workspace_bytes(recs, len(self.pipes), ctypes.byref(self.opts)))
+        if nb == 0:
+            raise ValueError("invalid batch")
+        self.batch_ws = torch.zeros(nb, dtype=torch.uint8, device=dev)
+        self.C = int(self.views[0].feat.shape[1])
+        self.dtype = _DT[self.views[0].feat.dtype]
+        self.backward_enabled = all(p.backward_enabled for p in self.pipes)
+
+    def _pass(self, pass_, h):
+        L.call("inpc_rasterize_batched", self.records, _p(self.table), len(self.pipes),
+               ctypes.byref(self.opts), self.C, self.dtype, pass_, _p(self.batch_ws),
+               self.batch_ws.numel(), h)
+
+    def step(self, stream: Optional[torch.cuda.Stream] = None):
+        h = _handle(stream or torch.cuda.current_stream())
+        self._pass(L.PASS_FORWARD, h)
+        if self.backward_enabled:
+            self._pass(L.PASS_BACKWARD, h)
+
+    def _time(self, reps: int) -> float:
+        s = torch.cuda.current_stream()
+        self.step(s)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            self.step(s)
+        e1.record(s)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def capture(self):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):  # warm-up outside capture, as torch requires
+            self.step(side)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step(torch.cuda.current_stream())
         self.graph = g
         return g
 

@@ -18,7 +18,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libinpc_raster.so")
-SOURCES = ["api.hip", "project.hip", "sort.hip", "blend.hip"]
+SOURCES = ["api.hip", "project.hip", "sort.hip", "blend.hip", "background.hip", "batch.hip",
+           "sh.hip"]
 ARCH = os.environ.get("INPC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

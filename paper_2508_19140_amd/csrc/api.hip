@@ -34,7 +34,7 @@ bool valid_opts(const inpc_opts_t* o) {
   return o && (o->tile == 8 || o->tile == 16 || o->tile == 32) && o->bin_points >= 0 &&
          o->bin_points % 1024 == 0 &&
          (o->splat == INPC_SPLAT_BILINEAR || o->splat == INPC_SPLAT_GAUSSIAN) &&
-         o->t_min >= 0.f && o->t_min <= 1.f &&
+         o->t_min >= 0.f && o->t_min <= 1.f && (o->bg_per_pixel == 0 || o->bg_per_pixel == 1) &&
          (o->splat == INPC_SPLAT_BILINEAR ||
           (o->dilation >= 0.f && o->cutoff > 0.f && o->max_radius >= 0.f &&
            isfinite(o->max_radius)));
@@ -310,6 +310,7 @@ static inpc_status_t blend_backward_impl(const char* who, const inpc_camera_t* c
   a.C = C;
   a.dtype = dtype;
   a.bg = bg;
+  a.bg_image = opts->bg_per_pixel;
   a.ranges = tile_ranges;
   a.order = tile_order;
   a.list = list;
@@ -328,9 +329,10 @@ static inpc_status_t blend_backward_impl(const char* who, const inpc_camera_t* c
   a.grad_uv = grad_uv;
   a.grad_bg = grad_bg;
   a.gsc = static_cast<float4*>(scratch);
-  a.bg_partial = grad_bg ? reinterpret_cast<float*>(static_cast<char*>(scratch) +
-                                                    scratch_scalar_bytes(n))
-                         : nullptr;
+  a.bg_partial = grad_bg && !opts->bg_per_pixel
+                     ? reinterpret_cast<float*>(static_cast<char*>(scratch) +
+                                                scratch_scalar_bytes(n))
+                     : nullptr;
   a.flags = w.flags;
   hipError_t e = launch_blend_backward(a, (hipStream_t)stream);
   return e == hipSuccess ? INPC_OK : hip_fail(e, who);
@@ -460,6 +462,7 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
   a.C = C;
   a.dtype = dtype;
   a.bg = bg;
+  a.bg_image = opts->bg_per_pixel;
   a.ranges = tile_ranges;
   a.order = tile_order;
   a.list = list;
@@ -539,6 +542,208 @@ inpc_status_t inpc_project_backward(const inpc_camera_t* cam, int64_t n, const f
   hipError_t e = launch_project_backward(to_cam(cam), n, pos, ntiles, grad_uv, grad_pos,
                                          (hipStream_t)stream);
   return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_project_backward");
+}
+
+inpc_status_t inpc_view_dirs(const inpc_camera_t* cam, float* dirs, void* stream) {
+  if (!valid_cam(cam)) return fail(INPC_ERR_INVALID, "invalid camera%s", "");
+  REQUIRE(dirs, "dirs");
+  hipError_t e = launch_view_dirs(to_cam(cam), dirs, (hipStream_t)stream);
+  return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_view_dirs");
+}
+
+static inpc_status_t envmap_checks(const inpc_camera_t* cam, const float* dirs, int32_t Hm,
+                                   int32_t Wm, int32_t C) {
+  if (!valid_cam(cam)) return fail(INPC_ERR_INVALID, "invalid camera%s", "");
+  REQUIRE(dirs, "dirs");
+  if (Hm < 1 || Wm < 1 || (int64_t)Hm * Wm > (int64_t)1 << 30)
+    return fail(INPC_ERR_INVALID, "environment map size out of range%s", "");
+  if (C < 1 || C > 64) return fail(INPC_ERR_INVALID, "channels must be in [1, 64]%s", "");
+  return INPC_OK;
+}
+
+inpc_status_t inpc_envmap_forward(const inpc_camera_t* cam, const float* dirs, const float* env,
+                                  int32_t Hm, int32_t Wm, int32_t C, float* bg, void* stream) {
+  inpc_status_t st = envmap_checks(cam, dirs, Hm, Wm, C);
+  if (st != INPC_OK) return st;
+  REQUIRE(env, "env");
+  REQUIRE(bg, "bg");
+  hipError_t e = launch_envmap_forward(to_cam(cam), dirs, env, Hm, Wm, C, bg, (hipStream_t)stream);
+  return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_envmap_forward");
+}
+
+inpc_status_t inpc_envmap_backward(const inpc_camera_t* cam, const float* dirs,
+                                   const float* grad_bg, int32_t Hm, int32_t Wm, int32_t C,
+                                   float* grad_env, void* stream) {
+  inpc_status_t st = envmap_checks(cam, dirs, Hm, Wm, C);
+  if (st != INPC_OK) return st;
+  REQUIRE(grad_bg, "grad_bg");
+  REQUIRE(grad_env, "grad_env");
+  hipError_t e = launch_envmap_backward(to_cam(cam), dirs, grad_bg, Hm, Wm, C, grad_env,
+                                        (hipStream_t)stream);
+  return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_envmap_backward");
+}
+
+// Batch workspace: per-view blend arguments, the (view, position) work
+// items, the queue counter.
+struct BatchLayout {
+  size_t args, items, counter, total;
+};
+static BatchLayout batch_layout(int nv, int64_t items) {
+  BatchLayout L;
+  L.args = 0;
+  L.items = align_up((size_t)nv * sizeof(BlendArgs));
+  L.counter = L.items + align_up((size_t)items * sizeof(uint2));
+  L.total = L.counter + kAlign;
+  return L;
+}
+
+static int64_t batch_items(const inpc_view_t* views, int nv, const inpc_opts_t* opts) {
+  int64_t total = 0;
+  for (int v = 0; v < nv; ++v) {
+    if (!valid_cam(&views[v].cam)) return -1;
+    total += num_tiles(&views[v].cam, opts);
+  }
+  return total;
+}
+
+size_t inpc_batch_workspace_bytes(const inpc_view_t* views_host, int32_t n_views,
+                                  const inpc_opts_t* opts) {
+  if (!views_host || n_views < 1 || n_views > kMaxBatchViews || !valid_opts(opts)) return 0;
+  const int64_t items = batch_items(views_host, n_views, opts);
+  if (items < 0 || items > (int64_t)0xffffffffLL) return 0;
+  return batch_layout(n_views, items).total;
+}
+
+inpc_status_t inpc_rasterize_batched(const inpc_view_t* views_host, const inpc_view_t* views_dev,
+                                     int32_t n_views, const inpc_opts_t* opts, int32_t C,
+                                     int32_t dtype, int32_t pass, void* batch_ws,
+                                     size_t batch_ws_bytes, void* stream) {
+  REQUIRE(views_host, "views_host");
+  REQUIRE(views_dev, "views_dev");
+  REQUIRE_ALIGNED(batch_ws, "batch_ws", 16);
+  if (n_views < 1 || n_views > kMaxBatchViews)
+    return fail(INPC_ERR_INVALID, "n_views must be in [1, 64]%s", "");
+  if (!valid_opts(opts)) return fail(INPC_ERR_INVALID, "invalid options%s", "");
+  if (pass != INPC_PASS_FORWARD && pass != INPC_PASS_BACKWARD)
+    return fail(INPC_ERR_INVALID, "unknown pass%s", "");
+  const bool fwd = pass == INPC_PASS_FORWARD;
+  if (!fwd && opts->splat != INPC_SPLAT_BILINEAR)
+    return fail(INPC_ERR_UNSUPPORTED, "backward of Gaussian splats%s", "");
+  const int64_t items = batch_items(views_host, n_views, opts);
+  if (items < 0) return fail(INPC_ERR_INVALID, "invalid camera%s", "");
+  if (items > (int64_t)0xffffffffLL) return fail(INPC_ERR_INVALID, "too many tiles%s", "");
+  const BatchLayout BL = batch_layout(n_views, items);
+  if (batch_ws_bytes < BL.total)
+    return fail(INPC_ERR_INVALID, "batch_ws smaller than inpc_batch_workspace_bytes()%s", "");
+  const hipStream_t s = (hipStream_t)stream;
+  BatchTiles bt;
+  bt.nv = n_views;
+  bt.start[0] = 0;
+  // per view: the checks of the single-view calls, then steps 1-3 (and the
+  // backward's zero fill)
+  for (int v = 0; v < n_views; ++v) {
+    const inpc_view_t& w = views_host[v];
+    bt.start[v + 1] = bt.start[v] + num_tiles(&w.cam, opts);
+    inpc_status_t st = blend_checks(&w.cam, opts, w.n, C, dtype, w.ws, w.ws_bytes);
+    if (st != INPC_OK) return st;
+    const bool bil = opts->splat == INPC_SPLAT_BILINEAR;
+    REQUIRE(w.tile_ranges, "tile_ranges");
+    REQUIRE(w.tile_order, "tile_order");
+    REQUIRE(w.list, "list");
+    if (bil) REQUIRE(w.lpos, "lpos");
+    if (w.n > 0) REQUIRE_ALIGNED(w.feat, "feat", 16);
+    if (fwd) {
+      REQUIRE(w.out, "out");
+      REQUIRE(w.t_final, "t_final");
+      REQUIRE(w.n_contrib, "n_contrib");
+    } else {
+      REQUIRE(w.state, "state");
+      REQUIRE(w.t_final, "t_final");
+      REQUIRE(w.grad_out, "grad_out");
+      REQUIRE_ALIGNED(w.scratch, "scratch", 16);
+      if (w.scratch_bytes < scratch_bytes(w.n, C, &w.cam, opts))
+        return fail(INPC_ERR_INVALID, "scratch smaller than inpc_backward_scratch_bytes()%s", "");
+      if (w.n > 0) {
+        REQUIRE_ALIGNED(w.grad_feat, "grad_feat", 16);
+        REQUIRE(w.grad_opacity, "grad_opacity");
+        REQUIRE_ALIGNED(w.grad_uv, "grad_uv", 8);
+        REQUIRE(w.grad_pos, "grad_pos");
+      }
+    }
+    st = inpc_project(&w.cam, opts, w.n, w.pos, w.opacity, w.radius, w.proj, w.depth_key,
+                      w.ntiles, w.ws, w.ws_bytes, stream);
+    if (st == INPC_OK)
+      st = inpc_bin(&w.cam, opts, w.n, w.proj, w.depth_key, w.ntiles, w.tile_ranges,
+                    w.tile_order, w.ws, w.ws_bytes, stream);
+    if (st == INPC_OK)
+      st = inpc_sort(&w.cam, opts, w.n, w.proj, w.tile_ranges, w.tile_order, w.list, w.lpos,
+                     w.ws, w.ws_bytes, stream);
+    if (st != INPC_OK) return st;
+    if (!fwd) {
+      const BlendArgs a = make_view_args(w, to_opts(&w.cam, opts), C, dtype, opts->bg_per_pixel);
+      hipError_t e = launch_blend_backward_pre(a, s);
+      if (e != hipSuccess) return hip_fail(e, "inpc_rasterize_batched");
+    }
+  }
+  char* b = static_cast<char*>(batch_ws);
+  BlendArgs* args = reinterpret_cast<BlendArgs*>(b + BL.args);
+  uint2* item = reinterpret_cast<uint2*>(b + BL.items);
+  uint32_t* counter = reinterpret_cast<uint32_t*>(b + BL.counter);
+  const Opts shared = to_opts(&views_host[0].cam, opts);
+  hipError_t e = launch_batch_prepare(views_dev, n_views, shared, C, dtype, opts->bg_per_pixel,
+                                      bt, args, item, counter, s);
+  if (e != hipSuccess) return hip_fail(e, "inpc_rasterize_batched");
+  // the persistent blend over every (view, tile) item
+  const BlendArgs shape = make_view_args(views_host[0], shared, C, dtype, opts->bg_per_pixel);
+  BatchQueue q;
+  q.args = args;
+  q.items = item;
+  q.counter = counter;
+  q.total = (uint32_t)items;
+  e = launch_blend_batched(fwd, shape, q, s);
+  if (e != hipSuccess) return hip_fail(e, "inpc_rasterize_batched");
+  if (fwd) return INPC_OK;
+  for (int v = 0; v < n_views; ++v) {
+    const inpc_view_t& w = views_host[v];
+    const BlendArgs a = make_view_args(w, to_opts(&w.cam, opts), C, dtype, opts->bg_per_pixel);
+    e = launch_blend_backward_post(a, s);
+    if (e != hipSuccess) return hip_fail(e, "inpc_rasterize_batched");
+    inpc_status_t st = inpc_project_backward(&w.cam, w.n, w.pos, w.ntiles, w.grad_uv, w.grad_pos,
+                                             stream);
+    if (st != INPC_OK) return st;
+  }
+  return INPC_OK;
+}
+
+inpc_status_t inpc_sh_features(const inpc_camera_t* cam, int64_t n, const float* pos,
+                               const float* sh, int32_t C, float* feat, void* stream) {
+  if (!valid_cam(cam)) return fail(INPC_ERR_INVALID, "invalid camera%s", "");
+  if (n < 0 || n > (int64_t)0x7fffffff) return fail(INPC_ERR_INVALID, "n out of range%s", "");
+  if (C < 1 || C > 64) return fail(INPC_ERR_INVALID, "channels must be in [1, 64]%s", "");
+  if (n > 0) {
+    REQUIRE(pos, "pos");
+    REQUIRE(sh, "sh");
+    REQUIRE(feat, "feat");
+  }
+  hipError_t e = launch_sh_forward(to_cam(cam), n, C, pos, sh, feat, (hipStream_t)stream);
+  return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_sh_features");
+}
+
+inpc_status_t inpc_sh_features_backward(const inpc_camera_t* cam, int64_t n, const float* pos,
+                                        const float* sh, int32_t C, const float* grad_feat,
+                                        float* grad_sh, float* grad_pos, void* stream) {
+  if (!valid_cam(cam)) return fail(INPC_ERR_INVALID, "invalid camera%s", "");
+  if (n < 0 || n > (int64_t)0x7fffffff) return fail(INPC_ERR_INVALID, "n out of range%s", "");
+  if (C < 1 || C > 64) return fail(INPC_ERR_INVALID, "channels must be in [1, 64]%s", "");
+  if (n > 0) {
+    REQUIRE(pos, "pos");
+    REQUIRE(sh, "sh");
+    REQUIRE(grad_feat, "grad_feat");
+    REQUIRE(grad_sh, "grad_sh");
+  }
+  hipError_t e = launch_sh_backward(to_cam(cam), n, C, pos, sh, grad_feat, grad_sh, grad_pos,
+                                    (hipStream_t)stream);
+  return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_sh_features_backward");
 }
 
 inpc_status_t inpc_check_sync(void* ws, size_t ws_bytes, void* stream) {

@@ -95,6 +95,42 @@ __device__ __forceinline__ uint32_t pack_xy(int x0, int y0) {
 __device__ __forceinline__ int unpack_x(uint32_t p) { return (int)(p & 0xffffu) - 1; }
 __device__ __forceinline__ int unpack_y(uint32_t p) { return (int)(p >> 16) - 1; }
 
+// Tile handled by this workgroup of a one-view launch: the order inpc_bin
+// produced (longest lists first), spread over the XCDs in runs of four.
+__device__ __forceinline__ uint32_t block_tile(const BlendArgs& a) {
+  return a.order ? a.order[xcd_pos(blockIdx.x, gridDim.x)] : blockIdx.x;
+}
+
+// Next item of a batch's work queue for this workgroup, the same for every
+// thread of it.  The queue is dealt to the 8 XCDs (workgroup b runs on XCD
+// b mod 8) in quads of consecutive positions, so the four neighbouring
+// tiles of a quad share one L2; each XCD has a counter of its own.
+// Returns a position >= the item count when this XCD's share is used up.
+template <int NTH>
+__device__ __forceinline__ uint32_t next_item(uint32_t* counter) {
+  const uint32_t x = blockIdx.x & 7u;
+  uint32_t j = 0u;
+  if constexpr (NTH == 64) {
+    if (threadIdx.x == 0) j = atomicAdd(counter + x, 1u);
+    j = __builtin_amdgcn_readfirstlane(__shfl((int)j, 0, 64));
+  } else {
+    __shared__ uint32_t s_item;
+    if (threadIdx.x == 0) s_item = atomicAdd(counter + x, 1u);
+    __syncthreads();
+    j = s_item;
+    __syncthreads();
+    j = __builtin_amdgcn_readfirstlane(j);
+  }
+  return ((j >> 2) * 8u + x) * 4u + (j & 3u);
+}
+
+// Background features behind pixel p, channel c: a constant [C] vector or a
+// per-pixel image [C][H][W] (for example an environment map sampled along
+// every pixel's view direction).
+__device__ __forceinline__ float bg_value(const BlendArgs& a, int c, int64_t P, int64_t p) {
+  return a.bg_image ? a.bg[c * P + p] : a.bg[c];
+}
+
 template <typename FT>
 __device__ __forceinline__ float half_bits_to_f32(uint32_t b);
 template <>
@@ -388,7 +424,7 @@ __device__ __forceinline__ bool copy_needed(const unsigned long long* __restrict
 // Forward, bilinear splats
 // ---------------------------------------------------------------------------
 template <int T, int CP, typename FT, bool FULL>
-__global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear(BlendArgs a) {
+__device__ __forceinline__ void blend_fwd_bilinear_tile(const BlendArgs& a, uint32_t tile) {
   using G = TileGeom<T>;
   constexpr int NW = G::NW, CH = G::CHUNK, MW = G::MW;
   __shared__ float4 s_geo[CH];
@@ -396,10 +432,8 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear(BlendArgs a) {
   __shared__ unsigned long long s_mask[2][G::NTH * MW];
   __shared__ unsigned long long s_need[MW];
   __shared__ uint32_t s_ml[NW];
-  if (a.flags[kFlagOverflow]) return;
 
   const int tid = threadIdx.x;
-  const uint32_t tile = a.order ? a.order[xcd_pos(blockIdx.x, gridDim.x)] : blockIdx.x;
   const int tx = (int)(tile % (uint32_t)a.opts.ntx), ty = (int)(tile / (uint32_t)a.opts.ntx);
   const int lx = tid % T, ly = tid / T;
   const int px = tx * T + lx, py = ty * T + ly;
@@ -508,7 +542,7 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear(BlendArgs a) {
   const int64_t p = (int64_t)py * a.cam.W + px;
 #pragma unroll
   for (int c = 0; c < CP; ++c)
-    if (c < a.C) a.out[c * P + p] = a.bg ? fmaf(Tr, a.bg[c], F[c]) : F[c];
+    if (c < a.C) a.out[c * P + p] = a.bg ? fmaf(Tr, bg_value(a, c, P, p), F[c]) : F[c];
   a.t_final[p] = Tr;
   a.n_contrib[p] = cnt;
   if (a.st_last) {
@@ -597,7 +631,7 @@ struct Compaction {
 };
 
 template <int CP, typename FT, bool FULL>
-__global__ __launch_bounds__(64) void k_blend_fwd_bilinear8(BlendArgs a) {
+__device__ __forceinline__ void blend_fwd_bilinear8_tile(const BlendArgs& a, uint32_t tile) {
   constexpr int T = 8;
   constexpr uint32_t SC = kSubs * 64;
   __shared__ float4 s_geo[64];
@@ -605,10 +639,8 @@ __global__ __launch_bounds__(64) void k_blend_fwd_bilinear8(BlendArgs a) {
   __shared__ unsigned long long s_mask[64];
   __shared__ uint2 s_sel[64];
   __shared__ uint32_t s_q1[64];  // one past the copy's position in the tile list
-  if (a.flags[kFlagOverflow]) return;
 
   const uint32_t lane = threadIdx.x;
-  const uint32_t tile = a.order ? a.order[xcd_pos(blockIdx.x, gridDim.x)] : blockIdx.x;
   const int tx = (int)(tile % (uint32_t)a.opts.ntx), ty = (int)(tile / (uint32_t)a.opts.ntx);
   const int px = tx * T + (int)(lane % T), py = ty * T + (int)(lane / T);
   const bool inside = px < a.cam.W && py < a.cam.H;
@@ -725,7 +757,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd_bilinear8(BlendArgs a) {
   const int64_t p = (int64_t)py * a.cam.W + px;
 #pragma unroll
   for (int c = 0; c < CP; ++c)
-    if (c < a.C) a.out[c * P + p] = a.bg ? fmaf(Tr, a.bg[c], F[c]) : F[c];
+    if (c < a.C) a.out[c * P + p] = a.bg ? fmaf(Tr, bg_value(a, c, P, p), F[c]) : F[c];
   a.t_final[p] = Tr;
   a.n_contrib[p] = cnt;
   if (a.st_last) {
@@ -739,16 +771,14 @@ __global__ __launch_bounds__(64) void k_blend_fwd_bilinear8(BlendArgs a) {
 // Forward, screen-space Gaussians (inference)
 // ---------------------------------------------------------------------------
 template <int T, int CP, typename FT, bool FULL>
-__global__ __launch_bounds__(T* T) void k_blend_fwd_gauss(BlendArgs a) {
+__device__ __forceinline__ void blend_fwd_gauss_tile(const BlendArgs& a, uint32_t tile) {
   using G = TileGeom<T>;
   constexpr int NW = G::NW;
   __shared__ float4 s_g0[G::CHUNK];  // u, v, o, s2
   __shared__ float4 s_g1[G::CHUNK];  // thr, packed (px0, py0), packed (px1, py1), -
   __shared__ __align__(16) float s_feat[G::CHUNK * fpad(CP)];
-  if (a.flags[kFlagOverflow]) return;
 
   const int tid = threadIdx.x;
-  const uint32_t tile = a.order ? a.order[xcd_pos(blockIdx.x, gridDim.x)] : blockIdx.x;
   const int tx = (int)(tile % (uint32_t)a.opts.ntx), ty = (int)(tile / (uint32_t)a.opts.ntx);
   const int px = tx * T + tid % T, py = ty * T + tid / T;
   const bool inside = px < a.cam.W && py < a.cam.H;
@@ -826,7 +856,7 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_gauss(BlendArgs a) {
   const int64_t p = (int64_t)py * a.cam.W + px;
 #pragma unroll
   for (int c = 0; c < CP; ++c)
-    if (c < a.C) a.out[c * P + p] = a.bg ? fmaf(Tr, a.bg[c], F[c]) : F[c];
+    if (c < a.C) a.out[c * P + p] = a.bg ? fmaf(Tr, bg_value(a, c, P, p), F[c]) : F[c];
   a.t_final[p] = Tr;
   a.n_contrib[p] = cnt;
 }
@@ -999,7 +1029,7 @@ __device__ __forceinline__ void write_chunk_rows(bool has, bool single, uint32_t
 }
 
 template <int T, int CP, typename FT, bool FULL>
-__global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
+__device__ __forceinline__ void blend_bwd_bilinear_tile(const BlendArgs& a, uint32_t tile) {
   using G = TileGeom<T>;
   constexpr int NW = G::NW, CH = G::CHUNK, MW = G::MW;
   __shared__ float4 s_geo[CH];
@@ -1009,10 +1039,8 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
   __shared__ __align__(16) float2 s_acc[CH * 4];  // per (copy, corner): (T alpha, dL/dalpha)
   __shared__ __align__(16) float s_G[G::NTH * fpad(CP)];  // dL/dF of every pixel of the tile
   __shared__ float s_red[NW][CP];
-  if (a.flags[kFlagOverflow]) return;
 
   const int tid = threadIdx.x;
-  const uint32_t tile = a.order ? a.order[xcd_pos(blockIdx.x, gridDim.x)] : blockIdx.x;
   const int tx = (int)(tile % (uint32_t)a.opts.ntx), ty = (int)(tile / (uint32_t)a.opts.ntx);
   const int lx = tid % T, ly = tid / T;
   const int px = tx * T + lx, py = ty * T + ly;
@@ -1035,7 +1063,9 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
     t_anchor = a.st_tanchor[p];
     Tf = a.t_final[p];
     if (a.bg)
-      for (int c = 0; c < C; ++c) gB = fmaf(Gv[c], a.bg[c], gB);
+      for (int c = 0; c < C; ++c) gB = fmaf(Gv[c], bg_value(a, c, P, p), gB);
+    if (a.bg_image && a.grad_bg)  // dL/df_bg(pixel) = T_final G
+      for (int c = 0; c < C; ++c) a.grad_bg[c * P + p] = Tf * Gv[c];
   }
   {
     float4* d4 = reinterpret_cast<float4*>(s_G + tid * fpad(CP));
@@ -1223,7 +1253,7 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
 // in list order and replayed in reverse, one virtual chunk of 64 at a time
 // (the previous virtual chunk's point data is fetched during the replay).
 template <int CP, typename FT, bool FULL>
-__global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
+__device__ __forceinline__ void blend_bwd_bilinear8_tile(const BlendArgs& a, uint32_t tile) {
   constexpr int T = 8;
   constexpr uint32_t SC = kSubs * 64;
   __shared__ float4 s_geo[64];
@@ -1236,10 +1266,8 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
   using PF = PointFetch<CP, FT, FULL>;
   __shared__ float4 s_prj[64];             // gathered projection records
   __shared__ uint4 s_fq[PF::QS * 64];      // gathered feature rows, row-major
-  if (a.flags[kFlagOverflow]) return;
 
   const uint32_t lane = threadIdx.x;
-  const uint32_t tile = a.order ? a.order[xcd_pos(blockIdx.x, gridDim.x)] : blockIdx.x;
   const int tx = (int)(tile % (uint32_t)a.opts.ntx), ty = (int)(tile / (uint32_t)a.opts.ntx);
   const int px = tx * T + (int)(lane % T), py = ty * T + (int)(lane / T);
   const bool inside = px < a.cam.W && py < a.cam.H;
@@ -1270,7 +1298,9 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
       t_anchor = a.st_tanchor[p];
       Tf = a.t_final[p];
       if (a.bg)
-        for (int c = 0; c < C; ++c) gB = fmaf(Gv[c], a.bg[c], gB);
+        for (int c = 0; c < C; ++c) gB = fmaf(Gv[c], bg_value(a, c, P, p), gB);
+      if (a.bg_image && a.grad_bg)  // dL/df_bg(pixel) = T_final G
+        for (int c = 0; c < C; ++c) a.grad_bg[c * P + p] = Tf * Gv[c];
     }
     float4* d4 = reinterpret_cast<float4*>(s_G + lane * fpad(CP));
 #pragma unroll
@@ -1441,6 +1471,116 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Kernels: one workgroup per tile (one view), or a persistent grid over the
+// (view, tile) items of a batch of views
+// ---------------------------------------------------------------------------
+
+template <int T, int CP, typename FT, bool FULL>
+__global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear(BlendArgs a) {
+  if (a.flags[kFlagOverflow]) return;
+  blend_fwd_bilinear_tile<T, CP, FT, FULL>(a, block_tile(a));
+}
+template <int T, int CP, typename FT, bool FULL>
+__global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear_batched(const BlendArgs* __restrict__ args, const uint2* __restrict__ items,
+                                        uint32_t* counter, uint32_t total) {
+  constexpr int NTH = T * T;
+  for (;;) {
+    const uint32_t it = next_item<NTH>(counter);
+    if (it >= total) break;
+    const uint2 vk = items[it];
+    const uint32_t v = __builtin_amdgcn_readfirstlane(vk.x);
+    const uint32_t k = __builtin_amdgcn_readfirstlane(vk.y);
+    const BlendArgs& a = args[v];  // read-only for the whole kernel: scalar loads
+    if (!a.flags[kFlagOverflow]) blend_fwd_bilinear_tile<T, CP, FT, FULL>(a, a.order[k]);
+    tile_sync<NTH / 64>();  // the next item reuses the LDS
+  }
+}
+
+template <int CP, typename FT, bool FULL>
+__global__ __launch_bounds__(64) void k_blend_fwd_bilinear8(BlendArgs a) {
+  if (a.flags[kFlagOverflow]) return;
+  blend_fwd_bilinear8_tile<CP, FT, FULL>(a, block_tile(a));
+}
+template <int CP, typename FT, bool FULL>
+__global__ __launch_bounds__(64) void k_blend_fwd_bilinear8_batched(const BlendArgs* __restrict__ args, const uint2* __restrict__ items,
+                                        uint32_t* counter, uint32_t total) {
+  constexpr int NTH = 64;
+  for (;;) {
+    const uint32_t it = next_item<NTH>(counter);
+    if (it >= total) break;
+    const uint2 vk = items[it];
+    const uint32_t v = __builtin_amdgcn_readfirstlane(vk.x);
+    const uint32_t k = __builtin_amdgcn_readfirstlane(vk.y);
+    const BlendArgs& a = args[v];  // read-only for the whole kernel: scalar loads
+    if (!a.flags[kFlagOverflow]) blend_fwd_bilinear8_tile<CP, FT, FULL>(a, a.order[k]);
+    tile_sync<NTH / 64>();  // the next item reuses the LDS
+  }
+}
+
+template <int T, int CP, typename FT, bool FULL>
+__global__ __launch_bounds__(T* T) void k_blend_fwd_gauss(BlendArgs a) {
+  if (a.flags[kFlagOverflow]) return;
+  blend_fwd_gauss_tile<T, CP, FT, FULL>(a, block_tile(a));
+}
+template <int T, int CP, typename FT, bool FULL>
+__global__ __launch_bounds__(T* T) void k_blend_fwd_gauss_batched(const BlendArgs* __restrict__ args, const uint2* __restrict__ items,
+                                        uint32_t* counter, uint32_t total) {
+  constexpr int NTH = T * T;
+  for (;;) {
+    const uint32_t it = next_item<NTH>(counter);
+    if (it >= total) break;
+    const uint2 vk = items[it];
+    const uint32_t v = __builtin_amdgcn_readfirstlane(vk.x);
+    const uint32_t k = __builtin_amdgcn_readfirstlane(vk.y);
+    const BlendArgs& a = args[v];  // read-only for the whole kernel: scalar loads
+    if (!a.flags[kFlagOverflow]) blend_fwd_gauss_tile<T, CP, FT, FULL>(a, a.order[k]);
+    tile_sync<NTH / 64>();  // the next item reuses the LDS
+  }
+}
+
+template <int T, int CP, typename FT, bool FULL>
+__global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
+  if (a.flags[kFlagOverflow]) return;
+  blend_bwd_bilinear_tile<T, CP, FT, FULL>(a, block_tile(a));
+}
+template <int T, int CP, typename FT, bool FULL>
+__global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear_batched(const BlendArgs* __restrict__ args, const uint2* __restrict__ items,
+                                        uint32_t* counter, uint32_t total) {
+  constexpr int NTH = T * T;
+  for (;;) {
+    const uint32_t it = next_item<NTH>(counter);
+    if (it >= total) break;
+    const uint2 vk = items[it];
+    const uint32_t v = __builtin_amdgcn_readfirstlane(vk.x);
+    const uint32_t k = __builtin_amdgcn_readfirstlane(vk.y);
+    const BlendArgs& a = args[v];  // read-only for the whole kernel: scalar loads
+    if (!a.flags[kFlagOverflow]) blend_bwd_bilinear_tile<T, CP, FT, FULL>(a, a.order[k]);
+    tile_sync<NTH / 64>();  // the next item reuses the LDS
+  }
+}
+
+template <int CP, typename FT, bool FULL>
+__global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
+  if (a.flags[kFlagOverflow]) return;
+  blend_bwd_bilinear8_tile<CP, FT, FULL>(a, block_tile(a));
+}
+template <int CP, typename FT, bool FULL>
+__global__ __launch_bounds__(64) void k_blend_bwd_bilinear8_batched(const BlendArgs* __restrict__ args, const uint2* __restrict__ items,
+                                        uint32_t* counter, uint32_t total) {
+  constexpr int NTH = 64;
+  for (;;) {
+    const uint32_t it = next_item<NTH>(counter);
+    if (it >= total) break;
+    const uint2 vk = items[it];
+    const uint32_t v = __builtin_amdgcn_readfirstlane(vk.x);
+    const uint32_t k = __builtin_amdgcn_readfirstlane(vk.y);
+    const BlendArgs& a = args[v];  // read-only for the whole kernel: scalar loads
+    if (!a.flags[kFlagOverflow]) blend_bwd_bilinear8_tile<CP, FT, FULL>(a, a.order[k]);
+    tile_sync<NTH / 64>();  // the next item reuses the LDS
+  }
+}
+
 // Zero n floats at p (4-byte aligned): 16-byte non-temporal stores for the
 // aligned body (a streaming fill that nothing reads back soon).
 __device__ __forceinline__ void zero_range(float* __restrict__ p, size_t n, size_t tid,
@@ -1524,13 +1664,34 @@ hipError_t fwd_launch(const BlendArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Every gradient starts at zero: points no blended fragment reached keep
+// it, single-tile points are overwritten, split points are added to.
+hipError_t bwd_pre(const BlendArgs& a, hipStream_t s) {
+  return launch_zero(a.grad_feat, (size_t)a.n * a.C, reinterpret_cast<float*>(a.gsc),
+                     (size_t)a.n * 4, s);
+}
+
+// After the tiles: the scalar rows into grad_opacity and grad_uv, and the
+// constant background's gradient from the per-tile shares.
+hipError_t bwd_post(const BlendArgs& a, hipStream_t s) {
+  const int64_t nt = (int64_t)a.opts.ntx * a.opts.nty;
+  if (a.n > 0) {
+    const int64_t g = std::min<int64_t>((a.n + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(k_unpack_scalars, dim3((unsigned)g), dim3(256), 0, s, a.gsc, a.n,
+                       a.grad_opacity, reinterpret_cast<float2*>(a.grad_uv));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (a.grad_bg && !a.bg_image)
+    hipLaunchKernelGGL(k_bg_reduce, dim3((unsigned)a.C), dim3(256), 0, s, a.bg_partial, nt, a.C,
+                       a.grad_bg);
+  return hipGetLastError();
+}
+
 template <int T, int CP, typename FT>
 hipError_t bwd_launch(const BlendArgs& a, hipStream_t s) {
   const int64_t nt = (int64_t)a.opts.ntx * a.opts.nty;
-  // Every gradient starts at zero: points no blended fragment reached keep
-  // it, single-tile points are overwritten, split points are added to.
-  hipError_t e = launch_zero(a.grad_feat, (size_t)a.n * a.C, reinterpret_cast<float*>(a.gsc),
-                            (size_t)a.n * 4, s);
+  hipError_t e = bwd_pre(a, s);
   if (e != hipSuccess) return e;
   if (T == 8 && a.C == CP)
     hipLaunchKernelGGL((k_blend_bwd_bilinear8<CP, FT, true>), dim3((unsigned)nt), dim3(64), 0, s,
@@ -1546,17 +1707,83 @@ hipError_t bwd_launch(const BlendArgs& a, hipStream_t s) {
                        0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (a.n > 0) {
-    const int64_t g = std::min<int64_t>((a.n + 255) / 256, 1 << 16);
-    hipLaunchKernelGGL(k_unpack_scalars, dim3((unsigned)g), dim3(256), 0, s, a.gsc, a.n,
-                       a.grad_opacity, reinterpret_cast<float2*>(a.grad_uv));
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  if (a.grad_bg)
-    hipLaunchKernelGGL(k_bg_reduce, dim3((unsigned)a.C), dim3(256), 0, s, a.bg_partial, nt, a.C,
-                       a.grad_bg);
+  return bwd_post(a, s);
+}
+
+// Persistent grid of a batched launch: as many workgroups as fit on the
+// device at once (they drain the queue), never more than there are items.
+template <typename K>
+hipError_t persistent_grid(K kernel, int threads, uint32_t total, int* grid) {
+  int dev = 0, cus = 0, per = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(kernel),
+                                                     threads, 0);
+  if (e != hipSuccess) return e;
+  const int64_t g = (int64_t)std::max(cus, 1) * std::max(per, 1);
+  *grid = (int)std::max<int64_t>(1, std::min<int64_t>(g, total));
+  return hipSuccess;
+}
+
+template <typename K>
+hipError_t launch_persistent(K kernel, int threads, const BatchQueue& q, hipStream_t s) {
+  int grid = 1;
+  hipError_t e = persistent_grid(kernel, threads, q.total, &grid);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(threads), 0, s, q.args, q.items, q.counter,
+                     q.total);
   return hipGetLastError();
+}
+
+template <int T, int CP, typename FT>
+hipError_t fwd_launch_q(const BlendArgs& a, const BatchQueue& q, hipStream_t s) {
+  const bool full = a.C == CP;
+  if (a.opts.splat == INPC_SPLAT_BILINEAR && T == 8)
+    return full ? launch_persistent(k_blend_fwd_bilinear8_batched<CP, FT, true>, 64, q, s)
+                : launch_persistent(k_blend_fwd_bilinear8_batched<CP, FT, false>, 64, q, s);
+  if (a.opts.splat == INPC_SPLAT_BILINEAR)
+    return full ? launch_persistent(k_blend_fwd_bilinear_batched<T, CP, FT, true>, T * T, q, s)
+                : launch_persistent(k_blend_fwd_bilinear_batched<T, CP, FT, false>, T * T, q, s);
+  return full ? launch_persistent(k_blend_fwd_gauss_batched<T, CP, FT, true>, T * T, q, s)
+              : launch_persistent(k_blend_fwd_gauss_batched<T, CP, FT, false>, T * T, q, s);
+}
+
+template <int T, int CP, typename FT>
+hipError_t bwd_launch_q(const BlendArgs& a, const BatchQueue& q, hipStream_t s) {
+  const bool full = a.C == CP;
+  if (T == 8)
+    return full ? launch_persistent(k_blend_bwd_bilinear8_batched<CP, FT, true>, 64, q, s)
+                : launch_persistent(k_blend_bwd_bilinear8_batched<CP, FT, false>, 64, q, s);
+  return full ? launch_persistent(k_blend_bwd_bilinear_batched<T, CP, FT, true>, T * T, q, s)
+              : launch_persistent(k_blend_bwd_bilinear_batched<T, CP, FT, false>, T * T, q, s);
+}
+
+template <int T, typename FT, bool FWD>
+hipError_t dispatch_cp_q(const BlendArgs& a, const BatchQueue& q, hipStream_t s) {
+  if (a.C <= 4) return FWD ? fwd_launch_q<T, 4, FT>(a, q, s) : bwd_launch_q<T, 4, FT>(a, q, s);
+  if (a.C <= 8) return FWD ? fwd_launch_q<T, 8, FT>(a, q, s) : bwd_launch_q<T, 8, FT>(a, q, s);
+  if (a.C <= 16) return FWD ? fwd_launch_q<T, 16, FT>(a, q, s) : bwd_launch_q<T, 16, FT>(a, q, s);
+  return FWD ? fwd_launch_q<T, 32, FT>(a, q, s) : bwd_launch_q<T, 32, FT>(a, q, s);
+}
+
+template <typename FT, bool FWD>
+hipError_t dispatch_t_q(const BlendArgs& a, const BatchQueue& q, hipStream_t s) {
+  switch (a.opts.T) {
+    case 8: return dispatch_cp_q<8, FT, FWD>(a, q, s);
+    case 16: return dispatch_cp_q<16, FT, FWD>(a, q, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <bool FWD>
+hipError_t dispatch_q(const BlendArgs& a, const BatchQueue& q, hipStream_t s) {
+  switch (a.dtype) {
+    case INPC_F32: return dispatch_t_q<float, FWD>(a, q, s);
+    case INPC_F16: return dispatch_t_q<__half, FWD>(a, q, s);
+    case INPC_BF16: return dispatch_t_q<__hip_bfloat16, FWD>(a, q, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int T, typename FT, bool FWD>
@@ -1648,6 +1875,15 @@ hipError_t launch_blend_forward(const BlendArgs& a, hipStream_t s) {
 hipError_t launch_blend_backward(const BlendArgs& a, hipStream_t s) {
   if (a.opts.ntx == 0 || a.opts.nty == 0) return hipSuccess;
   return dispatch<false>(a, s);
+}
+
+hipError_t launch_blend_backward_pre(const BlendArgs& a, hipStream_t s) { return bwd_pre(a, s); }
+hipError_t launch_blend_backward_post(const BlendArgs& a, hipStream_t s) { return bwd_post(a, s); }
+
+hipError_t launch_blend_batched(bool forward, const BlendArgs& shape, const BatchQueue& q,
+                                hipStream_t s) {
+  if (q.total == 0) return hipSuccess;
+  return forward ? dispatch_q<true>(shape, q, s) : dispatch_q<false>(shape, q, s);
 }
 
 }  // namespace inpc

@@ -16,7 +16,8 @@ struct BlendArgs {
   const void* feat;
   int C;
   int dtype;
-  const float* bg;
+  const float* bg;     // [C], or [C][H][W] when bg_image
+  int bg_image;
   const uint32_t* ranges;
   const uint32_t* order;  // [nt] tile processing order, or NULL for tile-index order
   const uint32_t* list;
@@ -36,11 +37,87 @@ struct BlendArgs {
   float* grad_feat;
   float* grad_opacity;
   float* grad_uv;
-  float* grad_bg;
-  float* bg_partial;  // [num_tiles][C] per-tile background gradients
+  float* grad_bg;     // [C], or [C][H][W] when bg_image (written per pixel)
+  float* bg_partial;  // [num_tiles][C] per-tile background gradients (constant background)
   float4* gsc;        // [n] (dL/do, dL/du, dL/dv, -) per point, unpacked into grad_opacity
                       // and grad_uv at the end (one 16-byte row per point for the atomics)
   const uint32_t* flags;
+};
+
+// A batch's work queue for the persistent blend kernels: per-view arguments
+// (device), the (view, position in the view's tile order) items and the 8
+// per-XCD counters the workgroups take items from.
+struct BatchQueue {
+  const BlendArgs* args;
+  const uint2* items;
+  uint32_t* counter;
+  uint32_t total;
+};
+
+// Blend arguments of one view of a batch (host and device: the batched
+// entry point builds them on the host for the per-view steps, and a kernel
+// builds the same from the device-resident view table for the persistent
+// blend kernels).
+__host__ __device__ inline BlendArgs make_view_args(const inpc_view_t& w, const Opts& shared,
+                                                    int C, int dtype, int bg_image) {
+  BlendArgs a = {};
+  a.cam.W = w.cam.width;
+  a.cam.H = w.cam.height;
+  a.cam.fx = w.cam.fx;
+  a.cam.fy = w.cam.fy;
+  a.cam.cx = w.cam.cx;
+  a.cam.cy = w.cam.cy;
+  for (int k = 0; k < 9; ++k) a.cam.R[k] = w.cam.R[k];
+  for (int k = 0; k < 3; ++k) a.cam.t[k] = w.cam.t[k];
+  a.cam.z_near = w.cam.z_near;
+  a.opts = shared;
+  a.opts.ntx = (w.cam.width + shared.T - 1) / shared.T;
+  a.opts.nty = (w.cam.height + shared.T - 1) / shared.T;
+  a.n = w.n;
+  a.proj = w.proj;
+  a.feat = w.feat;
+  a.C = C;
+  a.dtype = dtype;
+  a.bg = w.bg;
+  a.bg_image = bg_image;
+  a.ranges = w.tile_ranges;
+  a.order = w.tile_order;
+  a.list = w.list;
+  a.lpos = w.lpos;
+  a.out = w.out;
+  a.t_final = w.t_final;
+  a.n_contrib = w.n_contrib;
+  const int64_t P = (int64_t)w.cam.width * w.cam.height;
+  if (w.state) {
+    a.st_last = static_cast<uint32_t*>(w.state);
+    a.st_anchor = a.st_last + P;
+    a.st_tanchor = reinterpret_cast<float*>(a.st_anchor + P);
+    a.st_tile = a.st_last + 3 * P;
+  }
+  a.ntiles = w.ntiles;
+  a.grad_out = w.grad_out;
+  a.grad_t = w.grad_t;
+  a.grad_feat = w.grad_feat;
+  a.grad_opacity = w.grad_opacity;
+  a.grad_uv = w.grad_uv;
+  a.grad_bg = w.grad_bg;
+  a.gsc = static_cast<float4*>(w.scratch);
+  // the scratch holds a 16-byte row per point (rounded up to 256 bytes),
+  // then the per-tile background shares
+  a.bg_partial = (w.grad_bg && !bg_image && w.scratch)
+                     ? reinterpret_cast<float*>(static_cast<char*>(w.scratch) +
+                                                ((size_t)w.n * 16 + 255) / 256 * 256)
+                     : nullptr;
+  a.flags = static_cast<const uint32_t*>(w.ws);  // the workspace starts with its flags
+  return a;
+}
+
+// Tile counts of the views of a batch as an exclusive prefix (kernel
+// argument of the queue builder).
+constexpr int kMaxBatchViews = 64;
+struct BatchTiles {
+  int nv;
+  int64_t start[kMaxBatchViews + 1];
 };
 
 // Channel capacity of the kernel instantiation used for C channels.
@@ -59,6 +136,23 @@ hipError_t launch_lpos(const Cam& cam, const Opts& o, const uint32_t* ranges,
                        uint16_t* lpos, const uint32_t* flags, hipStream_t s);
 hipError_t launch_blend_forward(const BlendArgs& a, hipStream_t s);
 hipError_t launch_blend_backward(const BlendArgs& a, hipStream_t s);
+hipError_t launch_view_dirs(const Cam& c, float* dirs, hipStream_t s);
+hipError_t launch_envmap_forward(const Cam& c, const float* dirs, const float* env, int Hm, int Wm,
+                                 int C, float* bg, hipStream_t s);
+hipError_t launch_envmap_backward(const Cam& c, const float* dirs, const float* grad_bg, int Hm,
+                                  int Wm, int C, float* grad_env, hipStream_t s);
+hipError_t launch_blend_backward_pre(const BlendArgs& a, hipStream_t s);
+hipError_t launch_blend_backward_post(const BlendArgs& a, hipStream_t s);
+hipError_t launch_blend_batched(bool forward, const BlendArgs& shape, const BatchQueue& q,
+                                hipStream_t s);
+hipError_t launch_batch_prepare(const inpc_view_t* views_dev, int nv, const Opts& shared, int C,
+                                int dtype, int bg_image, const BatchTiles& bt, BlendArgs* args,
+                                uint2* items, uint32_t* counter, hipStream_t s);
+hipError_t launch_sh_forward(const Cam& c, int64_t n, int C, const float* pos, const float* sh,
+                             float* feat, hipStream_t s);
+hipError_t launch_sh_backward(const Cam& c, int64_t n, int C, const float* pos, const float* sh,
+                              const float* grad_feat, float* grad_sh, float* grad_pos,
+                              hipStream_t s);
 hipError_t launch_project_backward(const Cam& cam, int64_t n, const float* pos,
                                    const uint32_t* ntiles, const float* grad_uv, float* grad_pos,
                                    hipStream_t s);

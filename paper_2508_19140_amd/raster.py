@@ -34,10 +34,10 @@ class RasterSettings:
     keep_lists: bool = False    # keep tile lists for the backward instead of recomputing
     bin_points: int = 0         # points per workgroup of the binning passes (0 = automatic)
 
-    def opts(self) -> L.Opts:
+    def opts(self, bg_per_pixel: bool = False) -> L.Opts:
         splat = {"bilinear": L.SPLAT_BILINEAR, "gaussian": L.SPLAT_GAUSSIAN}[self.splat]
         return L.make_opts(splat, self.tile, self.t_min, self.dilation, self.cutoff,
-                           self.max_radius, self.bin_points)
+                           self.max_radius, self.bin_points, bg_per_pixel)
 
 
 def camera_struct(cam) -> L.Camera:
@@ -173,7 +173,7 @@ def blend_backward(b: Binning, feat, cam: L.Camera, opts: L.Opts, ws: torch.Tens
         grad_feat = torch.empty(n, C, dtype=torch.float32, device=dev)
         grad_opacity = torch.empty(n, dtype=torch.float32, device=dev)
         grad_uv = torch.empty(n, 2, dtype=torch.float32, device=dev)
-    grad_bg = torch.empty(C, dtype=torch.float32, device=dev) if bg is not None else None
+    grad_bg = torch.empty(bg.shape, dtype=torch.float32, device=dev) if bg is not None else None
     if scratch is None:
         scratch = torch.empty(backward_scratch_bytes(n, C, cam, opts), dtype=torch.uint8,
                               device=dev)
@@ -208,8 +208,10 @@ def _check_inputs(pos, opacity, feat, bg, radius, settings):
         raise ValueError("opacity must be float32 [N]")
     if feat.dim() != 2 or feat.shape[0] != n or feat.dtype not in _DTYPES:
         raise ValueError("feat must be [N, C] float32 / float16 / bfloat16")
-    if bg is not None and (bg.dtype != torch.float32 or bg.shape != (feat.shape[1],)):
-        raise ValueError("bg must be float32 [C]")
+    C = feat.shape[1]
+    if bg is not None and (bg.dtype != torch.float32 or bg.dim() not in (1, 3)
+                           or bg.shape[0] != C):
+        raise ValueError("bg must be float32 [C] or a per-pixel image [C, H, W]")
     if settings.splat == "gaussian":
         if radius is None or radius.dtype != torch.float32 or radius.shape != (n,):
             raise ValueError("Gaussian splats need radius float32 [N]")
@@ -218,7 +220,10 @@ def _check_inputs(pos, opacity, feat, bg, radius, settings):
 class _RasterizeFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, pos, opacity, feat, bg, radius, cam, settings, workspace):
-        opts = settings.opts()
+        bg_image = bg is not None and bg.dim() == 3
+        if bg_image and tuple(bg.shape[1:]) != (cam.height, cam.width):
+            raise ValueError("a background image must be [C, H, W] of the camera's size")
+        opts = settings.opts(bg_image)
         ws = workspace.get(pos.shape[0], cam, opts, pos.device)
         b = project_bin_sort(pos, opacity, cam, opts, ws, radius)
         out, t_final, n_contrib, state = blend_forward(
@@ -230,7 +235,7 @@ class _RasterizeFn(torch.autograd.Function):
             # splats make at most four copies per point and cannot overflow)
             check_capacity(ws)
         ctx.cam, ctx.settings, ctx.workspace = cam, settings, workspace
-        ctx.has_bg = bg is not None
+        ctx.has_bg, ctx.bg_image = bg is not None, bg_image
         saved = [pos, opacity, feat, bg if bg is not None else torch.empty(0, device=pos.device),
                  t_final, state if state is not None else torch.empty(0, device=pos.device)]
         if settings.keep_lists:
@@ -246,7 +251,7 @@ class _RasterizeFn(torch.autograd.Function):
         saved = ctx.saved_tensors
         pos, opacity, feat, bg, t_final, state = saved[:6]
         bg = bg if ctx.has_bg else None
-        cam, opts = ctx.cam, ctx.settings.opts()
+        cam, opts = ctx.cam, ctx.settings.opts(ctx.bg_image)
         ws = ctx.workspace.get(pos.shape[0], cam, opts, pos.device)
         if ctx.settings.keep_lists:
             b = Binning(*saved[6:])
@@ -263,6 +268,85 @@ class _RasterizeFn(torch.autograd.Function):
         return gpos, go, gf, gbg, None, None, None, None
 
 
+def view_directions(camera, device) -> torch.Tensor:
+    """[H, W, 3] unit camera-space view directions through the pixel centres
+    (they depend only on the intrinsics: compute once and keep)."""
+    cam = camera_struct(camera)
+    dirs = torch.empty(cam.height, cam.width, 3, dtype=torch.float32, device=device)
+    L.call("inpc_view_dirs", ctypes.byref(cam), _p(dirs), _stream(dirs.device))
+    return dirs
+
+
+class _EnvMapFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, env, dirs, cam):
+        Hm, Wm, C = env.shape
+        bg = torch.empty(C, cam.height, cam.width, dtype=torch.float32, device=env.device)
+        L.call("inpc_envmap_forward", ctypes.byref(cam), _p(dirs), _p(env), Hm, Wm, C, _p(bg),
+               _stream(env.device))
+        ctx.save_for_backward(dirs)
+        ctx.cam, ctx.shape = cam, (Hm, Wm, C)
+        return bg
+
+    @staticmethod
+    def backward(ctx, g):
+        (dirs,) = ctx.saved_tensors
+        Hm, Wm, C = ctx.shape
+        grad_env = torch.empty(Hm, Wm, C, dtype=torch.float32, device=dirs.device)
+        L.call("inpc_envmap_backward", ctypes.byref(ctx.cam), _p(dirs), _p(g.contiguous()), Hm,
+               Wm, C, _p(grad_env), _stream(dirs.device))
+        return grad_env, None, None
+
+
+def envmap_background(env: torch.Tensor, camera, dirs: Optional[torch.Tensor] = None):
+    """Background image [C, H, W] sampled from a spherical environment map
+    env [Hm, Wm, C] (equirectangular, bilinear) along every pixel's view
+    direction; differentiable with respect to env.  Pass it to rasterize()
+    as `bg` to composite it behind the points (F += T_final f_bg)."""
+    if env.dtype != torch.float32 or env.dim() != 3 or not env.is_cuda:
+        raise ValueError("env must be a float32 [Hm, Wm, C] device tensor")
+    cam = camera_struct(camera)
+    if dirs is None:
+        dirs = view_directions(cam, env.device)
+    if dirs.shape != (cam.height, cam.width, 3) or dirs.dtype != torch.float32:
+        raise ValueError("dirs must be float32 [H, W, 3]")
+    return _EnvMapFn.apply(env.contiguous(), dirs.contiguous(), cam)
+
+
+class _ShFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, pos, sh, cam):
+        n, C, _ = sh.shape
+        feat = torch.empty(n, C, dtype=torch.float32, device=pos.device)
+        L.call("inpc_sh_features", ctypes.byref(cam), n, _p(pos), _p(sh), C, _p(feat),
+               _stream(pos.device))
+        ctx.save_for_backward(pos, sh)
+        ctx.cam = cam
+        return feat
+
+    @staticmethod
+    def backward(ctx, g):
+        pos, sh = ctx.saved_tensors
+        n, C, _ = sh.shape
+        grad_sh = torch.empty_like(sh)
+        grad_pos = torch.empty_like(pos) if ctx.needs_input_grad[0] else None
+        L.call("inpc_sh_features_backward", ctypes.byref(ctx.cam), n, _p(pos), _p(sh), C,
+               _p(g.contiguous()), _p(grad_sh), _p(grad_pos), _stream(pos.device))
+        return grad_pos, grad_sh, None
+
+
+def sh_features(pos: torch.Tensor, sh: torch.Tensor, camera) -> torch.Tensor:
+    """View-dependent features [N, C] from degree-2 spherical-harmonics
+    coefficients sh [N, C, 9] at every point's view direction (from the
+    camera centre to the point); differentiable in sh and pos.  Its output
+    is the `feat` of rasterize()."""
+    if (not pos.is_cuda or pos.dtype != torch.float32 or pos.dim() != 2 or pos.shape[1] != 3
+            or sh.dtype != torch.float32 or sh.dim() != 3 or sh.shape[0] != pos.shape[0]
+            or sh.shape[2] != 9):
+        raise ValueError("pos must be float32 [N, 3] and sh float32 [N, C, 9] device tensors")
+    return _ShFn.apply(pos.contiguous(), sh.contiguous(), camera_struct(camera))
+
+
 def rasterize(pos: torch.Tensor, opacity: torch.Tensor, feat: torch.Tensor, camera,
               bg: Optional[torch.Tensor] = None, radius: Optional[torch.Tensor] = None,
               settings: RasterSettings = RasterSettings(),
@@ -270,7 +354,8 @@ def rasterize(pos: torch.Tensor, opacity: torch.Tensor, feat: torch.Tensor, came
     """Render a feature image.
 
     pos [N,3] f32, opacity [N] f32 in [0,1], feat [N,C] f32/f16/bf16,
-    bg [C] f32 or None, radius [N] f32 (Gaussian splats).
+    bg [C] f32, a per-pixel background [C,H,W] f32 (e.g. envmap_background)
+    or None, radius [N] f32 (Gaussian splats).
     Returns out [C,H,W] f32, t_final [H,W] f32, n_contrib [H,W] int32.
     """
     _check_inputs(pos, opacity, feat, bg, radius, settings)
