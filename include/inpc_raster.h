@@ -324,21 +324,26 @@ inpc_status_t inpc_envmap_backward(const inpc_camera_t* cam, const float* dirs,
  * dtype.
  *
  * inpc_rasterize_batched(pass = INPC_PASS_FORWARD): every view's tile
- *   lists are built (steps 1-3), then ONE persistent launch blends every
- *   (view, tile) item: its workgroups take items from a device work queue
- *   until it is empty, the views interleaved in proportion to their tile
- *   counts, every view's tiles longest first.  Writes out, t_final,
- *   n_contrib and state of every view, exactly as inpc_blend_forward would.
+ *   lists are built (steps 1-3), then ONE launch blends every (view, tile)
+ *   item: a kernel lays out a device work queue of all items (the views
+ *   interleaved quad by quad in proportion to their tile counts, every
+ *   view's tiles longest first) and the blend takes one item per workgroup
+ *   in queue order.  Writes out, t_final, n_contrib and state of every
+ *   view, exactly as inpc_blend_forward would.
  * inpc_rasterize_batched(pass = INPC_PASS_BACKWARD): the lists are built
- *   again (bilinear splats only), ONE persistent launch replays every
- *   (view, tile) item backwards, then every view's gradients are finished
- *   and chained to positions: grad_feat, grad_opacity, grad_uv, grad_pos
- *   and grad_bg as inpc_blend_backward + inpc_project_backward give them.
+ *   again (bilinear splats only), ONE launch replays every (view, tile) item
+ *   backwards, then every view's gradients are finished and chained to
+ *   positions: grad_feat, grad_opacity, grad_uv, grad_pos and grad_bg as
+ *   inpc_blend_backward + inpc_project_backward give them.
  * batch_ws: device scratch of inpc_batch_workspace_bytes(views_host, ...)
- *   bytes (per-view kernel arguments, the work queue and its counter).
- * Everything is asynchronous on `stream` and allocates nothing, so a pass
- * can be captured into a HIP graph.  Host-side checks as for the
- * single-view calls; n_views must be in [1, 64].
+ *   bytes (per-view kernel arguments and the work queue).
+ * Everything is ordered on `stream` and allocates no device memory, so a
+ * pass can be captured into a HIP graph: the views' own steps (lists, the
+ * backward's zero fill and finishing passes) run side by side on up to 8
+ * library-owned streams (default priority, created on the first call on a
+ * device and kept until the process ends), forked from `stream` and joined
+ * back to it with events.  Host-side checks as for the single-view calls,
+ * all before any launch; n_views must be in [1, 64].
  */
 typedef struct {
     inpc_camera_t cam;

@@ -583,25 +583,75 @@ inpc_status_t inpc_envmap_backward(const inpc_camera_t* cam, const float* dirs,
   return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_envmap_backward");
 }
 
-// Batch workspace: per-view blend arguments, the (view, position) work
-// items, the queue counter.
-struct BatchLayout {
-  size_t args, items, counter, total;
+// Side streams of the batched entry point, per device, created on first use
+// and kept until the process ends (default priority, non-blocking), with the
+// events that fork them from and join them back to the caller's stream.
+constexpr int kSideStreams = 8;
+struct SideStreams {
+  std::mutex mu;  // one batched call issues its work at a time
+  hipStream_t st[kSideStreams];
+  hipEvent_t fork, join[kSideStreams];
 };
-static BatchLayout batch_layout(int nv, int64_t items) {
+std::mutex g_side_mu;
+SideStreams* g_side[kMaxDevices];
+
+static inpc_status_t side_streams(SideStreams** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "inpc_rasterize_batched: hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(INPC_ERR_INVALID, "device index out of range%s", "");
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  if (!g_side[dev]) {
+    SideStreams* p = new SideStreams();
+    for (int k = 0; k < kSideStreams && e == hipSuccess; ++k)
+      e = hipStreamCreateWithFlags(&p->st[k], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+    for (int k = 0; k < kSideStreams && e == hipSuccess; ++k)
+      e = hipEventCreateWithFlags(&p->join[k], hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "inpc_rasterize_batched: side streams");
+    g_side[dev] = p;
+  }
+  *out = g_side[dev];
+  return INPC_OK;
+}
+
+// The first ns side streams wait for everything issued to s so far.
+static inpc_status_t fork_sides(SideStreams* p, hipStream_t s, int ns) {
+  hipError_t e = hipEventRecord(p->fork, s);
+  for (int k = 0; k < ns && e == hipSuccess; ++k) e = hipStreamWaitEvent(p->st[k], p->fork, 0);
+  return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_rasterize_batched: fork");
+}
+
+// s waits for everything issued to the first ns side streams.
+static inpc_status_t join_sides(SideStreams* p, hipStream_t s, int ns) {
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < ns && e == hipSuccess; ++k) {
+    e = hipEventRecord(p->join[k], p->st[k]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, p->join[k], 0);
+  }
+  return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_rasterize_batched: join");
+}
+
+// Batch workspace: per-view blend arguments, then the queue slots (whole
+// quads of four per view).
+struct BatchLayout {
+  size_t args, items, total;
+};
+static BatchLayout batch_layout(int nv, int64_t slots) {
   BatchLayout L;
   L.args = 0;
   L.items = align_up((size_t)nv * sizeof(BlendArgs));
-  L.counter = L.items + align_up((size_t)items * sizeof(uint2));
-  L.total = L.counter + kAlign;
+  L.total = L.items + align_up((size_t)slots * sizeof(uint2));
   return L;
 }
 
+// Queue slots of a batch: 4 ceil(tiles / 4) per view; -1 if a camera is invalid.
 static int64_t batch_items(const inpc_view_t* views, int nv, const inpc_opts_t* opts) {
   int64_t total = 0;
   for (int v = 0; v < nv; ++v) {
     if (!valid_cam(&views[v].cam)) return -1;
-    total += num_tiles(&views[v].cam, opts);
+    total += 4 * ((num_tiles(&views[v].cam, opts) + 3) / 4);
   }
   return total;
 }
@@ -639,11 +689,11 @@ inpc_status_t inpc_rasterize_batched(const inpc_view_t* views_host, const inpc_v
   BatchTiles bt;
   bt.nv = n_views;
   bt.start[0] = 0;
-  // per view: the checks of the single-view calls, then steps 1-3 (and the
-  // backward's zero fill)
+  // every view's checks (those of the single-view calls) before any launch
   for (int v = 0; v < n_views; ++v) {
     const inpc_view_t& w = views_host[v];
-    bt.start[v + 1] = bt.start[v] + num_tiles(&w.cam, opts);
+    bt.tiles[v] = num_tiles(&w.cam, opts);
+    bt.start[v + 1] = bt.start[v] + (bt.tiles[v] + 3) / 4;
     inpc_status_t st = blend_checks(&w.cam, opts, w.n, C, dtype, w.ws, w.ws_bytes);
     if (st != INPC_OK) return st;
     const bool bil = opts->splat == INPC_SPLAT_BILINEAR;
@@ -651,7 +701,15 @@ inpc_status_t inpc_rasterize_batched(const inpc_view_t* views_host, const inpc_v
     REQUIRE(w.tile_order, "tile_order");
     REQUIRE(w.list, "list");
     if (bil) REQUIRE(w.lpos, "lpos");
-    if (w.n > 0) REQUIRE_ALIGNED(w.feat, "feat", 16);
+    if (w.n > 0) {
+      REQUIRE(w.pos, "pos");
+      REQUIRE(w.opacity, "opacity");
+      REQUIRE_PROJ(w.proj);
+      REQUIRE(w.depth_key, "depth_key");
+      REQUIRE(w.ntiles, "ntiles");
+      REQUIRE_ALIGNED(w.feat, "feat", 16);
+      if (!bil) REQUIRE(w.radius, "radius");
+    }
     if (fwd) {
       REQUIRE(w.out, "out");
       REQUIRE(w.t_final, "t_final");
@@ -670,49 +728,66 @@ inpc_status_t inpc_rasterize_batched(const inpc_view_t* views_host, const inpc_v
         REQUIRE(w.grad_pos, "grad_pos");
       }
     }
+  }
+  // The views' own steps (lists, the backward's zero fill and its finishing
+  // passes) are independent and mostly latency-bound on their own, so they
+  // run side by side on the library's side streams, forked from and joined
+  // back to `stream` with events (capturable into a graph).
+  SideStreams* side = nullptr;
+  inpc_status_t st = side_streams(&side);
+  if (st != INPC_OK) return st;
+  std::lock_guard<std::mutex> lock(side->mu);
+  const int ns = std::min(n_views, kSideStreams);
+  st = fork_sides(side, s, ns);
+  if (st != INPC_OK) return st;
+  for (int v = 0; v < n_views; ++v) {
+    const inpc_view_t& w = views_host[v];
+    void* vs = side->st[v % kSideStreams];
     st = inpc_project(&w.cam, opts, w.n, w.pos, w.opacity, w.radius, w.proj, w.depth_key,
-                      w.ntiles, w.ws, w.ws_bytes, stream);
+                      w.ntiles, w.ws, w.ws_bytes, vs);
     if (st == INPC_OK)
       st = inpc_bin(&w.cam, opts, w.n, w.proj, w.depth_key, w.ntiles, w.tile_ranges,
-                    w.tile_order, w.ws, w.ws_bytes, stream);
+                    w.tile_order, w.ws, w.ws_bytes, vs);
     if (st == INPC_OK)
       st = inpc_sort(&w.cam, opts, w.n, w.proj, w.tile_ranges, w.tile_order, w.list, w.lpos,
-                     w.ws, w.ws_bytes, stream);
+                     w.ws, w.ws_bytes, vs);
     if (st != INPC_OK) return st;
     if (!fwd) {
       const BlendArgs a = make_view_args(w, to_opts(&w.cam, opts), C, dtype, opts->bg_per_pixel);
-      hipError_t e = launch_blend_backward_pre(a, s);
+      hipError_t e = launch_blend_backward_pre(a, (hipStream_t)vs);
       if (e != hipSuccess) return hip_fail(e, "inpc_rasterize_batched");
     }
   }
+  st = join_sides(side, s, ns);
+  if (st != INPC_OK) return st;
   char* b = static_cast<char*>(batch_ws);
   BlendArgs* args = reinterpret_cast<BlendArgs*>(b + BL.args);
   uint2* item = reinterpret_cast<uint2*>(b + BL.items);
-  uint32_t* counter = reinterpret_cast<uint32_t*>(b + BL.counter);
   const Opts shared = to_opts(&views_host[0].cam, opts);
   hipError_t e = launch_batch_prepare(views_dev, n_views, shared, C, dtype, opts->bg_per_pixel,
-                                      bt, args, item, counter, s);
+                                      bt, args, item, s);
   if (e != hipSuccess) return hip_fail(e, "inpc_rasterize_batched");
-  // the persistent blend over every (view, tile) item
+  // one blend launch over every (view, tile) slot
   const BlendArgs shape = make_view_args(views_host[0], shared, C, dtype, opts->bg_per_pixel);
   BatchQueue q;
   q.args = args;
   q.items = item;
-  q.counter = counter;
   q.total = (uint32_t)items;
   e = launch_blend_batched(fwd, shape, q, s);
   if (e != hipSuccess) return hip_fail(e, "inpc_rasterize_batched");
   if (fwd) return INPC_OK;
+  st = fork_sides(side, s, ns);
+  if (st != INPC_OK) return st;
   for (int v = 0; v < n_views; ++v) {
     const inpc_view_t& w = views_host[v];
+    void* vs = side->st[v % kSideStreams];
     const BlendArgs a = make_view_args(w, to_opts(&w.cam, opts), C, dtype, opts->bg_per_pixel);
-    e = launch_blend_backward_post(a, s);
+    e = launch_blend_backward_post(a, (hipStream_t)vs);
     if (e != hipSuccess) return hip_fail(e, "inpc_rasterize_batched");
-    inpc_status_t st = inpc_project_backward(&w.cam, w.n, w.pos, w.ntiles, w.grad_uv, w.grad_pos,
-                                             stream);
+    st = inpc_project_backward(&w.cam, w.n, w.pos, w.ntiles, w.grad_uv, w.grad_pos, vs);
     if (st != INPC_OK) return st;
   }
-  return INPC_OK;
+  return join_sides(side, s, ns);
 }
 
 inpc_status_t inpc_sh_features(const inpc_camera_t* cam, int64_t n, const float* pos,

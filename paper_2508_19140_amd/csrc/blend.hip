@@ -101,29 +101,6 @@ __device__ __forceinline__ uint32_t block_tile(const BlendArgs& a) {
   return a.order ? a.order[xcd_pos(blockIdx.x, gridDim.x)] : blockIdx.x;
 }
 
-// Next item of a batch's work queue for this workgroup, the same for every
-// thread of it.  The queue is dealt to the 8 XCDs (workgroup b runs on XCD
-// b mod 8) in quads of consecutive positions, so the four neighbouring
-// tiles of a quad share one L2; each XCD has a counter of its own.
-// Returns a position >= the item count when this XCD's share is used up.
-template <int NTH>
-__device__ __forceinline__ uint32_t next_item(uint32_t* counter) {
-  const uint32_t x = blockIdx.x & 7u;
-  uint32_t j = 0u;
-  if constexpr (NTH == 64) {
-    if (threadIdx.x == 0) j = atomicAdd(counter + x, 1u);
-    j = __builtin_amdgcn_readfirstlane(__shfl((int)j, 0, 64));
-  } else {
-    __shared__ uint32_t s_item;
-    if (threadIdx.x == 0) s_item = atomicAdd(counter + x, 1u);
-    __syncthreads();
-    j = s_item;
-    __syncthreads();
-    j = __builtin_amdgcn_readfirstlane(j);
-  }
-  return ((j >> 2) * 8u + x) * 4u + (j & 3u);
-}
-
 // Background features behind pixel p, channel c: a constant [C] vector or a
 // per-pixel image [C][H][W] (for example an environment map sampled along
 // every pixel's view direction).
@@ -1472,8 +1449,8 @@ __device__ __forceinline__ void blend_bwd_bilinear8_tile(const BlendArgs& a, uin
 }
 
 // ---------------------------------------------------------------------------
-// Kernels: one workgroup per tile (one view), or a persistent grid over the
-// (view, tile) items of a batch of views
+// Kernels: one workgroup per tile of one view, or one workgroup per
+// (view, tile) slot of a batch's queue
 // ---------------------------------------------------------------------------
 
 template <int T, int CP, typename FT, bool FULL>
@@ -1482,19 +1459,14 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear(BlendArgs a) {
   blend_fwd_bilinear_tile<T, CP, FT, FULL>(a, block_tile(a));
 }
 template <int T, int CP, typename FT, bool FULL>
-__global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear_batched(const BlendArgs* __restrict__ args, const uint2* __restrict__ items,
-                                        uint32_t* counter, uint32_t total) {
-  constexpr int NTH = T * T;
-  for (;;) {
-    const uint32_t it = next_item<NTH>(counter);
-    if (it >= total) break;
-    const uint2 vk = items[it];
-    const uint32_t v = __builtin_amdgcn_readfirstlane(vk.x);
-    const uint32_t k = __builtin_amdgcn_readfirstlane(vk.y);
-    const BlendArgs& a = args[v];  // read-only for the whole kernel: scalar loads
-    if (!a.flags[kFlagOverflow]) blend_fwd_bilinear_tile<T, CP, FT, FULL>(a, a.order[k]);
-    tile_sync<NTH / 64>();  // the next item reuses the LDS
-  }
+__global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear_batched(const BlendArgs* __restrict__ args,
+                                                              const uint2* __restrict__ items) {
+  const uint2 vk = items[xcd_pos(blockIdx.x, gridDim.x)];
+  const uint32_t v = __builtin_amdgcn_readfirstlane(vk.x);
+  if (v == kNoItem) return;  // padding of a view's last quad
+  const BlendArgs& a = args[v];  // read-only for the whole kernel: scalar loads
+  if (a.flags[kFlagOverflow]) return;
+  blend_fwd_bilinear_tile<T, CP, FT, FULL>(a, a.order[__builtin_amdgcn_readfirstlane(vk.y)]);
 }
 
 template <int CP, typename FT, bool FULL>
@@ -1503,19 +1475,14 @@ __global__ __launch_bounds__(64) void k_blend_fwd_bilinear8(BlendArgs a) {
   blend_fwd_bilinear8_tile<CP, FT, FULL>(a, block_tile(a));
 }
 template <int CP, typename FT, bool FULL>
-__global__ __launch_bounds__(64) void k_blend_fwd_bilinear8_batched(const BlendArgs* __restrict__ args, const uint2* __restrict__ items,
-                                        uint32_t* counter, uint32_t total) {
-  constexpr int NTH = 64;
-  for (;;) {
-    const uint32_t it = next_item<NTH>(counter);
-    if (it >= total) break;
-    const uint2 vk = items[it];
-    const uint32_t v = __builtin_amdgcn_readfirstlane(vk.x);
-    const uint32_t k = __builtin_amdgcn_readfirstlane(vk.y);
-    const BlendArgs& a = args[v];  // read-only for the whole kernel: scalar loads
-    if (!a.flags[kFlagOverflow]) blend_fwd_bilinear8_tile<CP, FT, FULL>(a, a.order[k]);
-    tile_sync<NTH / 64>();  // the next item reuses the LDS
-  }
+__global__ __launch_bounds__(64) void k_blend_fwd_bilinear8_batched(const BlendArgs* __restrict__ args,
+                                                              const uint2* __restrict__ items) {
+  const uint2 vk = items[xcd_pos(blockIdx.x, gridDim.x)];
+  const uint32_t v = __builtin_amdgcn_readfirstlane(vk.x);
+  if (v == kNoItem) return;  // padding of a view's last quad
+  const BlendArgs& a = args[v];  // read-only for the whole kernel: scalar loads
+  if (a.flags[kFlagOverflow]) return;
+  blend_fwd_bilinear8_tile<CP, FT, FULL>(a, a.order[__builtin_amdgcn_readfirstlane(vk.y)]);
 }
 
 template <int T, int CP, typename FT, bool FULL>
@@ -1524,19 +1491,14 @@ __global__ __launch_bounds__(T* T) void k_blend_fwd_gauss(BlendArgs a) {
   blend_fwd_gauss_tile<T, CP, FT, FULL>(a, block_tile(a));
 }
 template <int T, int CP, typename FT, bool FULL>
-__global__ __launch_bounds__(T* T) void k_blend_fwd_gauss_batched(const BlendArgs* __restrict__ args, const uint2* __restrict__ items,
-                                        uint32_t* counter, uint32_t total) {
-  constexpr int NTH = T * T;
-  for (;;) {
-    const uint32_t it = next_item<NTH>(counter);
-    if (it >= total) break;
-    const uint2 vk = items[it];
-    const uint32_t v = __builtin_amdgcn_readfirstlane(vk.x);
-    const uint32_t k = __builtin_amdgcn_readfirstlane(vk.y);
-    const BlendArgs& a = args[v];  // read-only for the whole kernel: scalar loads
-    if (!a.flags[kFlagOverflow]) blend_fwd_gauss_tile<T, CP, FT, FULL>(a, a.order[k]);
-    tile_sync<NTH / 64>();  // the next item reuses the LDS
-  }
+__global__ __launch_bounds__(T* T) void k_blend_fwd_gauss_batched(const BlendArgs* __restrict__ args,
+                                                              const uint2* __restrict__ items) {
+  const uint2 vk = items[xcd_pos(blockIdx.x, gridDim.x)];
+  const uint32_t v = __builtin_amdgcn_readfirstlane(vk.x);
+  if (v == kNoItem) return;  // padding of a view's last quad
+  const BlendArgs& a = args[v];  // read-only for the whole kernel: scalar loads
+  if (a.flags[kFlagOverflow]) return;
+  blend_fwd_gauss_tile<T, CP, FT, FULL>(a, a.order[__builtin_amdgcn_readfirstlane(vk.y)]);
 }
 
 template <int T, int CP, typename FT, bool FULL>
@@ -1545,19 +1507,14 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear(BlendArgs a) {
   blend_bwd_bilinear_tile<T, CP, FT, FULL>(a, block_tile(a));
 }
 template <int T, int CP, typename FT, bool FULL>
-__global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear_batched(const BlendArgs* __restrict__ args, const uint2* __restrict__ items,
-                                        uint32_t* counter, uint32_t total) {
-  constexpr int NTH = T * T;
-  for (;;) {
-    const uint32_t it = next_item<NTH>(counter);
-    if (it >= total) break;
-    const uint2 vk = items[it];
-    const uint32_t v = __builtin_amdgcn_readfirstlane(vk.x);
-    const uint32_t k = __builtin_amdgcn_readfirstlane(vk.y);
-    const BlendArgs& a = args[v];  // read-only for the whole kernel: scalar loads
-    if (!a.flags[kFlagOverflow]) blend_bwd_bilinear_tile<T, CP, FT, FULL>(a, a.order[k]);
-    tile_sync<NTH / 64>();  // the next item reuses the LDS
-  }
+__global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear_batched(const BlendArgs* __restrict__ args,
+                                                              const uint2* __restrict__ items) {
+  const uint2 vk = items[xcd_pos(blockIdx.x, gridDim.x)];
+  const uint32_t v = __builtin_amdgcn_readfirstlane(vk.x);
+  if (v == kNoItem) return;  // padding of a view's last quad
+  const BlendArgs& a = args[v];  // read-only for the whole kernel: scalar loads
+  if (a.flags[kFlagOverflow]) return;
+  blend_bwd_bilinear_tile<T, CP, FT, FULL>(a, a.order[__builtin_amdgcn_readfirstlane(vk.y)]);
 }
 
 template <int CP, typename FT, bool FULL>
@@ -1566,19 +1523,14 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
   blend_bwd_bilinear8_tile<CP, FT, FULL>(a, block_tile(a));
 }
 template <int CP, typename FT, bool FULL>
-__global__ __launch_bounds__(64) void k_blend_bwd_bilinear8_batched(const BlendArgs* __restrict__ args, const uint2* __restrict__ items,
-                                        uint32_t* counter, uint32_t total) {
-  constexpr int NTH = 64;
-  for (;;) {
-    const uint32_t it = next_item<NTH>(counter);
-    if (it >= total) break;
-    const uint2 vk = items[it];
-    const uint32_t v = __builtin_amdgcn_readfirstlane(vk.x);
-    const uint32_t k = __builtin_amdgcn_readfirstlane(vk.y);
-    const BlendArgs& a = args[v];  // read-only for the whole kernel: scalar loads
-    if (!a.flags[kFlagOverflow]) blend_bwd_bilinear8_tile<CP, FT, FULL>(a, a.order[k]);
-    tile_sync<NTH / 64>();  // the next item reuses the LDS
-  }
+__global__ __launch_bounds__(64) void k_blend_bwd_bilinear8_batched(const BlendArgs* __restrict__ args,
+                                                              const uint2* __restrict__ items) {
+  const uint2 vk = items[xcd_pos(blockIdx.x, gridDim.x)];
+  const uint32_t v = __builtin_amdgcn_readfirstlane(vk.x);
+  if (v == kNoItem) return;  // padding of a view's last quad
+  const BlendArgs& a = args[v];  // read-only for the whole kernel: scalar loads
+  if (a.flags[kFlagOverflow]) return;
+  blend_bwd_bilinear8_tile<CP, FT, FULL>(a, a.order[__builtin_amdgcn_readfirstlane(vk.y)]);
 }
 
 // Zero n floats at p (4-byte aligned): 16-byte non-temporal stores for the
@@ -1710,29 +1662,13 @@ hipError_t bwd_launch(const BlendArgs& a, hipStream_t s) {
   return bwd_post(a, s);
 }
 
-// Persistent grid of a batched launch: as many workgroups as fit on the
-// device at once (they drain the queue), never more than there are items.
+// One launch over every (view, tile) slot of a batch's queue: workgroup b
+// takes slot xcd_pos(b), so each quad of neighbouring tiles runs on one XCD
+// (its L2) and the hardware dispatches the slots in queue order, longest
+// tiles first.
 template <typename K>
-hipError_t persistent_grid(K kernel, int threads, uint32_t total, int* grid) {
-  int dev = 0, cus = 0, per = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(kernel),
-                                                     threads, 0);
-  if (e != hipSuccess) return e;
-  const int64_t g = (int64_t)std::max(cus, 1) * std::max(per, 1);
-  *grid = (int)std::max<int64_t>(1, std::min<int64_t>(g, total));
-  return hipSuccess;
-}
-
-template <typename K>
-hipError_t launch_persistent(K kernel, int threads, const BatchQueue& q, hipStream_t s) {
-  int grid = 1;
-  hipError_t e = persistent_grid(kernel, threads, q.total, &grid);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(threads), 0, s, q.args, q.items, q.counter,
-                     q.total);
+hipError_t launch_queue(K kernel, int threads, const BatchQueue& q, hipStream_t s) {
+  hipLaunchKernelGGL(kernel, dim3(q.total), dim3(threads), 0, s, q.args, q.items);
   return hipGetLastError();
 }
 
@@ -1740,23 +1676,23 @@ template <int T, int CP, typename FT>
 hipError_t fwd_launch_q(const BlendArgs& a, const BatchQueue& q, hipStream_t s) {
   const bool full = a.C == CP;
   if (a.opts.splat == INPC_SPLAT_BILINEAR && T == 8)
-    return full ? launch_persistent(k_blend_fwd_bilinear8_batched<CP, FT, true>, 64, q, s)
-                : launch_persistent(k_blend_fwd_bilinear8_batched<CP, FT, false>, 64, q, s);
+    return full ? launch_queue(k_blend_fwd_bilinear8_batched<CP, FT, true>, 64, q, s)
+                : launch_queue(k_blend_fwd_bilinear8_batched<CP, FT, false>, 64, q, s);
   if (a.opts.splat == INPC_SPLAT_BILINEAR)
-    return full ? launch_persistent(k_blend_fwd_bilinear_batched<T, CP, FT, true>, T * T, q, s)
-                : launch_persistent(k_blend_fwd_bilinear_batched<T, CP, FT, false>, T * T, q, s);
-  return full ? launch_persistent(k_blend_fwd_gauss_batched<T, CP, FT, true>, T * T, q, s)
-              : launch_persistent(k_blend_fwd_gauss_batched<T, CP, FT, false>, T * T, q, s);
+    return full ? launch_queue(k_blend_fwd_bilinear_batched<T, CP, FT, true>, T * T, q, s)
+                : launch_queue(k_blend_fwd_bilinear_batched<T, CP, FT, false>, T * T, q, s);
+  return full ? launch_queue(k_blend_fwd_gauss_batched<T, CP, FT, true>, T * T, q, s)
+              : launch_queue(k_blend_fwd_gauss_batched<T, CP, FT, false>, T * T, q, s);
 }
 
 template <int T, int CP, typename FT>
 hipError_t bwd_launch_q(const BlendArgs& a, const BatchQueue& q, hipStream_t s) {
   const bool full = a.C == CP;
   if (T == 8)
-    return full ? launch_persistent(k_blend_bwd_bilinear8_batched<CP, FT, true>, 64, q, s)
-                : launch_persistent(k_blend_bwd_bilinear8_batched<CP, FT, false>, 64, q, s);
-  return full ? launch_persistent(k_blend_bwd_bilinear_batched<T, CP, FT, true>, T * T, q, s)
-              : launch_persistent(k_blend_bwd_bilinear_batched<T, CP, FT, false>, T * T, q, s);
+    return full ? launch_queue(k_blend_bwd_bilinear8_batched<CP, FT, true>, 64, q, s)
+                : launch_queue(k_blend_bwd_bilinear8_batched<CP, FT, false>, 64, q, s);
+  return full ? launch_queue(k_blend_bwd_bilinear_batched<T, CP, FT, true>, T * T, q, s)
+              : launch_queue(k_blend_bwd_bilinear_batched<T, CP, FT, false>, T * T, q, s);
 }
 
 template <int T, typename FT, bool FWD>

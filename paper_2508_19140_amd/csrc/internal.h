@@ -44,14 +44,15 @@ struct BlendArgs {
   const uint32_t* flags;
 };
 
-// A batch's work queue for the persistent blend kernels: per-view arguments
-// (device), the (view, position in the view's tile order) items and the 8
-// per-XCD counters the workgroups take items from.
+// A batch's work queue for the batched blend kernels: per-view arguments
+// (device) and the (view, position in the view's tile order) slots, one
+// workgroup per slot.  Views contribute whole quads of four slots; slots past
+// a view's last tile hold kNoItem.
+constexpr uint32_t kNoItem = 0xffffffffu;
 struct BatchQueue {
   const BlendArgs* args;
   const uint2* items;
-  uint32_t* counter;
-  uint32_t total;
+  uint32_t total;  // slots
 };
 
 // Blend arguments of one view of a batch (host and device: the batched
@@ -112,12 +113,13 @@ __host__ __device__ inline BlendArgs make_view_args(const inpc_view_t& w, const 
   return a;
 }
 
-// Tile counts of the views of a batch as an exclusive prefix (kernel
-// argument of the queue builder).
+// Quad counts (ceil(tiles / 4)) of the views of a batch as an exclusive
+// prefix, and the tile counts (kernel argument of the queue builder).
 constexpr int kMaxBatchViews = 64;
 struct BatchTiles {
   int nv;
   int64_t start[kMaxBatchViews + 1];
+  int64_t tiles[kMaxBatchViews];
 };
 
 // Channel capacity of the kernel instantiation used for C channels.
@@ -147,7 +149,7 @@ hipError_t launch_blend_batched(bool forward, const BlendArgs& shape, const Batc
                                 hipStream_t s);
 hipError_t launch_batch_prepare(const inpc_view_t* views_dev, int nv, const Opts& shared, int C,
                                 int dtype, int bg_image, const BatchTiles& bt, BlendArgs* args,
-                                uint2* items, uint32_t* counter, hipStream_t s);
+                                uint2* items, hipStream_t s);
 hipError_t launch_sh_forward(const Cam& c, int64_t n, int C, const float* pos, const float* sh,
                              float* feat, hipStream_t s);
 hipError_t launch_sh_backward(const Cam& c, int64_t n, int C, const float* pos, const float* sh,
