@@ -204,6 +204,133 @@ __device__ __forceinline__ void block_rank(const uint32_t (&d)[ITEMS], const boo
   bsync<WAVE_ONLY>();
 }
 
+// Bucket-rank sort of n <= NW*ITEMS*64 (key, idx) pairs of one segment in
+// LDS: one pass splits the segment into 2^HB buckets by the top HB bits of
+// the pair's offset from the segment's smallest pair, (key - kmin) followed
+// by (idx - imin); then every element's place is its bucket's start plus the
+// number of pairs in its bucket smaller than its own (pairs are unique, so
+// this is a permutation).  No barrier separates the rank counts, and a
+// segment costs one histogram, one scan and one scatter instead of a radix
+// pass per digit.  Returns false (having written nothing) when a bucket holds
+// more than MAXB pairs, where counting would cost more than the radix sort.
+template <int NW, int ITEMS, int HB, bool WAVE_ONLY, int MAXB>
+__device__ bool bucket_sort_segment(const uint2* __restrict__ seg, uint32_t n,
+                                    const ListOut& out, uint32_t base, const SortSmem& sm) {
+  constexpr int NB = 1 << HB;             // buckets
+  constexpr int NT = WAVE_ONLY ? 64 : NW * 64;
+  constexpr int BPT = NB / NT;            // buckets per thread in the scan
+  static_assert(BPT >= 1 && NB % NT == 0, "bucket count must be a multiple of the threads");
+  const uint32_t lane = __lane_id();
+  const uint32_t w = WAVE_ONLY ? 0u : (threadIdx.x >> 6);
+  const int tid = WAVE_ONLY ? (int)lane : (int)threadIdx.x;
+  const int ni = (int)((n + NW * 64 - 1) / (NW * 64));
+  const uint32_t base_e = w * (uint32_t)ni * 64u;
+  uint32_t* hist = sm.hist;  // [NB]
+  for (int b = tid; b < NB; b += NT) hist[b] = 0u;
+
+  uint32_t key[ITEMS], idx[ITEMS], dg[ITEMS], slot[ITEMS];
+  bool valid[ITEMS];
+  uint32_t kmin = 0xffffffffu, kmax = 0u, imin = 0xffffffffu, imax = 0u;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const uint32_t e = base_e + j * 64 + lane;
+    valid[j] = j < ni && e < n;
+    const uint2 v = valid[j] ? seg[e] : make_uint2(0u, 0u);
+    key[j] = v.x;
+    idx[j] = v.y;
+    if (valid[j]) {
+      kmin = min(kmin, key[j]); kmax = max(kmax, key[j]);
+      imin = min(imin, idx[j]); imax = max(imax, idx[j]);
+    }
+  }
+  kmin = wave_min(kmin); kmax = wave_max(kmax);
+  imin = wave_min(imin); imax = wave_max(imax);
+  if (!WAVE_ONLY) {
+    if (lane == 0) {
+      sm.red[w * 4 + 0] = kmin; sm.red[w * 4 + 1] = kmax;
+      sm.red[w * 4 + 2] = imin; sm.red[w * 4 + 3] = imax;
+    }
+    __syncthreads();
+    kmin = 0xffffffffu; kmax = 0; imin = 0xffffffffu; imax = 0;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) {
+      kmin = min(kmin, sm.red[ww * 4 + 0]); kmax = max(kmax, sm.red[ww * 4 + 1]);
+      imin = min(imin, sm.red[ww * 4 + 2]); imax = max(imax, sm.red[ww * 4 + 3]);
+    }
+  }
+  // digit: top HB bits of ((key - kmin) << ib) | (idx - imin)
+  const uint32_t ib = nbits(imax - imin);
+  const uint32_t total = nbits(kmax - kmin) + ib;
+  const uint32_t sh = total > (uint32_t)HB ? total - (uint32_t)HB : 0u;
+  bsync<WAVE_ONLY>();  // hist cleared, sm.red read
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    if (!valid[j]) continue;
+    const uint64_t c = ((uint64_t)(key[j] - kmin) << ib) | (uint64_t)(idx[j] - imin);
+    dg[j] = (uint32_t)(c >> sh);
+    slot[j] = atomicAdd(&hist[dg[j]], 1u);
+  }
+  bsync<WAVE_ONLY>();
+  // exclusive scan of the bucket counts (BPT consecutive buckets per thread),
+  // and the largest bucket
+  uint32_t cnt[BPT];
+  uint32_t sum = 0, mx = 0;
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    cnt[q] = hist[tid * BPT + q];
+    sum += cnt[q];
+    mx = max(mx, cnt[q]);
+  }
+  const uint32_t incl = wave_incl_scan(sum);
+  mx = wave_max(mx);
+  uint32_t wbase = 0u;
+  if (!WAVE_ONLY) {
+    if (lane == 63) sm.red[w] = incl;
+    if (lane == 0) sm.red[NW + w] = mx;
+    __syncthreads();
+    mx = 0;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) {
+      if (ww < (int)w) wbase += sm.red[ww];
+      mx = max(mx, sm.red[NW + ww]);
+    }
+  }
+  if (mx > (uint32_t)MAXB) {
+    bsync<WAVE_ONLY>();  // everybody has read hist and sm.red
+    return false;
+  }
+  uint32_t ex = wbase + incl - sum;
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    hist[tid * BPT + q] = ex;  // bucket start
+    ex += cnt[q];
+  }
+  bsync<WAVE_ONLY>();
+  // scatter into the buckets (order inside a bucket is arbitrary)
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    if (!valid[j]) continue;
+    const uint32_t p = hist[dg[j]] + slot[j];
+    sm.key[p] = key[j];
+    sm.idx[p] = idx[j];
+  }
+  bsync<WAVE_ONLY>();
+  // rank inside the bucket
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    if (!valid[j]) continue;
+    const uint32_t b0 = hist[dg[j]];
+    const uint32_t b1 = dg[j] + 1 < (uint32_t)NB ? hist[dg[j] + 1] : n;
+    const uint64_t me = ((uint64_t)key[j] << 32) | idx[j];
+    uint32_t r = 0;
+    for (uint32_t q = b0; q < b1; ++q)
+      r += (((uint64_t)sm.key[q] << 32) | sm.idx[q]) < me;
+    out.put(base + b0 + r, idx[j]);
+  }
+  bsync<WAVE_ONLY>();  // the LDS is reused by the next segment
+  return true;
+}
+
 // Sort n <= NW*ITEMS*64 (key, idx) pairs of one segment entirely in LDS and
 // write the point indices in (key, idx) order to out[0..n).  Each wave holds
 // ni = ceil(n / (64 NW)) items per lane, so the ranking work follows the
@@ -387,6 +514,10 @@ constexpr int kW_CAP = kW_ITEMS * 64;
 // rest take W segments, so that neither class leaves a tail of idle compute
 // units behind it.  Both roles carve their LDS from one arena.
 constexpr int kM_NW = 4, kM_ITEMS = 8, kM_CAP = kM_NW * kM_ITEMS * 64;
+// Bucket bits of the bucket-rank sorts (the bucket counts fit the radix
+// histograms: 256 per wavefront) and the largest bucket worth counting in.
+constexpr int kW_HB = 8, kM_HB = 10;
+constexpr int kBucketMax = 256;
 constexpr int kM_WORDS = 2 * kM_CAP + kM_NW * 256 + 256 + 64;
 constexpr int kW_WORDS = 2 * kW_CAP + 256 + 256 + 64;  // per wavefront
 static_assert(kW_WORDS % 4 == 0, "wavefront arenas must stay 16-byte aligned");
@@ -404,7 +535,9 @@ __global__ __launch_bounds__(256) void k_sort_wm(int gm, const uint2* __restrict
     const uint32_t count = flags[kFlagCountM];
     for (uint32_t i = blockIdx.x; i < count; i += (uint32_t)gm) {
       const uint2 sg = seg_m[i];
-      sort_segment_lds<kM_NW, kM_ITEMS, false>(bucket + sg.x, sg.y, out, sg.x, sm);
+      if (!bucket_sort_segment<kM_NW, kM_ITEMS, kM_HB, false, kBucketMax>(bucket + sg.x, sg.y,
+                                                                            out, sg.x, sm))
+        sort_segment_lds<kM_NW, kM_ITEMS, false>(bucket + sg.x, sg.y, out, sg.x, sm);
     }
   } else {
     const uint32_t w = threadIdx.x >> 6;
@@ -416,7 +549,8 @@ __global__ __launch_bounds__(256) void k_sort_wm(int gm, const uint2* __restrict
       const uint2 sg = seg_w[i];
       if (sg.y <= 64)
         rank_sort_wave(bucket + sg.x, sg.y, out, sg.x, reinterpret_cast<uint2*>(b));
-      else
+      else if (!bucket_sort_segment<1, kW_ITEMS, kW_HB, true, kBucketMax>(bucket + sg.x, sg.y,
+                                                                           out, sg.x, sm))
         sort_segment_lds<1, kW_ITEMS, true>(bucket + sg.x, sg.y, out, sg.x, sm);
     }
   }
@@ -704,6 +838,7 @@ __device__ void sort_x_blocks(const Ws& ws, const ListOut& out, uint32_t* s_hist
 // LSD in LDS) on workgroups [0, gl) and the global-memory LSD sort of what
 // is larger on the rest, in one launch.
 constexpr int kL_NW = 16, kL_ITEMS = kSortCapLB / 1024, kL_CAP = kL_NW * kL_ITEMS * 64;
+constexpr int kL_HB = 12;
 
 __global__ __launch_bounds__(1024) void k_sort_lx(int gl, Ws ws, ListOut out) {
   __shared__ uint32_t s_key[kL_CAP];
@@ -721,7 +856,9 @@ __global__ __launch_bounds__(1024) void k_sort_lx(int gl, Ws ws, ListOut out) {
   const uint32_t count = ws.flags[kFlagCountL];
   for (uint32_t i = blockIdx.x; i < count; i += (uint32_t)gl) {
     const uint2 sg = ws.seg_l[i];
-    sort_segment_lds<kL_NW, kL_ITEMS, false>(ws.bucket + sg.x, sg.y, out, sg.x, sm);
+    if (!bucket_sort_segment<kL_NW, kL_ITEMS, kL_HB, false, kBucketMax>(ws.bucket + sg.x, sg.y,
+                                                                        out, sg.x, sm))
+      sort_segment_lds<kL_NW, kL_ITEMS, false>(ws.bucket + sg.x, sg.y, out, sg.x, sm);
   }
 }
 
