@@ -213,6 +213,7 @@ __device__ __forceinline__ void block_rank(const uint32_t (&d)[ITEMS], const boo
 // segment costs one histogram, one scan and one scatter instead of a radix
 // pass per digit.  Returns false (having written nothing) when a bucket holds
 // more than MAXB pairs, where counting would cost more than the radix sort.
+// sm.idx must follow sm.key directly (the pairs are stored as one array).
 template <int NW, int ITEMS, int HB, bool WAVE_ONLY, int MAXB>
 __device__ bool bucket_sort_segment(const uint2* __restrict__ seg, uint32_t n,
                                     const ListOut& out, uint32_t base, const SortSmem& sm) {
@@ -306,26 +307,30 @@ __device__ bool bucket_sort_segment(const uint2* __restrict__ seg, uint32_t n,
     ex += cnt[q];
   }
   bsync<WAVE_ONLY>();
-  // scatter into the buckets (order inside a bucket is arbitrary)
+  // scatter into the buckets (order inside a bucket is arbitrary); the
+  // pairs go to the key and index arrays taken as one array of pairs
+  uint2* kv = reinterpret_cast<uint2*>(sm.key);
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     if (!valid[j]) continue;
-    const uint32_t p = hist[dg[j]] + slot[j];
-    sm.key[p] = key[j];
-    sm.idx[p] = idx[j];
+    kv[hist[dg[j]] + slot[j]] = make_uint2(key[j], idx[j]);
   }
   bsync<WAVE_ONLY>();
-  // rank inside the bucket
-#pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
-    if (!valid[j]) continue;
-    const uint32_t b0 = hist[dg[j]];
-    const uint32_t b1 = dg[j] + 1 < (uint32_t)NB ? hist[dg[j] + 1] : n;
-    const uint64_t me = ((uint64_t)key[j] << 32) | idx[j];
+  // rank inside the bucket, by position in the bucketed array: neighbouring
+  // lanes mostly share a bucket, so their reads of it are broadcasts
+  for (uint32_t p = tid; p < n; p += NT) {
+    const uint2 v = kv[p];
+    const uint64_t c = ((uint64_t)(v.x - kmin) << ib) | (uint64_t)(v.y - imin);
+    const uint32_t d = (uint32_t)(c >> sh);
+    const uint32_t b0 = hist[d];
+    const uint32_t b1 = d + 1 < (uint32_t)NB ? hist[d + 1] : n;
+    const uint64_t me = ((uint64_t)v.x << 32) | v.y;
     uint32_t r = 0;
-    for (uint32_t q = b0; q < b1; ++q)
-      r += (((uint64_t)sm.key[q] << 32) | sm.idx[q]) < me;
-    out.put(base + b0 + r, idx[j]);
+    for (uint32_t q = b0; q < b1; ++q) {
+      const uint2 o = kv[q];
+      r += (((uint64_t)o.x << 32) | o.y) < me;
+    }
+    out.put(base + b0 + r, v.y);
   }
   bsync<WAVE_ONLY>();  // the LDS is reused by the next segment
   return true;
@@ -516,7 +521,7 @@ constexpr int kW_CAP = kW_ITEMS * 64;
 constexpr int kM_NW = 4, kM_ITEMS = 8, kM_CAP = kM_NW * kM_ITEMS * 64;
 // Bucket bits of the bucket-rank sorts (the bucket counts fit the radix
 // histograms: 256 per wavefront) and the largest bucket worth counting in.
-constexpr int kW_HB = 8, kM_HB = 10;
+constexpr int kW_HB = 8, kM_HB = 10, kL_HB = 12;
 constexpr int kBucketMax = 256;
 constexpr int kM_WORDS = 2 * kM_CAP + kM_NW * 256 + 256 + 64;
 constexpr int kW_WORDS = 2 * kW_CAP + 256 + 256 + 64;  // per wavefront
@@ -838,11 +843,11 @@ __device__ void sort_x_blocks(const Ws& ws, const ListOut& out, uint32_t* s_hist
 // LSD in LDS) on workgroups [0, gl) and the global-memory LSD sort of what
 // is larger on the rest, in one launch.
 constexpr int kL_NW = 16, kL_ITEMS = kSortCapLB / 1024, kL_CAP = kL_NW * kL_ITEMS * 64;
-constexpr int kL_HB = 12;
 
 __global__ __launch_bounds__(1024) void k_sort_lx(int gl, Ws ws, ListOut out) {
-  __shared__ uint32_t s_key[kL_CAP];
-  __shared__ uint32_t s_idx[kL_CAP];
+  __shared__ __align__(16) uint32_t s_kv[2 * kL_CAP];  // keys, then indices
+  uint32_t* s_key = s_kv;
+  uint32_t* s_idx = s_kv + kL_CAP;
   __shared__ uint32_t s_hist[kL_NW * 256];
   __shared__ uint32_t s_off[256];
   __shared__ uint32_t s_red[64];
