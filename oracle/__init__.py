@@ -61,7 +61,7 @@ class _Cam(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("splat", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("t_min", ctypes.c_float), ("dilation", ctypes.c_float),
-                ("cutoff", ctypes.c_float)]
+                ("cutoff", ctypes.c_float), ("ewa_sigma", ctypes.c_float)]
 
 
 _lib = None
@@ -79,7 +79,7 @@ def _load():
         lib.oracle_tile_lists.argtypes = [P, P, ctypes.c_int64, P, P, P, P]
         lib.oracle_tile_lists.restype = ctypes.c_int64
         lib.oracle_render.argtypes = [P, P, ctypes.c_int64, P, P, P, P, ctypes.c_int32] + [P] * 18 \
-            + [ctypes.c_int32]
+            + [ctypes.c_int32, P, P]
         lib.oracle_render.restype = ctypes.c_int
         lib.oracle_count_fragments.argtypes = [P, P, ctypes.c_int64, P, P]
         lib.oracle_count_fragments.restype = ctypes.c_int64
@@ -111,12 +111,15 @@ def _cam(camera) -> _Cam:
 
 SPLAT_BILINEAR = 0
 SPLAT_GAUSSIAN = 1
+SPLAT_EWA = 2  # world-space Gaussians of standard deviation ewa_sigma, EWA projection
 
 
-def _opts(splat=SPLAT_BILINEAR, tile=8, t_min=1e-4, dilation=0.16, cutoff=3.0) -> _Opts:
+def _opts(splat=SPLAT_BILINEAR, tile=8, t_min=1e-4, dilation=0.16, cutoff=3.0,
+          ewa_sigma=0.0) -> _Opts:
     o = _Opts()
     o.splat, o.tile = int(splat), int(tile)
     o.t_min, o.dilation, o.cutoff = float(t_min), float(dilation), float(cutoff)
+    o.ewa_sigma = float(ewa_sigma)
     return o
 
 
@@ -136,7 +139,8 @@ def set_num_threads(n: int) -> None:
     _load().oracle_set_num_threads(int(n))
 
 
-def project(camera, pos, radius=None, splat=SPLAT_BILINEAR, tile=8, dilation=0.16, cutoff=3.0):
+def project(camera, pos, radius=None, splat=SPLAT_BILINEAR, tile=8, dilation=0.16, cutoff=3.0,
+            ewa_sigma=0.0):
     """Decision stage per point: visibility, (u, v), depth key, camera-space
     coordinates, inclusive pixel rect of candidate fragments, tiles touched."""
     lib = _load()
@@ -149,14 +153,14 @@ def project(camera, pos, radius=None, splat=SPLAT_BILINEAR, tile=8, dilation=0.1
     xyz = np.zeros((n, 3), np.float32)
     rect = np.zeros((n, 4), np.int32)
     nt = np.zeros(n, np.uint32)
-    cam, o = _cam(camera), _opts(splat, tile, 0.0, dilation, cutoff)
+    cam, o = _cam(camera), _opts(splat, tile, 0.0, dilation, cutoff, ewa_sigma)
     lib.oracle_project(ctypes.byref(cam), ctypes.byref(o), n, _ptr(pos), _ptr(rad), _ptr(vis),
                        _ptr(uv), _ptr(key), _ptr(xyz), _ptr(rect), _ptr(nt))
     return dict(visible=vis.astype(bool), uv=uv, key=key, xyz=xyz, rect=rect, ntiles=nt)
 
 
 def tile_lists(camera, pos, radius=None, splat=SPLAT_BILINEAR, tile=8, dilation=0.16,
-               cutoff=3.0):
+               cutoff=3.0, ewa_sigma=0.0):
     """Per-tile counts, ranges [nt+1] and concatenated lists ordered by
     (depth key, point index) inside each tile."""
     lib = _load()
@@ -166,7 +170,7 @@ def tile_lists(camera, pos, radius=None, splat=SPLAT_BILINEAR, tile=8, dilation=
     ntx = (camera.width + tile - 1) // tile
     nty = (camera.height + tile - 1) // tile
     counts = np.zeros(ntx * nty, np.uint32)
-    cam, o = _cam(camera), _opts(splat, tile, 0.0, dilation, cutoff)
+    cam, o = _cam(camera), _opts(splat, tile, 0.0, dilation, cutoff, ewa_sigma)
     total = lib.oracle_tile_lists(ctypes.byref(cam), ctypes.byref(o), n, _ptr(pos), _ptr(rad),
                                   _ptr(counts), None)
     lst = np.zeros(max(int(total), 1), np.uint32)
@@ -178,7 +182,8 @@ def tile_lists(camera, pos, radius=None, splat=SPLAT_BILINEAR, tile=8, dilation=
 
 
 def render(camera, pos, opacity, feat, radius=None, bg=None, splat=SPLAT_BILINEAR, tile=8,
-           t_min=1e-4, dilation=0.16, cutoff=3.0, grad_out=None, grad_t=None, pixel_mask=None):
+           t_min=1e-4, dilation=0.16, cutoff=3.0, grad_out=None, grad_t=None, pixel_mask=None,
+           ewa_sigma=0.0):
     """Forward (and, with grad_out, backward) render in FP64.
 
     feat is upcast exactly to float64 (FP16/BF16 values included).
@@ -214,11 +219,13 @@ def render(camera, pos, opacity, feat, radius=None, bg=None, splat=SPLAT_BILINEA
             r[k] = np.zeros(shp)
             r[k + "_abs"] = np.zeros(shp)
         r["grad_bg"] = (np.zeros((C, H, W) if bg_image else C) if bg is not None else None)
+        r["grad_z"] = np.zeros(n)
+        r["grad_z_abs"] = np.zeros(n)
     if pixel_mask is not None:
         if grad_out is not None:
             raise ValueError("pixel_mask is for the forward pass only")
         pixel_mask = np.ascontiguousarray(np.asarray(pixel_mask, bool).reshape(H, W), np.uint8)
-    cam, o = _cam(camera), _opts(splat, tile, t_min, dilation, cutoff)
+    cam, o = _cam(camera), _opts(splat, tile, t_min, dilation, cutoff, ewa_sigma)
     g = r.get
     lib.oracle_render(ctypes.byref(cam), ctypes.byref(o), n, _ptr(pos), _ptr(rad), _ptr(opacity),
                       _ptr(feat), C, _ptr(bgd), _ptr(r["out"]), _ptr(r["out_abs"]),
@@ -226,17 +233,18 @@ def render(camera, pos, opacity, feat, radius=None, bg=None, splat=SPLAT_BILINEA
                       _ptr(gt), _ptr(g("grad_feat")), _ptr(g("grad_opacity")), _ptr(g("grad_uv")),
                       _ptr(g("grad_pos")), _ptr(g("grad_bg")), _ptr(g("grad_feat_abs")),
                       _ptr(g("grad_opacity_abs")), _ptr(g("grad_uv_abs")),
-                      _ptr(g("grad_pos_abs")), _ptr(pixel_mask), int(bg_image))
+                      _ptr(g("grad_pos_abs")), _ptr(pixel_mask), int(bg_image),
+                      _ptr(g("grad_z")), _ptr(g("grad_z_abs")))
     return r
 
 
 def count_fragments(camera, pos, radius=None, splat=SPLAT_BILINEAR, tile=8, dilation=0.16,
-                    cutoff=3.0) -> int:
+                    cutoff=3.0, ewa_sigma=0.0) -> int:
     lib = _load()
     pos = _f32(pos, (-1, 3))
     n = pos.shape[0]
     rad = None if radius is None else _f32(radius, (n,))
-    cam, o = _cam(camera), _opts(splat, tile, 0.0, dilation, cutoff)
+    cam, o = _cam(camera), _opts(splat, tile, 0.0, dilation, cutoff, ewa_sigma)
     return int(lib.oracle_count_fragments(ctypes.byref(cam), ctypes.byref(o), n, _ptr(pos),
                                           _ptr(rad)))
 

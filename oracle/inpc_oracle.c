@@ -55,11 +55,12 @@ typedef struct {
 } ocam_t;
 
 typedef struct {
-    int32_t splat; /* 0 bilinear, 1 Gaussian */
+    int32_t splat; /* 0 bilinear, 1 screen-space Gaussian, 2 world-space Gaussian (EWA) */
     int32_t tile;
     float t_min;
     float dilation;
     float cutoff;
+    float ewa_sigma; /* splat 2: world-space standard deviation of every point */
 } oopts_t;
 
 /* ------------------------------------------------------------------ */
@@ -74,6 +75,8 @@ typedef struct {
     int32_t x0, y0;             /* bilinear: top-left pixel of the 2x2 splat */
     float a, b;                 /* bilinear: sub-pixel offsets */
     float s2, thr;              /* Gaussian: effective variance, squared cut radius */
+    float ca, cb, cc;           /* EWA: inverse of the projected covariance (conic) */
+    int ewa;                    /* a world-space (EWA) Gaussian */
 } opoint_t;
 
 static uint32_t f32_bits(float f) {
@@ -112,6 +115,43 @@ static void decide_point(const ocam_t* cam, const oopts_t* o, const float* p, fl
         q->px1 = q->x0 + 1 > W - 1 ? W - 1 : q->x0 + 1;
         q->py1 = q->y0 + 1 > H - 1 ? H - 1 : q->y0 + 1;
         q->visible = 1;
+    } else if (o->splat == 2) {
+        /* World-space isotropic Gaussian of standard deviation sigma (Sec. 3.2
+         * "Rendering Points as Small Gaussians"), projected with the affine
+         * (EWA) approximation of the perspective map: covariance
+         * sigma^2 J J^T with J the projection's Jacobian at the point, plus
+         * the dilation.  With xh = X/Z = (u - cx)/fx, yh = (v - cy)/fy,
+         * jx = fx/Z, jy = fy/Z this is
+         *   a = sigma^2 jx^2 (1 + xh^2) + dil, b = sigma^2 jx jy xh yh,
+         *   c = sigma^2 jy^2 (1 + yh^2) + dil,
+         * written from the FP32 u, v, Z so that the kernels reach the same
+         * FP32 decisions; cut where the Mahalanobis distance exceeds
+         * `cutoff`; the candidate box is the ellipse's bounding box,
+         * |dx| <= cutoff sqrt(a), |dy| <= cutoff sqrt(c). */
+        float xh = (u - cam->cx) / cam->fx, yh = (v - cam->cy) / cam->fy;
+        float jx = cam->fx / Z, jy = cam->fy / Z;
+        float s2w = o->ewa_sigma * o->ewa_sigma;
+        float a = s2w * ((jx * jx) * (1.0f + xh * xh)) + o->dilation;
+        float b = s2w * ((jx * jy) * (xh * yh));
+        float c = s2w * ((jy * jy) * (1.0f + yh * yh)) + o->dilation;
+        float det = a * c - b * b;
+        q->ca = c / det;
+        q->cb = -(b / det);
+        q->cc = a / det;
+        float Rx = o->cutoff * sqrtf(a), Ry = o->cutoff * sqrtf(c);
+        float xs = u - 0.5f, ys = v - 0.5f;
+        float lx = ceilf(xs - Rx), hx = floorf(xs + Rx);
+        float ly = ceilf(ys - Ry), hy = floorf(ys + Ry);
+        if (lx < 0.0f) lx = 0.0f;
+        if (ly < 0.0f) ly = 0.0f;
+        if (hx > Wf - 1.0f) hx = Wf - 1.0f;
+        if (hy > Hf - 1.0f) hy = Hf - 1.0f;
+        if (!(lx <= hx && ly <= hy)) return;
+        q->px0 = (int32_t)lx; q->px1 = (int32_t)hx;
+        q->py0 = (int32_t)ly; q->py1 = (int32_t)hy;
+        q->thr = o->cutoff * o->cutoff;
+        q->ewa = 1;
+        q->visible = 1;
     } else {
         /* isotropic screen-space Gaussian, dilated and cut at `cutoff` sigma */
         float s2 = radius * radius + o->dilation;
@@ -132,11 +172,18 @@ static void decide_point(const ocam_t* cam, const oopts_t* o, const float* p, fl
     }
 }
 
-/* Is pixel (px, py) of a visible Gaussian point a fragment?  FP32. */
+/* Is pixel (px, py) of a visible Gaussian point a fragment?  FP32.
+ * Screen-space: d2 = dx^2 + dy^2 against cutoff^2 s2; world-space (EWA):
+ * the Mahalanobis distance d2 = A dx^2 + 2 B dx dy + C dy^2 against
+ * cutoff^2. */
 static int gauss_frag(const opoint_t* q, int px, int py, float* d2_out) {
     float dx = ((float)px + 0.5f) - q->u;
     float dy = ((float)py + 0.5f) - q->v;
-    float d2 = dx * dx + dy * dy;
+    float d2;
+    if (!q->ewa)
+        d2 = dx * dx + dy * dy;
+    else
+        d2 = (q->ca * (dx * dx) + (2.0f * q->cb) * (dx * dy)) + q->cc * (dy * dy);
     *d2_out = d2;
     return d2 <= q->thr;
 }
@@ -230,6 +277,7 @@ typedef struct {
     float w32;       /* FP32 weight (bilinear decisions) */
     double w;        /* FP64 weight */
     double dw_du, dw_dv;
+    double dw_dz;    /* EWA: through the covariance's dependence on Z at fixed u, v */
     /* filled by the blend */
     double Ta;       /* T_k * a_k of this fragment */
     double da;       /* dL/da_k */
@@ -261,6 +309,42 @@ static int cmp_frag(const void* pa, const void* pb) {
  * fragment set would not fit in memory: each kept pixel's list is still
  * complete, so its blend is exact). */
 static int keep_pixel(const uint8_t* mask, int64_t pixel) { return !mask || mask[pixel]; }
+
+/* World-space Gaussian fragment: w = exp(-d2 / 2) with the conic computed in
+ * FP64 from the FP32 u, v, Z, and dw/du, dw/dv (through the offset and the
+ * covariance) and dw/dZ (through the covariance at fixed u, v). */
+static void ewa_weight(const ocam_t* cam, const oopts_t* o, const opoint_t* q, double dx,
+                       double dy, ofrag_t* g) {
+    const double fx = cam->fx, fy = cam->fy, Z = q->Z;
+    const double xh = ((double)q->u - cam->cx) / fx, yh = ((double)q->v - cam->cy) / fy;
+    const double jx = fx / Z, jy = fy / Z, s = (double)o->ewa_sigma * o->ewa_sigma;
+    const double dil = o->dilation;
+    const double a = s * jx * jx * (1.0 + xh * xh) + dil;
+    const double b = s * jx * jy * xh * yh;
+    const double c = s * jy * jy * (1.0 + yh * yh) + dil;
+    const double det = a * c - b * b, inv = 1.0 / det, inv2 = inv * inv;
+    const double A = c * inv, B = -b * inv, C = a * inv;
+    const double d2 = A * dx * dx + 2.0 * B * dx * dy + C * dy * dy;
+    const double w = exp(-0.5 * d2);
+    g->w = w;
+    g->w32 = (float)w;
+    /* through the offsets dx = px + 1/2 - u, dy = py + 1/2 - v */
+    double du = w * (A * dx + B * dy), dv = w * (B * dx + C * dy);
+    /* through the conic */
+    const double gA = -0.5 * w * dx * dx, gB = -w * dx * dy, gC = -0.5 * w * dy * dy;
+    const double ga = gA * (-c * c * inv2) + gB * (b * c * inv2) + gC * (-b * b * inv2);
+    const double gb = gA * (2.0 * b * c * inv2) + gB * (-(a * c + b * b) * inv2) +
+                      gC * (2.0 * a * b * inv2);
+    const double gc = gA * (-b * b * inv2) + gB * (a * b * inv2) + gC * (-a * a * inv2);
+    /* covariance entries as functions of u, v (through xh, yh) and Z (through jx, jy) */
+    du += ga * (s * jx * jx * 2.0 * xh / fx) + gb * (s * jx * jy * yh / fx);
+    dv += gb * (s * jx * jy * xh / fy) + gc * (s * jy * jy * 2.0 * yh / fy);
+    g->dw_du = du;
+    g->dw_dv = dv;
+    g->dw_dz = ga * (-2.0 * s * jx * jx * (1.0 + xh * xh) / Z) +
+               gb * (-2.0 * s * jx * jy * xh * yh / Z) +
+               gc * (-2.0 * s * jy * jy * (1.0 + yh * yh) / Z);
+}
 
 static void build_fragments(const ocam_t* cam, const oopts_t* o, int64_t n, const float* pos,
                             const float* radius, const uint8_t* mask, oscene_t* s) {
@@ -326,15 +410,19 @@ static void build_fragments(const ocam_t* cam, const oopts_t* o, int64_t n, cons
                     g->key = q->key;
                     g->idx = (uint32_t)i;
                     g->corner = -1;
-                    /* weight exp(-d^2 / (2 s2)); derivatives w.r.t. u, v */
                     double dx = ((double)px + 0.5) - (double)q->u;
                     double dy = ((double)py + 0.5) - (double)q->v;
-                    double s2 = (double)q->s2;
-                    double w = exp(-0.5 * (dx * dx + dy * dy) / s2);
-                    g->w = w;
-                    g->w32 = (float)w;
-                    g->dw_du = w * dx / s2;
-                    g->dw_dv = w * dy / s2;
+                    if (o->splat == 1) {
+                        /* weight exp(-d^2 / (2 s2)); derivatives w.r.t. u, v */
+                        double s2 = (double)q->s2;
+                        double w = exp(-0.5 * (dx * dx + dy * dy) / s2);
+                        g->w = w;
+                        g->w32 = (float)w;
+                        g->dw_du = w * dx / s2;
+                        g->dw_dv = w * dy / s2;
+                    } else {
+                        ewa_weight(cam, o, q, dx, dy, g);
+                    }
                 }
         }
     }
@@ -374,6 +462,8 @@ static void free_scene(oscene_t* s) {
  * Backward outputs: grad_feat [n][C], grad_opacity [n], grad_uv [n][2],
  *                   grad_pos [n][3], grad_bg [C] (if bg), and the matching
  *                   *_abs magnitude bounds (same shapes).
+ * grad_z, grad_z_abs: [n] or NULL; world-space Gaussians: dL/dZ through the
+ *                   projected covariance at fixed (u, v) (grad_pos includes it)
  * pixel_mask:       [H][W] or NULL: forward only, computes the masked pixels
  *                   (the others are left as zero); -1 if combined with a
  *                   backward pass.
@@ -385,7 +475,8 @@ int oracle_render(const ocam_t* cam, const oopts_t* o, int64_t n, const float* p
                   const float* grad_t, double* grad_feat, double* grad_opacity,
                   double* grad_uv, double* grad_pos, double* grad_bg,
                   double* grad_feat_abs, double* grad_opacity_abs, double* grad_uv_abs,
-                  double* grad_pos_abs, const uint8_t* pixel_mask, int32_t bg_image) {
+                  double* grad_pos_abs, const uint8_t* pixel_mask, int32_t bg_image,
+                  double* grad_z, double* grad_z_abs) {
     const int W = cam->width, H = cam->height;
     const int64_t P = (int64_t)W * H;
     if (pixel_mask && grad_out) return -1;
@@ -492,6 +583,7 @@ int oracle_render(const ocam_t* cam, const oopts_t* o, int64_t n, const float* p
             double* gfa = grad_feat_abs + i * C;
             for (int c = 0; c < C; ++c) { gfe[c] = 0.0; gfa[c] = 0.0; }
             double go = 0.0, goa = 0.0, gu = 0.0, gv = 0.0, gua = 0.0, gva = 0.0;
+            double gz = 0.0, gza = 0.0;
             const double o64 = (double)opacity[i];
             for (int64_t f = s.pt_start[i]; f < s.pt_start[i + 1]; ++f) {
                 const ofrag_t* g = &s.frag[f];
@@ -507,6 +599,12 @@ int oracle_render(const ocam_t* cam, const oopts_t* o, int64_t n, const float* p
                 gv += o64 * g->dw_dv * g->da;
                 gua += fabs(o64 * g->dw_du) * g->da_abs;
                 gva += fabs(o64 * g->dw_dv) * g->da_abs;
+                gz += o64 * g->dw_dz * g->da;
+                gza += fabs(o64 * g->dw_dz) * g->da_abs;
+            }
+            if (grad_z) {
+                grad_z[i] = gz;
+                grad_z_abs[i] = gza;
             }
             grad_opacity[i] = go;
             grad_opacity_abs[i] = goa;
@@ -523,9 +621,9 @@ int oracle_render(const ocam_t* cam, const oopts_t* o, int64_t n, const float* p
                 double Z = R[6] * px + R[7] * py + R[8] * pz + cam->t[2];
                 double fx = cam->fx, fy = cam->fy;
                 double dX = gu * fx / Z, dY = gv * fy / Z;
-                double dZ = -(gu * fx * X + gv * fy * Y) / (Z * Z);
+                double dZ = gz - (gu * fx * X + gv * fy * Y) / (Z * Z);
                 double aX = gua * fx / Z, aY = gva * fy / Z;
-                double aZ = (gua * fx * fabs(X) + gva * fy * fabs(Y)) / (Z * Z);
+                double aZ = gza + (gua * fx * fabs(X) + gva * fy * fabs(Y)) / (Z * Z);
                 for (int j = 0; j < 3; ++j) {
                     gp[j] = R[j] * dX + R[3 + j] * dY + R[6 + j] * dZ;
                     gpa[j] = fabs(R[j]) * aX + fabs(R[3 + j]) * aY + fabs(R[6 + j]) * aZ;
