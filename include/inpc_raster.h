@@ -63,7 +63,12 @@ enum {
     INPC_ERR_UNSUPPORTED = -4  /* valid but not implemented combination */
 };
 
-enum { INPC_SPLAT_BILINEAR = 0, INPC_SPLAT_GAUSSIAN = 1 };
+/* Splat kinds (Sec. 3.2): bilinear 2x2 splats (training), isotropic
+ * screen-space Gaussians of a per-point radius, and isotropic world-space
+ * Gaussians of one standard deviation ewa_sigma projected with the affine
+ * (EWA) approximation of the perspective map ("Rendering Points as Small
+ * Gaussians"). */
+enum { INPC_SPLAT_BILINEAR = 0, INPC_SPLAT_GAUSSIAN = 1, INPC_SPLAT_EWA = 2 };
 enum { INPC_F32 = 0, INPC_F16 = 1, INPC_BF16 = 2 };
 
 /* Pinhole camera, OpenCV axes (+z forward, +y down).  A world point p goes
@@ -79,13 +84,16 @@ typedef struct {
 } inpc_camera_t;
 
 typedef struct {
-    int32_t splat;      /* INPC_SPLAT_BILINEAR or INPC_SPLAT_GAUSSIAN */
+    int32_t splat;      /* INPC_SPLAT_BILINEAR, INPC_SPLAT_GAUSSIAN or INPC_SPLAT_EWA */
     int32_t tile;       /* tile edge in pixels: 8, 16 or 32 (Sec. 3.2 uses 8) */
     float t_min;        /* fragment k is blended iff the transmittance in front of it is >= t_min;
                            0 blends every fragment (exact Eq. (1)); typical 1e-4 */
-    float dilation;     /* Gaussian: variance added to r^2 (paper: 0.16) */
-    float cutoff;       /* Gaussian: truncation in standard deviations (paper: 3) */
-    float max_radius;   /* Gaussian: largest radius_px any point may have; sizes the workspace */
+    float dilation;     /* Gaussians: variance added to the projected covariance (paper: 0.16) */
+    float cutoff;       /* Gaussians: truncation in standard deviations (paper: 3) */
+    float max_radius;   /* Gaussians: largest projected standard deviation in pixels, before
+                           dilation, of any point (screen-space: radius; world-space: the
+                           square root of the larger diagonal entry of sigma^2 J J^T); sizes
+                           the workspace */
     int32_t bin_points; /* points per workgroup of the counting and scatter passes of steps 1-2:
                            0 = automatic (8192, or n/256 when larger), else a multiple of
                            1024; never fewer than n/256 (a tuning knob: results do not
@@ -93,6 +101,12 @@ typedef struct {
     int32_t bg_per_pixel; /* 0: the blend's background `bg` (and grad_bg) is one [C] vector;
                              1: a per-pixel image [C][H][W] (e.g. from inpc_envmap_forward),
                              and grad_bg is [C][H][W] as well */
+    float ewa_sigma;    /* INPC_SPLAT_EWA: world-space standard deviation of every point
+                           (finite, > 0); projected covariance sigma^2 J J^T + dilation I with
+                           J the Jacobian of the perspective map at the point.  The paper's
+                           default makes a point at the near plane that projects to the image
+                           centre 5 px wide: sigma = 5 z_near / max(fx, fy).  Ignored for the
+                           other splats. */
 } inpc_opts_t;
 
 /* Bytes of workspace needed for n points with this camera and options.
@@ -116,10 +130,13 @@ int64_t inpc_num_tiles(const inpc_camera_t* cam, const inpc_opts_t* opts);
  * camera; Sec. 3.2: 32-bit depth keys).
  *   pos      [n][3] f32 world positions
  *   opacity  [n] f32 in [0, 1]
- *   radius   [n] f32 Gaussian standard deviation in pixels (before
- *            dilation), NULL for bilinear splats
+ *   radius   [n] f32 screen-space Gaussian standard deviation in pixels
+ *            (before dilation); NULL for bilinear and world-space splats
  *   proj     [n][4] f32 out, 16-byte aligned: per point (u, v, opacity,
- *            radius or 0), the image coordinates next to what the blend
+ *            w) with w the radius (screen-space Gaussians), the camera-space
+ *            depth Z (world-space Gaussians: the projected covariance is a
+ *            function of u, v and Z) or 0, the image coordinates next to
+ *            what the blend
  *            passes read with them, so that one 16-byte load fetches all of
  *            a point's footprint data
  *   depth_key[n] u32 out: bit pattern of camera-space Z (monotone in Z > 0)
@@ -182,7 +199,7 @@ int64_t inpc_copy_capacity(int64_t n, const inpc_camera_t* cam, const inpc_opts_
  * For every pixel, the fragments of its tile's list in order: alpha = o w
  * (w bilinear weight or Gaussian value), F += T alpha f, T *= 1 - alpha;
  * stops before the first fragment whose T < t_min; finally F += T f_bg.
- *   proj       output of inpc_project (position, opacity, radius)
+ *   proj       output of inpc_project (position, opacity, radius or depth)
  *   feat       [n][C] features, dtype INPC_F32 / INPC_F16 / INPC_BF16
  *              (blending and accumulation are FP32 for every dtype)
  *   bg         [C] f32 constant background features, [C][H][W] per-pixel
@@ -212,7 +229,11 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
  *   dL/dalpha_k = T_k (G . f_k - G . B_k) - G_T T_k prod_{j>k} (1 - alpha_j),
  * B_k the blend of everything behind fragment k including the background;
  * then dL/df, dL/do = w dL/dalpha, dL/d(u,v) = o dw/d(u,v) dL/dalpha.
- * Bilinear splats only (INPC_ERR_UNSUPPORTED for Gaussians).
+ * Every splat kind.  Screen-space Gaussians: w = exp(-|d|^2 / (2 s2)) with
+ * s2 = r^2 + dilation, differentiated in (u, v) (not in the radius).
+ * World-space Gaussians: w = exp(-d^T S^-1 d / 2) with S the projected
+ * covariance, differentiated in (u, v) through both the offset d and S, and
+ * in the depth Z through S (grad_z; inpc_project_backward adds it).
  *   proj, ntiles, tile_ranges, tile_order, list, lpos: from steps 1-3
  *              (recomputed or kept)
  *   t_final, state: from inpc_blend_forward with the same inputs
@@ -221,14 +242,16 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
  *   grad_feat  [n][C] f32 out (FP32 for every feature dtype)
  *   grad_opacity [n] f32 out
  *   grad_uv    [n][2] f32 out (input of inpc_project_backward)
+ *   grad_z     [n] f32 out: dL/dZ at fixed (u, v) (world-space Gaussians;
+ *              may be NULL for the other splats, else written with zeros)
  *   grad_bg    [C] f32 out (sum over pixels of T_final G), [C][H][W] (T_final G
  *              per pixel) when opts->bg_per_pixel, or NULL
  *   scratch    device scratch of inpc_backward_scratch_bytes(n, C, ...) bytes
  * Every output element is written (zero for culled points and for points no
  * blended fragment reached).  A point whose footprint lies in one tile gets
- * its gradient stored by that tile; a point split over several tiles (at
- * most four) gets each tile's share added with float atomics, so the last
- * bits of those gradients depend on the order the tiles finish in.
+ * its gradient stored by that tile; a point split over several tiles gets
+ * each tile's share added with float atomics, so the last bits of those
+ * gradients depend on the order the tiles finish in.
  */
 inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
                                   const float* proj, const void* feat, int32_t C, int32_t dtype,
@@ -237,9 +260,9 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
                                   const uint32_t* tile_order, const uint32_t* list,
                                   const uint16_t* lpos, const float* t_final, const void* state,
                                   const float* grad_out, const float* grad_t, float* grad_feat,
-                                  float* grad_opacity, float* grad_uv, float* grad_bg,
-                                  void* scratch, size_t scratch_bytes, void* ws, size_t ws_bytes,
-                                  void* stream);
+                                  float* grad_opacity, float* grad_uv, float* grad_z,
+                                  float* grad_bg, void* scratch, size_t scratch_bytes, void* ws,
+                                  size_t ws_bytes, void* stream);
 
 /*
  * Step 5 without allocation -- for callers that cannot allocate device
@@ -261,11 +284,11 @@ inpc_status_t inpc_blend_backward_noalloc(
     const void* feat, int32_t C, int32_t dtype, const float* bg, const uint32_t* ntiles,
     const uint32_t* tile_ranges, const uint32_t* tile_order, const uint32_t* list,
     const uint16_t* lpos, const float* t_final, const void* state, const float* grad_out,
-    const float* grad_t, float* grad_feat, float* grad_opacity, float* grad_uv, float* grad_bg,
-    void* ws, size_t ws_bytes, void* stream);
+    const float* grad_t, float* grad_feat, float* grad_opacity, float* grad_uv, float* grad_z,
+    float* grad_bg, void* ws, size_t ws_bytes, void* stream);
 
 /* Bytes of the scratch inpc_blend_backward needs for n points and C channels:
- * 16 per point (the opacity and position gradients as one row per point,
+ * 16 per point (the opacity, position and depth gradients as one row per point,
  * which the atomics of points split over tiles add to) plus 4 C per tile
  * (the per-tile shares of the background gradient).  0 if invalid. */
 size_t inpc_backward_scratch_bytes(int64_t n, int32_t C, const inpc_camera_t* cam,
@@ -273,13 +296,14 @@ size_t inpc_backward_scratch_bytes(int64_t n, int32_t C, const inpc_camera_t* ca
 
 /*
  * Step 6 -- project backward: dL/dX = G_u fx/Z, dL/dY = G_v fy/Z,
- * dL/dZ = -(G_u fx X + G_v fy Y)/Z^2, dL/dp = R^T (dL/dX, dL/dY, dL/dZ);
+ * dL/dZ = G_Z - (G_u fx X + G_v fy Y)/Z^2, dL/dp = R^T (dL/dX, dL/dY, dL/dZ);
  * zero for culled points (ntiles == 0).
- *   grad_uv [n][2] f32, grad_pos [n][3] f32 out
+ *   grad_uv [n][2] f32; grad_z [n] f32 (the blend's dL/dZ at fixed (u, v),
+ *   world-space Gaussians) or NULL (G_Z = 0); grad_pos [n][3] f32 out
  */
 inpc_status_t inpc_project_backward(const inpc_camera_t* cam, int64_t n, const float* pos,
                                     const uint32_t* ntiles, const float* grad_uv,
-                                    float* grad_pos, void* stream);
+                                    const float* grad_z, float* grad_pos, void* stream);
 
 /*
  * Background from a spherical environment map (Sec. 3.2 "Faster Background
@@ -331,7 +355,7 @@ inpc_status_t inpc_envmap_backward(const inpc_camera_t* cam, const float* dirs,
  *   in queue order.  Writes out, t_final, n_contrib and state of every
  *   view, exactly as inpc_blend_forward would.
  * inpc_rasterize_batched(pass = INPC_PASS_BACKWARD): the lists are built
- *   again (bilinear splats only), ONE launch replays every (view, tile) item
+ *   again, ONE launch replays every (view, tile) item
  *   backwards, then every view's gradients are finished and chained to
  *   positions: grad_feat, grad_opacity, grad_uv, grad_pos and grad_bg as
  *   inpc_blend_backward + inpc_project_backward give them.
@@ -350,7 +374,7 @@ typedef struct {
     int64_t n;
     const float* pos;          /* [n][3] */
     const float* opacity;      /* [n] */
-    const float* radius;       /* [n] Gaussian radii, or NULL (bilinear) */
+    const float* radius;       /* [n] screen-space Gaussian radii, or NULL */
     const void* feat;          /* [n][C] of the batch's dtype */
     const float* bg;           /* [C] or [C][H][W] (opts->bg_per_pixel), or NULL */
     float* proj;               /* [n][4], 16-byte aligned */
@@ -360,7 +384,7 @@ typedef struct {
     uint32_t* tile_order;      /* [num_tiles] */
     uint32_t* list;            /* [copy capacity] */
     uint16_t* lpos;            /* [copy capacity] (bilinear) */
-    void* state;               /* inpc_state_bytes() (bilinear) */
+    void* state;               /* inpc_state_bytes() */
     void* ws;                  /* inpc_workspace_bytes(), zeroed when first allocated */
     size_t ws_bytes;
     void* scratch;             /* inpc_backward_scratch_bytes() (backward pass) */
@@ -375,6 +399,7 @@ typedef struct {
     float* grad_uv;            /* [n][2] */
     float* grad_pos;           /* [n][3] */
     float* grad_bg;            /* like bg, or NULL */
+    float* grad_z;             /* [n] (world-space Gaussians, backward), else NULL */
 } inpc_view_t;
 
 enum { INPC_PASS_FORWARD = 0, INPC_PASS_BACKWARD = 1 };

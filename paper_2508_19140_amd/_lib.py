@@ -19,6 +19,7 @@ INPC_ERR_UNSUPPORTED = -4
 
 SPLAT_BILINEAR = 0
 SPLAT_GAUSSIAN = 1
+SPLAT_EWA = 2
 
 DTYPE_F32 = 0
 DTYPE_F16 = 1
@@ -52,7 +53,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("splat", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("t_min", ctypes.c_float), ("dilation", ctypes.c_float),
                 ("cutoff", ctypes.c_float), ("max_radius", ctypes.c_float),
-                ("bin_points", ctypes.c_int32), ("bg_per_pixel", ctypes.c_int32)]
+                ("bin_points", ctypes.c_int32), ("bg_per_pixel", ctypes.c_int32),
+                ("ewa_sigma", ctypes.c_float)]
 
 
 _VP = ctypes.c_void_p
@@ -68,7 +70,7 @@ class ViewRecord(ctypes.Structure):
                 ("scratch", _VP), ("scratch_bytes", ctypes.c_size_t),
                 ("out", _VP), ("t_final", _VP), ("n_contrib", _VP),
                 ("grad_out", _VP), ("grad_t", _VP), ("grad_feat", _VP), ("grad_opacity", _VP),
-                ("grad_uv", _VP), ("grad_pos", _VP), ("grad_bg", _VP)]
+                ("grad_uv", _VP), ("grad_pos", _VP), ("grad_bg", _VP), ("grad_z", _VP)]
 
 
 class InpcError(RuntimeError):
@@ -102,9 +104,9 @@ def lib():
         "inpc_blend_forward": (I32, [CP, OP, I64, P, P, I32, I32, P, P, P, P, P, P, P, P, P,
                                      P, SZ, P]),
         "inpc_blend_backward": (I32, [CP, OP, I64, P, P, I32, I32, P, P, P, P, P, P, P, P, P,
-                                      P, P, P, P, P, P, SZ, P, SZ, P]),
+                                      P, P, P, P, P, P, P, SZ, P, SZ, P]),
         "inpc_blend_backward_noalloc": (I32, [CP, OP, I64, P, P, I32, I32, P, P, P, P, P, P, P,
-                                              P, P, P, P, P, P, P, P, SZ, P]),
+                                              P, P, P, P, P, P, P, P, P, SZ, P]),
         "inpc_backward_scratch_bytes": (SZ, [I64, I32, CP, OP]),
         "inpc_view_dirs": (I32, [CP, P, P]),
         "inpc_envmap_forward": (I32, [CP, P, P, I32, I32, I32, P, P]),
@@ -114,7 +116,7 @@ def lib():
         "inpc_batch_workspace_bytes": (SZ, [ctypes.POINTER(ViewRecord), I32, OP]),
         "inpc_rasterize_batched": (I32, [ctypes.POINTER(ViewRecord), P, I32, OP, I32, I32, I32,
                                          P, SZ, P]),
-        "inpc_project_backward": (I32, [CP, I64, P, P, P, P, P]),
+        "inpc_project_backward": (I32, [CP, I64, P, P, P, P, P, P]),
         "inpc_check_sync": (I32, [P, SZ, P]),
         "inpc_status_string": (ctypes.c_char_p, [I32]),
         "inpc_last_error": (ctypes.c_char_p, []),
@@ -154,10 +156,11 @@ def make_camera(width, height, fx, fy, cx, cy, R, t, z_near=0.2) -> Camera:
 
 
 def make_opts(splat=SPLAT_BILINEAR, tile=8, t_min=1e-4, dilation=0.16, cutoff=3.0,
-              max_radius=0.0, bin_points=0, bg_per_pixel=False) -> Opts:
+              max_radius=0.0, bin_points=0, bg_per_pixel=False, ewa_sigma=0.0) -> Opts:
     o = Opts()
     o.bin_points = int(bin_points)
     o.bg_per_pixel = int(bool(bg_per_pixel))
+    o.ewa_sigma = float(ewa_sigma)
     o.splat, o.tile = int(splat), int(tile)
     o.t_min, o.dilation, o.cutoff, o.max_radius = float(t_min), float(dilation), float(cutoff), \
         float(max_radius)

@@ -30,7 +30,7 @@ from typing import Dict, List, Optional, Sequence, Tuple
 import torch
 
 from . import _lib as L
-from .raster import RasterSettings, camera_struct
+from .raster import RasterSettings, camera_struct, ewa_max_radius
 
 _DT = {torch.float32: L.DTYPE_F32, torch.float16: L.DTYPE_F16, torch.bfloat16: L.DTYPE_BF16}
 
@@ -44,7 +44,7 @@ class ViewInputs:
     """Device tensors of one view: pos [n,3] f32, opacity [n] f32, feat
     [n,C] (f32/f16/bf16), camera (scenes.Camera or L.Camera), grad_out
     [C,H,W] f32 (upstream gradient of the feature image; None: forward only),
-    radius [n] f32 for Gaussian splats."""
+    radius [n] f32 for screen-space Gaussian splats."""
     pos: torch.Tensor
     opacity: torch.Tensor
     feat: torch.Tensor
@@ -59,9 +59,10 @@ class ViewPipeline:
     def __init__(self, v: ViewInputs, settings: RasterSettings):
         dev = v.pos.device
         self.v, self.settings = v, settings
-        self.gauss = settings.splat == "gaussian"
+        self.gauss = settings.splat != "bilinear"
+        self.ewa = settings.splat == "ewa"
         self.cam = camera_struct(v.camera)
-        self.opts = settings.opts()
+        self.opts = settings.opts(cam=self.cam)
         self.cb, self.ob = ctypes.byref(self.cam), ctypes.byref(self.opts)
         lib = L.lib()
         self.lib = lib
@@ -82,12 +83,13 @@ class ViewPipeline:
         self.ranges, self.order = mk(nt + 1, dt=i32), mk(max(nt, 1), dt=i32)
         self.list, self.lpos = mk(max(cap, 1), dt=i32), mk(max(cap, 1), dt=torch.int16)
         self.out, self.tf, self.nc = mk(C, H, W), mk(H, W), mk(H, W, dt=i32)
-        self.backward_enabled = v.grad_out is not None and not self.gauss
-        self.state = None
-        if not self.gauss:
-            self.state = mk(int(lib.inpc_state_bytes(self.cb, self.ob)), dt=torch.uint8)
+        self.backward_enabled = v.grad_out is not None
+        self.state = mk(int(lib.inpc_state_bytes(self.cb, self.ob)), dt=torch.uint8)
+        self.gz = None
         if self.backward_enabled:
             self.gf, self.go, self.guv, self.gpos = mk(n, C), mk(n), mk(n, 2), mk(n, 3)
+            if self.ewa:
+                self.gz = mk(n)
             self.scratch = mk(int(lib.inpc_backward_scratch_bytes(n, C, self.cb, self.ob)),
                               dt=torch.uint8)
 
@@ -97,7 +99,8 @@ class ViewPipeline:
         ptr = lambda t: None if t is None else t.data_ptr()
         r.cam = self.cam
         r.n = self.n
-        r.pos, r.opacity, r.radius, r.feat = ptr(v.pos), ptr(v.opacity), ptr(v.radius), ptr(v.feat)
+        radius = v.radius if self.settings.splat == "gaussian" else None
+        r.pos, r.opacity, r.radius, r.feat = ptr(v.pos), ptr(v.opacity), ptr(radius), ptr(v.feat)
         r.bg = None
         r.proj, r.depth_key, r.ntiles = ptr(self.proj), ptr(self.key), ptr(self.ntiles)
         r.tile_ranges, r.tile_order = ptr(self.ranges), ptr(self.order)
@@ -108,7 +111,7 @@ class ViewPipeline:
         if self.backward_enabled:
             r.scratch, r.scratch_bytes = ptr(self.scratch), self.scratch.numel()
             r.grad_feat, r.grad_opacity = ptr(self.gf), ptr(self.go)
-            r.grad_uv, r.grad_pos = ptr(self.guv), ptr(self.gpos)
+            r.grad_uv, r.grad_pos, r.grad_z = ptr(self.guv), ptr(self.gpos), ptr(self.gz)
 
     def _call(self, name, *args):
         st = getattr(self.lib, name)(*args)
@@ -118,8 +121,9 @@ class ViewPipeline:
     # one method per entry point, each on stream handle s
     def project(self, s):
         v, ws = self.v, self.ws
+        radius = v.radius if self.settings.splat == "gaussian" else None
         self._call("inpc_project", self.cb, self.ob, self.n, _p(v.pos), _p(v.opacity),
-                   _p(v.radius), _p(self.proj), _p(self.key), _p(self.ntiles), _p(ws),
+                   _p(radius), _p(self.proj), _p(self.key), _p(self.ntiles), _p(ws),
                    ws.numel(), s)
 
     def bin(self, s):
@@ -144,13 +148,13 @@ class ViewPipeline:
         self._call("inpc_blend_backward", self.cb, self.ob, self.n, _p(self.proj), _p(v.feat),
                    self.C, self.dtype, None, _p(self.ntiles), _p(self.ranges), _p(self.order),
                    _p(self.list), _p(self.lpos), _p(self.tf), _p(self.state), _p(v.grad_out),
-                   None, _p(self.gf), _p(self.go), _p(self.guv), None, _p(self.scratch),
-                   self.scratch.numel(), _p(ws), ws.numel(), s)
+                   None, _p(self.gf), _p(self.go), _p(self.guv), _p(self.gz), None,
+                   _p(self.scratch), self.scratch.numel(), _p(ws), ws.numel(), s)
 
     def project_bwd(self, s):
         v = self.v
         self._call("inpc_project_backward", self.cb, self.n, _p(v.pos), _p(self.ntiles),
-                   _p(self.guv), _p(self.gpos), s)
+                   _p(self.guv), _p(self.gz), _p(self.gpos), s)
 
     def phases(self):
         """(entry point, fn(stream)) of one training pass: forward, then the
@@ -172,6 +176,8 @@ class ViewPipeline:
         if self.backward_enabled:
             r.update(grad_feat=self.gf, grad_opacity=self.go, grad_uv=self.guv,
                      grad_pos=self.gpos)
+            if self.gz is not None:
+                r["grad_z"] = self.gz
         return r
 
 
@@ -340,6 +346,13 @@ class BatchedRasterizer:
         C, dt = self.views[0].feat.shape[1], self.views[0].feat.dtype
         if any(v.feat.shape[1] != C or v.feat.dtype != dt for v in self.views):
             raise ValueError("all views of a batch share the channel count and feature dtype")
+        if settings.splat == "ewa":
+            # one sigma and one workspace bound shared by every view of the batch
+            cams = [camera_struct(v.camera) for v in self.views]
+            sigma = settings.sigma(cams[0])
+            bound = settings.ewa_max_radius or max(
+                ewa_max_radius(c, sigma, settings.dilation, settings.cutoff) for c in cams)
+            settings = dataclasses.replace(settings, ewa_sigma=sigma, ewa_max_radius=bound)
         self.base = settings
         self.cache_path = cache_path or default_cache_path()
         self.key = batch_key(self.views, settings)
@@ -363,7 +376,7 @@ class BatchedRasterizer:
     def _build(self, settings: RasterSettings):
         self.settings = settings
         self.pipes = [ViewPipeline(v, settings) for v in self.views]
-        self.opts = settings.opts()
+        self.opts = settings.opts(cam=self.pipes[0].cam)
         recs = (L.ViewRecord * len(self.pipes))()
         for r, p in zip(recs, self.pipes):
             p.fill_record(r)

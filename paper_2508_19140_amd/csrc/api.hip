@@ -33,11 +33,13 @@ bool valid_cam(const inpc_camera_t* c) {
 bool valid_opts(const inpc_opts_t* o) {
   return o && (o->tile == 8 || o->tile == 16 || o->tile == 32) && o->bin_points >= 0 &&
          o->bin_points % 1024 == 0 &&
-         (o->splat == INPC_SPLAT_BILINEAR || o->splat == INPC_SPLAT_GAUSSIAN) &&
+         (o->splat == INPC_SPLAT_BILINEAR || o->splat == INPC_SPLAT_GAUSSIAN ||
+          o->splat == INPC_SPLAT_EWA) &&
          o->t_min >= 0.f && o->t_min <= 1.f && (o->bg_per_pixel == 0 || o->bg_per_pixel == 1) &&
          (o->splat == INPC_SPLAT_BILINEAR ||
-          (o->dilation >= 0.f && o->cutoff > 0.f && o->max_radius >= 0.f &&
-           isfinite(o->max_radius)));
+          (o->dilation >= 0.f && isfinite(o->dilation) && o->cutoff > 0.f &&
+           isfinite(o->cutoff) && o->max_radius >= 0.f && isfinite(o->max_radius))) &&
+         (o->splat != INPC_SPLAT_EWA || (o->ewa_sigma > 0.f && isfinite(o->ewa_sigma)));
 }
 
 int64_t num_tiles(const inpc_camera_t* c, const inpc_opts_t* o) {
@@ -183,6 +185,7 @@ Opts to_opts(const inpc_camera_t* c, const inpc_opts_t* o) {
   k.t_min = o->t_min;
   k.dilation = o->dilation;
   k.cutoff = o->cutoff;
+  k.ewa_sigma = o->splat == INPC_SPLAT_EWA ? o->ewa_sigma : 0.f;
   return k;
 }
 
@@ -273,19 +276,17 @@ static inpc_status_t blend_backward_impl(const char* who, const inpc_camera_t* c
                                   const uint32_t* tile_order, const uint32_t* list,
                                   const uint16_t* lpos, const float* t_final, const void* state,
                                   const float* grad_out, const float* grad_t, float* grad_feat,
-                                  float* grad_opacity, float* grad_uv, float* grad_bg,
-                                  void* scratch, size_t scratch_size, void* ws, size_t ws_bytes,
-                                  void* stream) {
+                                  float* grad_opacity, float* grad_uv, float* grad_z,
+                                  float* grad_bg, void* scratch, size_t scratch_size, void* ws,
+                                  size_t ws_bytes, void* stream) {
   inpc_status_t st = blend_checks(cam, opts, n, C, dtype, ws, ws_bytes);
   if (st != INPC_OK) return st;
-  if (opts->splat != INPC_SPLAT_BILINEAR)
-    return fail(INPC_ERR_UNSUPPORTED, "backward of Gaussian splats%s", "");
   REQUIRE(scratch, "scratch");
   if (scratch_size < scratch_bytes(n, C, cam, opts))
     return fail(INPC_ERR_INVALID, "scratch smaller than inpc_backward_scratch_bytes()%s", "");
   REQUIRE(tile_ranges, "tile_ranges");
   REQUIRE(list, "list");
-  REQUIRE(lpos, "lpos");
+  if (opts->splat == INPC_SPLAT_BILINEAR) REQUIRE(lpos, "lpos");
   REQUIRE(t_final, "t_final");
   REQUIRE(state, "state");
   REQUIRE(grad_out, "grad_out");
@@ -298,6 +299,7 @@ static inpc_status_t blend_backward_impl(const char* who, const inpc_camera_t* c
     REQUIRE_ALIGNED(grad_feat, "grad_feat", 16);
     REQUIRE(grad_opacity, "grad_opacity");
     REQUIRE_ALIGNED(grad_uv, "grad_uv", 8);
+    if (opts->splat == INPC_SPLAT_EWA) REQUIRE(grad_z, "grad_z");
   }
   const Ws w = make_ws(ws, n, cam, opts);
   BlendArgs a;
@@ -327,6 +329,7 @@ static inpc_status_t blend_backward_impl(const char* who, const inpc_camera_t* c
   a.grad_feat = grad_feat;
   a.grad_opacity = grad_opacity;
   a.grad_uv = grad_uv;
+  a.grad_z = grad_z;
   a.grad_bg = grad_bg;
   a.gsc = static_cast<float4*>(scratch);
   a.bg_partial = grad_bg && !opts->bg_per_pixel
@@ -470,7 +473,7 @@ inpc_status_t inpc_blend_forward(const inpc_camera_t* cam, const inpc_opts_t* op
   a.out = out;
   a.t_final = t_final;
   a.n_contrib = n_contrib;
-  if (state && opts->splat == INPC_SPLAT_BILINEAR) {
+  if (state) {
     const size_t P = (size_t)cam->width * cam->height;
     a.st_last = static_cast<uint32_t*>(state);
     a.st_anchor = a.st_last + P;
@@ -489,13 +492,13 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
                                   const uint32_t* tile_order, const uint32_t* list,
                                   const uint16_t* lpos, const float* t_final, const void* state,
                                   const float* grad_out, const float* grad_t, float* grad_feat,
-                                  float* grad_opacity, float* grad_uv, float* grad_bg,
-                                  void* scratch, size_t scratch_size, void* ws, size_t ws_bytes,
-                                  void* stream) {
+                                  float* grad_opacity, float* grad_uv, float* grad_z,
+                                  float* grad_bg, void* scratch, size_t scratch_size, void* ws,
+                                  size_t ws_bytes, void* stream) {
   return blend_backward_impl("inpc_blend_backward", cam, opts, n, proj, feat, C, dtype, bg,
                              ntiles, tile_ranges, tile_order, list, lpos, t_final, state,
-                             grad_out, grad_t, grad_feat, grad_opacity, grad_uv, grad_bg, scratch,
-                             scratch_size, ws, ws_bytes, stream);
+                             grad_out, grad_t, grad_feat, grad_opacity, grad_uv, grad_z, grad_bg,
+                             scratch, scratch_size, ws, ws_bytes, stream);
 }
 
 inpc_status_t inpc_blend_backward_noalloc(
@@ -503,8 +506,8 @@ inpc_status_t inpc_blend_backward_noalloc(
     const void* feat, int32_t C, int32_t dtype, const float* bg, const uint32_t* ntiles,
     const uint32_t* tile_ranges, const uint32_t* tile_order, const uint32_t* list,
     const uint16_t* lpos, const float* t_final, const void* state, const float* grad_out,
-    const float* grad_t, float* grad_feat, float* grad_opacity, float* grad_uv, float* grad_bg,
-    void* ws, size_t ws_bytes, void* stream) {
+    const float* grad_t, float* grad_feat, float* grad_opacity, float* grad_uv, float* grad_z,
+    float* grad_bg, void* ws, size_t ws_bytes, void* stream) {
   if (!valid_cam(cam)) return fail(INPC_ERR_INVALID, "invalid camera%s", "");
   if (!valid_opts(opts)) return fail(INPC_ERR_INVALID, "invalid options%s", "");
   if (n < 0 || n > (int64_t)0x7fffffff) return fail(INPC_ERR_INVALID, "n out of range%s", "");
@@ -524,13 +527,13 @@ inpc_status_t inpc_blend_backward_noalloc(
   if (st != INPC_OK) return st;
   return blend_backward_impl("inpc_blend_backward_noalloc", cam, opts, n, proj, feat, C, dtype,
                              bg, ntiles, tile_ranges, tile_order, list, lpos, t_final, state,
-                             grad_out, grad_t, grad_feat, grad_opacity, grad_uv, grad_bg, scr,
-                             kStaticScratchBytes, ws, ws_bytes, stream);
+                             grad_out, grad_t, grad_feat, grad_opacity, grad_uv, grad_z, grad_bg,
+                             scr, kStaticScratchBytes, ws, ws_bytes, stream);
 }
 
 inpc_status_t inpc_project_backward(const inpc_camera_t* cam, int64_t n, const float* pos,
                                     const uint32_t* ntiles, const float* grad_uv,
-                                    float* grad_pos, void* stream) {
+                                    const float* grad_z, float* grad_pos, void* stream) {
   if (!valid_cam(cam)) return fail(INPC_ERR_INVALID, "invalid camera%s", "");
   if (n < 0 || n > (int64_t)0x7fffffff) return fail(INPC_ERR_INVALID, "n out of range%s", "");
   if (n > 0) {
@@ -539,7 +542,7 @@ inpc_status_t inpc_project_backward(const inpc_camera_t* cam, int64_t n, const f
     REQUIRE(grad_uv, "grad_uv");
     REQUIRE(grad_pos, "grad_pos");
   }
-  hipError_t e = launch_project_backward(to_cam(cam), n, pos, ntiles, grad_uv, grad_pos,
+  hipError_t e = launch_project_backward(to_cam(cam), n, pos, ntiles, grad_uv, grad_z, grad_pos,
                                          (hipStream_t)stream);
   return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_project_backward");
 }
@@ -677,8 +680,6 @@ inpc_status_t inpc_rasterize_batched(const inpc_view_t* views_host, const inpc_v
   if (pass != INPC_PASS_FORWARD && pass != INPC_PASS_BACKWARD)
     return fail(INPC_ERR_INVALID, "unknown pass%s", "");
   const bool fwd = pass == INPC_PASS_FORWARD;
-  if (!fwd && opts->splat != INPC_SPLAT_BILINEAR)
-    return fail(INPC_ERR_UNSUPPORTED, "backward of Gaussian splats%s", "");
   const int64_t items = batch_items(views_host, n_views, opts);
   if (items < 0) return fail(INPC_ERR_INVALID, "invalid camera%s", "");
   if (items > (int64_t)0xffffffffLL) return fail(INPC_ERR_INVALID, "too many tiles%s", "");
@@ -708,7 +709,7 @@ inpc_status_t inpc_rasterize_batched(const inpc_view_t* views_host, const inpc_v
       REQUIRE(w.depth_key, "depth_key");
       REQUIRE(w.ntiles, "ntiles");
       REQUIRE_ALIGNED(w.feat, "feat", 16);
-      if (!bil) REQUIRE(w.radius, "radius");
+      if (opts->splat == INPC_SPLAT_GAUSSIAN) REQUIRE(w.radius, "radius");
     }
     if (fwd) {
       REQUIRE(w.out, "out");
@@ -726,6 +727,7 @@ inpc_status_t inpc_rasterize_batched(const inpc_view_t* views_host, const inpc_v
         REQUIRE(w.grad_opacity, "grad_opacity");
         REQUIRE_ALIGNED(w.grad_uv, "grad_uv", 8);
         REQUIRE(w.grad_pos, "grad_pos");
+        if (opts->splat == INPC_SPLAT_EWA) REQUIRE(w.grad_z, "grad_z");
       }
     }
   }
@@ -784,7 +786,8 @@ inpc_status_t inpc_rasterize_batched(const inpc_view_t* views_host, const inpc_v
     const BlendArgs a = make_view_args(w, to_opts(&w.cam, opts), C, dtype, opts->bg_per_pixel);
     e = launch_blend_backward_post(a, (hipStream_t)vs);
     if (e != hipSuccess) return hip_fail(e, "inpc_rasterize_batched");
-    st = inpc_project_backward(&w.cam, w.n, w.pos, w.ntiles, w.grad_uv, w.grad_pos, vs);
+    st = inpc_project_backward(&w.cam, w.n, w.pos, w.ntiles, w.grad_uv, w.grad_z, w.grad_pos,
+                               vs);
     if (st != INPC_OK) return st;
   }
   return join_sides(side, s, ns);

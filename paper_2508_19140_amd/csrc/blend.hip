@@ -747,13 +747,62 @@ __device__ __forceinline__ void blend_fwd_bilinear8_tile(const BlendArgs& a, uin
 // ---------------------------------------------------------------------------
 // Forward, screen-space Gaussians (inference)
 // ---------------------------------------------------------------------------
+// A staged Gaussian copy: s_g0 = (u, v, opacity, s2) and s_g1 = (cut
+// threshold, packed (px0, py0), packed (px1, py1), -) for a screen-space
+// Gaussian; s_g0 = (u, v, opacity, conic A) and s_g1 = (conic B, packed
+// corners, conic C) for a world-space one (cut at cutoff^2, the same for
+// every copy).
+__device__ __forceinline__ void stage_gauss(const BlendArgs& a, bool ewa, float4 p,
+                                            float4* __restrict__ g0, float4* __restrict__ g1) {
+  const Footprint f = footprint(a.opts, a.cam, p.x, p.y, p.w);
+  *g0 = make_float4(p.x, p.y, p.z, ewa ? f.ca : f.s2);
+  *g1 = make_float4(ewa ? f.cb : f.thr, __uint_as_float(pack_xy(f.px0, f.py0)),
+                    __uint_as_float(pack_xy(f.px1, f.py1)), f.cc);
+}
+
+// Whether pixel-centre offset (dx, dy) lies inside a staged Gaussian's cut,
+// with the squared distance in its metric (FP32, one rounding per
+// operation, as in the projection).
+__device__ __forceinline__ bool gauss_inside(bool ewa, float thr_ewa, float4 g0, float4 g1,
+                                             float dx, float dy, float& d2) {
+  d2 = ewa ? gauss_d2(true, dx, dy, g0.w, g1.x, g1.w) : gauss_d2(false, dx, dy, 0.f, 0.f, 0.f);
+  return d2 <= (ewa ? thr_ewa : g1.x);
+}
+
+// Gaussian value w at squared distance d2 (the forward and the backward
+// evaluate the same expression, so the replay sees the forward's alphas).
+__device__ __forceinline__ float gauss_value(bool ewa, float d2, float s2) {
+  return expf(ewa ? -0.5f * d2 : -0.5f * d2 / s2);
+}
+
+// Largest `last` over the tile's pixels into st_tile[tile].
+template <int NW>
+__device__ __forceinline__ void write_tile_last(const BlendArgs& a, uint32_t tile, uint32_t last,
+                                                uint32_t* s_ml) {
+  const int tid = threadIdx.x;
+  uint32_t ml = last;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) ml = max(ml, (uint32_t)__shfl_xor((int)ml, o, 64));
+  if constexpr (NW == 1) {
+    if (tid == 0) a.st_tile[tile] = ml;
+  } else {
+    if ((tid & 63) == 0) s_ml[tid >> 6] = ml;
+    __syncthreads();
+    if (tid == 0) {
+      for (int w = 0; w < NW; ++w) ml = max(ml, s_ml[w]);
+      a.st_tile[tile] = ml;
+    }
+  }
+}
+
 template <int T, int CP, typename FT, bool FULL>
 __device__ __forceinline__ void blend_fwd_gauss_tile(const BlendArgs& a, uint32_t tile) {
   using G = TileGeom<T>;
   constexpr int NW = G::NW;
-  __shared__ float4 s_g0[G::CHUNK];  // u, v, o, s2
-  __shared__ float4 s_g1[G::CHUNK];  // thr, packed (px0, py0), packed (px1, py1), -
+  __shared__ float4 s_g0[G::CHUNK];
+  __shared__ float4 s_g1[G::CHUNK];
   __shared__ __align__(16) float s_feat[G::CHUNK * fpad(CP)];
+  __shared__ uint32_t s_ml[NW];
 
   const int tid = threadIdx.x;
   const int tx = (int)(tile % (uint32_t)a.opts.ntx), ty = (int)(tile / (uint32_t)a.opts.ntx);
@@ -761,14 +810,16 @@ __device__ __forceinline__ void blend_fwd_gauss_tile(const BlendArgs& a, uint32_
   const bool inside = px < a.cam.W && py < a.cam.H;
   const uint32_t start = a.ranges[tile], end = a.ranges[tile + 1];
   const float t_min = a.opts.t_min;
+  const bool ewa = a.opts.splat == INPC_SPLAT_EWA;
+  const float thr_ewa = fmul(a.opts.cutoff, a.opts.cutoff);
   const float pxc = fadd((float)px, 0.5f), pyc = fadd((float)py, 0.5f);
   const bool stager = tid < G::CHUNK;
 
   float F[CP];
 #pragma unroll
   for (int c = 0; c < CP; ++c) F[c] = 0.f;
-  float Tr = 1.f;
-  uint32_t cnt = 0;
+  float Tr = 1.f, t_anchor = 1.f;
+  uint32_t cnt = 0, last = 0, anchor = 0;
   bool done = !inside;
 
   Prefetch<CP, FT, FULL> pf;
@@ -786,11 +837,7 @@ __device__ __forceinline__ void blend_fwd_gauss_tile(const BlendArgs& a, uint32_
     if (!tile_any<NW>(!done)) break;
     const uint32_t nh = min((uint32_t)G::CHUNK, end - base);
     if (pf.valid) {
-      const Footprint f = gaussian_footprint(pf.p.x, pf.p.y, pf.p.w, a.cam.W, a.cam.H,
-                                             a.opts.dilation, a.opts.cutoff);
-      s_g0[tid] = make_float4(pf.p.x, pf.p.y, pf.p.z, f.s2);
-      s_g1[tid] = make_float4(f.thr, __uint_as_float(pack_xy(f.px0, f.py0)),
-                              __uint_as_float(pack_xy(f.px1, f.py1)), 0.f);
+      stage_gauss(a, ewa, pf.p, &s_g0[tid], &s_g1[tid]);
       pf.f.store_f32(s_feat + tid * fpad(CP));
     }
     pf.fetch(a, nv, nidx);
@@ -804,14 +851,13 @@ __device__ __forceinline__ void blend_fwd_gauss_tile(const BlendArgs& a, uint32_
         if (px < unpack_x(lo) || px > unpack_x(hi) || py < unpack_y(lo) || py > unpack_y(hi))
           continue;
         const float4 g0 = s_g0[kk];
-        const float dx = fsub(pxc, g0.x), dy = fsub(pyc, g0.y);
-        const float d2 = fadd(fmul(dx, dx), fmul(dy, dy));
-        if (!(d2 <= g1.x)) continue;
+        float d2;
+        if (!gauss_inside(ewa, thr_ewa, g0, g1, fsub(pxc, g0.x), fsub(pyc, g0.y), d2)) continue;
         if (Tr < t_min) {
           done = true;
           break;
         }
-        const float al = g0.z * expf(-0.5f * d2 / g0.w);
+        const float al = g0.z * gauss_value(ewa, d2, g0.w);
         const float wt = Tr * al;
         const float4* fr = reinterpret_cast<const float4*>(s_feat + kk * fpad(CP));
 #pragma unroll
@@ -822,12 +868,19 @@ __device__ __forceinline__ void blend_fwd_gauss_tile(const BlendArgs& a, uint32_
           F[4 * q + 2] = fmaf(wt, f4.z, F[4 * q + 2]);
           F[4 * q + 3] = fmaf(wt, f4.w, F[4 * q + 3]);
         }
+        const uint32_t q1 = base - start + kk + 1u;
+        if (Tr > 0.f) {
+          anchor = q1;
+          t_anchor = Tr;
+        }
         Tr = fmul(Tr, fsub(1.f, al));
         ++cnt;
+        last = q1;
       }
     }
     tile_sync<NW>();
   }
+  if (a.st_tile) write_tile_last<NW>(a, tile, last, s_ml);
   if (!inside) return;
   const int64_t P = (int64_t)a.cam.W * a.cam.H;
   const int64_t p = (int64_t)py * a.cam.W + px;
@@ -836,6 +889,11 @@ __device__ __forceinline__ void blend_fwd_gauss_tile(const BlendArgs& a, uint32_
     if (c < a.C) a.out[c * P + p] = a.bg ? fmaf(Tr, bg_value(a, c, P, p), F[c]) : F[c];
   a.t_final[p] = Tr;
   a.n_contrib[p] = cnt;
+  if (a.st_last) {
+    a.st_last[p] = last;
+    a.st_anchor[p] = anchor;
+    a.st_tanchor[p] = t_anchor;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1453,6 +1511,354 @@ __device__ __forceinline__ void blend_bwd_bilinear8_tile(const BlendArgs& a, uin
 // (view, tile) slot of a batch's queue
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// Backward, Gaussian splats
+// ---------------------------------------------------------------------------
+//
+// Every pixel replays its blended fragments back to front as above.  A
+// Gaussian copy covers many pixels of the tile, so its gradient is a sum over
+// them: the pixels step through a chunk's copies together (back to front),
+// and for each copy every wavefront sums its lanes' terms with cross-lane
+// adds (skipped when none of its lanes blended the copy), leaving one row of
+// sums per copy in LDS.  The copy's thread then adds the wavefronts' rows,
+// chains the world-space terms through the projected covariance to (u, v, Z)
+// and writes the point's gradient (a point inside this tile only) or adds
+// this tile's share with float atomics.
+//
+// Per fragment, with e = w dL/dalpha and d = (px + 1/2 - u, py + 1/2 - v):
+//   dL/do += e;  screen-space (s2 = r^2 + dilation): dL/du += o e dx / s2,
+//   dL/dv += o e dy / s2;  world-space (conic [[A, B], [B, C]] = S^-1):
+//   dL/du += o e (A dx + B dy), dL/dv += o e (B dx + C dy) through the offset,
+//   dL/dA += -o e dx^2 / 2, dL/dB += -o e dx dy, dL/dC += -o e dy^2 / 2,
+// and per copy (A, B, C) -> covariance (a, b, c) -> (u, v, Z) by the chain
+// rule, the covariance a function of u, v through X/Z, Y/Z and of Z through
+// fx/Z, fy/Z.
+
+// x from the lane DPP control CTRL selects, in the rows ROWS enables (0 in
+// the others).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_src(float x) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xF, false));
+}
+
+// Sum of v over the 64 lanes of a wavefront, valid in lane 63 (every lane
+// must be active): lane pairs and quads by quad permutes, half rows and rows
+// of 16 by mirrors, then rows 0 + 1 and 2 + 3 by the broadcast of lane 15 of
+// each row, and all four by the broadcast of lane 31.
+__device__ __forceinline__ float wave_sum_last(float v) {
+  v += dpp_src<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_src<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_src<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_src<0x140, 0xF>(v);  // row_mirror
+  v += dpp_src<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_src<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+// This tile's gradient share of every Gaussian copy of the wavefront with
+// `mine` set, added to the point's gradient with float atomics: staged as
+// rows of CP + 8 floats (features, dL/do, dL/du, dL/dv, dL/dZ, point index)
+// in `tr` (512 floats owned by this wavefront), then each group of CP lanes
+// adds one row, so that one atomic instruction covers 64 / CP point rows.
+// The scalar row gets its first `nsc` components added (3, or 4 with dL/dZ).
+template <int CP>
+__device__ __forceinline__ void add_gauss_shares(bool mine, uint32_t idx, const float (&g)[CP],
+                                                 float4 sc, uint32_t nsc,
+                                                 float* __restrict__ tr, const BlendArgs& a) {
+  constexpr uint32_t RS = CP + 8;
+  constexpr uint32_t ROWS = 512 / RS;
+  constexpr uint32_t PER = 64 / CP;
+  const uint64_t m = __ballot(mine);
+  if (m == 0ull) return;
+  const uint32_t lane = __lane_id();
+  const uint32_t total = (uint32_t)__popcll(m);
+  const uint32_t r = mbcnt64(m);
+  const uint32_t C = (uint32_t)a.C;
+  for (uint32_t b0 = 0; b0 < total; b0 += ROWS) {
+    const uint32_t nb = min(total - b0, ROWS);
+    if (mine && r >= b0 && r < b0 + nb) {
+      float4* d = reinterpret_cast<float4*>(tr + (r - b0) * RS);
+#pragma unroll
+      for (int q = 0; q < CP / 4; ++q)
+        d[q] = make_float4(g[4 * q], g[4 * q + 1], g[4 * q + 2], g[4 * q + 3]);
+      d[CP / 4] = sc;
+      d[CP / 4 + 1] = make_float4(__uint_as_float(idx), 0.f, 0.f, 0.f);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // every LDS read of the batch is issued before its first atomic
+    constexpr uint32_t IT = (ROWS + PER - 1) / PER;  // feature rows per lane
+    constexpr uint32_t IS = (4 * ROWS + 63) / 64;    // scalar slots per lane
+    const uint32_t c = lane % CP;
+    uint32_t fp[IT], sp[IS];
+    float fv[IT], sv[IS];
+#pragma unroll
+    for (uint32_t it = 0; it < IT; ++it) {
+      const uint32_t row = lane / CP + it * PER;
+      const bool ok = c < C && row < nb;
+      fp[it] = ok ? __float_as_uint(tr[row * RS + CP + 4]) : 0u;
+      fv[it] = ok ? tr[row * RS + c] : 0.f;
+    }
+#pragma unroll
+    for (uint32_t is = 0; is < IS; ++is) {
+      const uint32_t k = lane + 64u * is, row = k >> 2, comp = k & 3u;
+      const bool ok = row < nb && comp < nsc;
+      sp[is] = ok ? __float_as_uint(tr[row * RS + CP + 4]) : 0u;
+      sv[is] = ok ? tr[row * RS + CP + comp] : 0.f;
+    }
+#pragma unroll
+    for (uint32_t it = 0; it < IT; ++it)
+      if (c < C && lane / CP + it * PER < nb)
+        atomicAdd(a.grad_feat + (size_t)fp[it] * C + c, fv[it]);
+#pragma unroll
+    for (uint32_t is = 0; is < IS; ++is) {
+      const uint32_t k = lane + 64u * is;
+      if ((k >> 2) < nb && (k & 3u) < nsc)
+        atomicAdd(reinterpret_cast<float*>(a.gsc + sp[is]) + (k & 3u), sv[is]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+template <int T, int CP, typename FT, bool FULL>
+__device__ __forceinline__ void blend_bwd_gauss_tile(const BlendArgs& a, uint32_t tile) {
+  using G = TileGeom<T>;
+  constexpr int NW = G::NW, CH = 64, SH = G::SH;
+  // per (wavefront, copy): CP feature sums, then e, e du, e dv, e dx^2,
+  // e dx dy, e dy^2 (see above) and whether the wavefront blended the copy
+  constexpr int RS = CP + 8;
+  __shared__ float4 s_g0[CH];
+  __shared__ float4 s_g1[CH];
+  __shared__ __align__(16) float s_feat[CH * fpad(CP)];
+  __shared__ __align__(16) float s_part[NW * CH * RS];
+  __shared__ float s_red[NW][CP];
+
+  const int tid = threadIdx.x;
+  const uint32_t lane = __lane_id();
+  const int tx = (int)(tile % (uint32_t)a.opts.ntx), ty = (int)(tile / (uint32_t)a.opts.ntx);
+  const int px = tx * T + tid % T, py = ty * T + tid / T;
+  const bool inside = px < a.cam.W && py < a.cam.H;
+  const uint32_t start = a.ranges[tile], end = a.ranges[tile + 1];
+  const int64_t P = (int64_t)a.cam.W * a.cam.H;
+  const int64_t p = (int64_t)py * a.cam.W + px;
+  const int C = a.C;
+  const bool ewa = a.opts.splat == INPC_SPLAT_EWA;
+  const float thr_ewa = fmul(a.opts.cutoff, a.opts.cutoff);
+  const float pxc = fadd((float)px, 0.5f), pyc = fadd((float)py, 0.5f);
+  const bool stager = tid < CH;
+
+  float Gv[CP];
+  float gB = 0.f, GT = 0.f, Tf = 0.f, t_anchor = 0.f;
+  uint32_t last = 0, anchor = 0;
+#pragma unroll
+  for (int c = 0; c < CP; ++c) Gv[c] = (inside && c < C) ? a.grad_out[c * P + p] : 0.f;
+  if (inside) {
+    GT = a.grad_t ? a.grad_t[p] : 0.f;
+    last = a.st_last[p];
+    anchor = a.st_anchor[p];
+    t_anchor = a.st_tanchor[p];
+    Tf = a.t_final[p];
+    if (a.bg)
+      for (int c = 0; c < C; ++c) gB = fmaf(Gv[c], bg_value(a, c, P, p), gB);
+    if (a.bg_image && a.grad_bg)  // dL/df_bg(pixel) = T_final G
+      for (int c = 0; c < C; ++c) a.grad_bg[c * P + p] = Tf * Gv[c];
+  }
+  if (a.bg_partial) {  // background: this tile's share of sum_p T_final G
+#pragma unroll
+    for (int c = 0; c < CP; ++c) {
+      float v = Tf * Gv[c];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if ((tid & 63) == 0) s_red[tid >> 6][c] = v;
+    }
+    __syncthreads();
+    if (tid < C) {
+      float v = 0.f;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) v += s_red[w][tid];
+      a.bg_partial[(size_t)tile * C + tid] = v;
+    }
+  }
+
+  // the forward pass blended nothing beyond list position st_tile[tile]
+  const uint32_t maxlast = min(a.st_tile[tile], end - start);
+  const int nchunks = (int)((maxlast + CH - 1) / CH);
+  auto list_at = [&](uint32_t q) { return a.list[q < end ? q : end - 1]; };
+
+  Prefetch<CP, FT, FULL> pf;
+  pf.valid = false;
+  if (nchunks > 0) {
+    const uint32_t rb0 = (uint32_t)(nchunks - 1) * CH;
+    pf.fetch(a, stager && rb0 + tid < maxlast, list_at(start + rb0 + tid));
+  }
+
+  float Pi = 1.f, Tcur = 0.f;
+  float* const part = s_part + (tid >> 6) * CH * RS;  // this wavefront's rows
+  for (int ci = nchunks - 1; ci >= 0; --ci) {
+    const uint32_t rb = (uint32_t)ci * CH;
+    const int nh = (int)min((uint32_t)CH, maxlast - rb);
+    const bool cur = pf.valid;
+    const uint32_t cur_idx = pf.idx;
+    const float4 cur_p = pf.p;
+    if (cur) {
+      stage_gauss(a, ewa, pf.p, &s_g0[tid], &s_g1[tid]);
+      pf.f.store_f32(s_feat + tid * fpad(CP));
+    }
+    if (ci >= 1) pf.fetch(a, stager, list_at(start + rb - CH + tid));
+    tile_sync<NW>();
+    for (int kk = nh - 1; kk >= 0; --kk) {
+      const uint32_t q1 = rb + (uint32_t)kk + 1u;  // one past the relative position
+      float ta = 0.f, e = 0.f, su = 0.f, sv = 0.f, sxx = 0.f, sxy = 0.f, syy = 0.f;
+      bool has = false;
+      if (q1 <= last) {
+        const float4 g1 = s_g1[kk];
+        const uint32_t lo = __float_as_uint(g1.y), hi = __float_as_uint(g1.z);
+        if (px >= unpack_x(lo) && px <= unpack_x(hi) && py >= unpack_y(lo) &&
+            py <= unpack_y(hi)) {
+          const float4 g0 = s_g0[kk];
+          const float dx = fsub(pxc, g0.x), dy = fsub(pyc, g0.y);
+          float d2;
+          if (gauss_inside(ewa, thr_ewa, g0, g1, dx, dy, d2)) {
+            const float w = gauss_value(ewa, d2, g0.w);
+            const float al = g0.z * w;
+            const float om = fsub(1.f, al);
+            float Tk;
+            if (q1 > anchor)
+              Tk = 0.f;
+            else if (q1 == anchor)
+              Tk = t_anchor;
+            else
+              Tk = __fdividef(Tcur, om);
+            const float4* fr = reinterpret_cast<const float4*>(s_feat + kk * fpad(CP));
+            float gf = 0.f;
+#pragma unroll
+            for (int q = 0; q < CP / 4; ++q) {
+              const float4 f4 = fr[q];
+              gf = fmaf(Gv[4 * q], f4.x, gf);
+              gf = fmaf(Gv[4 * q + 1], f4.y, gf);
+              gf = fmaf(Gv[4 * q + 2], f4.z, gf);
+              gf = fmaf(Gv[4 * q + 3], f4.w, gf);
+            }
+            const float da = Tk * (gf - gB) - GT * Tk * Pi;
+            ta = Tk * al;
+            e = da * w;
+            if (ewa) {
+              su = e * (g0.w * dx + g1.x * dy);
+              sv = e * (g1.x * dx + g1.w * dy);
+              sxx = e * (dx * dx);
+              sxy = e * (dx * dy);
+              syy = e * (dy * dy);
+            } else {
+              su = e * dx;
+              sv = e * dy;
+            }
+            gB = fmaf(al, gf, om * gB);
+            Pi = Pi * om;
+            Tcur = Tk;
+            has = true;
+          }
+        }
+      }
+      float4* row = reinterpret_cast<float4*>(part + kk * RS);
+      if (__ballot(has) != 0ull) {  // uniform over the wavefront: every lane takes part
+#pragma unroll
+        for (int q = 0; q < CP / 4; ++q) {
+          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (4 * q < C) {
+            v.x = wave_sum_last(ta * Gv[4 * q]);
+            v.y = wave_sum_last(ta * Gv[4 * q + 1]);
+            v.z = wave_sum_last(ta * Gv[4 * q + 2]);
+            v.w = wave_sum_last(ta * Gv[4 * q + 3]);
+          }
+          if (lane == 63u) row[q] = v;
+        }
+        const float r0 = wave_sum_last(e), r1 = wave_sum_last(su), r2 = wave_sum_last(sv);
+        float r3 = 0.f, r4 = 0.f, r5 = 0.f;
+        if (ewa) {
+          r3 = wave_sum_last(sxx);
+          r4 = wave_sum_last(sxy);
+          r5 = wave_sum_last(syy);
+        }
+        if (lane == 63u) {
+          row[CP / 4] = make_float4(r0, r1, r2, r3);
+          row[CP / 4 + 1] = make_float4(r4, r5, 1.f, 0.f);
+        }
+      } else if (lane == 63u) {
+        row[CP / 4 + 1] = make_float4(0.f, 0.f, 0.f, 0.f);  // not blended here
+      }
+    }
+    tile_sync<NW>();
+    // the copy's thread: its rows summed over the wavefronts, chained, written
+    float gfeat[CP];
+#pragma unroll
+    for (int c = 0; c < CP; ++c) gfeat[c] = 0.f;
+    float4 sc = make_float4(0.f, 0.f, 0.f, 0.f);
+    bool touched = false, single = false;
+    if (cur) {
+      float S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const float4* r = reinterpret_cast<const float4*>(s_part + (w * CH + tid) * RS);
+        const float4 t1 = r[CP / 4 + 1];
+        if (t1.z == 0.f) continue;  // this wavefront did not blend the copy
+        touched = true;
+#pragma unroll
+        for (int q = 0; q < CP / 4; ++q) {
+          const float4 f4 = r[q];
+          gfeat[4 * q] += f4.x;
+          gfeat[4 * q + 1] += f4.y;
+          gfeat[4 * q + 2] += f4.z;
+          gfeat[4 * q + 3] += f4.w;
+        }
+        const float4 t0 = r[CP / 4];
+        S[0] += t0.x; S[1] += t0.y; S[2] += t0.z; S[3] += t0.w;
+        S[4] += t1.x; S[5] += t1.y;
+      }
+      const float o = cur_p.z;
+      const float4 g0 = s_g0[tid], g1 = s_g1[tid];
+      float gu, gv, gz = 0.f;
+      if (!ewa) {
+        gu = o * S[1] / g0.w;
+        gv = o * S[2] / g0.w;
+      } else {
+        const EwaCov k = ewa_cov(cur_p.x, cur_p.y, cur_p.w, a.cam, a.opts.dilation,
+                                 a.opts.ewa_sigma);
+        const float gA = -0.5f * o * S[3], gBc = -o * S[4], gC = -0.5f * o * S[5];
+        const float inv = 1.f / (k.a * k.c - k.b * k.b);
+        const float ga = (-k.c * k.c * gA + k.b * k.c * gBc - k.b * k.b * gC) * inv * inv;
+        const float gb = (2.f * k.b * k.c * gA - (k.a * k.c + k.b * k.b) * gBc +
+                          2.f * k.a * k.b * gC) * inv * inv;
+        const float gc = (-k.b * k.b * gA + k.a * k.b * gBc - k.a * k.a * gC) * inv * inv;
+        const float kxx = k.s2w * k.jx * k.jx, kxy = k.s2w * k.jx * k.jy,
+                    kyy = k.s2w * k.jy * k.jy;
+        gu = o * S[1] + (ga * kxx * 2.f * k.xh + gb * kxy * k.yh) / a.cam.fx;
+        gv = o * S[2] + (gb * kxy * k.xh + gc * kyy * 2.f * k.yh) / a.cam.fy;
+        gz = -2.f / cur_p.w *
+             (ga * kxx * (1.f + k.xh * k.xh) + gb * kxy * (k.xh * k.yh) +
+              gc * kyy * (1.f + k.yh * k.yh));
+      }
+      sc = make_float4(S[0], gu, gv, gz);
+      const uint32_t lo = __float_as_uint(g1.y), hi = __float_as_uint(g1.z);
+      single = (unpack_x(lo) >> SH) == (unpack_x(hi) >> SH) &&
+               (unpack_y(lo) >> SH) == (unpack_y(hi) >> SH);
+      if (touched && single) {  // the only tile of this point: its whole gradient
+        store_row<CP>(a.grad_feat + (size_t)cur_idx * C, gfeat, C);
+        a.gsc[cur_idx] = sc;
+      }
+    }
+    // split points: this tile's share by float atomics, staged in the first
+    // wavefront's rows (only it holds copies; its reads above are done)
+    if (tid < 64)
+      add_gauss_shares<CP>(cur && touched && !single, cur_idx, gfeat, sc, ewa ? 4u : 3u,
+                           s_part, a);
+    tile_sync<NW>();
+  }
+}
+
 template <int T, int CP, typename FT, bool FULL>
 __global__ __launch_bounds__(T* T) void k_blend_fwd_bilinear(BlendArgs a) {
   if (a.flags[kFlagOverflow]) return;
@@ -1517,6 +1923,22 @@ __global__ __launch_bounds__(T* T) void k_blend_bwd_bilinear_batched(const Blend
   blend_bwd_bilinear_tile<T, CP, FT, FULL>(a, a.order[__builtin_amdgcn_readfirstlane(vk.y)]);
 }
 
+template <int T, int CP, typename FT, bool FULL>
+__global__ __launch_bounds__(T* T) void k_blend_bwd_gauss(BlendArgs a) {
+  if (a.flags[kFlagOverflow]) return;
+  blend_bwd_gauss_tile<T, CP, FT, FULL>(a, block_tile(a));
+}
+template <int T, int CP, typename FT, bool FULL>
+__global__ __launch_bounds__(T* T) void k_blend_bwd_gauss_batched(const BlendArgs* __restrict__ args,
+                                                              const uint2* __restrict__ items) {
+  const uint2 vk = items[xcd_pos(blockIdx.x, gridDim.x)];
+  const uint32_t v = __builtin_amdgcn_readfirstlane(vk.x);
+  if (v == kNoItem) return;  // padding of a view's last quad
+  const BlendArgs& a = args[v];  // read-only for the whole kernel: scalar loads
+  if (a.flags[kFlagOverflow]) return;
+  blend_bwd_gauss_tile<T, CP, FT, FULL>(a, a.order[__builtin_amdgcn_readfirstlane(vk.y)]);
+}
+
 template <int CP, typename FT, bool FULL>
 __global__ __launch_bounds__(64) void k_blend_bwd_bilinear8(BlendArgs a) {
   if (a.flags[kFlagOverflow]) return;
@@ -1558,15 +1980,17 @@ __global__ __launch_bounds__(256) void k_zero(float* __restrict__ p0, size_t n0,
   if (p1) zero_range(p1, n1, tid, stride);
 }
 
-// grad_opacity and grad_uv from the per-point scalar rows.
+// grad_opacity, grad_uv and grad_z (if wanted) from the per-point scalar rows.
 __global__ __launch_bounds__(256) void k_unpack_scalars(const float4* __restrict__ gsc, int64_t n,
                                                         float* __restrict__ go,
-                                                        float2* __restrict__ guv) {
+                                                        float2* __restrict__ guv,
+                                                        float* __restrict__ gz) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const float4 v = gsc[i];
     go[i] = v.x;
     guv[i] = make_float2(v.y, v.z);
+    if (gz) gz[i] = v.w;
   }
 }
 
@@ -1630,7 +2054,7 @@ hipError_t bwd_post(const BlendArgs& a, hipStream_t s) {
   if (a.n > 0) {
     const int64_t g = std::min<int64_t>((a.n + 255) / 256, 1 << 16);
     hipLaunchKernelGGL(k_unpack_scalars, dim3((unsigned)g), dim3(256), 0, s, a.gsc, a.n,
-                       a.grad_opacity, reinterpret_cast<float2*>(a.grad_uv));
+                       a.grad_opacity, reinterpret_cast<float2*>(a.grad_uv), a.grad_z);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -1645,7 +2069,13 @@ hipError_t bwd_launch(const BlendArgs& a, hipStream_t s) {
   const int64_t nt = (int64_t)a.opts.ntx * a.opts.nty;
   hipError_t e = bwd_pre(a, s);
   if (e != hipSuccess) return e;
-  if (T == 8 && a.C == CP)
+  if (a.opts.splat != INPC_SPLAT_BILINEAR && a.C == CP)
+    hipLaunchKernelGGL((k_blend_bwd_gauss<T, CP, FT, true>), dim3((unsigned)nt), dim3(T * T), 0, s,
+                       a);
+  else if (a.opts.splat != INPC_SPLAT_BILINEAR)
+    hipLaunchKernelGGL((k_blend_bwd_gauss<T, CP, FT, false>), dim3((unsigned)nt), dim3(T * T), 0,
+                       s, a);
+  else if (T == 8 && a.C == CP)
     hipLaunchKernelGGL((k_blend_bwd_bilinear8<CP, FT, true>), dim3((unsigned)nt), dim3(64), 0, s,
                        a);
   else if (T == 8)
@@ -1688,6 +2118,9 @@ hipError_t fwd_launch_q(const BlendArgs& a, const BatchQueue& q, hipStream_t s) 
 template <int T, int CP, typename FT>
 hipError_t bwd_launch_q(const BlendArgs& a, const BatchQueue& q, hipStream_t s) {
   const bool full = a.C == CP;
+  if (a.opts.splat != INPC_SPLAT_BILINEAR)
+    return full ? launch_queue(k_blend_bwd_gauss_batched<T, CP, FT, true>, T * T, q, s)
+                : launch_queue(k_blend_bwd_gauss_batched<T, CP, FT, false>, T * T, q, s);
   if (T == 8)
     return full ? launch_queue(k_blend_bwd_bilinear8_batched<CP, FT, true>, 64, q, s)
                 : launch_queue(k_blend_bwd_bilinear8_batched<CP, FT, false>, 64, q, s);

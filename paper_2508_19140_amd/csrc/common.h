@@ -55,6 +55,7 @@ struct Opts {
   int T;     // tile edge
   int ntx, nty;
   float t_min, dilation, cutoff;
+  float ewa_sigma;  // world-space Gaussians: standard deviation in world units
 };
 
 // Workspace flag slots.
@@ -160,6 +161,8 @@ struct Footprint {
   float a, b;
   // Gaussian
   float s2, thr;
+  // world-space Gaussian: inverse of the projected covariance (conic)
+  float ca, cb, cc;
 };
 
 // Bilinear 2x2 splat: the four pixels whose centres surround (u, v).
@@ -169,6 +172,7 @@ __device__ __forceinline__ Footprint bilinear_footprint(float u, float v, int W,
   f.visible = (u >= -0.5f) && (u < fadd(Wf, 0.5f)) && (v >= -0.5f) && (v < fadd(Hf, 0.5f));
   f.s2 = 0.f;
   f.thr = 0.f;
+  f.ca = f.cb = f.cc = 0.f;
   if (!f.visible) {
     f.px0 = f.py0 = 0; f.px1 = f.py1 = -1; f.x0 = f.y0 = 0; f.a = f.b = 0.f;
     return f;
@@ -193,6 +197,7 @@ __device__ __forceinline__ Footprint gaussian_footprint(float u, float v, float 
   Footprint f;
   f.x0 = f.y0 = 0;
   f.a = f.b = 0.f;
+  f.ca = f.cb = f.cc = 0.f;
   const float s2 = fadd(fmul(r, r), dilation);
   const float Rc = fmul(cutoff, fsqrt(s2));
   const float xs = fsub(u, 0.5f), ys = fsub(v, 0.5f);
@@ -214,11 +219,84 @@ __device__ __forceinline__ Footprint gaussian_footprint(float u, float v, float 
   return f;
 }
 
+// World-space isotropic Gaussian of standard deviation sigma, projected with
+// the affine (EWA) approximation of the perspective map: covariance
+// sigma^2 J J^T plus the dilation, J the projection's Jacobian at the point.
+// With xh = (u - cx) / fx, yh = (v - cy) / fy (= X/Z, Y/Z), jx = fx / Z,
+// jy = fy / Z:  a = sigma^2 jx^2 (1 + xh^2) + dil, b = sigma^2 jx jy xh yh,
+// c = sigma^2 jy^2 (1 + yh^2) + dil.  Computed from the FP32 u, v, Z (the
+// projection record) with one rounding per operation, so the blend passes
+// recompute exactly the projection's decisions.  Cut where the Mahalanobis
+// distance exceeds `cutoff`; candidates are the ellipse's bounding box,
+// |dx| <= cutoff sqrt(a), |dy| <= cutoff sqrt(c).
+struct EwaCov {
+  float xh, yh, jx, jy, s2w;  // X/Z, Y/Z, fx/Z, fy/Z, sigma^2
+  float a, b, c;              // projected covariance [[a, b], [b, c]], dilation included
+};
+__device__ __forceinline__ EwaCov ewa_cov(float u, float v, float Z, const Cam& c, float dilation,
+                                          float sigma) {
+  EwaCov k;
+  k.xh = fdiv(fsub(u, c.cx), c.fx);
+  k.yh = fdiv(fsub(v, c.cy), c.fy);
+  k.jx = fdiv(c.fx, Z);
+  k.jy = fdiv(c.fy, Z);
+  k.s2w = fmul(sigma, sigma);
+  k.a = fadd(fmul(k.s2w, fmul(fmul(k.jx, k.jx), fadd(1.f, fmul(k.xh, k.xh)))), dilation);
+  k.b = fmul(k.s2w, fmul(fmul(k.jx, k.jy), fmul(k.xh, k.yh)));
+  k.c = fadd(fmul(k.s2w, fmul(fmul(k.jy, k.jy), fadd(1.f, fmul(k.yh, k.yh)))), dilation);
+  return k;
+}
+
+__device__ __forceinline__ Footprint ewa_footprint(float u, float v, float Z, const Cam& c,
+                                                   float dilation, float cutoff, float sigma) {
+  Footprint f;
+  f.x0 = f.y0 = 0;
+  f.a = f.b = 0.f;
+  f.s2 = 0.f;
+  const EwaCov k = ewa_cov(u, v, Z, c, dilation, sigma);
+  const float a = k.a, b = k.b, cc = k.c;
+  const float det = fsub(fmul(a, cc), fmul(b, b));
+  f.ca = fdiv(cc, det);
+  f.cb = -fdiv(b, det);
+  f.cc = fdiv(a, det);
+  const float Rx = fmul(cutoff, fsqrt(a)), Ry = fmul(cutoff, fsqrt(cc));
+  const float xs = fsub(u, 0.5f), ys = fsub(v, 0.5f);
+  float lx = ceilf(fsub(xs, Rx)), hx = floorf(fadd(xs, Rx));
+  float ly = ceilf(fsub(ys, Ry)), hy = floorf(fadd(ys, Ry));
+  lx = lx < 0.f ? 0.f : lx;
+  ly = ly < 0.f ? 0.f : ly;
+  hx = hx > (float)(c.W - 1) ? (float)(c.W - 1) : hx;
+  hy = hy > (float)(c.H - 1) ? (float)(c.H - 1) : hy;
+  f.visible = (lx <= hx) && (ly <= hy);
+  if (!f.visible) {
+    f.px0 = f.py0 = 0; f.px1 = f.py1 = -1; f.thr = 0.f;
+    return f;
+  }
+  f.px0 = (int)lx; f.px1 = (int)hx;
+  f.py0 = (int)ly; f.py1 = (int)hy;
+  f.thr = fmul(cutoff, cutoff);
+  return f;
+}
+
+// Footprint of a point from its projection record: w is the screen-space
+// radius (Gaussian) or the camera-space depth Z (world-space Gaussian).
 __device__ __forceinline__ Footprint footprint(const Opts& o, const Cam& c, float u, float v,
-                                               float r) {
-  return o.splat == INPC_SPLAT_BILINEAR ? bilinear_footprint(u, v, c.W, c.H)
-                                        : gaussian_footprint(u, v, r, c.W, c.H, o.dilation,
-                                                             o.cutoff);
+                                               float w) {
+  if (o.splat == INPC_SPLAT_BILINEAR) return bilinear_footprint(u, v, c.W, c.H);
+  if (o.splat == INPC_SPLAT_EWA) return ewa_footprint(u, v, w, c, o.dilation, o.cutoff,
+                                                      o.ewa_sigma);
+  return gaussian_footprint(u, v, w, c.W, c.H, o.dilation, o.cutoff);
+}
+
+// Squared distance of pixel centre offset (dx, dy) = (px + 1/2 - u, py + 1/2 - v)
+// in the Gaussian's metric, FP32 with one rounding per operation: Euclidean
+// (screen-space Gaussian; compared with cutoff^2 s2) or Mahalanobis through
+// the conic (world-space; compared with cutoff^2).
+__device__ __forceinline__ float gauss_d2(bool ewa, float dx, float dy, float ca, float cb,
+                                          float cc) {
+  if (!ewa) return fadd(fmul(dx, dx), fmul(dy, dy));
+  return fadd(fadd(fmul(ca, fmul(dx, dx)), fmul(fmul(2.f, cb), fmul(dx, dy))),
+              fmul(cc, fmul(dy, dy)));
 }
 
 // Position in a tile order handled by workgroup b of an nb-workgroup launch.

@@ -12,7 +12,7 @@ struct BlendArgs {
   Cam cam;
   Opts opts;
   int64_t n;
-  const float* proj;  // [n][4] (u, v, opacity, radius)
+  const float* proj;  // [n][4] (u, v, opacity, radius | depth Z | 0)
   const void* feat;
   int C;
   int dtype;
@@ -37,10 +37,12 @@ struct BlendArgs {
   float* grad_feat;
   float* grad_opacity;
   float* grad_uv;
+  float* grad_z;      // [n] dL/dZ at fixed (u, v) (world-space Gaussians), or NULL
   float* grad_bg;     // [C], or [C][H][W] when bg_image (written per pixel)
   float* bg_partial;  // [num_tiles][C] per-tile background gradients (constant background)
-  float4* gsc;        // [n] (dL/do, dL/du, dL/dv, -) per point, unpacked into grad_opacity
-                      // and grad_uv at the end (one 16-byte row per point for the atomics)
+  float4* gsc;        // [n] (dL/do, dL/du, dL/dv, dL/dZ) per point, unpacked into
+                      // grad_opacity, grad_uv and grad_z at the end (one 16-byte row per
+                      // point for the atomics)
   const uint32_t* flags;
 };
 
@@ -101,6 +103,7 @@ __host__ __device__ inline BlendArgs make_view_args(const inpc_view_t& w, const 
   a.grad_feat = w.grad_feat;
   a.grad_opacity = w.grad_opacity;
   a.grad_uv = w.grad_uv;
+  a.grad_z = w.grad_z;
   a.grad_bg = w.grad_bg;
   a.gsc = static_cast<float4*>(w.scratch);
   // the scratch holds a 16-byte row per point (rounded up to 256 bytes),
@@ -156,7 +159,7 @@ hipError_t launch_sh_backward(const Cam& c, int64_t n, int C, const float* pos, 
                               const float* grad_feat, float* grad_sh, float* grad_pos,
                               hipStream_t s);
 hipError_t launch_project_backward(const Cam& cam, int64_t n, const float* pos,
-                                   const uint32_t* ntiles, const float* grad_uv, float* grad_pos,
-                                   hipStream_t s);
+                                   const uint32_t* ntiles, const float* grad_uv,
+                                   const float* grad_z, float* grad_pos, hipStream_t s);
 
 }  // namespace inpc

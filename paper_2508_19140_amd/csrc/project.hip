@@ -58,10 +58,13 @@ __device__ __forceinline__ TileRect project_one(const Cam& cam, const Opts& o, i
                                                 uint32_t* __restrict__ key,
                                                 uint32_t* __restrict__ ntiles) {
   const Proj p = project_point(cam, x, y, z);
+  // the record's last slot: the radius, or for world-space Gaussians the
+  // depth their projected covariance is recomputed from
+  const float w = o.splat == INPC_SPLAT_EWA ? p.Z : rad;
   Footprint f;
   f.visible = false;
-  if (p.in_front) f = footprint(o, cam, p.u, p.v, rad);
-  proj[i] = make_float4(p.u, p.v, op, rad);
+  if (p.in_front) f = footprint(o, cam, p.u, p.v, w);
+  proj[i] = make_float4(p.u, p.v, op, w);
   key[i] = __float_as_uint(p.Z);
   const TileRect r = tile_rect(f, sh);
   ntiles[i] = r.count();
@@ -475,6 +478,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(Cam cam, int64_t n,
                                                         const float* __restrict__ pos,
                                                         const uint32_t* __restrict__ ntiles,
                                                         const float2* __restrict__ grad_uv,
+                                                        const float* __restrict__ grad_z,
                                                         float* __restrict__ grad_pos) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -485,7 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(Cam cam, int64_t n,
       const float iz = 1.0f / p.Z;
       const float gx = g.x * cam.fx * iz;
       const float gy = g.y * cam.fy * iz;
-      const float gz = -(gx * p.X + gy * p.Y) * iz;
+      const float gz = (grad_z ? grad_z[i] : 0.f) - (gx * p.X + gy * p.Y) * iz;
       g0 = cam.R[0] * gx + cam.R[3] * gy + cam.R[6] * gz;
       g1 = cam.R[1] * gx + cam.R[4] * gy + cam.R[7] * gz;
       g2 = cam.R[2] * gx + cam.R[5] * gy + cam.R[8] * gz;
@@ -575,11 +579,11 @@ hipError_t launch_bin(const Cam& cam, const Opts& o, int64_t n, const float* pro
 }
 
 hipError_t launch_project_backward(const Cam& cam, int64_t n, const float* pos,
-                                   const uint32_t* ntiles, const float* grad_uv, float* grad_pos,
-                                   hipStream_t s) {
+                                   const uint32_t* ntiles, const float* grad_uv,
+                                   const float* grad_z, float* grad_pos, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_project_bwd, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, cam, n, pos,
-                     ntiles, reinterpret_cast<const float2*>(grad_uv), grad_pos);
+                     ntiles, reinterpret_cast<const float2*>(grad_uv), grad_z, grad_pos);
   return hipGetLastError();
 }
 

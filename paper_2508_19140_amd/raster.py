@@ -6,14 +6,17 @@ rasterizer runs in the HIP library (libinpc_raster.so) through the C ABI.
     out, t_final, n_contrib = rasterize(pos, opacity, feat, camera)
 
 `rasterize` is differentiable with respect to positions, opacities, features
-and the background (bilinear splats).  The backward pass re-runs project /
-bin / sort instead of keeping the tile lists (set keep_lists=True to keep
-them), and reads only a 12-byte per-pixel state saved by the forward pass.
+and the background, for every splat kind (bilinear 2x2 splats, screen-space
+Gaussians of a given radius, world-space Gaussians projected with the EWA
+approximation).  The backward pass re-runs project / bin / sort instead of
+keeping the tile lists (set keep_lists=True to keep them), and reads only a
+12-byte per-pixel state saved by the forward pass.
 """
 from __future__ import annotations
 
 import ctypes
 import dataclasses
+import math
 from typing import NamedTuple, Optional
 
 import torch
@@ -23,21 +26,67 @@ from . import _lib as L
 _DTYPES = {torch.float32: L.DTYPE_F32, torch.float16: L.DTYPE_F16, torch.bfloat16: L.DTYPE_BF16}
 
 
+_SPLATS = {"bilinear": L.SPLAT_BILINEAR, "gaussian": L.SPLAT_GAUSSIAN, "ewa": L.SPLAT_EWA}
+
+
 @dataclasses.dataclass(frozen=True)
 class RasterSettings:
-    splat: str = "bilinear"     # or "gaussian" (forward only)
+    splat: str = "bilinear"     # "bilinear" (2x2 splats), "gaussian" (screen-space, per-point
+                                # radius in pixels) or "ewa" (world-space, one sigma)
     tile: int = 8               # 8, 16 or 32 pixels
     t_min: float = 1e-4         # blend fragment k iff transmittance in front of it >= t_min
     dilation: float = 0.16      # Gaussian dilation variance
     cutoff: float = 3.0         # Gaussian truncation in standard deviations
-    max_radius: float = 3.0     # largest Gaussian radius (px); sizes the workspace
+    max_radius: float = 3.0     # largest screen-space Gaussian radius (px); sizes the workspace
+                                # ("ewa" derives its bound from the camera and sigma)
     keep_lists: bool = False    # keep tile lists for the backward instead of recomputing
     bin_points: int = 0         # points per workgroup of the binning passes (0 = automatic)
+    ewa_sigma: float = 0.0      # "ewa": world-space standard deviation; 0 = the paper's
+                                # default, 5 px at the near plane through the image centre
+    ewa_px: float = 5.0         # that default's width in pixels
+    ewa_max_radius: float = 0.0  # "ewa": workspace bound on the projected standard deviation
+                                 # (px); 0 = derived from the camera and sigma
 
-    def opts(self, bg_per_pixel: bool = False) -> L.Opts:
-        splat = {"bilinear": L.SPLAT_BILINEAR, "gaussian": L.SPLAT_GAUSSIAN}[self.splat]
+    def sigma(self, cam: L.Camera) -> float:
+        """World-space standard deviation of "ewa" splats for this camera."""
+        if self.ewa_sigma > 0.0:
+            return float(self.ewa_sigma)
+        return self.ewa_px * float(cam.z_near) / max(float(cam.fx), float(cam.fy))
+
+    def opts(self, bg_per_pixel: bool = False, cam: Optional[L.Camera] = None) -> L.Opts:
+        splat = _SPLATS[self.splat]
+        max_radius, sigma = self.max_radius, 0.0
+        if splat == L.SPLAT_EWA:
+            if cam is None:
+                raise ValueError("world-space Gaussians need the camera for their options")
+            sigma = self.sigma(cam)
+            max_radius = (self.ewa_max_radius if self.ewa_max_radius > 0.0 else
+                          ewa_max_radius(cam, sigma, self.dilation, self.cutoff))
         return L.make_opts(splat, self.tile, self.t_min, self.dilation, self.cutoff,
-                           self.max_radius, self.bin_points, bg_per_pixel)
+                           max_radius, self.bin_points, bg_per_pixel, sigma)
+
+
+def ewa_max_radius(cam: L.Camera, sigma: float, dilation: float, cutoff: float) -> float:
+    """Bound on the projected standard deviation (pixels, before dilation) of
+    a world-space Gaussian of standard deviation sigma in front of the near
+    plane whose footprint meets the image: sqrt(sigma^2 (f/Z)^2 (1 + (x/Z)^2))
+    with Z >= z_near and the offset |u - c| at most the image's reach plus the
+    footprint's own half-width (a fixed point, reached in a few steps)."""
+    zn = max(float(cam.z_near), 1e-12)
+    bound = 0.0
+    for f, c, size in ((float(cam.fx), float(cam.cx), cam.width),
+                       (float(cam.fy), float(cam.cy), cam.height)):
+        reach = max(abs(c), abs(size - c)) + 1.0
+        r = sigma * f / zn
+        for _ in range(32):
+            m = (reach + cutoff * math.sqrt(r * r + dilation)) / f
+            r_new = sigma * f / zn * math.sqrt(1.0 + m * m)
+            if r_new <= r * (1.0 + 1e-9):
+                r = r_new
+                break
+            r = r_new
+        bound = max(bound, r)
+    return bound * 1.001 + 1e-6
 
 
 def camera_struct(cam) -> L.Camera:
@@ -155,9 +204,18 @@ def backward_scratch_bytes(n: int, C: int, cam: L.Camera, opts: L.Opts) -> int:
     return int(L.lib().inpc_backward_scratch_bytes(n, C, ctypes.byref(cam), ctypes.byref(opts)))
 
 
+class BlendGrads(NamedTuple):
+    feat: torch.Tensor               # [n, C] f32
+    opacity: torch.Tensor            # [n]
+    uv: torch.Tensor                 # [n, 2]
+    z: Optional[torch.Tensor]        # [n] dL/dZ at fixed (u, v) (world-space Gaussians)
+    bg: Optional[torch.Tensor]       # like bg
+
+
 def blend_backward(b: Binning, feat, cam: L.Camera, opts: L.Opts, ws: torch.Tensor, t_final,
-                   state, grad_out, grad_t=None, bg=None, scratch=None, outputs=None):
-    """Step 5.  Returns grad_feat [n,C] f32, grad_opacity [n], grad_uv [n,2], grad_bg [C]|None.
+                   state, grad_out, grad_t=None, bg=None, scratch=None,
+                   outputs=None) -> BlendGrads:
+    """Step 5.  Returns BlendGrads (grad_z only for world-space Gaussians).
     outputs: optional preallocated (grad_feat, grad_opacity, grad_uv); every element is
     overwritten."""
     dev = feat.device
@@ -174,22 +232,24 @@ def blend_backward(b: Binning, feat, cam: L.Camera, opts: L.Opts, ws: torch.Tens
         grad_opacity = torch.empty(n, dtype=torch.float32, device=dev)
         grad_uv = torch.empty(n, 2, dtype=torch.float32, device=dev)
     grad_bg = torch.empty(bg.shape, dtype=torch.float32, device=dev) if bg is not None else None
+    grad_z = (torch.empty(n, dtype=torch.float32, device=dev) if opts.splat == L.SPLAT_EWA
+              else None)
     if scratch is None:
         scratch = torch.empty(backward_scratch_bytes(n, C, cam, opts), dtype=torch.uint8,
                               device=dev)
     L.call("inpc_blend_backward", ctypes.byref(cam), ctypes.byref(opts), n, _p(b.proj), _p(feat),
            C, _DTYPES[feat.dtype], _p(bg), _p(b.ntiles), _p(b.ranges), _p(b.order), _p(b.list),
            _p(b.lpos), _p(t_final), _p(state), _p(grad_out), _p(grad_t), _p(grad_feat),
-           _p(grad_opacity), _p(grad_uv), _p(grad_bg), _p(scratch), scratch.numel(), _p(ws),
-           ws.numel(), _stream(dev))
-    return grad_feat, grad_opacity, grad_uv, grad_bg
+           _p(grad_opacity), _p(grad_uv), _p(grad_z), _p(grad_bg), _p(scratch), scratch.numel(),
+           _p(ws), ws.numel(), _stream(dev))
+    return BlendGrads(grad_feat, grad_opacity, grad_uv, grad_z, grad_bg)
 
 
-def project_backward(pos, b: Binning, cam: L.Camera, grad_uv):
-    """Step 6.  Returns grad_pos [n, 3]."""
+def project_backward(pos, b: Binning, cam: L.Camera, grad_uv, grad_z=None):
+    """Step 6.  Returns grad_pos [n, 3] (grad_z: the blend's dL/dZ, world-space Gaussians)."""
     grad_pos = torch.empty_like(pos)
     L.call("inpc_project_backward", ctypes.byref(cam), pos.shape[0], _p(pos), _p(b.ntiles),
-           _p(grad_uv), _p(grad_pos), _stream(pos.device))
+           _p(grad_uv), _p(grad_z), _p(grad_pos), _stream(pos.device))
     return grad_pos
 
 
@@ -212,9 +272,11 @@ def _check_inputs(pos, opacity, feat, bg, radius, settings):
     if bg is not None and (bg.dtype != torch.float32 or bg.dim() not in (1, 3)
                            or bg.shape[0] != C):
         raise ValueError("bg must be float32 [C] or a per-pixel image [C, H, W]")
+    if settings.splat not in _SPLATS:
+        raise ValueError(f"unknown splat kind {settings.splat!r}")
     if settings.splat == "gaussian":
         if radius is None or radius.dtype != torch.float32 or radius.shape != (n,):
-            raise ValueError("Gaussian splats need radius float32 [N]")
+            raise ValueError("screen-space Gaussian splats need radius float32 [N]")
 
 
 class _RasterizeFn(torch.autograd.Function):
@@ -223,11 +285,12 @@ class _RasterizeFn(torch.autograd.Function):
         bg_image = bg is not None and bg.dim() == 3
         if bg_image and tuple(bg.shape[1:]) != (cam.height, cam.width):
             raise ValueError("a background image must be [C, H, W] of the camera's size")
-        opts = settings.opts(bg_image)
+        opts = settings.opts(bg_image, cam)
         ws = workspace.get(pos.shape[0], cam, opts, pos.device)
+        if settings.splat != "gaussian":
+            radius = None
         b = project_bin_sort(pos, opacity, cam, opts, ws, radius)
-        out, t_final, n_contrib, state = blend_forward(
-            b, feat, cam, opts, ws, bg, with_state=settings.splat == "bilinear")
+        out, t_final, n_contrib, state = blend_forward(b, feat, cam, opts, ws, bg)
         if settings.splat != "bilinear":
             # Gaussians wider than settings.max_radius can make more tile
             # copies than the workspace holds; the kernels then skip their
@@ -236,8 +299,9 @@ class _RasterizeFn(torch.autograd.Function):
             check_capacity(ws)
         ctx.cam, ctx.settings, ctx.workspace = cam, settings, workspace
         ctx.has_bg, ctx.bg_image = bg is not None, bg_image
-        saved = [pos, opacity, feat, bg if bg is not None else torch.empty(0, device=pos.device),
-                 t_final, state if state is not None else torch.empty(0, device=pos.device)]
+        empty = torch.empty(0, device=pos.device)
+        saved = [pos, opacity, feat, bg if bg is not None else empty, t_final, state,
+                 radius if radius is not None else empty]
         if settings.keep_lists:
             saved += list(b)
         ctx.save_for_backward(*saved)
@@ -246,26 +310,24 @@ class _RasterizeFn(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g_out, g_t, _g_n):
-        if ctx.settings.splat != "bilinear":
-            raise NotImplementedError("the backward pass covers bilinear splats")
         saved = ctx.saved_tensors
-        pos, opacity, feat, bg, t_final, state = saved[:6]
+        pos, opacity, feat, bg, t_final, state, radius = saved[:7]
         bg = bg if ctx.has_bg else None
-        cam, opts = ctx.cam, ctx.settings.opts(ctx.bg_image)
+        radius = radius if ctx.settings.splat == "gaussian" else None
+        cam, opts = ctx.cam, ctx.settings.opts(ctx.bg_image, ctx.cam)
         ws = ctx.workspace.get(pos.shape[0], cam, opts, pos.device)
         if ctx.settings.keep_lists:
-            b = Binning(*saved[6:])
+            b = Binning(*saved[7:])
         else:
-            b = project_bin_sort(pos, opacity, cam, opts, ws)
+            b = project_bin_sort(pos, opacity, cam, opts, ws, radius)
         g_out = g_out.contiguous() if g_out is not None else torch.zeros(
             feat.shape[1], cam.height, cam.width, device=pos.device)
         g_t = g_t.contiguous() if g_t is not None else None
-        gf, go, guv, gbg = blend_backward(b, feat, cam, opts, ws, t_final, state, g_out,
-                                          g_t, bg)
-        gpos = project_backward(pos, b, cam, guv)
-        if feat.dtype != torch.float32:
-            gf = gf.to(feat.dtype)
-        return gpos, go, gf, gbg, None, None, None, None
+        gr = blend_backward(b, feat, cam, opts, ws, t_final, state, g_out, g_t, bg)
+        gpos = project_backward(pos, b, cam, gr.uv, gr.z)
+        gf = gr.feat if feat.dtype == torch.float32 else gr.feat.to(feat.dtype)
+        # screen-space radii are inputs without a gradient (as in the paper's inference use)
+        return gpos, gr.opacity, gf, gr.bg, None, None, None, None
 
 
 def view_directions(camera, device) -> torch.Tensor:

@@ -11,14 +11,26 @@ from paper_2508_19140_amd import raster
 DEV = "cuda:0"
 
 
-def settings_opts(splat="bilinear", tile=8, t_min=1e-4, max_radius=3.0):
-    return inpc.RasterSettings(splat=splat, tile=tile, t_min=t_min, max_radius=max_radius)
+def settings_opts(splat="bilinear", tile=8, t_min=1e-4, max_radius=3.0, ewa_sigma=0.0):
+    return inpc.RasterSettings(splat=splat, tile=tile, t_min=t_min, max_radius=max_radius,
+                               ewa_sigma=ewa_sigma)
+
+
+def oracle_kw(scene, settings):
+    """The oracle's splat options for these rasterizer settings (the
+    world-space sigma as the FP32 value the library receives)."""
+    splat = {"bilinear": oracle.SPLAT_BILINEAR, "gaussian": oracle.SPLAT_GAUSSIAN,
+             "ewa": oracle.SPLAT_EWA}[settings.splat]
+    sigma = 0.0
+    if settings.splat == "ewa":
+        sigma = float(np.float32(settings.sigma(inpc.camera_struct(scene.camera))))
+    return dict(splat=splat, tile=settings.tile, ewa_sigma=sigma)
 
 
 def run_gpu(scene, settings, bg=None, feat_dtype=torch.float32, backward=True, feat=None):
     """All steps on the GPU; returns numpy copies of every intermediate."""
     cam = inpc.camera_struct(scene.camera)
-    opts = settings.opts()
+    opts = settings.opts(bg_per_pixel=bg is not None and np.ndim(bg) == 3, cam=cam)
     pos = torch.from_numpy(scene.pos).to(DEV)
     op = torch.from_numpy(scene.opacity).to(DEV)
     ft = torch.from_numpy(scene.feat if feat is None else feat).to(DEV).to(feat_dtype)
@@ -26,8 +38,7 @@ def run_gpu(scene, settings, bg=None, feat_dtype=torch.float32, backward=True, f
     bgt = None if bg is None else torch.as_tensor(bg, dtype=torch.float32, device=DEV)
     ws = inpc.Workspace().get(pos.shape[0], cam, opts, DEV)
     b = inpc.project_bin_sort(pos, op, cam, opts, ws, rad if settings.splat == "gaussian" else None)
-    out, tf, nc, state = inpc.blend_forward(b, ft, cam, opts, ws, bgt,
-                                            with_state=settings.splat == "bilinear")
+    out, tf, nc, state = inpc.blend_forward(b, ft, cam, opts, ws, bgt)
     inpc.check_capacity(ws)
     proj = b.proj.cpu().numpy()
     r = dict(uv=np.ascontiguousarray(proj[:, :2]), proj=proj, key=b.key.cpu().numpy().view(np.uint32),
@@ -36,9 +47,10 @@ def run_gpu(scene, settings, bg=None, feat_dtype=torch.float32, backward=True, f
              out=out.cpu().numpy(), t_final=tf.cpu().numpy(), n_contrib=nc.cpu().numpy().view(np.uint32),
              order=b.order.cpu().numpy().view(np.uint32), tile=settings.tile,
              W=cam.width, H=cam.height, opacity=scene.opacity,
-             radius=scene.radius if settings.splat == "gaussian" else np.zeros_like(scene.opacity),
+             radius=(scene.radius if settings.splat == "gaussian" else
+                     None if settings.splat == "ewa" else np.zeros_like(scene.opacity)),
              lpos=b.lpos.cpu().numpy().view(np.uint16) if settings.splat == "bilinear" else None)
-    if backward and scene.grad is not None and settings.splat == "bilinear":
+    if backward and scene.grad is not None:
         g = torch.from_numpy(scene.grad).to(DEV)
         gt = None if scene.grad_t is None else torch.from_numpy(scene.grad_t).to(DEV)
         # outputs and scratch start as NaN: every element the backward does
@@ -47,27 +59,43 @@ def run_gpu(scene, settings, bg=None, feat_dtype=torch.float32, backward=True, f
         nan = lambda *s: torch.full(s, float("nan"), dtype=torch.float32, device=DEV)
         scratch = torch.full((raster.backward_scratch_bytes(n, C, cam, opts),), 0xFF,
                              dtype=torch.uint8, device=DEV)
-        gf, go, guv, gbg = inpc.blend_backward(b, ft, cam, opts, ws, tf, state, g, gt, bgt,
-                                               scratch=scratch,
-                                               outputs=(nan(n, C), nan(n), nan(n, 2)))
-        gpos = inpc.project_backward(pos, b, cam, guv)
+        gr = inpc.blend_backward(b, ft, cam, opts, ws, tf, state, g, gt, bgt, scratch=scratch,
+                                 outputs=(nan(n, C), nan(n), nan(n, 2)))
+        gpos = inpc.project_backward(pos, b, cam, gr.uv, gr.z)
         torch.cuda.synchronize()
-        r.update(grad_feat=gf.cpu().numpy(), grad_opacity=go.cpu().numpy(),
-                 grad_uv=guv.cpu().numpy(), grad_pos=gpos.cpu().numpy(),
-                 grad_bg=None if gbg is None else gbg.cpu().numpy())
+        r.update(grad_feat=gr.feat.cpu().numpy(), grad_opacity=gr.opacity.cpu().numpy(),
+                 grad_uv=gr.uv.cpu().numpy(), grad_pos=gpos.cpu().numpy(),
+                 grad_z=None if gr.z is None else gr.z.cpu().numpy(),
+                 grad_bg=None if gr.bg is None else gr.bg.cpu().numpy())
     return r
 
 
 def run_oracle(scene, settings, bg=None, feat=None, backward=True):
-    splat = 0 if settings.splat == "bilinear" else 1
+    kw = oracle_kw(scene, settings)
     f = scene.feat if feat is None else feat
-    proj = oracle.project(scene.camera, scene.pos, scene.radius, splat=splat, tile=settings.tile)
-    tl = oracle.tile_lists(scene.camera, scene.pos, scene.radius, splat=splat, tile=settings.tile)
-    go = scene.grad if (backward and splat == 0) else None
-    rr = oracle.render(scene.camera, scene.pos, scene.opacity, f, radius=scene.radius, bg=bg,
-                       splat=splat, tile=settings.tile, t_min=settings.t_min, grad_out=go,
-                       grad_t=scene.grad_t if go is not None else None)
+    rad = scene.radius if settings.splat == "gaussian" else None
+    proj = oracle.project(scene.camera, scene.pos, rad, **kw)
+    tl = oracle.tile_lists(scene.camera, scene.pos, rad, **kw)
+    go = scene.grad if backward else None
+    rr = oracle.render(scene.camera, scene.pos, scene.opacity, f, radius=rad, bg=bg,
+                       t_min=settings.t_min, grad_out=go,
+                       grad_t=scene.grad_t if go is not None else None, **kw)
     return proj, tl, rr
+
+
+def mask_flagged(scene, settings, bg=None):
+    """Zero the upstream gradients at the pixels whose FP64 transmittance
+    sits on the t_min threshold (Gaussians; the oracle flags them): there the
+    GPU's FP32 termination may keep one fragment more or less, and with
+    G = G_T = 0 such a pixel contributes nothing to any gradient on either
+    side.  Returns the forward's keep-mask."""
+    _, _, rr = run_oracle(scene, settings, bg=bg, backward=False)
+    ok = rr["flags"] == 0
+    if scene.grad is not None:
+        scene.grad = np.where(ok[None], scene.grad, 0.0).astype(np.float32)
+    if scene.grad_t is not None:
+        scene.grad_t = np.where(ok, scene.grad_t, 0.0).astype(np.float32)
+    return ok
 
 
 def assert_binning_exact(g, proj, tl):
@@ -77,7 +105,10 @@ def assert_binning_exact(g, proj, tl):
     np.testing.assert_array_equal(g["uv"][vis].view(np.uint32), proj["uv"][vis].view(np.uint32))
     if g.get("opacity") is not None:  # the projection record carries opacity and radius
         np.testing.assert_array_equal(g["proj"][:, 2], g["opacity"])
-        np.testing.assert_array_equal(g["proj"][:, 3], g["radius"])
+        if g.get("radius") is not None:
+            np.testing.assert_array_equal(g["proj"][:, 3], g["radius"])
+        else:  # world-space Gaussians: the camera-space depth, whose bits are the key
+            np.testing.assert_array_equal(g["proj"][vis, 3].view(np.uint32), g["key"][vis])
     np.testing.assert_array_equal(g["key"][vis], proj["key"][vis])
     np.testing.assert_array_equal(g["ranges"].astype(np.int64), tl["ranges"])
     M = int(tl["ranges"][-1])
@@ -157,10 +188,16 @@ def assert_forward(g, rr, flags_ok=None):
 
 def assert_backward(g, rr, grad_out=None):
     st = {}
-    for k in ("grad_feat", "grad_opacity", "grad_uv", "grad_pos"):
+    keys = ["grad_feat", "grad_opacity", "grad_uv", "grad_pos"]
+    if g.get("grad_z") is not None:
+        keys.append("grad_z")
+    for k in keys:
         st[k] = assert_close(k, g[k], rr[k], rr[k + "_abs"])
     if rr.get("grad_bg") is not None:
         # sum over pixels of T_final G: bounded by the sum of the magnitudes
-        mag = np.abs(rr["t_final"][None] * np.asarray(grad_out, np.float64)).sum(axis=(1, 2))
+        # (a per-pixel background: T_final G itself)
+        mag = np.abs(rr["t_final"][None] * np.asarray(grad_out, np.float64))
+        if np.ndim(rr["grad_bg"]) == 1:
+            mag = mag.sum(axis=(1, 2))
         st["grad_bg"] = assert_close("grad_bg", g["grad_bg"], rr["grad_bg"], mag)
     return st

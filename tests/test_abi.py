@@ -111,17 +111,33 @@ def test_blend_rejects_bad_channels_and_dtype():
     assert lib.inpc_blend_forward(*base, 48, L.DTYPE_F32, *tail) == L.INPC_ERR_UNSUPPORTED
 
 
-def test_backward_rejects_gaussians():
+def test_world_space_gaussian_options_and_checks():
+    """World-space (EWA) splats: sigma must be finite and positive; the
+    workspace bound follows max_radius as for a screen-space Gaussian of that
+    radius; the backward needs grad_z (and no lpos)."""
     lib = L.lib()
     c = cam()
-    g = L.make_opts(splat=L.SPLAT_GAUSSIAN, max_radius=2.0)
     n = 10
-    wsb = lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(g))
-    st = lib.inpc_blend_backward(ctypes.byref(c), ctypes.byref(g), n, FAKE, FAKE, 4,
-                                 L.DTYPE_F32, None, FAKE, FAKE, None, FAKE, FAKE, FAKE, FAKE,
-                                 FAKE, None, FAKE, FAKE, FAKE, None, FAKE, 1 << 20, FAKE, wsb,
-                                 None)
-    assert st == L.INPC_ERR_UNSUPPORTED
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        o = L.make_opts(splat=L.SPLAT_EWA, max_radius=2.0, ewa_sigma=bad)
+        assert lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(o)) == 0
+    e = L.make_opts(splat=L.SPLAT_EWA, max_radius=2.0, ewa_sigma=0.01)
+    g = L.make_opts(splat=L.SPLAT_GAUSSIAN, max_radius=2.0)
+    wsb = lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(e))
+    assert wsb > 0 and wsb == lib.inpc_workspace_bytes(n, ctypes.byref(c), ctypes.byref(g))
+    assert lib.inpc_copy_capacity(n, ctypes.byref(c), ctypes.byref(e)) == \
+        lib.inpc_copy_capacity(n, ctypes.byref(c), ctypes.byref(g))
+    # backward: feat, ntiles, ranges, list, t_final, state, grad_out, grad_feat,
+    # grad_opacity, grad_uv given; grad_z missing
+    st = lib.inpc_blend_backward(ctypes.byref(c), ctypes.byref(e), n, FAKE, FAKE, 4,
+                                 L.DTYPE_F32, None, FAKE, FAKE, None, FAKE, None, FAKE, FAKE,
+                                 FAKE, None, FAKE, FAKE, FAKE, None, None, FAKE, 1 << 20, FAKE,
+                                 wsb, None)
+    assert st == L.INPC_ERR_INVALID and b"grad_z" in lib.inpc_last_error()
+    # project: world-space splats take no radius, but still need the outputs
+    st = lib.inpc_project(ctypes.byref(c), ctypes.byref(e), n, FAKE, FAKE, None, None, FAKE,
+                          FAKE, FAKE, wsb, None)
+    assert st == L.INPC_ERR_INVALID and b"proj" in lib.inpc_last_error()
 
 
 def test_backward_rejects_small_scratch():
@@ -133,7 +149,7 @@ def test_backward_rejects_small_scratch():
     nt = lib.inpc_num_tiles(ctypes.byref(c), ctypes.byref(o))
     assert need >= n * 16 + nt * C * 4  # scalar gradient rows, background shares
     args = [ctypes.byref(c), ctypes.byref(o), n, FAKE, FAKE, C, L.DTYPE_F32, None, FAKE,
-            FAKE, None, FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, FAKE, None]
+            FAKE, None, FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, FAKE, None, None]
     assert lib.inpc_blend_backward(*args, FAKE, need - 1, FAKE, wsb, None) == L.INPC_ERR_INVALID
     assert lib.inpc_blend_backward(*args, None, need, FAKE, wsb, None) == L.INPC_ERR_INVALID
 

@@ -24,7 +24,7 @@ def test_noalloc_rejects_more_than_the_static_scratch():
     need = lib.inpc_backward_scratch_bytes(n, 16, ctypes.byref(c), ctypes.byref(o))
     assert need > L.STATIC_SCRATCH_BYTES
     st = lib.inpc_blend_backward_noalloc(ctypes.byref(c), ctypes.byref(o), n, *([None] * 2), 16,
-                                         L.DTYPE_F32, *([None] * 15), 0, None)
+                                         L.DTYPE_F32, *([None] * 16), 0, None)
     assert st == L.INPC_ERR_INVALID
     assert b"static" in lib.inpc_last_error()
 
@@ -50,10 +50,11 @@ def _backward_both(scene, bg):
     p = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
     L.call("inpc_blend_backward_noalloc", ctypes.byref(cam), ctypes.byref(opts), n, p(b.proj),
            p(ft), C, L.DTYPE_F32, p(bgt), p(b.ntiles), p(b.ranges), p(b.order), p(b.list),
-           p(b.lpos), p(tf), p(state), p(g), None, p(gf), p(go), p(guv), p(gbg), p(ws),
+           p(b.lpos), p(tf), p(state), p(g), None, p(gf), p(go), p(guv), None, p(gbg), p(ws),
            ws.numel(), ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
     torch.cuda.synchronize()
     assert raster.backward_scratch_bytes(n, C, cam, opts) <= L.STATIC_SCRATCH_BYTES
+    ref = [ref.feat, ref.opacity, ref.uv, ref.bg]
     return [t.cpu().numpy() for t in ref], [gf.cpu().numpy(), go.cpu().numpy(),
                                             guv.cpu().numpy(), gbg.cpu().numpy()], b
 
