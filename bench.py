@@ -1,16 +1,19 @@
 """Benchmark: forward + backward rasterization of 2^23 points at 1920x1080.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--config H|C2|C3|C5] [--dtype f32|bf16|f16] [--tile 8|16]
-                    [--errors] [--profile-steps S]
+                    [--config H|C2|C3|C5|C4|R] [--splat ewa] [--dtype f32|bf16|f16]
+                    [--tile 8|16] [--errors] [--profile-steps S]
 
 One step is one training pass of the whole rasterizer on one view, exactly
 what rasterize(...) followed by .backward() runs:
   forward : project -> bin -> sort -> blend forward
   backward: project -> bin -> sort (lists recomputed, not stored)
             -> blend backward -> project backward
-(--config C3, Gaussian splats, is forward only: the paper uses Gaussians at
-inference.)  Inputs (a seeded synthetic scene shaped like the paper's
+(--config C3, screen-space Gaussian splats, is forward only: the paper uses
+Gaussians at inference.  --splat ewa renders the configuration's points as
+world-space Gaussians of the paper's default scale, forward + backward.
+--config R renders the union of a ring buffer of four view-specific clouds,
+forward only, one new cloud pushed into the ring per frame.)  Inputs (a seeded synthetic scene shaped like the paper's
 view-specific clouds) are resident in HBM before the timed region.  Every
 entry point is bracketed by HIP events on the stream it runs on, inside the
 timed region; the entry point with the largest share of the step is the
@@ -38,8 +41,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="H", choices=["H", "C2", "C3", "C5", "C4"],
-                    help="C4: 8 views of uneven size in one autotuned graph launch")
+    ap.add_argument("--config", default="H", choices=["H", "C2", "C3", "C5", "C4", "R"],
+                    help="C4: 8 views of uneven size in one autotuned graph launch; R: a ring "
+                         "of four clouds (2^21 points per slot, 1920x1080) rendered as one")
+    ap.add_argument("--splat", default="auto", choices=["auto", "ewa"],
+                    help="ewa: world-space Gaussians (EWA projection, default sigma), fwd+bwd")
     ap.add_argument("--tile", type=int, default=8, choices=[8, 16])
     ap.add_argument("--dtype", default=None, choices=["f32", "bf16", "f16"],
                     help="feature storage type (default: bf16 for C5, f32 otherwise)")
@@ -203,22 +209,25 @@ def summarize_pmc(fetch_dir, write_dir, entry, steps, command):
         print(f"sha256 {src} {h}")
 
 
-def make_step(sc, tile, keep_lists, dtype, dev):
-    """The preallocated pipeline of one view (every buffer allocated here)."""
+def make_step(sc, tile, keep_lists, dtype, dev, splat="auto", ring_counts=None):
+    """The preallocated pipeline of one view (every buffer allocated here).
+    Screen-space Gaussians (a scene with radii) and rings run forward only."""
     import torch
     import paper_2508_19140_amd as inpc
     tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[dtype]
-    gauss = sc.radius is not None
+    kind = "ewa" if splat == "ewa" else ("gaussian" if sc.radius is not None else "bilinear")
+    backward = kind != "gaussian" and ring_counts is None
     v = inpc.ViewInputs(pos=torch.from_numpy(sc.pos).to(dev),
                         opacity=torch.from_numpy(sc.opacity).to(dev),
                         feat=torch.from_numpy(sc.feat).to(dev).to(tdt).contiguous(),
                         camera=sc.camera,
-                        grad_out=None if gauss else torch.from_numpy(sc.grad).to(dev),
-                        radius=torch.from_numpy(sc.radius).to(dev) if gauss else None)
-    st = inpc.RasterSettings(splat="gaussian" if gauss else "bilinear", tile=tile,
-                             keep_lists=keep_lists,
-                             max_radius=float(sc.radius.max()) if gauss else 0.0)
+                        grad_out=torch.from_numpy(sc.grad).to(dev) if backward else None,
+                        radius=torch.from_numpy(sc.radius).to(dev) if kind == "gaussian" else None,
+                        ring_counts=ring_counts)
+    st = inpc.RasterSettings(splat=kind, tile=tile, keep_lists=keep_lists,
+                             max_radius=float(sc.radius.max()) if kind == "gaussian" else 0.0)
     step = inpc.ViewPipeline(v, st)
+    step.kind = kind
     step.bf = 4 if dtype == "f32" else 2
     step.P = sc.camera.width * sc.camera.height
     return step
@@ -246,10 +255,32 @@ def measured_traffic(entry, config):
     return traffic if ok else None
 
 
-def byte_models(n, V, M, P, C, nt, bf=4, gauss=False, keep_lists=False):
+def byte_models(n, V, M, P, C, nt, bf=4, gauss=False, keep_lists=False, kind=None,
+                backward=None):
     """Algorithmic bytes: the B_min / B_method models of the whole pass and
-    the per-entry-point minima (each input read once, each output written once)."""
+    the per-entry-point minima (each input read once, each output written once).
+    kind: "bilinear", "gaussian" (screen-space, forward) or "ewa" (world-space,
+    forward + backward: no splat positions, and the depth gradient)."""
+    kind = kind or ("gaussian" if gauss else "bilinear")
+    backward = (kind != "gaussian") if backward is None else backward
+    gauss = kind != "bilinear"
     D = M / max(V, 1)
+    if kind == "ewa" and backward:
+        per_kernel = {
+            "project": 12 * n + 4 * n + 16 * n + 8 * n,
+            "bin": 4 * n + 20 * V + 8 * M + 8 * nt,
+            "sort": 8 * M + 4 * M + 4 * nt,
+            # list + point data once + image, t_final, n_contrib, state written
+            "blend_fwd": 4 * M + 4 * nt + V * (16 + C * bf) + P * (4 * C + 20),
+            # list + point data once + G, t_final, state read + ntiles and the gradients
+            # (features, opacity, image position, depth)
+            "blend_bwd": 4 * M + 4 * nt + V * (16 + C * bf) + P * (4 * C + 16) + n * (4 * C + 20),
+            # positions, ntiles, grad_uv, grad_z read; grad_pos written
+            "project_bwd": 12 * n + 4 * n + 8 * n + 4 * n + 12 * n,
+        }
+        b_min = 2 * n * (16 + C * bf) + n * (20 + 4 * C) + 8 * D * V + 8 * P * (C + 1)
+        b_sort = 64 * V + 24 * D * V
+        return b_min, b_min + (1 if keep_lists else 2) * b_sort, per_kernel
     per_kernel = {
         # read positions, opacity (and radii); write the projection record, key, ntiles
         "project": 12 * n + 4 * n + 16 * n + 8 * n + (4 * n if gauss else 0),
@@ -276,17 +307,33 @@ def byte_models(n, V, M, P, C, nt, bf=4, gauss=False, keep_lists=False):
     return b_min, b_min + (1 if keep_lists else 2) * b_sort, per_kernel
 
 
-def cpu_baseline(sc):
+def oracle_args(step, sc):
+    """The oracle's splat options and inputs for a bench pipeline."""
+    import numpy as np
+    kw = {"splat": {"bilinear": 0, "gaussian": 1, "ewa": 2}[step.kind]}
+    if step.kind == "ewa":
+        kw["ewa_sigma"] = float(np.float32(step.settings.sigma(step.cam)))
+    rad = sc.radius if step.kind == "gaussian" else None
+    return kw, rad
+
+
+def cpu_baseline(sc, step, live=None):
+    """The oracle on the same frame (live: the ring's live point indices)."""
     import oracle
     oracle.build(force=False)
+    kw, rad = oracle_args(step, sc)
+    pos, op, ft = sc.pos, sc.opacity, sc.feat
+    if live is not None:
+        pos, op, ft = pos[live], op[live], ft[live]
+    grad = sc.grad if step.backward_enabled else None
     t0 = time.perf_counter()
-    oracle.render(sc.camera, sc.pos, sc.opacity, sc.feat, radius=sc.radius,
-                  splat=1 if sc.radius is not None else 0, grad_out=sc.grad)
+    oracle.render(sc.camera, pos, op, ft, radius=rad, grad_out=grad, **kw)
     dt = time.perf_counter() - t0
-    what = "fwd" if sc.radius is not None else "fwd+bwd"
-    return {"value": sc.n / dt, "unit": "points/s", "cores": oracle.num_threads(),
+    what = "fwd+bwd" if grad is not None else "fwd"
+    n = pos.shape[0]
+    return {"value": n / dt, "unit": "points/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"one full {what} frame of the same scene ({sc.n} points, "
+            "sample": f"one full {what} frame of the same scene ({n} points, "
                       f"{sc.camera.width}x{sc.camera.height}, C={sc.feat.shape[1]}), "
                       f"{dt:.1f} s wall"}
 
@@ -334,14 +381,18 @@ def error_table(step, sc, tile):
     step.step(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
     torch.cuda.synchronize()
     gpu = {"out": step.out.cpu().numpy(), "t_final": step.tf.cpu().numpy()}
-    if not step.gauss:
+    if step.backward_enabled:
         gpu.update(grad_feat=step.gf.cpu().numpy(), grad_opacity=step.go.cpu().numpy(),
                    grad_pos=step.gpos.cpu().numpy())
+        if step.gz is not None:
+            gpu["grad_z"] = step.gz.cpu().numpy()
     stored = step.v.feat.float().cpu().numpy()
+    kw, rad = oracle_args(step, sc)
+    grad = sc.grad if step.backward_enabled else None
     table = {}
     for label, feat in (("vs_stored_features", stored), ("vs_fp32_features", sc.feat)):
-        rr = oracle.render(sc.camera, sc.pos, sc.opacity, feat, radius=sc.radius,
-                           splat=1 if step.gauss else 0, tile=tile, grad_out=sc.grad)
+        rr = oracle.render(sc.camera, sc.pos, sc.opacity, feat, radius=rad, tile=tile,
+                           grad_out=grad, **kw)
         mask = rr["flags"] == 0
         row = {}
         for k, g in gpu.items():
@@ -477,16 +528,26 @@ def main():
     from scenes import CONFIGS, make_scene
 
     dtype = args.dtype or ("bf16" if args.config == "C5" else "f32")
-    spec = CONFIGS[args.config]
-    sc = make_scene(spec)
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    step = make_step(sc, args.tile, args.keep_lists, dtype, dev)
+    ring = None
+    if args.config == "R":
+        sc, ring = ring_scene()
+        step = make_step(sc, args.tile, args.keep_lists, dtype, dev, ring_counts=ring["counts"])
+        ring_push = make_ring_push(step, ring, dev)
+    else:
+        sc = make_scene(CONFIGS[args.config])
+        step = make_step(sc, args.tile, args.keep_lists, dtype, dev, splat=args.splat)
     h = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def phases():
+        ph = step.phases()
+        return ([("push", lambda _h: ring_push())] + ph) if ring is not None else ph
 
     if args.profile_steps:
         for _ in range(args.profile_steps):
-            step.step(h)
+            for _, f in phases():
+                f(h)
         if args.copy_probe_mib:
             src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
             dst = torch.empty_like(src)
@@ -498,22 +559,25 @@ def main():
         return
 
     for _ in range(args.warmup):
-        step.step(h)
+        for _, f in phases():
+            f(h)
     torch.cuda.synchronize()
 
     # Timed region: K steps, every entry point bracketed by HIP events on the
     # stream the library launches on (torch's current stream).
-    names = [nm for nm, _ in step.phases()]
+    names = [nm for nm, _ in phases()]
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
            for _ in range(args.steps)]
     torch.cuda.synchronize()
     for s in range(args.steps):
         evs[s][0].record()
-        for i, (_, f) in enumerate(step.phases()):
+        for i, (_, f) in enumerate(phases()):
             f(h)
             evs[s][i + 1].record()
     torch.cuda.synchronize()
     ms = evs[0][0].elapsed_time(evs[-1][-1]) / args.steps
+    ms_median = float(np.median([evs[s][0].elapsed_time(evs[s][-1])
+                                 for s in range(args.steps)]))
     phase_ms, per_launch_ms = {}, {}
     for i, nm in enumerate(names):
         t = float(np.mean([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(args.steps)]))
@@ -527,13 +591,29 @@ def main():
     V = int((ntiles > 0).sum())
     M = int(step.ranges[-1].item())
     n, C, P = step.n, step.C, step.P
+    backward = step.backward_enabled
     b_min, b_method, per_kernel = byte_models(n, V, M, P, C, step.nt, step.bf, step.gauss,
-                                              args.keep_lists)
+                                              args.keep_lists, kind=step.kind,
+                                              backward=backward)
+    if ring is not None:
+        # one new cloud into the ring: positions, opacities, features read and written
+        per_kernel["push"] = 2 * ring["pushed"] * (16 + C * step.bf)
     dominant = max(phase_ms, key=lambda k: phase_ms[k])
     dom_bytes = per_kernel[dominant]
     dom_gbs = dom_bytes / (per_launch_ms[dominant] * 1e-3) / 1e9
     t_s = ms * 1e-3
-    pas = "fwd" if step.gauss else "fwd+bwd"
+    pas = "fwd+bwd" if backward else "fwd"
+    kind_name = {"bilinear": "bilinear", "gaussian": "screen-space Gaussian",
+                 "ewa": "world-space Gaussian (EWA)"}[step.kind]
+    workload = (f"{args.config}: {n} points, {sc.camera.width}x{sc.camera.height}, C={C} "
+                f"{dtype}, {kind_name}, tile {args.tile}, {pas}" +
+                ("" if not backward else (", lists kept" if args.keep_lists
+                                          else ", lists recomputed in bwd")))
+    if ring is not None:
+        workload = (f"R: ring of {len(ring['counts'])} clouds ({V} visible of {n} slots' "
+                    f"points, live {sum(ring['counts'])}), {sc.camera.width}x"
+                    f"{sc.camera.height}, C={C} {dtype}, bilinear, tile {args.tile}, fwd; one "
+                    f"{ring['pushed']}-point cloud pushed per frame")
     res = {
         "metric": METRIC,
         "value": n / t_s,
@@ -547,12 +627,7 @@ def main():
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic (seeded scene: 70% of points on 4 planes/spheres, 30% uniform)",
-        "config": {"workload": f"{args.config}: {n} points, {sc.camera.width}x"
-                               f"{sc.camera.height}, C={C} {dtype}, "
-                               f"{'Gaussian' if step.gauss else 'bilinear'}, tile {args.tile}, "
-                               f"{pas}" + ("" if step.gauss else
-                                           (", lists kept" if args.keep_lists
-                                            else ", lists recomputed in bwd")),
+        "config": {"workload": workload,
                    "points": n, "width": sc.camera.width, "height": sc.camera.height,
                    "channels": C, "tile": args.tile, "keep_lists": args.keep_lists},
         "visible_points_per_s": V / t_s,
@@ -565,6 +640,7 @@ def main():
         "copy_bw_GBps": copy_gbs,
         "B_min_frac_of_copy": b_min / t_s / 1e9 / copy_gbs,
         "B_method_frac_of_copy": b_method / t_s / 1e9 / copy_gbs,
+        "ms_per_step_median": ms_median,
         "phase_ms": phase_ms,
         "roofline": {"bound": "hbm", "kernel": f"inpc_{dominant}", "achieved": dom_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS,
@@ -572,11 +648,58 @@ def main():
                      "bytes_per_launch": dom_bytes, "ms_per_launch": per_launch_ms[dominant],
                      "traffic": measured_traffic(dominant, args.config)},
     }
-    if args.errors:
+    if args.errors and ring is None:
         res["errors"] = error_table(step, sc, args.tile)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(sc)
+        live = None
+        if ring is not None:
+            live = np.concatenate([np.arange(k * ring["per_slot"], k * ring["per_slot"] + c)
+                                   for k, c in enumerate(ring["counts"])])
+        res["cpu_baseline"] = cpu_baseline(sc, step, live)
     print(json.dumps(res), flush=True)
+
+
+def ring_scene(slots=4, per_slot=1 << 21):
+    """Four view-specific clouds of the H scene's generator (2^21 points per
+    slot, 1920x1080, C=16) in a ring: slot s holds cloud s; slots 1 and 3 hold
+    a little fewer points (the rest of their slots is stale data that the
+    projection culls); a fifth cloud of 2^21 points is pushed into the oldest
+    slot every frame, in turn with the cloud it replaced, so that the live
+    counts stay fixed."""
+    import dataclasses
+    import numpy as np
+    from scenes import CONFIGS, Scene, make_scene
+    spec = dataclasses.replace(CONFIGS["H"], n=slots * per_slot)
+    full = make_scene(spec)
+    counts = [per_slot, per_slot - 100_000, per_slot, per_slot - 50_000]
+    extra = make_scene(dataclasses.replace(CONFIGS["H"], n=per_slot, seed=spec.seed + 7))
+    sc = Scene(pos=full.pos, opacity=full.opacity, feat=full.feat, camera=full.camera,
+               grad=None, spec=spec)
+    return sc, {"counts": counts, "per_slot": per_slot, "extra": extra, "pushed": per_slot,
+                "np": np}
+
+
+def make_ring_push(step, ring, dev):
+    """The frame's ring update: the new cloud is copied into a slot (the
+    sampler's output buffer to the ring; stream-ordered device copies; slot 0
+    every frame, which slot does not change the work), alternating between
+    the extra cloud and the one it displaced, so the live counts stay fixed."""
+    import torch
+    ex = ring["extra"]
+    per = ring["per_slot"]
+    v = step.v
+    src = [(torch.from_numpy(ex.pos).to(dev), torch.from_numpy(ex.opacity).to(dev),
+            torch.from_numpy(ex.feat).to(dev).to(v.feat.dtype)),
+           (v.pos[:per].clone(), v.opacity[:per].clone(), v.feat[:per].clone())]
+    state = {"k": 0}
+
+    def push():
+        p, o, f = src[state["k"] & 1]
+        v.pos[:per].copy_(p)
+        v.opacity[:per].copy_(o)
+        v.feat[:per].copy_(f)
+        state["k"] += 1
+    return push
 
 
 def copy_bandwidth(dev, mib=512, reps=20):

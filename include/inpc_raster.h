@@ -149,6 +149,29 @@ inpc_status_t inpc_project(const inpc_camera_t* cam, const inpc_opts_t* opts, in
                            size_t ws_bytes, void* stream);
 
 /*
+ * Step 1 over a ring buffer of point clouds (Sec. 3.1 "Fast and Stable
+ * View-Specific Sampling during Inference": instead of sampling several
+ * view-specific clouds for every frame, each frame samples one and reuses
+ * the clouds of the previous frames).  The ring is one allocation of
+ * n_slots slots of slot_cap points: point j of slot s is index
+ * s * slot_cap + j of pos, opacity, radius (and of feat in the blend), and
+ * slot s holds counts[s] <= slot_cap live points at its start (counts: host
+ * array); the rest of a slot is never interpreted (any contents).  Same
+ * outputs as inpc_project for n = n_slots * slot_cap points, with the slot
+ * tails culled (ntiles = 0), so the later steps render the union of the
+ * slots' clouds in one pass, ordered by (depth key, ring index), and the
+ * backward writes every slot's gradients in place (zero for the tails).
+ * A frame overwrites the oldest slot and renders the ring; no cloud is
+ * copied to assemble the union.  n_slots in [1, 16], n_slots * slot_cap
+ * < 2^31; INPC_ERR_INVALID otherwise or for a count outside [0, slot_cap].
+ */
+inpc_status_t inpc_project_ring(const inpc_camera_t* cam, const inpc_opts_t* opts,
+                                int32_t n_slots, int64_t slot_cap, const int64_t* counts,
+                                const float* pos, const float* opacity, const float* radius,
+                                float* proj, uint32_t* depth_key, uint32_t* ntiles, void* ws,
+                                size_t ws_bytes, void* stream);
+
+/*
  * Step 2 -- bin (Sec. 3.2 "Tiled Rendering": one copy of a point per tile
  * its footprint meets).  Exclusive scan of the per-tile counts gathered by
  * inpc_project into tile_ranges, then one (depth key, point index) copy per
@@ -400,6 +423,9 @@ typedef struct {
     float* grad_pos;           /* [n][3] */
     float* grad_bg;            /* like bg, or NULL */
     float* grad_z;             /* [n] (world-space Gaussians, backward), else NULL */
+    int32_t ring_slots;        /* > 0: the points are a ring of ring_slots slots of
+                                  n / ring_slots points (inpc_project_ring); 0: one cloud */
+    const int64_t* ring_counts; /* host [ring_slots]: live points per slot (ring views) */
 } inpc_view_t;
 
 enum { INPC_PASS_FORWARD = 0, INPC_PASS_BACKWARD = 1 };

@@ -6,6 +6,7 @@ projection), and the backward pass, as HIP kernels behind a C ABI
 """
 from . import _lib  # noqa: F401
 from .batched import BatchedRasterizer, MultiViewRasterizer, ViewInputs, ViewPipeline  # noqa: F401
+from .ring import PointRing  # noqa: F401
 from .raster import (  # noqa: F401
     Binning,
     BlendGrads,
@@ -27,5 +28,5 @@ from .raster import (  # noqa: F401
 __all__ = [
     "BatchedRasterizer", "MultiViewRasterizer", "ViewInputs", "ViewPipeline", "Binning", "BlendGrads", "RasterSettings", "Workspace", "blend_backward", "blend_forward",
     "camera_struct", "check_capacity", "project_backward", "project_bin_sort", "rasterize", "envmap_background", "view_directions", "sh_features",
-    "ewa_max_radius",
+    "ewa_max_radius", "PointRing",
 ]

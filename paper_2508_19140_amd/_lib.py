@@ -31,7 +31,7 @@ EXPORTS = (
     "inpc_workspace_bytes", "inpc_state_bytes", "inpc_num_tiles", "inpc_copy_capacity",
     "inpc_project", "inpc_bin", "inpc_sort", "inpc_blend_forward", "inpc_blend_backward",
     "inpc_project_backward", "inpc_check_sync", "inpc_status_string", "inpc_last_error",
-    "inpc_backward_scratch_bytes", "inpc_blend_backward_noalloc",
+    "inpc_backward_scratch_bytes", "inpc_blend_backward_noalloc", "inpc_project_ring",
     "inpc_view_dirs", "inpc_envmap_forward", "inpc_envmap_backward",
     "inpc_batch_workspace_bytes", "inpc_rasterize_batched",
     "inpc_sh_features", "inpc_sh_features_backward",
@@ -70,7 +70,8 @@ class ViewRecord(ctypes.Structure):
                 ("scratch", _VP), ("scratch_bytes", ctypes.c_size_t),
                 ("out", _VP), ("t_final", _VP), ("n_contrib", _VP),
                 ("grad_out", _VP), ("grad_t", _VP), ("grad_feat", _VP), ("grad_opacity", _VP),
-                ("grad_uv", _VP), ("grad_pos", _VP), ("grad_bg", _VP), ("grad_z", _VP)]
+                ("grad_uv", _VP), ("grad_pos", _VP), ("grad_bg", _VP), ("grad_z", _VP),
+                ("ring_slots", ctypes.c_int32), ("ring_counts", _VP)]
 
 
 class InpcError(RuntimeError):
@@ -99,6 +100,7 @@ def lib():
         "inpc_num_tiles": (I64, [CP, OP]),
         "inpc_copy_capacity": (I64, [I64, CP, OP]),
         "inpc_project": (I32, [CP, OP, I64, P, P, P, P, P, P, P, SZ, P]),
+        "inpc_project_ring": (I32, [CP, OP, I32, I64, P, P, P, P, P, P, P, P, SZ, P]),
         "inpc_bin": (I32, [CP, OP, I64, P, P, P, P, P, P, SZ, P]),
         "inpc_sort": (I32, [CP, OP, I64, P, P, P, P, P, P, SZ, P]),
         "inpc_blend_forward": (I32, [CP, OP, I64, P, P, I32, I32, P, P, P, P, P, P, P, P, P,

@@ -44,13 +44,16 @@ class ViewInputs:
     """Device tensors of one view: pos [n,3] f32, opacity [n] f32, feat
     [n,C] (f32/f16/bf16), camera (scenes.Camera or L.Camera), grad_out
     [C,H,W] f32 (upstream gradient of the feature image; None: forward only),
-    radius [n] f32 for screen-space Gaussian splats."""
+    radius [n] f32 for screen-space Gaussian splats, ring_counts: the points
+    are a ring of len(ring_counts) equal slots with that many live points
+    each (PointRing)."""
     pos: torch.Tensor
     opacity: torch.Tensor
     feat: torch.Tensor
     camera: object
     grad_out: Optional[torch.Tensor] = None
     radius: Optional[torch.Tensor] = None
+    ring_counts: Optional[Sequence[int]] = None
 
 
 class ViewPipeline:
@@ -86,6 +89,12 @@ class ViewPipeline:
         self.backward_enabled = v.grad_out is not None
         self.state = mk(int(lib.inpc_state_bytes(self.cb, self.ob)), dt=torch.uint8)
         self.gz = None
+        self.ring = None
+        if v.ring_counts is not None:
+            k = len(v.ring_counts)
+            if k < 1 or n % k:
+                raise ValueError("a ring view's point count must be slots * slot capacity")
+            self.ring = (ctypes.c_int64 * k)(*[int(c) for c in v.ring_counts])
         if self.backward_enabled:
             self.gf, self.go, self.guv, self.gpos = mk(n, C), mk(n), mk(n, 2), mk(n, 3)
             if self.ewa:
@@ -108,6 +117,8 @@ class ViewPipeline:
         r.ws, r.ws_bytes = ptr(self.ws), self.ws.numel()
         r.out, r.t_final, r.n_contrib = ptr(self.out), ptr(self.tf), ptr(self.nc)
         r.grad_out, r.grad_t, r.grad_bg = ptr(v.grad_out), None, None
+        r.ring_slots = 0 if self.ring is None else len(self.ring)
+        r.ring_counts = None if self.ring is None else ctypes.cast(self.ring, ctypes.c_void_p)
         if self.backward_enabled:
             r.scratch, r.scratch_bytes = ptr(self.scratch), self.scratch.numel()
             r.grad_feat, r.grad_opacity = ptr(self.gf), ptr(self.go)
@@ -122,6 +133,12 @@ class ViewPipeline:
     def project(self, s):
         v, ws = self.v, self.ws
         radius = v.radius if self.settings.splat == "gaussian" else None
+        if self.ring is not None:
+            k = len(self.ring)
+            self._call("inpc_project_ring", self.cb, self.ob, k, self.n // k, self.ring,
+                       _p(v.pos), _p(v.opacity), _p(radius), _p(self.proj), _p(self.key),
+                       _p(self.ntiles), _p(ws), ws.numel(), s)
+            return
         self._call("inpc_project", self.cb, self.ob, self.n, _p(v.pos), _p(v.opacity),
                    _p(radius), _p(self.proj), _p(self.key), _p(self.ntiles), _p(ws),
                    ws.numel(), s)

@@ -374,10 +374,31 @@ int64_t inpc_copy_capacity(int64_t n, const inpc_camera_t* cam, const inpc_opts_
   return copy_capacity(n, cam, opts);
 }
 
-inpc_status_t inpc_project(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
-                           const float* pos, const float* opacity, const float* radius,
+namespace inpc {
+namespace {
+
+// The ring description of inpc_project_ring, checked.
+inpc_status_t make_ring(int32_t n_slots, int64_t slot_cap, const int64_t* counts, Ring* r) {
+  if (n_slots < 1 || n_slots > kMaxRingSlots)
+    return fail(INPC_ERR_INVALID, "n_slots must be in [1, 16]%s", "");
+  if (slot_cap < 1 || slot_cap * n_slots > (int64_t)0x7fffffff)
+    return fail(INPC_ERR_INVALID, "slot_cap out of range%s", "");
+  REQUIRE(counts, "counts");
+  memset(r, 0, sizeof(*r));
+  r->slots = n_slots;
+  r->cap = (uint32_t)slot_cap;
+  for (int s = 0; s < n_slots; ++s) {
+    if (counts[s] < 0 || counts[s] > slot_cap)
+      return fail(INPC_ERR_INVALID, "ring slot count outside [0, slot_cap]%s", "");
+    r->count[s] = (uint32_t)counts[s];
+  }
+  return INPC_OK;
+}
+
+inpc_status_t project_impl(const char* who, const inpc_camera_t* cam, const inpc_opts_t* opts,
+                           int64_t n, const float* pos, const float* opacity, const float* radius,
                            float* proj, uint32_t* depth_key, uint32_t* ntiles, void* ws,
-                           size_t ws_bytes, void* stream) {
+                           size_t ws_bytes, const Ring& ring, void* stream) {
   inpc_status_t st = check_common(cam, opts, n, ws, ws_bytes);
   if (st != INPC_OK) return st;
   if (n > 0) {
@@ -391,8 +412,33 @@ inpc_status_t inpc_project(const inpc_camera_t* cam, const inpc_opts_t* opts, in
   const Ws w = make_ws(ws, n, cam, opts);
   hipError_t e = launch_project(to_cam(cam), to_opts(cam, opts), n, pos, opacity,
                                 opts->splat == INPC_SPLAT_GAUSSIAN ? radius : nullptr, proj,
-                                depth_key, ntiles, w, (hipStream_t)stream);
-  return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_project");
+                                depth_key, ntiles, w, ring, (hipStream_t)stream);
+  return e == hipSuccess ? INPC_OK : hip_fail(e, who);
+}
+
+}  // namespace
+}  // namespace inpc
+
+inpc_status_t inpc_project(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
+                           const float* pos, const float* opacity, const float* radius,
+                           float* proj, uint32_t* depth_key, uint32_t* ntiles, void* ws,
+                           size_t ws_bytes, void* stream) {
+  Ring none;
+  memset(&none, 0, sizeof(none));
+  return project_impl("inpc_project", cam, opts, n, pos, opacity, radius, proj, depth_key,
+                      ntiles, ws, ws_bytes, none, stream);
+}
+
+inpc_status_t inpc_project_ring(const inpc_camera_t* cam, const inpc_opts_t* opts,
+                                int32_t n_slots, int64_t slot_cap, const int64_t* counts,
+                                const float* pos, const float* opacity, const float* radius,
+                                float* proj, uint32_t* depth_key, uint32_t* ntiles, void* ws,
+                                size_t ws_bytes, void* stream) {
+  Ring r;
+  inpc_status_t st = make_ring(n_slots, slot_cap, counts, &r);
+  if (st != INPC_OK) return st;
+  return project_impl("inpc_project_ring", cam, opts, (int64_t)n_slots * slot_cap, pos, opacity,
+                      radius, proj, depth_key, ntiles, ws, ws_bytes, r, stream);
 }
 
 inpc_status_t inpc_bin(const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n,
@@ -711,6 +757,13 @@ inpc_status_t inpc_rasterize_batched(const inpc_view_t* views_host, const inpc_v
       REQUIRE_ALIGNED(w.feat, "feat", 16);
       if (opts->splat == INPC_SPLAT_GAUSSIAN) REQUIRE(w.radius, "radius");
     }
+    if (w.ring_slots != 0) {
+      Ring r;
+      if (w.ring_slots < 0 || w.n % w.ring_slots != 0)
+        return fail(INPC_ERR_INVALID, "a ring view's n must be ring_slots * slot_cap%s", "");
+      st = make_ring(w.ring_slots, w.n / w.ring_slots, w.ring_counts, &r);
+      if (st != INPC_OK) return st;
+    }
     if (fwd) {
       REQUIRE(w.out, "out");
       REQUIRE(w.t_final, "t_final");
@@ -745,8 +798,13 @@ inpc_status_t inpc_rasterize_batched(const inpc_view_t* views_host, const inpc_v
   for (int v = 0; v < n_views; ++v) {
     const inpc_view_t& w = views_host[v];
     void* vs = side->st[v % kSideStreams];
-    st = inpc_project(&w.cam, opts, w.n, w.pos, w.opacity, w.radius, w.proj, w.depth_key,
-                      w.ntiles, w.ws, w.ws_bytes, vs);
+    if (w.ring_slots > 0)
+      st = inpc_project_ring(&w.cam, opts, w.ring_slots, w.n / w.ring_slots, w.ring_counts,
+                             w.pos, w.opacity, w.radius, w.proj, w.depth_key, w.ntiles, w.ws,
+                             w.ws_bytes, vs);
+    else
+      st = inpc_project(&w.cam, opts, w.n, w.pos, w.opacity, w.radius, w.proj, w.depth_key,
+                        w.ntiles, w.ws, w.ws_bytes, vs);
     if (st == INPC_OK)
       st = inpc_bin(&w.cam, opts, w.n, w.proj, w.depth_key, w.ntiles, w.tile_ranges,
                     w.tile_order, w.ws, w.ws_bytes, vs);

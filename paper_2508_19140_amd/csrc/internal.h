@@ -125,13 +125,29 @@ struct BatchTiles {
   int64_t tiles[kMaxBatchViews];
 };
 
+// A ring buffer of point clouds in one allocation: `slots` slots of `cap`
+// points; point j of slot s is index s * cap + j, and only the first
+// count[s] points of slot s are live (the others are culled).  slots = 0: every
+// point is live.
+constexpr int kMaxRingSlots = 16;
+struct Ring {
+  int slots;
+  uint32_t cap;
+  uint32_t count[kMaxRingSlots];
+};
+__host__ __device__ inline bool ring_live(const Ring& r, int64_t i) {
+  if (r.slots == 0) return true;
+  const uint32_t s = (uint32_t)i / r.cap;
+  return (uint32_t)i - s * r.cap < r.count[s];
+}
+
 // Channel capacity of the kernel instantiation used for C channels.
 inline int channel_capacity(int C) { return C <= 4 ? 4 : (C <= 8 ? 8 : (C <= 16 ? 16 : 32)); }
 
 hipError_t launch_clear(uint32_t* p, size_t n, hipStream_t s);
 hipError_t launch_project(const Cam& cam, const Opts& o, int64_t n, const float* pos,
                           const float* opacity, const float* radius, float* proj, uint32_t* key,
-                          uint32_t* ntiles, const Ws& ws, hipStream_t s);
+                          uint32_t* ntiles, const Ws& ws, const Ring& ring, hipStream_t s);
 hipError_t launch_bin(const Cam& cam, const Opts& o, int64_t n, const float* proj,
                       const uint32_t* key, const uint32_t* ntiles, uint32_t* ranges,
                       uint32_t* order, const Ws& ws, hipStream_t s);

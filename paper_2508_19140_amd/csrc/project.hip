@@ -54,7 +54,7 @@ __device__ __forceinline__ TileRect tile_rect(const Footprint& f, int sh) {
 
 __device__ __forceinline__ TileRect project_one(const Cam& cam, const Opts& o, int sh, float x,
                                                 float y, float z, float rad, int64_t i, float op,
-                                                float4* __restrict__ proj,
+                                                bool live, float4* __restrict__ proj,
                                                 uint32_t* __restrict__ key,
                                                 uint32_t* __restrict__ ntiles) {
   const Proj p = project_point(cam, x, y, z);
@@ -63,7 +63,7 @@ __device__ __forceinline__ TileRect project_one(const Cam& cam, const Opts& o, i
   const float w = o.splat == INPC_SPLAT_EWA ? p.Z : rad;
   Footprint f;
   f.visible = false;
-  if (p.in_front) f = footprint(o, cam, p.u, p.v, w);
+  if (p.in_front && live) f = footprint(o, cam, p.u, p.v, w);
   proj[i] = make_float4(p.u, p.v, op, w);
   key[i] = __float_as_uint(p.Z);
   const TileRect r = tile_rect(f, sh);
@@ -83,8 +83,8 @@ __device__ __forceinline__ Chunk chunk_of(int64_t n, int64_t chunk) {
 }
 
 // Step 1 with per-workgroup tile histograms in LDS (nt <= kLdsBins).
-__global__ __launch_bounds__(kBinBlock) void k_project_count(Cam cam, Opts o, int64_t n,
-                                                             int64_t chunk,
+__global__ __launch_bounds__(kBinBlock) void k_project_count(Cam cam, Opts o, Ring ring,
+                                                             int64_t n, int64_t chunk,
                                                              const float* __restrict__ pos,
                                                              const float* __restrict__ opacity,
                                                              const float* __restrict__ radius,
@@ -121,7 +121,8 @@ __global__ __launch_bounds__(kBinBlock) void k_project_count(Cam cam, Opts o, in
       const int64_t i = i0 + (int64_t)k * kBinBlock;
       if (i >= c.end) break;
       const TileRect r =
-          project_one(cam, o, sh, x[k], y[k], z[k], rad[k], i, op[k], proj, key, ntiles);
+          project_one(cam, o, sh, x[k], y[k], z[k], rad[k], i, op[k], ring_live(ring, i), proj,
+                      key, ntiles);
       for (int ty = r.ty0; ty <= r.ty1; ++ty)
         for (int tx = r.tx0; tx <= r.tx1; ++tx) atomicAdd(&bins[ty * o.ntx + tx], 1u);
     }
@@ -253,7 +254,8 @@ __global__ __launch_bounds__(1024) void k_colscan(int64_t nt, int rows, uint32_t
 
 // Step 1 for very large tile counts: one global atomic per copy.
 __global__ __launch_bounds__(kBlock) void k_project_count_global(
-    Cam cam, Opts o, int64_t n, const float* __restrict__ pos, const float* __restrict__ opacity,
+    Cam cam, Opts o, Ring ring, int64_t n, const float* __restrict__ pos,
+    const float* __restrict__ opacity,
     const float* __restrict__ radius, float4* __restrict__ proj, uint32_t* __restrict__ key,
     uint32_t* __restrict__ ntiles,
     uint32_t* __restrict__ tile_count) {
@@ -261,7 +263,8 @@ __global__ __launch_bounds__(kBlock) void k_project_count_global(
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const TileRect r = project_one(cam, o, sh, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2],
-                                   radius ? radius[i] : 0.f, i, opacity[i], proj, key, ntiles);
+                                   radius ? radius[i] : 0.f, i, opacity[i], ring_live(ring, i),
+                                   proj, key, ntiles);
     for (int ty = r.ty0; ty <= r.ty1; ++ty)
       for (int tx = r.tx0; tx <= r.tx1; ++tx) atomicAdd(&tile_count[ty * o.ntx + tx], 1u);
   }
@@ -520,8 +523,7 @@ hipError_t launch_clear(uint32_t* p, size_t n, hipStream_t s) {
 
 hipError_t launch_project(const Cam& cam, const Opts& o, int64_t n, const float* pos,
                           const float* opacity, const float* radius, float* proj, uint32_t* key,
-                          uint32_t* ntiles,
-                          const Ws& ws, hipStream_t s) {
+                          uint32_t* ntiles, const Ws& ws, const Ring& ring, hipStream_t s) {
   const int64_t nt = (int64_t)o.ntx * o.nty;
   hipError_t e = hipSuccess;
   if (n == 0 || nt > kLdsBins) {  // else k_project_count clears the counters
@@ -537,8 +539,8 @@ hipError_t launch_project(const Cam& cam, const Opts& o, int64_t n, const float*
   }
   if (nt <= kLdsBins) {
     const int64_t chunk = ws.chunk, rows = ws.rows;
-    hipLaunchKernelGGL(k_project_count, dim3((unsigned)rows), dim3(kBinBlock), 0, s, cam, o, n,
-                       chunk, pos, opacity, radius, reinterpret_cast<float4*>(proj), key, ntiles,
+    hipLaunchKernelGGL(k_project_count, dim3((unsigned)rows), dim3(kBinBlock), 0, s, cam, o, ring,
+                       n, chunk, pos, opacity, radius, reinterpret_cast<float4*>(proj), key, ntiles,
                        ws.blk, ws.flags);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -547,7 +549,7 @@ hipError_t launch_project(const Cam& cam, const Opts& o, int64_t n, const float*
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_project_count_global, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, cam, o,
-                     n, pos, opacity, radius, reinterpret_cast<float4*>(proj), key, ntiles,
+                     ring, n, pos, opacity, radius, reinterpret_cast<float4*>(proj), key, ntiles,
                      ws.tile_count);
   e = hipGetLastError();
   if (e != hipSuccess) return e;

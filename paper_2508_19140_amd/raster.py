@@ -17,7 +17,7 @@ from __future__ import annotations
 import ctypes
 import dataclasses
 import math
-from typing import NamedTuple, Optional
+from typing import NamedTuple, Optional, Sequence
 
 import torch
 
@@ -154,8 +154,11 @@ class Binning(NamedTuple):
 
 
 def project_bin_sort(pos: torch.Tensor, opacity: torch.Tensor, cam: L.Camera, opts: L.Opts,
-                     ws: torch.Tensor, radius: Optional[torch.Tensor] = None) -> Binning:
-    """Steps 1-3: project, bin into tiles, sort every tile by (depth, index)."""
+                     ws: torch.Tensor, radius: Optional[torch.Tensor] = None,
+                     ring_counts: Optional[Sequence[int]] = None) -> Binning:
+    """Steps 1-3: project, bin into tiles, sort every tile by (depth, index).
+    ring_counts: the points are a ring of len(ring_counts) equal slots whose
+    first ring_counts[s] points are live (inpc_project_ring)."""
     dev = pos.device
     n = pos.shape[0]
     lib = L.lib()
@@ -171,8 +174,16 @@ def project_bin_sort(pos: torch.Tensor, opacity: torch.Tensor, cam: L.Camera, op
     s = _stream(dev)
     cb, ob = ctypes.byref(cam), ctypes.byref(opts)
     wsb = ws.numel()
-    L.call("inpc_project", cb, ob, n, _p(pos), _p(opacity), _p(radius), _p(proj), _p(key),
-           _p(ntiles), _p(ws), wsb, s)
+    if ring_counts is None:
+        L.call("inpc_project", cb, ob, n, _p(pos), _p(opacity), _p(radius), _p(proj), _p(key),
+               _p(ntiles), _p(ws), wsb, s)
+    else:
+        k = len(ring_counts)
+        if k < 1 or n % k:
+            raise ValueError("a ring's point count must be slots * slot capacity")
+        counts = (ctypes.c_int64 * k)(*[int(c) for c in ring_counts])
+        L.call("inpc_project_ring", cb, ob, k, n // k, counts, _p(pos), _p(opacity), _p(radius),
+               _p(proj), _p(key), _p(ntiles), _p(ws), wsb, s)
     L.call("inpc_bin", cb, ob, n, _p(proj), _p(key), _p(ntiles), _p(ranges), _p(order), _p(ws),
            wsb, s)
     L.call("inpc_sort", cb, ob, n, _p(proj), _p(ranges), _p(order), _p(lst), _p(lpos), _p(ws),
@@ -281,7 +292,7 @@ def _check_inputs(pos, opacity, feat, bg, radius, settings):
 
 class _RasterizeFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, pos, opacity, feat, bg, radius, cam, settings, workspace):
+    def forward(ctx, pos, opacity, feat, bg, radius, cam, settings, workspace, ring_counts):
         bg_image = bg is not None and bg.dim() == 3
         if bg_image and tuple(bg.shape[1:]) != (cam.height, cam.width):
             raise ValueError("a background image must be [C, H, W] of the camera's size")
@@ -289,7 +300,7 @@ class _RasterizeFn(torch.autograd.Function):
         ws = workspace.get(pos.shape[0], cam, opts, pos.device)
         if settings.splat != "gaussian":
             radius = None
-        b = project_bin_sort(pos, opacity, cam, opts, ws, radius)
+        b = project_bin_sort(pos, opacity, cam, opts, ws, radius, ring_counts)
         out, t_final, n_contrib, state = blend_forward(b, feat, cam, opts, ws, bg)
         if settings.splat != "bilinear":
             # Gaussians wider than settings.max_radius can make more tile
@@ -298,6 +309,7 @@ class _RasterizeFn(torch.autograd.Function):
             # splats make at most four copies per point and cannot overflow)
             check_capacity(ws)
         ctx.cam, ctx.settings, ctx.workspace = cam, settings, workspace
+        ctx.ring_counts = ring_counts
         ctx.has_bg, ctx.bg_image = bg is not None, bg_image
         empty = torch.empty(0, device=pos.device)
         saved = [pos, opacity, feat, bg if bg is not None else empty, t_final, state,
@@ -319,7 +331,7 @@ class _RasterizeFn(torch.autograd.Function):
         if ctx.settings.keep_lists:
             b = Binning(*saved[7:])
         else:
-            b = project_bin_sort(pos, opacity, cam, opts, ws, radius)
+            b = project_bin_sort(pos, opacity, cam, opts, ws, radius, ctx.ring_counts)
         g_out = g_out.contiguous() if g_out is not None else torch.zeros(
             feat.shape[1], cam.height, cam.width, device=pos.device)
         g_t = g_t.contiguous() if g_t is not None else None
@@ -327,7 +339,7 @@ class _RasterizeFn(torch.autograd.Function):
         gpos = project_backward(pos, b, cam, gr.uv, gr.z)
         gf = gr.feat if feat.dtype == torch.float32 else gr.feat.to(feat.dtype)
         # screen-space radii are inputs without a gradient (as in the paper's inference use)
-        return gpos, gr.opacity, gf, gr.bg, None, None, None, None
+        return gpos, gr.opacity, gf, gr.bg, None, None, None, None, None
 
 
 def view_directions(camera, device) -> torch.Tensor:
@@ -412,12 +424,16 @@ def sh_features(pos: torch.Tensor, sh: torch.Tensor, camera) -> torch.Tensor:
 def rasterize(pos: torch.Tensor, opacity: torch.Tensor, feat: torch.Tensor, camera,
               bg: Optional[torch.Tensor] = None, radius: Optional[torch.Tensor] = None,
               settings: RasterSettings = RasterSettings(),
-              workspace: Optional[Workspace] = None):
+              workspace: Optional[Workspace] = None,
+              ring_counts: Optional[Sequence[int]] = None):
     """Render a feature image.
 
     pos [N,3] f32, opacity [N] f32 in [0,1], feat [N,C] f32/f16/bf16,
     bg [C] f32, a per-pixel background [C,H,W] f32 (e.g. envmap_background)
-    or None, radius [N] f32 (Gaussian splats).
+    or None, radius [N] f32 (screen-space Gaussian splats).
+    ring_counts: the N points are a ring of len(ring_counts) equal slots of
+    which slot s holds ring_counts[s] live points at its start (PointRing);
+    the union of the live points is rendered, the rest is ignored.
     Returns out [C,H,W] f32, t_final [H,W] f32, n_contrib [H,W] int32.
     """
     _check_inputs(pos, opacity, feat, bg, radius, settings)
@@ -428,4 +444,5 @@ def rasterize(pos: torch.Tensor, opacity: torch.Tensor, feat: torch.Tensor, came
         feat = feat.clone()
     return _RasterizeFn.apply(pos.contiguous(), opacity.contiguous(), feat,
                               None if bg is None else bg.contiguous(),
-                              None if radius is None else radius.contiguous(), cam, settings, ws)
+                              None if radius is None else radius.contiguous(), cam, settings, ws,
+                              None if ring_counts is None else tuple(int(c) for c in ring_counts))

@@ -27,8 +27,11 @@ def oracle_kw(scene, settings):
     return dict(splat=splat, tile=settings.tile, ewa_sigma=sigma)
 
 
-def run_gpu(scene, settings, bg=None, feat_dtype=torch.float32, backward=True, feat=None):
-    """All steps on the GPU; returns numpy copies of every intermediate."""
+def run_gpu(scene, settings, bg=None, feat_dtype=torch.float32, backward=True, feat=None,
+            ring_counts=None):
+    """All steps on the GPU; returns numpy copies of every intermediate
+    (ring_counts: the scene's points are a ring of that many live points per
+    slot, projected with inpc_project_ring)."""
     cam = inpc.camera_struct(scene.camera)
     opts = settings.opts(bg_per_pixel=bg is not None and np.ndim(bg) == 3, cam=cam)
     pos = torch.from_numpy(scene.pos).to(DEV)
@@ -37,7 +40,8 @@ def run_gpu(scene, settings, bg=None, feat_dtype=torch.float32, backward=True, f
     rad = None if scene.radius is None else torch.from_numpy(scene.radius).to(DEV)
     bgt = None if bg is None else torch.as_tensor(bg, dtype=torch.float32, device=DEV)
     ws = inpc.Workspace().get(pos.shape[0], cam, opts, DEV)
-    b = inpc.project_bin_sort(pos, op, cam, opts, ws, rad if settings.splat == "gaussian" else None)
+    b = inpc.project_bin_sort(pos, op, cam, opts, ws, rad if settings.splat == "gaussian" else None,
+                              ring_counts)
     out, tf, nc, state = inpc.blend_forward(b, ft, cam, opts, ws, bgt)
     inpc.check_capacity(ws)
     proj = b.proj.cpu().numpy()

@@ -173,3 +173,27 @@ def test_status_strings():
     for s in (L.INPC_OK, L.INPC_ERR_INVALID, L.INPC_ERR_CAPACITY, L.INPC_ERR_HIP,
               L.INPC_ERR_UNSUPPORTED):
         assert lib.inpc_status_string(s)
+
+
+def test_project_ring_checks():
+    """inpc_project_ring: slot count in [1, 16], counts within [0, slot_cap],
+    counts given; every check before any launch."""
+    lib = L.lib()
+    c, o = cam(), L.make_opts(tile=8)
+    cap = 100
+    wsb = lib.inpc_workspace_bytes(4 * cap, ctypes.byref(c), ctypes.byref(o))
+    ok = (ctypes.c_int64 * 4)(100, 0, 37, 100)
+
+    def call(k, slot_cap, counts, ws_bytes=wsb):
+        return lib.inpc_project_ring(ctypes.byref(c), ctypes.byref(o), k, slot_cap, counts,
+                                     FAKE, FAKE, None, FAKE, FAKE, FAKE, FAKE, ws_bytes, None)
+    assert call(0, cap, ok) == L.INPC_ERR_INVALID
+    assert call(17, cap, (ctypes.c_int64 * 17)()) == L.INPC_ERR_INVALID
+    assert call(4, 0, ok) == L.INPC_ERR_INVALID
+    assert call(4, cap, None) == L.INPC_ERR_INVALID
+    assert call(4, cap, (ctypes.c_int64 * 4)(100, 101, 0, 0)) == L.INPC_ERR_INVALID
+    assert b"slot count" in lib.inpc_last_error()
+    assert call(4, cap, (ctypes.c_int64 * 4)(-1, 0, 0, 0)) == L.INPC_ERR_INVALID
+    # the workspace is checked for n = slots * slot_cap points
+    small = lib.inpc_workspace_bytes(cap, ctypes.byref(c), ctypes.byref(o))
+    assert call(4, cap, ok, small) == L.INPC_ERR_INVALID
