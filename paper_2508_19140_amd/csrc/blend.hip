@@ -760,6 +760,39 @@ __device__ __forceinline__ void stage_gauss(const BlendArgs& a, bool ewa, float4
                     __uint_as_float(pack_xy(f.px1, f.py1)), f.cc);
 }
 
+// The pixels of this tile inside a staged Gaussian's candidate rectangle
+// (packed corners lo, hi), as NW 64-bit words: word w holds tile-local
+// pixels 64 w .. 64 w + 63 (those of wavefront w), bit = pixel index mod 64.
+template <int T, int NW>
+__device__ __forceinline__ void rect_pixel_mask(uint32_t lo, uint32_t hi, int tx, int ty,
+                                                unsigned long long* __restrict__ out) {
+  constexpr int RPW = 64 / T;  // pixel rows per word
+  const int x0 = max(unpack_x(lo) - tx * T, 0), x1 = min(unpack_x(hi) - tx * T, T - 1);
+  const int y0 = max(unpack_y(lo) - ty * T, 0), y1 = min(unpack_y(hi) - ty * T, T - 1);
+  const unsigned long long row = x0 <= x1 ? (2ull << x1) - (1ull << x0) : 0ull;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    unsigned long long m = 0ull;
+    for (int y = max(y0, w * RPW); y <= min(y1, w * RPW + RPW - 1); ++y)
+      m |= row << ((y - w * RPW) * T);
+    out[w] = m;
+  }
+}
+
+// This lane's candidates among staged copies [j0, j0 + n), n <= 64: bit j
+// set iff copy j0 + j's rectangle holds the lane's pixel (word `wv` of every
+// copy's pixel mask, bit `lb`).  The reads are independent, so their LDS
+// latencies overlap.
+template <int NW>
+__device__ __forceinline__ unsigned long long candidates(const unsigned long long* __restrict__ pm,
+                                                         int j0, int n, int wv, uint32_t lb) {
+  unsigned long long m = 0ull;
+#pragma unroll 8
+  for (int j = 0; j < 64; ++j)
+    if (j < n) m |= ((pm[(j0 + j) * NW + wv] >> lb) & 1ull) << j;
+  return m;
+}
+
 // Whether pixel-centre offset (dx, dy) lies inside a staged Gaussian's cut,
 // with the squared distance in its metric (FP32, one rounding per
 // operation, as in the projection).
@@ -802,6 +835,7 @@ __device__ __forceinline__ void blend_fwd_gauss_tile(const BlendArgs& a, uint32_
   __shared__ float4 s_g0[G::CHUNK];
   __shared__ float4 s_g1[G::CHUNK];
   __shared__ __align__(16) float s_feat[G::CHUNK * fpad(CP)];
+  __shared__ unsigned long long s_pm[G::CHUNK * NW];  // pixel masks of the staged copies
   __shared__ uint32_t s_ml[NW];
 
   const int tid = threadIdx.x;
@@ -838,18 +872,22 @@ __device__ __forceinline__ void blend_fwd_gauss_tile(const BlendArgs& a, uint32_
     const uint32_t nh = min((uint32_t)G::CHUNK, end - base);
     if (pf.valid) {
       stage_gauss(a, ewa, pf.p, &s_g0[tid], &s_g1[tid]);
+      rect_pixel_mask<T, NW>(__float_as_uint(s_g1[tid].y), __float_as_uint(s_g1[tid].z), tx, ty,
+                             &s_pm[tid * NW]);
       pf.f.store_f32(s_feat + tid * fpad(CP));
     }
     pf.fetch(a, nv, nidx);
     nv = stager && base + 2 * G::CHUNK + tid < end;
     nidx = list_at(base + 2 * G::CHUNK + tid);
     tile_sync<NW>();
-    if (!done) {
-      for (uint32_t kk = 0; kk < nh; ++kk) {
+    for (int w0 = 0; w0 < G::MW && !done; ++w0) {
+      unsigned long long m = candidates<NW>(s_pm, 64 * w0, (int)nh - 64 * w0, tid >> 6,
+                                            (uint32_t)tid & 63u);
+      while (m) {
+        const int j = __ffsll(m) - 1;
+        m &= m - 1ull;
+        const uint32_t kk = 64u * (uint32_t)w0 + (uint32_t)j;
         const float4 g1 = s_g1[kk];
-        const uint32_t lo = __float_as_uint(g1.y), hi = __float_as_uint(g1.z);
-        if (px < unpack_x(lo) || px > unpack_x(hi) || py < unpack_y(lo) || py > unpack_y(hi))
-          continue;
         const float4 g0 = s_g0[kk];
         float d2;
         if (!gauss_inside(ewa, thr_ewa, g0, g1, fsub(pxc, g0.x), fsub(pyc, g0.y), d2)) continue;
@@ -1517,44 +1555,23 @@ __device__ __forceinline__ void blend_bwd_bilinear8_tile(const BlendArgs& a, uin
 //
 // Every pixel replays its blended fragments back to front as above.  A
 // Gaussian copy covers many pixels of the tile, so its gradient is a sum over
-// them: the pixels step through a chunk's copies together (back to front),
-// and for each copy every wavefront sums its lanes' terms with cross-lane
-// adds (skipped when none of its lanes blended the copy), leaving one row of
-// sums per copy in LDS.  The copy's thread then adds the wavefronts' rows,
-// chains the world-space terms through the projected covariance to (u, v, Z)
-// and writes the point's gradient (a point inside this tile only) or adds
-// this tile's share with float atomics.
-//
-// Per fragment, with e = w dL/dalpha and d = (px + 1/2 - u, py + 1/2 - v):
-//   dL/do += e;  screen-space (s2 = r^2 + dilation): dL/du += o e dx / s2,
+// them, formed in two phases per chunk of copies.  In the replay the pixels
+// step through the chunk's copies together (back to front); for every copy
+// whose footprint rectangle holds the pixel, the pixel's lane writes two
+// numbers into a (copy, pixel) table in LDS: T_k alpha_k and
+// e = w dL/dalpha_k (zero where the pixel has no blended fragment of the
+// copy).  Then each copy's own thread walks its rectangle (clipped to the
+// tile) and sums, in parallel over the chunk's copies:
+//   dL/df += (T alpha) G (G of the pixel, from LDS), dL/do += e,
+//   screen-space (s2 = r^2 + dilation): dL/du += o e dx / s2,
 //   dL/dv += o e dy / s2;  world-space (conic [[A, B], [B, C]] = S^-1):
-//   dL/du += o e (A dx + B dy), dL/dv += o e (B dx + C dy) through the offset,
-//   dL/dA += -o e dx^2 / 2, dL/dB += -o e dx dy, dL/dC += -o e dy^2 / 2,
-// and per copy (A, B, C) -> covariance (a, b, c) -> (u, v, Z) by the chain
-// rule, the covariance a function of u, v through X/Z, Y/Z and of Z through
-// fx/Z, fy/Z.
-
-// x from the lane DPP control CTRL selects, in the rows ROWS enables (0 in
-// the others).
-template <int CTRL, int ROWS>
-__device__ __forceinline__ float dpp_src(float x) {
-  return __int_as_float(
-      __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xF, false));
-}
-
-// Sum of v over the 64 lanes of a wavefront, valid in lane 63 (every lane
-// must be active): lane pairs and quads by quad permutes, half rows and rows
-// of 16 by mirrors, then rows 0 + 1 and 2 + 3 by the broadcast of lane 15 of
-// each row, and all four by the broadcast of lane 31.
-__device__ __forceinline__ float wave_sum_last(float v) {
-  v += dpp_src<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
-  v += dpp_src<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
-  v += dpp_src<0x141, 0xF>(v);  // row_half_mirror
-  v += dpp_src<0x140, 0xF>(v);  // row_mirror
-  v += dpp_src<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_src<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-  return v;
-}
+//   dL/du += o e (A dx + B dy), dL/dv += o e (B dx + C dy) through the offset
+//   d = (px + 1/2 - u, py + 1/2 - v), and dL/dA += -o e dx^2 / 2,
+//   dL/dB += -o e dx dy, dL/dC += -o e dy^2 / 2,
+// then chains (A, B, C) -> covariance (a, b, c) -> (u, v, Z) (the covariance
+// a function of u, v through X/Z, Y/Z and of Z through fx/Z, fy/Z) and writes
+// the point's gradient (a point inside this tile only) or adds this tile's
+// share with float atomics.
 
 // This tile's gradient share of every Gaussian copy of the wavefront with
 // `mine` set, added to the point's gradient with float atomics: staged as
@@ -1627,18 +1644,20 @@ __device__ __forceinline__ void add_gauss_shares(bool mine, uint32_t idx, const 
 template <int T, int CP, typename FT, bool FULL>
 __device__ __forceinline__ void blend_bwd_gauss_tile(const BlendArgs& a, uint32_t tile) {
   using G = TileGeom<T>;
-  constexpr int NW = G::NW, CH = 64, SH = G::SH;
-  // per (wavefront, copy): CP feature sums, then e, e du, e dv, e dx^2,
-  // e dx dy, e dy^2 (see above) and whether the wavefront blended the copy
-  constexpr int RS = CP + 8;
+  constexpr int NW = G::NW, NTH = G::NTH;
+  // copies per chunk: the (copy, pixel) tables stay at 2 x 8 KB
+  constexpr int CH = 2048 / NTH;
+  constexpr int TS = NTH + 1;  // table row stride (a copy's row; odd: no bank conflicts)
   __shared__ float4 s_g0[CH];
   __shared__ float4 s_g1[CH];
   __shared__ __align__(16) float s_feat[CH * fpad(CP)];
-  __shared__ __align__(16) float s_part[NW * CH * RS];
+  __shared__ __align__(16) float s_G[NTH * fpad(CP)];  // dL/dF of every pixel of the tile
+  __shared__ __align__(16) float s_ta[CH * TS];        // T alpha per (copy, pixel)
+  __shared__ __align__(16) float s_e[CH * TS];         // w dL/dalpha per (copy, pixel)
+  __shared__ unsigned long long s_pm[CH * NW];          // pixel masks of the staged copies
   __shared__ float s_red[NW][CP];
 
   const int tid = threadIdx.x;
-  const uint32_t lane = __lane_id();
   const int tx = (int)(tile % (uint32_t)a.opts.ntx), ty = (int)(tile / (uint32_t)a.opts.ntx);
   const int px = tx * T + tid % T, py = ty * T + tid / T;
   const bool inside = px < a.cam.W && py < a.cam.H;
@@ -1666,6 +1685,12 @@ __device__ __forceinline__ void blend_bwd_gauss_tile(const BlendArgs& a, uint32_
       for (int c = 0; c < C; ++c) gB = fmaf(Gv[c], bg_value(a, c, P, p), gB);
     if (a.bg_image && a.grad_bg)  // dL/df_bg(pixel) = T_final G
       for (int c = 0; c < C; ++c) a.grad_bg[c * P + p] = Tf * Gv[c];
+  }
+  {
+    float4* d4 = reinterpret_cast<float4*>(s_G + tid * fpad(CP));
+#pragma unroll
+    for (int q = 0; q < CP / 4; ++q)
+      d4[q] = make_float4(Gv[4 * q], Gv[4 * q + 1], Gv[4 * q + 2], Gv[4 * q + 3]);
   }
   if (a.bg_partial) {  // background: this tile's share of sum_p T_final G
 #pragma unroll
@@ -1697,137 +1722,119 @@ __device__ __forceinline__ void blend_bwd_gauss_tile(const BlendArgs& a, uint32_
   }
 
   float Pi = 1.f, Tcur = 0.f;
-  float* const part = s_part + (tid >> 6) * CH * RS;  // this wavefront's rows
   for (int ci = nchunks - 1; ci >= 0; --ci) {
     const uint32_t rb = (uint32_t)ci * CH;
     const int nh = (int)min((uint32_t)CH, maxlast - rb);
     const bool cur = pf.valid;
     const uint32_t cur_idx = pf.idx;
-    const float4 cur_p = pf.p;
+    const float cur_z = pf.p.w;
     if (cur) {
       stage_gauss(a, ewa, pf.p, &s_g0[tid], &s_g1[tid]);
+      rect_pixel_mask<T, NW>(__float_as_uint(s_g1[tid].y), __float_as_uint(s_g1[tid].z), tx, ty,
+                             &s_pm[tid * NW]);
       pf.f.store_f32(s_feat + tid * fpad(CP));
     }
     if (ci >= 1) pf.fetch(a, stager, list_at(start + rb - CH + tid));
-    tile_sync<NW>();
-    for (int kk = nh - 1; kk >= 0; --kk) {
+    tile_sync<NW>();  // staged copies (and, the first time, s_G) visible
+    // replay: the (copy, pixel) table entries of every copy whose rectangle
+    // holds this pixel, back to front
+    unsigned long long m = candidates<NW>(s_pm, 0, nh, tid >> 6, (uint32_t)tid & 63u);
+    while (m) {
+      const int kk = 63 - __clzll(m);
+      m &= ~(1ull << kk);
+      const float4 g1 = s_g1[kk];
       const uint32_t q1 = rb + (uint32_t)kk + 1u;  // one past the relative position
-      float ta = 0.f, e = 0.f, su = 0.f, sv = 0.f, sxx = 0.f, sxy = 0.f, syy = 0.f;
-      bool has = false;
+      float ta = 0.f, e = 0.f;
       if (q1 <= last) {
-        const float4 g1 = s_g1[kk];
-        const uint32_t lo = __float_as_uint(g1.y), hi = __float_as_uint(g1.z);
-        if (px >= unpack_x(lo) && px <= unpack_x(hi) && py >= unpack_y(lo) &&
-            py <= unpack_y(hi)) {
-          const float4 g0 = s_g0[kk];
-          const float dx = fsub(pxc, g0.x), dy = fsub(pyc, g0.y);
-          float d2;
-          if (gauss_inside(ewa, thr_ewa, g0, g1, dx, dy, d2)) {
-            const float w = gauss_value(ewa, d2, g0.w);
-            const float al = g0.z * w;
-            const float om = fsub(1.f, al);
-            float Tk;
-            if (q1 > anchor)
-              Tk = 0.f;
-            else if (q1 == anchor)
-              Tk = t_anchor;
-            else
-              Tk = __fdividef(Tcur, om);
-            const float4* fr = reinterpret_cast<const float4*>(s_feat + kk * fpad(CP));
-            float gf = 0.f;
+        const float4 g0 = s_g0[kk];
+        float d2;
+        if (gauss_inside(ewa, thr_ewa, g0, g1, fsub(pxc, g0.x), fsub(pyc, g0.y), d2)) {
+          const float w = gauss_value(ewa, d2, g0.w);
+          const float al = g0.z * w;
+          const float om = fsub(1.f, al);
+          float Tk;
+          if (q1 > anchor)
+            Tk = 0.f;
+          else if (q1 == anchor)
+            Tk = t_anchor;
+          else
+            Tk = __fdividef(Tcur, om);
+          const float4* fr = reinterpret_cast<const float4*>(s_feat + kk * fpad(CP));
+          float gf = 0.f;
 #pragma unroll
-            for (int q = 0; q < CP / 4; ++q) {
-              const float4 f4 = fr[q];
-              gf = fmaf(Gv[4 * q], f4.x, gf);
-              gf = fmaf(Gv[4 * q + 1], f4.y, gf);
-              gf = fmaf(Gv[4 * q + 2], f4.z, gf);
-              gf = fmaf(Gv[4 * q + 3], f4.w, gf);
-            }
-            const float da = Tk * (gf - gB) - GT * Tk * Pi;
-            ta = Tk * al;
-            e = da * w;
-            if (ewa) {
-              su = e * (g0.w * dx + g1.x * dy);
-              sv = e * (g1.x * dx + g1.w * dy);
-              sxx = e * (dx * dx);
-              sxy = e * (dx * dy);
-              syy = e * (dy * dy);
-            } else {
-              su = e * dx;
-              sv = e * dy;
-            }
-            gB = fmaf(al, gf, om * gB);
-            Pi = Pi * om;
-            Tcur = Tk;
-            has = true;
+          for (int q = 0; q < CP / 4; ++q) {
+            const float4 f4 = fr[q];
+            gf = fmaf(Gv[4 * q], f4.x, gf);
+            gf = fmaf(Gv[4 * q + 1], f4.y, gf);
+            gf = fmaf(Gv[4 * q + 2], f4.z, gf);
+            gf = fmaf(Gv[4 * q + 3], f4.w, gf);
           }
+          const float da = Tk * (gf - gB) - GT * Tk * Pi;
+          ta = Tk * al;
+          e = da * w;
+          gB = fmaf(al, gf, om * gB);
+          Pi = Pi * om;
+          Tcur = Tk;
         }
       }
-      float4* row = reinterpret_cast<float4*>(part + kk * RS);
-      if (__ballot(has) != 0ull) {  // uniform over the wavefront: every lane takes part
-#pragma unroll
-        for (int q = 0; q < CP / 4; ++q) {
-          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (4 * q < C) {
-            v.x = wave_sum_last(ta * Gv[4 * q]);
-            v.y = wave_sum_last(ta * Gv[4 * q + 1]);
-            v.z = wave_sum_last(ta * Gv[4 * q + 2]);
-            v.w = wave_sum_last(ta * Gv[4 * q + 3]);
-          }
-          if (lane == 63u) row[q] = v;
-        }
-        const float r0 = wave_sum_last(e), r1 = wave_sum_last(su), r2 = wave_sum_last(sv);
-        float r3 = 0.f, r4 = 0.f, r5 = 0.f;
-        if (ewa) {
-          r3 = wave_sum_last(sxx);
-          r4 = wave_sum_last(sxy);
-          r5 = wave_sum_last(syy);
-        }
-        if (lane == 63u) {
-          row[CP / 4] = make_float4(r0, r1, r2, r3);
-          row[CP / 4 + 1] = make_float4(r4, r5, 1.f, 0.f);
-        }
-      } else if (lane == 63u) {
-        row[CP / 4 + 1] = make_float4(0.f, 0.f, 0.f, 0.f);  // not blended here
-      }
+      s_ta[kk * TS + tid] = ta;
+      s_e[kk * TS + tid] = e;
     }
     tile_sync<NW>();
-    // the copy's thread: its rows summed over the wavefronts, chained, written
+    // the copy's thread: its rectangle's table entries summed, chained, written
     float gfeat[CP];
 #pragma unroll
     for (int c = 0; c < CP; ++c) gfeat[c] = 0.f;
     float4 sc = make_float4(0.f, 0.f, 0.f, 0.f);
     bool touched = false, single = false;
     if (cur) {
-      float S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        const float4* r = reinterpret_cast<const float4*>(s_part + (w * CH + tid) * RS);
-        const float4 t1 = r[CP / 4 + 1];
-        if (t1.z == 0.f) continue;  // this wavefront did not blend the copy
-        touched = true;
-#pragma unroll
-        for (int q = 0; q < CP / 4; ++q) {
-          const float4 f4 = r[q];
-          gfeat[4 * q] += f4.x;
-          gfeat[4 * q + 1] += f4.y;
-          gfeat[4 * q + 2] += f4.z;
-          gfeat[4 * q + 3] += f4.w;
-        }
-        const float4 t0 = r[CP / 4];
-        S[0] += t0.x; S[1] += t0.y; S[2] += t0.z; S[3] += t0.w;
-        S[4] += t1.x; S[5] += t1.y;
-      }
-      const float o = cur_p.z;
       const float4 g0 = s_g0[tid], g1 = s_g1[tid];
+      const uint32_t lo = __float_as_uint(g1.y), hi = __float_as_uint(g1.z);
+      const int x0 = max(unpack_x(lo) - tx * T, 0), x1 = min(unpack_x(hi) - tx * T, T - 1);
+      const int y0 = max(unpack_y(lo) - ty * T, 0), y1 = min(unpack_y(hi) - ty * T, T - 1);
+      single = (unpack_x(lo) >> G::SH) == (unpack_x(hi) >> G::SH) &&
+               (unpack_y(lo) >> G::SH) == (unpack_y(hi) >> G::SH);
+      float se = 0.f, su = 0.f, sv = 0.f, sxx = 0.f, sxy = 0.f, syy = 0.f;
+      const float* rta = s_ta + tid * TS;
+      const float* re = s_e + tid * TS;
+      for (int y = y0; y <= y1; ++y) {
+        const float dy = fsub(fadd((float)(ty * T + y), 0.5f), g0.y);
+        for (int x = x0; x <= x1; ++x) {
+          const int q = y * T + x;
+          const float ta = rta[q], e = re[q];
+          if (ta == 0.f && e == 0.f) continue;
+          touched = true;
+          const float4* gp = reinterpret_cast<const float4*>(s_G + q * fpad(CP));
+#pragma unroll
+          for (int k = 0; k < CP / 4; ++k) {
+            const float4 g4 = gp[k];
+            gfeat[4 * k] = fmaf(ta, g4.x, gfeat[4 * k]);
+            gfeat[4 * k + 1] = fmaf(ta, g4.y, gfeat[4 * k + 1]);
+            gfeat[4 * k + 2] = fmaf(ta, g4.z, gfeat[4 * k + 2]);
+            gfeat[4 * k + 3] = fmaf(ta, g4.w, gfeat[4 * k + 3]);
+          }
+          const float dx = fsub(fadd((float)(tx * T + x), 0.5f), g0.x);
+          se += e;
+          if (ewa) {
+            su = fmaf(e, g0.w * dx + g1.x * dy, su);
+            sv = fmaf(e, g1.x * dx + g1.w * dy, sv);
+            sxx = fmaf(e, dx * dx, sxx);
+            sxy = fmaf(e, dx * dy, sxy);
+            syy = fmaf(e, dy * dy, syy);
+          } else {
+            su = fmaf(e, dx, su);
+            sv = fmaf(e, dy, sv);
+          }
+        }
+      }
+      const float o = g0.z;
       float gu, gv, gz = 0.f;
       if (!ewa) {
-        gu = o * S[1] / g0.w;
-        gv = o * S[2] / g0.w;
+        gu = o * su / g0.w;
+        gv = o * sv / g0.w;
       } else {
-        const EwaCov k = ewa_cov(cur_p.x, cur_p.y, cur_p.w, a.cam, a.opts.dilation,
-                                 a.opts.ewa_sigma);
-        const float gA = -0.5f * o * S[3], gBc = -o * S[4], gC = -0.5f * o * S[5];
+        const EwaCov k = ewa_cov(g0.x, g0.y, cur_z, a.cam, a.opts.dilation, a.opts.ewa_sigma);
+        const float gA = -0.5f * o * sxx, gBc = -o * sxy, gC = -0.5f * o * syy;
         const float inv = 1.f / (k.a * k.c - k.b * k.b);
         const float ga = (-k.c * k.c * gA + k.b * k.c * gBc - k.b * k.b * gC) * inv * inv;
         const float gb = (2.f * k.b * k.c * gA - (k.a * k.c + k.b * k.b) * gBc +
@@ -1835,26 +1842,24 @@ __device__ __forceinline__ void blend_bwd_gauss_tile(const BlendArgs& a, uint32_
         const float gc = (-k.b * k.b * gA + k.a * k.b * gBc - k.a * k.a * gC) * inv * inv;
         const float kxx = k.s2w * k.jx * k.jx, kxy = k.s2w * k.jx * k.jy,
                     kyy = k.s2w * k.jy * k.jy;
-        gu = o * S[1] + (ga * kxx * 2.f * k.xh + gb * kxy * k.yh) / a.cam.fx;
-        gv = o * S[2] + (gb * kxy * k.xh + gc * kyy * 2.f * k.yh) / a.cam.fy;
-        gz = -2.f / cur_p.w *
+        gu = o * su + (ga * kxx * 2.f * k.xh + gb * kxy * k.yh) / a.cam.fx;
+        gv = o * sv + (gb * kxy * k.xh + gc * kyy * 2.f * k.yh) / a.cam.fy;
+        gz = -2.f / cur_z *
              (ga * kxx * (1.f + k.xh * k.xh) + gb * kxy * (k.xh * k.yh) +
               gc * kyy * (1.f + k.yh * k.yh));
       }
-      sc = make_float4(S[0], gu, gv, gz);
-      const uint32_t lo = __float_as_uint(g1.y), hi = __float_as_uint(g1.z);
-      single = (unpack_x(lo) >> SH) == (unpack_x(hi) >> SH) &&
-               (unpack_y(lo) >> SH) == (unpack_y(hi) >> SH);
+      sc = make_float4(se, gu, gv, gz);
       if (touched && single) {  // the only tile of this point: its whole gradient
         store_row<CP>(a.grad_feat + (size_t)cur_idx * C, gfeat, C);
         a.gsc[cur_idx] = sc;
       }
     }
     // split points: this tile's share by float atomics, staged in the first
-    // wavefront's rows (only it holds copies; its reads above are done)
+    // wavefront's part of the tables (only it holds copies; its reads above
+    // are done)
     if (tid < 64)
-      add_gauss_shares<CP>(cur && touched && !single, cur_idx, gfeat, sc, ewa ? 4u : 3u,
-                           s_part, a);
+      add_gauss_shares<CP>(cur && touched && !single, cur_idx, gfeat, sc, ewa ? 4u : 3u, s_ta,
+                           a);
     tile_sync<NW>();
   }
 }
