@@ -11,6 +11,10 @@ oracle on the same seeded inputs, element by element.
   C3  2^23 screen-space Gaussians, 1920x1080, C = 16, forward: binning and
       tile lists in full, the image on a sample of whole tiles (the oracle's
       full fragment set, about 900 M fragments, would not fit in host memory)
+  H as world-space Gaussians (EWA projection, the paper's default scale),
+      forward + backward, the depth gradient included
+  R   a ring of four 2^21-point clouds (two slots partly stale) rendered as
+      one, forward + backward, against the concatenated live points
 
 Binning, keys, per-tile counts and lists bit-exact; images and gradients
 within 1e-6 + 1e-5 max(|oracle|, sum of term magnitudes)."""
@@ -86,3 +90,59 @@ def test_c3_full_gaussian_forward_sampled_tiles():
     np.testing.assert_array_equal(g["n_contrib"][ok], rr["n_contrib"][ok])
     assert_close("out", g["out"], rr["out"], rr["out_abs"], mask=ok)
     assert_close("t_final", g["t_final"], rr["t_final"], rr["t_final"], mask=ok)
+
+
+def test_h_full_world_space_forward_backward():
+    """The H scene as world-space Gaussians of the paper's default scale (5 px
+    at the near plane): binning bit-exact, every image and gradient element
+    (the depth gradient through the projected covariance included) within
+    tolerance; pixels on the t_min threshold have their upstream gradients
+    set to zero on both sides."""
+    from gpu_helpers import mask_flagged
+    print("case H ewa: generating the scene", flush=True)
+    sc = make_scene(CONFIGS["H"])
+    st = settings_opts(splat="ewa", tile=8)
+    ok = mask_flagged(sc, st)
+    print(f"case H ewa: {int((~ok).sum())} flagged pixels", flush=True)
+    assert ok.mean() > 0.999
+    g = run_gpu(sc, st)
+    print(f"case H ewa: GPU done, copies={int(g['ranges'][-1])}", flush=True)
+    proj, tl, rr = run_oracle(sc, st)
+    print("case H ewa: oracle done", flush=True)
+    assert_binning_exact(g, proj, tl)
+    assert_forward(g, rr, flags_ok=ok)
+    assert_backward(g, rr, sc.grad)
+
+
+def test_ring_full_size_union():
+    """The ring of the R workload (four 2^21-point clouds, two slots partly
+    stale, 1920x1080, C = 16) rendered as one, forward and backward, against
+    the oracle on the concatenated live points; slot tails get no copies and
+    zero gradients."""
+    import dataclasses
+    from scenes import Scene
+    per = 1 << 21
+    counts = [per, per - 100_000, per, per - 50_000]
+    spec = dataclasses.replace(CONFIGS["H"], n=4 * per)
+    full = make_scene(spec)
+    live = np.concatenate([np.arange(k * per, k * per + c) for k, c in enumerate(counts)])
+    st = settings_opts(tile=8)
+    sc = Scene(pos=full.pos, opacity=full.opacity, feat=full.feat, camera=full.camera,
+               grad=full.grad)
+    g = run_gpu(sc, st, ring_counts=counts)
+    print(f"case ring: GPU done, copies={int(g['ranges'][-1])}", flush=True)
+    sub = Scene(pos=full.pos[live], opacity=full.opacity[live], feat=full.feat[live],
+                camera=full.camera, grad=full.grad)
+    proj, tl, rr = run_oracle(sub, st)
+    print("case ring: oracle done", flush=True)
+    dead = np.ones(4 * per, bool)
+    dead[live] = False
+    assert (g["ntiles"][dead] == 0).all()
+    np.testing.assert_array_equal(g["ntiles"][live], proj["ntiles"])
+    np.testing.assert_array_equal(g["ranges"].astype(np.int64), tl["ranges"])
+    M = int(tl["ranges"][-1])
+    np.testing.assert_array_equal(g["list"][:M].astype(np.int64), live[tl["list"]])
+    assert_forward(g, rr)
+    for k in ("grad_feat", "grad_opacity", "grad_uv", "grad_pos"):
+        assert (g[k][dead] == 0).all(), k
+        assert_close(k, g[k][live], rr[k], rr[k + "_abs"])
