@@ -79,8 +79,9 @@ def parse():
     return ap.parse_args()
 
 
-# Kernels launched by each C-ABI entry point (name prefixes) and how many
-# times a recomputing training step calls the entry point.
+# Kernels launched by each C-ABI entry point (name prefixes).  Every entry
+# point launches at least one of its kernels exactly once per call, so its
+# number of calls in a trace is the smallest launch count among its kernels.
 ENTRY_KERNELS = {
     "project": ("k_project_count", "k_colscan", "k_clear", "k_groups"),
     "bin": ("k_group_scan", "k_place", "k_scatter"),
@@ -92,8 +93,12 @@ ENTRY_KERNELS = {
     "background": ("k_view_dirs", "k_envmap_fwd", "k_envmap_bwd", "k_fill_zero"),
     "sh": ("k_sh_fwd", "k_sh_bwd"),
 }
-CALLS_PER_STEP = {"project": 2, "bin": 2, "sort": 2, "blend_fwd": 1, "blend_bwd": 1,
-                  "project_bwd": 1}
+
+
+def _entry_calls(launches, entry):
+    """Calls of `entry` from {kernel: launch count} of a trace."""
+    c = [n for k, n in launches.items() if _entry_of(k) == entry and n > 0]
+    return min(c) if c else 0
 SOURCES = ["include/inpc_raster.h"] + [f"paper_2508_19140_amd/csrc/{f}" for f in
                                        ("api.hip", "project.hip", "sort.hip", "blend.hip",
                                         "background.hip", "batch.hip", "sh.hip", "common.h",
@@ -131,14 +136,17 @@ def summarize_trace(d, steps, command):
     print(f"Command: `{command}`\n\nrocprofv3 `run_kernel_stats.csv`, {steps} steps, "
           f"averages per launch.\n")
     print("\n".join(out))
-    per_entry = {}
+    per_entry, launches = {}, {}
     for r in rows:
-        e = _entry_of(_kernel_short(r["Name"]))
+        k = _kernel_short(r["Name"])
+        e = _entry_of(k)
         if e:
             per_entry[e] = per_entry.get(e, 0.0) + float(r["TotalDurationNs"])
-    print("\n| entry point | kernel time per call, us |\n|---|---:|")
+            launches[k] = launches.get(k, 0) + int(r["Calls"])
+    print("\n| entry point | calls/step | kernel time per call, us |\n|---|---:|---:|")
     for e, t in sorted(per_entry.items(), key=lambda x: -x[1]):
-        print(f"| inpc_{e} | {t / steps / CALLS_PER_STEP[e] / 1e3:.1f} |")
+        calls = _entry_calls(launches, e)
+        print(f"| inpc_{e} | {calls / steps:g} | {t / calls / 1e3:.1f} |")
     print(f"\nsum of kernel time per step: {tot / steps / 1e3:.1f} us")
 
 
@@ -185,7 +193,7 @@ def summarize_pmc(fetch_dir, write_dir, entry, steps, command):
     fetch_scale, write_scale = cw / cf, 1.0
     lines = []
     per_launch_f = per_launch_w = 0.0
-    calls = CALLS_PER_STEP[entry] * steps
+    calls = _entry_calls({k: len(v) for k, v in fetch.items()}, entry)
     for k in sorted(set(fetch) | set(write)):
         if _entry_of(k) != entry:
             continue

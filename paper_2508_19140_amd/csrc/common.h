@@ -69,6 +69,8 @@ enum : int {
   kFlagCountB1 = 6,  // sub-segments to split a second time
   kFlagCountG = 7,   // sub-segments of more than 16384 copies to split through global memory again
   kFlagCountX2 = 8,  // segments left for the global-memory LSD sort
+  kFlagSplitNext0 = 9,   // work counters of the two split rounds (segments taken so far)
+  kFlagSplitNext1 = 10,
   kFlagSlots = 16
 };
 

@@ -352,6 +352,13 @@ __global__ __launch_bounds__(64) void k_place(int64_t nt, const uint32_t* __rest
     ws.flags[kFlagCountM] = (uint32_t)ws.coltot[2];
     ws.flags[kFlagCountB0] = (uint32_t)ws.coltot[3];
     ws.flags[kFlagCountX] = (uint32_t)ws.coltot[4];
+    // the sort's own counters start at zero for every bin
+    ws.flags[kFlagCountB1] = 0u;
+    ws.flags[kFlagCountG] = 0u;
+    ws.flags[kFlagCountL] = 0u;
+    ws.flags[kFlagCountX2] = 0u;
+    ws.flags[kFlagSplitNext0] = 0u;
+    ws.flags[kFlagSplitNext1] = 0u;
     if (total > (uint64_t)ws.cap) ws.flags[kFlagOverflow] = 1u;
   }
   if (order) {

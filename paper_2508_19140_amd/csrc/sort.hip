@@ -605,144 +605,140 @@ __device__ void push_segments(uint2 sg, int round, const Ws& ws, uint32_t* s_cnt
   __syncthreads();
 }
 
-// MSD split of segments with 2048 < n <= 16384 copies (in place).
-__device__ void split_global_blocks(int round, const Ws& ws, uint32_t b, uint32_t nb,
-                                    uint32_t* s_cnt, uint32_t* s_off, uint32_t* s_red,
-                                    uint32_t* s_pc, uint32_t* s_pb);
+// Digit of a split: the top 8 bits of ((key - kmin) << ib) | (idx - imin),
+// from the segment's key and index ranges (min/max of its pairs reduced over
+// the block).
+struct SplitDigit {
+  uint32_t k0, i0, ib, sh;
+  __device__ __forceinline__ uint32_t operator()(uint2 v) const {
+    const uint64_t c = ((uint64_t)(v.x - k0) << ib) | (uint64_t)(v.y - i0);
+    return (uint32_t)(c >> sh);
+  }
+};
 
-// One split round: workgroups [0, gl) split the LDS-sized segments of the
-// round (2048 < n <= 16384) in LDS, the others split the larger ones through
-// global memory.
-__global__ __launch_bounds__(1024) void k_split(int round, int gl, Ws ws) {
+__device__ __forceinline__ SplitDigit split_digit(uint32_t kmin, uint32_t kmax, uint32_t imin,
+                                                  uint32_t imax, uint32_t* s_red) {
+  const uint32_t lane = __lane_id(), w = threadIdx.x >> 6;
+  kmin = wave_min(kmin); kmax = wave_max(kmax);
+  imin = wave_min(imin); imax = wave_max(imax);
+  if (lane == 0) {
+    s_red[w * 4 + 0] = kmin; s_red[w * 4 + 1] = kmax;
+    s_red[w * 4 + 2] = imin; s_red[w * 4 + 3] = imax;
+  }
+  __syncthreads();
+  kmin = 0xffffffffu; kmax = 0; imin = 0xffffffffu; imax = 0;
+  for (int ww = 0; ww < 16; ++ww) {
+    kmin = min(kmin, s_red[ww * 4 + 0]); kmax = max(kmax, s_red[ww * 4 + 1]);
+    imin = min(imin, s_red[ww * 4 + 2]); imax = max(imax, s_red[ww * 4 + 3]);
+  }
+  SplitDigit d;
+  d.ib = nbits(imax - imin);
+  const uint32_t total = nbits(kmax - kmin) + d.ib;
+  d.sh = total > 8 ? total - 8 : 0;
+  d.k0 = kmin;
+  d.i0 = imin;
+  return d;
+}
+
+// Exclusive scan of the 256 digit counts into s_off (first wavefront), and
+// the sub-segment of digit threadIdx.x (threads < 256), taken before the
+// offsets are consumed.
+__device__ __forceinline__ uint2 split_offsets(uint2 sg, const uint32_t* s_cnt, uint32_t* s_off) {
+  const uint32_t lane = __lane_id(), w = threadIdx.x >> 6;
+  if (w == 0) {
+    uint32_t t4[4], s = 0;
+    for (int q = 0; q < 4; ++q) { t4[q] = s_cnt[lane * 4 + q]; s += t4[q]; }
+    uint32_t ex = wave_incl_scan(s) - s;
+    for (int q = 0; q < 4; ++q) { s_off[lane * 4 + q] = ex; ex += t4[q]; }
+  }
+  __syncthreads();
+  uint2 sub = make_uint2(0u, 0u);
+  if (threadIdx.x < 256) sub = make_uint2(sg.x + s_off[threadIdx.x], s_cnt[threadIdx.x]);
+  __syncthreads();
+  return sub;
+}
+
+// MSD split of one segment of 2048 < n <= 16384 copies in LDS (in place).
+__device__ void split_lds(uint2 sg, int round, const Ws& ws, uint2* s_e, uint32_t* s_cnt,
+                          uint32_t* s_off, uint32_t* s_red, uint32_t* s_pc, uint32_t* s_pb) {
+  const uint32_t n = sg.y;
+  uint2* g = ws.bucket + sg.x;
+  uint32_t kmin = 0xffffffffu, kmax = 0, imin = 0xffffffffu, imax = 0;
+  for (uint32_t e = threadIdx.x; e < n; e += 1024) {
+    const uint2 v = g[e];
+    s_e[e] = v;
+    kmin = min(kmin, v.x); kmax = max(kmax, v.x);
+    imin = min(imin, v.y); imax = max(imax, v.y);
+  }
+  if (threadIdx.x < 256) s_cnt[threadIdx.x] = 0;
+  const SplitDigit digit = split_digit(kmin, kmax, imin, imax, s_red);
+  for (uint32_t e = threadIdx.x; e < n; e += 1024) atomicAdd(&s_cnt[digit(s_e[e])], 1u);
+  __syncthreads();
+  const uint2 sub = split_offsets(sg, s_cnt, s_off);
+  for (uint32_t e = threadIdx.x; e < n; e += 1024) {
+    const uint2 v = s_e[e];
+    g[atomicAdd(&s_off[digit(v)], 1u)] = v;
+  }
+  push_segments(sub, round == 0 ? kLdsRound0 : kLdsRound1, ws, s_pc, s_pb);
+}
+
+// MSD split of one segment of more than 16384 copies, through global memory:
+// the same digit, the segment scattered by digit into the ping-pong buffer
+// and copied back.
+__device__ void split_global(uint2 sg, int round, const Ws& ws, uint32_t* s_cnt, uint32_t* s_off,
+                             uint32_t* s_red, uint32_t* s_pc, uint32_t* s_pb) {
+  const uint32_t n = sg.y;
+  uint2* g = ws.bucket + sg.x;
+  uint2* x = ws.xbucket + sg.x;
+  uint32_t kmin = 0xffffffffu, kmax = 0, imin = 0xffffffffu, imax = 0;
+  for (uint32_t e = threadIdx.x; e < n; e += 1024) {
+    const uint2 v = g[e];
+    kmin = min(kmin, v.x); kmax = max(kmax, v.x);
+    imin = min(imin, v.y); imax = max(imax, v.y);
+  }
+  if (threadIdx.x < 256) s_cnt[threadIdx.x] = 0;
+  const SplitDigit digit = split_digit(kmin, kmax, imin, imax, s_red);
+  for (uint32_t e = threadIdx.x; e < n; e += 1024) atomicAdd(&s_cnt[digit(g[e])], 1u);
+  __syncthreads();
+  const uint2 sub = split_offsets(sg, s_cnt, s_off);
+  for (uint32_t e = threadIdx.x; e < n; e += 1024) {
+    const uint2 v = g[e];
+    x[atomicAdd(&s_off[digit(v)], 1u)] = v;
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (uint32_t e = threadIdx.x; e < n; e += 1024) g[e] = x[e];
+  __threadfence_block();
+  push_segments(sub, round == 0 ? kGlobalRound0 : kGlobalRound1, ws, s_pc, s_pb);
+}
+
+// One split round over a work counter: the segments of more than 16384
+// copies first (each takes a workgroup far longer), then the LDS-sized ones
+// (2048 < n <= 16384), each workgroup taking the next segment when done, so
+// that the long global splits start at once and the rest fill in around them.
+__global__ __launch_bounds__(1024) void k_split(int round, Ws ws) {
   __shared__ uint2 s_e[kSortCapL];
   __shared__ uint32_t s_cnt[256], s_off[256];
   __shared__ uint32_t s_red[64];
   __shared__ uint32_t s_pc[4], s_pb[4];
+  __shared__ uint32_t s_item;
   if (ws.flags[kFlagOverflow]) return;
-  if ((int)blockIdx.x >= gl) {
-    split_global_blocks(round, ws, blockIdx.x - (uint32_t)gl, gridDim.x - (uint32_t)gl, s_cnt,
-                        s_off, s_red, s_pc, s_pb);
-    return;
-  }
-  const uint2* segs = round == 0 ? ws.seg_b0 : ws.seg_b1;
-  const uint32_t count = ws.flags[round == 0 ? kFlagCountB0 : kFlagCountB1];
-  const uint32_t lane = __lane_id(), w = threadIdx.x >> 6;
-  for (uint32_t i = blockIdx.x; i < count; i += (uint32_t)gl) {
-    const uint2 sg = segs[i];
-    const uint32_t n = sg.y;
-    uint2* g = ws.bucket + sg.x;
-    uint32_t kmin = 0xffffffffu, kmax = 0, imin = 0xffffffffu, imax = 0;
-    for (uint32_t e = threadIdx.x; e < n; e += 1024) {
-      const uint2 v = g[e];
-      s_e[e] = v;
-      kmin = min(kmin, v.x); kmax = max(kmax, v.x);
-      imin = min(imin, v.y); imax = max(imax, v.y);
-    }
-    if (threadIdx.x < 256) s_cnt[threadIdx.x] = 0;
-    kmin = wave_min(kmin); kmax = wave_max(kmax);
-    imin = wave_min(imin); imax = wave_max(imax);
-    if (lane == 0) {
-      s_red[w * 4 + 0] = kmin; s_red[w * 4 + 1] = kmax;
-      s_red[w * 4 + 2] = imin; s_red[w * 4 + 3] = imax;
-    }
+  const uint2* big = round == 0 ? ws.seg_x : ws.seg_g;
+  const uint2* mid = round == 0 ? ws.seg_b0 : ws.seg_b1;
+  const uint32_t nbig = ws.flags[round == 0 ? kFlagCountX : kFlagCountG];
+  const uint32_t nmid = ws.flags[round == 0 ? kFlagCountB0 : kFlagCountB1];
+  uint32_t* next = &ws.flags[round == 0 ? kFlagSplitNext0 : kFlagSplitNext1];
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(next, 1u);
     __syncthreads();
-    kmin = 0xffffffffu; kmax = 0; imin = 0xffffffffu; imax = 0;
-    for (int ww = 0; ww < 16; ++ww) {
-      kmin = min(kmin, s_red[ww * 4 + 0]); kmax = max(kmax, s_red[ww * 4 + 1]);
-      imin = min(imin, s_red[ww * 4 + 2]); imax = max(imax, s_red[ww * 4 + 3]);
-    }
-    // digit: top 8 bits of ((key - kmin) << ib) | (idx - imin)
-    const uint32_t ib = nbits(imax - imin);
-    const uint32_t total = nbits(kmax - kmin) + ib;
-    const uint32_t sh = total > 8 ? total - 8 : 0;
-    const uint32_t k0 = kmin, i0 = imin;
-    auto digit = [=](uint2 v) -> uint32_t {
-      const uint64_t c = ((uint64_t)(v.x - k0) << ib) | (uint64_t)(v.y - i0);
-      return (uint32_t)(c >> sh);
-    };
-    for (uint32_t e = threadIdx.x; e < n; e += 1024) atomicAdd(&s_cnt[digit(s_e[e])], 1u);
-    __syncthreads();
-    if (w == 0) {
-      uint32_t t4[4], s = 0;
-      for (int q = 0; q < 4; ++q) { t4[q] = s_cnt[lane * 4 + q]; s += t4[q]; }
-      uint32_t ex = wave_incl_scan(s) - s;
-      for (int q = 0; q < 4; ++q) { s_off[lane * 4 + q] = ex; ex += t4[q]; }
-    }
-    __syncthreads();
-    // sub-segment descriptors, taken before the offsets are consumed
-    uint2 sub = make_uint2(0u, 0u);
-    if (threadIdx.x < 256) sub = make_uint2(sg.x + s_off[threadIdx.x], s_cnt[threadIdx.x]);
-    __syncthreads();
-    for (uint32_t e = threadIdx.x; e < n; e += 1024) {
-      const uint2 v = s_e[e];
-      g[atomicAdd(&s_off[digit(v)], 1u)] = v;
-    }
-    push_segments(sub, round == 0 ? kLdsRound0 : kLdsRound1, ws, s_pc, s_pb);
-  }
-}
-
-// MSD split of segments of more than 16384 copies, through global memory:
-// the same digit as the LDS split, the segment scattered by digit into the
-// ping-pong buffer and copied back, its sub-segments queued by size.
-__device__ void split_global_blocks(int round, const Ws& ws, uint32_t b, uint32_t nb,
-                                    uint32_t* s_cnt, uint32_t* s_off, uint32_t* s_red,
-                                    uint32_t* s_pc, uint32_t* s_pb) {
-  const uint2* segs = round == 0 ? ws.seg_x : ws.seg_g;
-  const uint32_t count = ws.flags[round == 0 ? kFlagCountX : kFlagCountG];
-  const uint32_t lane = __lane_id(), w = threadIdx.x >> 6;
-  for (uint32_t i = b; i < count; i += nb) {
-    const uint2 sg = segs[i];
-    const uint32_t n = sg.y;
-    uint2* g = ws.bucket + sg.x;
-    uint2* x = ws.xbucket + sg.x;
-    uint32_t kmin = 0xffffffffu, kmax = 0, imin = 0xffffffffu, imax = 0;
-    for (uint32_t e = threadIdx.x; e < n; e += 1024) {
-      const uint2 v = g[e];
-      kmin = min(kmin, v.x); kmax = max(kmax, v.x);
-      imin = min(imin, v.y); imax = max(imax, v.y);
-    }
-    if (threadIdx.x < 256) s_cnt[threadIdx.x] = 0;
-    kmin = wave_min(kmin); kmax = wave_max(kmax);
-    imin = wave_min(imin); imax = wave_max(imax);
-    if (lane == 0) {
-      s_red[w * 4 + 0] = kmin; s_red[w * 4 + 1] = kmax;
-      s_red[w * 4 + 2] = imin; s_red[w * 4 + 3] = imax;
-    }
-    __syncthreads();
-    kmin = 0xffffffffu; kmax = 0; imin = 0xffffffffu; imax = 0;
-    for (int ww = 0; ww < 16; ++ww) {
-      kmin = min(kmin, s_red[ww * 4 + 0]); kmax = max(kmax, s_red[ww * 4 + 1]);
-      imin = min(imin, s_red[ww * 4 + 2]); imax = max(imax, s_red[ww * 4 + 3]);
-    }
-    const uint32_t ib = nbits(imax - imin);
-    const uint32_t total = nbits(kmax - kmin) + ib;
-    const uint32_t sh = total > 8 ? total - 8 : 0;
-    const uint32_t k0 = kmin, i0 = imin;
-    auto digit = [=](uint2 v) -> uint32_t {
-      const uint64_t c = ((uint64_t)(v.x - k0) << ib) | (uint64_t)(v.y - i0);
-      return (uint32_t)(c >> sh);
-    };
-    for (uint32_t e = threadIdx.x; e < n; e += 1024) atomicAdd(&s_cnt[digit(g[e])], 1u);
-    __syncthreads();
-    if (w == 0) {
-      uint32_t t4[4], s = 0;
-      for (int q = 0; q < 4; ++q) { t4[q] = s_cnt[lane * 4 + q]; s += t4[q]; }
-      uint32_t ex = wave_incl_scan(s) - s;
-      for (int q = 0; q < 4; ++q) { s_off[lane * 4 + q] = ex; ex += t4[q]; }
-    }
-    __syncthreads();
-    uint2 sub = make_uint2(0u, 0u);
-    if (threadIdx.x < 256) sub = make_uint2(sg.x + s_off[threadIdx.x], s_cnt[threadIdx.x]);
-    __syncthreads();
-    for (uint32_t e = threadIdx.x; e < n; e += 1024) {
-      const uint2 v = g[e];
-      x[atomicAdd(&s_off[digit(v)], 1u)] = v;
-    }
-    __threadfence_block();
-    __syncthreads();
-    for (uint32_t e = threadIdx.x; e < n; e += 1024) g[e] = x[e];
-    __threadfence_block();
-    push_segments(sub, round == 0 ? kGlobalRound0 : kGlobalRound1, ws, s_pc, s_pb);
+    const uint32_t it = s_item;
+    __syncthreads();  // every thread has read s_item before it is taken again
+    if (it < nbig)
+      split_global(big[it], round, ws, s_cnt, s_off, s_red, s_pc, s_pb);
+    else if (it - nbig < nmid)
+      split_lds(mid[it - nbig], round, ws, s_e, s_cnt, s_off, s_red, s_pc, s_pb);
+    else
+      break;
   }
 }
 
@@ -878,9 +874,10 @@ hipError_t launch_sort(const Ws& ws, uint32_t* list, uint16_t* lpos, int64_t nt,
   const int64_t big_max = std::max<int64_t>(1, (int64_t)ws.cap / (int64_t)(kSortCapM + 1));
   const int grid_split = (int)std::min<int64_t>(big_max, 1024);
   const int grid_rare = (int)std::min<int64_t>(big_max, 256);
-  const int grid_huge = (int)std::min<int64_t>(std::max<int64_t>(1, (int64_t)ws.cap / (kSortCapL + 1)), 64);
-  hipLaunchKernelGGL(k_split, dim3(grid_split + grid_huge), dim3(1024), 0, stream, 0, grid_split, ws);
-  hipLaunchKernelGGL(k_split, dim3(grid_rare + grid_huge), dim3(1024), 0, stream, 1, grid_rare, ws);
+  // the split rounds: one workgroup per CU (128 KB of LDS each) over a work
+  // counter
+  hipLaunchKernelGGL(k_split, dim3(std::min(grid_split, 256)), dim3(1024), 0, stream, 0, ws);
+  hipLaunchKernelGGL(k_split, dim3(std::min(grid_rare, 256)), dim3(1024), 0, stream, 1, ws);
   const int grid_w = (int)std::min<int64_t>((nt + 3) / 4 + (int64_t)ws.cap / 256, 8192);
   const int grid_m = (int)std::min<int64_t>(nt + (int64_t)ws.cap / 2048, 4096);
   hipLaunchKernelGGL(k_sort_wm, dim3(std::max(grid_m, 1) + std::max(grid_w, 1)), dim3(256), 0,

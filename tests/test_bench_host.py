@@ -68,7 +68,9 @@ def test_summarize_trace_per_step(tmp_path, capsys):
     b.summarize_trace(str(tmp_path), 3, "cmd")
     out = capsys.readouterr().out
     assert "`k_scatter` | bin | 6 | 2 | 200.0 | 400.0 |" in out
-    assert "| inpc_blend_fwd | 300.0 |" in out
+    # calls per step from the launch counts: bin twice, the forward blend once
+    assert "| inpc_blend_fwd | 1 | 300.0 |" in out
+    assert "| inpc_bin | 2 | 200.0 |" in out
     assert "sum of kernel time per step: 700.0 us" in out
 
 
