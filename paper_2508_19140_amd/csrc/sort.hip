@@ -482,11 +482,17 @@ __device__ void sort_segment_lds(const uint2* __restrict__ seg, uint32_t n, cons
 // Lanes without an element publish an all-ones pair, which no element
 // (key bit 31 is clear) counts as smaller, so the count runs over whole
 // groups of eight with 16-byte LDS reads.
-__device__ void rank_sort_wave(const uint2* __restrict__ seg, uint32_t n, const ListOut& out,
-                               uint32_t base, uint2* __restrict__ s) {
+// The lane's pair of a segment of n <= 64 (all ones past the end).
+__device__ __forceinline__ uint2 small_pair(const uint2* __restrict__ bucket, uint2 sg) {
+  const uint32_t lane = __lane_id();
+  return sg.y <= 64u && lane < sg.y ? bucket[sg.x + lane] : make_uint2(0xffffffffu, 0xffffffffu);
+}
+
+// `v`: the lane's pair (small_pair).
+__device__ void rank_sort_wave(uint2 v, uint32_t n, const ListOut& out, uint32_t base,
+                               uint2* __restrict__ s) {
   const uint32_t lane = __lane_id();
   const bool valid = lane < n;
-  const uint2 v = valid ? seg[lane] : make_uint2(0xffffffffu, 0xffffffffu);
   s[lane] = v;
   bsync<true>();
   const uint64_t me = ((uint64_t)v.x << 32) | v.y;
@@ -549,14 +555,30 @@ __global__ __launch_bounds__(256) void k_sort_wm(int gm, const uint2* __restrict
     uint32_t* b = s_lds + w * kW_WORDS;  // 16-byte aligned: kW_WORDS is a multiple of 4
     const SortSmem sm{b, b + kW_CAP, b + 2 * kW_CAP, b + 2 * kW_CAP + 256, b + 2 * kW_CAP + 512};
     const uint32_t count = flags[kFlagCountW];
-    const uint32_t nb = gridDim.x - (uint32_t)gm;
-    for (uint32_t i = (blockIdx.x - (uint32_t)gm) * 4 + w; i < count; i += nb * 4) {
-      const uint2 sg = seg_w[i];
-      if (sg.y <= 64)
-        rank_sort_wave(bucket + sg.x, sg.y, out, sg.x, reinterpret_cast<uint2*>(b));
-      else if (!bucket_sort_segment<1, kW_ITEMS, kW_HB, true, kBucketMax>(bucket + sg.x, sg.y,
-                                                                           out, sg.x, sm))
-        sort_segment_lds<1, kW_ITEMS, true>(bucket + sg.x, sg.y, out, sg.x, sm);
+    const uint32_t stride = (gridDim.x - (uint32_t)gm) * 4u;
+    const uint2 none = make_uint2(0u, 0u);
+    // Most segments are small (the MSD split leaves thousands of sub-segments
+    // of a few dozen copies), and each is a chain of two dependent loads
+    // (descriptor, then pairs): the wavefront keeps the descriptor of the
+    // segment after next and the pairs of the next one in flight while it
+    // sorts the current one.
+    uint32_t i = (blockIdx.x - (uint32_t)gm) * 4u + w;
+    uint2 sg = i < count ? seg_w[i] : none;
+    uint2 sg1 = i + stride < count ? seg_w[i + stride] : none;
+    uint2 v = small_pair(bucket, sg);
+    for (; i < count; i += stride) {
+      const uint2 sg2 = i + 2u * stride < count ? seg_w[i + 2u * stride] : none;
+      const uint2 v1 = small_pair(bucket, sg1);
+      const uint2 cur = sg;
+      const uint2 vc = v;
+      sg = sg1;
+      sg1 = sg2;
+      v = v1;
+      if (cur.y <= 64)
+        rank_sort_wave(vc, cur.y, out, cur.x, reinterpret_cast<uint2*>(b));
+      else if (!bucket_sort_segment<1, kW_ITEMS, kW_HB, true, kBucketMax>(bucket + cur.x, cur.y,
+                                                                           out, cur.x, sm))
+        sort_segment_lds<1, kW_ITEMS, true>(bucket + cur.x, cur.y, out, cur.x, sm);
     }
   }
 }
