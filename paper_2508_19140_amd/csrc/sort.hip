@@ -662,27 +662,60 @@ __device__ __forceinline__ SplitDigit split_digit(uint32_t kmin, uint32_t kmax, 
   return d;
 }
 
-// Exclusive scan of the 256 digit counts into s_off (first wavefront), and
-// the sub-segment of digit threadIdx.x (threads < 256), taken before the
-// offsets are consumed.
-__device__ __forceinline__ uint2 split_offsets(uint2 sg, const uint32_t* s_cnt, uint32_t* s_off) {
+// The sub-segments of a split: groups of consecutive digit buckets.  A
+// bucket of more than kGroupCopies copies stands alone (the next round splits
+// it if it still holds more than 2048); the other buckets are grouped by the
+// window floor(start / kGroupCopies) their start falls in, so that a group
+// holds fewer than 2 kGroupCopies copies.  Depth keys of a tile spread over
+// 256 buckets leave hundreds of buckets of a few dozen copies; as groups they
+// become a few sub-segments of block-class size, which sort at a fraction of
+// the per-copy cost of as many tiny segments.
+constexpr uint32_t kGroupCopies = 128;
+
+// Exclusive scan of the 256 digit counts into s_off (first wavefront), the
+// group starts into s_grp (s_grp[256]: the number of groups), and the
+// sub-segment of group threadIdx.x (threads below the group count), taken
+// before the offsets are consumed.
+__device__ __forceinline__ uint2 split_offsets(uint2 sg, const uint32_t* s_cnt, uint32_t* s_off,
+                                               uint32_t* s_grp) {
   const uint32_t lane = __lane_id(), w = threadIdx.x >> 6;
   if (w == 0) {
-    uint32_t t4[4], s = 0;
+    uint32_t t4[4], o4[4], s = 0;
     for (int q = 0; q < 4; ++q) { t4[q] = s_cnt[lane * 4 + q]; s += t4[q]; }
     uint32_t ex = wave_incl_scan(s) - s;
-    for (int q = 0; q < 4; ++q) { s_off[lane * 4 + q] = ex; ex += t4[q]; }
+    for (int q = 0; q < 4; ++q) { o4[q] = ex; s_off[lane * 4 + q] = ex; ex += t4[q]; }
+    // the bucket before this lane's first: the previous lane's last
+    const uint32_t pc = __shfl_up(t4[3], 1, 64), po = __shfl_up(o4[3], 1, 64);
+    bool f[4];
+    uint32_t nst = 0;
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t c0 = q ? t4[q - 1] : pc, p0 = q ? o4[q - 1] : po;
+      f[q] = (lane == 0 && q == 0) || t4[q] > kGroupCopies || c0 > kGroupCopies ||
+             o4[q] / kGroupCopies != p0 / kGroupCopies;
+      nst += f[q] ? 1u : 0u;
+    }
+    const uint32_t incl = wave_incl_scan(nst);
+    uint32_t g = incl - nst;
+    for (int q = 0; q < 4; ++q)
+      if (f[q]) s_grp[g++] = o4[q];
+    if (lane == 63) s_grp[256] = incl;
   }
   __syncthreads();
+  const uint32_t ng = s_grp[256];
   uint2 sub = make_uint2(0u, 0u);
-  if (threadIdx.x < 256) sub = make_uint2(sg.x + s_off[threadIdx.x], s_cnt[threadIdx.x]);
+  if (threadIdx.x < ng) {
+    const uint32_t a = s_grp[threadIdx.x];
+    const uint32_t b = threadIdx.x + 1 < ng ? s_grp[threadIdx.x + 1] : sg.y;
+    sub = make_uint2(sg.x + a, b - a);
+  }
   __syncthreads();
   return sub;
 }
 
 // MSD split of one segment of 2048 < n <= 16384 copies in LDS (in place).
 __device__ void split_lds(uint2 sg, int round, const Ws& ws, uint2* s_e, uint32_t* s_cnt,
-                          uint32_t* s_off, uint32_t* s_red, uint32_t* s_pc, uint32_t* s_pb) {
+                          uint32_t* s_off, uint32_t* s_grp, uint32_t* s_red, uint32_t* s_pc,
+                          uint32_t* s_pb) {
   const uint32_t n = sg.y;
   uint2* g = ws.bucket + sg.x;
   uint32_t kmin = 0xffffffffu, kmax = 0, imin = 0xffffffffu, imax = 0;
@@ -696,7 +729,7 @@ __device__ void split_lds(uint2 sg, int round, const Ws& ws, uint2* s_e, uint32_
   const SplitDigit digit = split_digit(kmin, kmax, imin, imax, s_red);
   for (uint32_t e = threadIdx.x; e < n; e += 1024) atomicAdd(&s_cnt[digit(s_e[e])], 1u);
   __syncthreads();
-  const uint2 sub = split_offsets(sg, s_cnt, s_off);
+  const uint2 sub = split_offsets(sg, s_cnt, s_off, s_grp);
   for (uint32_t e = threadIdx.x; e < n; e += 1024) {
     const uint2 v = s_e[e];
     g[atomicAdd(&s_off[digit(v)], 1u)] = v;
@@ -708,7 +741,7 @@ __device__ void split_lds(uint2 sg, int round, const Ws& ws, uint2* s_e, uint32_
 // the same digit, the segment scattered by digit into the ping-pong buffer
 // and copied back.
 __device__ void split_global(uint2 sg, int round, const Ws& ws, uint32_t* s_cnt, uint32_t* s_off,
-                             uint32_t* s_red, uint32_t* s_pc, uint32_t* s_pb) {
+                             uint32_t* s_grp, uint32_t* s_red, uint32_t* s_pc, uint32_t* s_pb) {
   const uint32_t n = sg.y;
   uint2* g = ws.bucket + sg.x;
   uint2* x = ws.xbucket + sg.x;
@@ -722,7 +755,7 @@ __device__ void split_global(uint2 sg, int round, const Ws& ws, uint32_t* s_cnt,
   const SplitDigit digit = split_digit(kmin, kmax, imin, imax, s_red);
   for (uint32_t e = threadIdx.x; e < n; e += 1024) atomicAdd(&s_cnt[digit(g[e])], 1u);
   __syncthreads();
-  const uint2 sub = split_offsets(sg, s_cnt, s_off);
+  const uint2 sub = split_offsets(sg, s_cnt, s_off, s_grp);
   for (uint32_t e = threadIdx.x; e < n; e += 1024) {
     const uint2 v = g[e];
     x[atomicAdd(&s_off[digit(v)], 1u)] = v;
@@ -740,7 +773,7 @@ __device__ void split_global(uint2 sg, int round, const Ws& ws, uint32_t* s_cnt,
 // that the long global splits start at once and the rest fill in around them.
 __global__ __launch_bounds__(1024) void k_split(int round, Ws ws) {
   __shared__ uint2 s_e[kSortCapL];
-  __shared__ uint32_t s_cnt[256], s_off[256];
+  __shared__ uint32_t s_cnt[256], s_off[256], s_grp[257];
   __shared__ uint32_t s_red[64];
   __shared__ uint32_t s_pc[4], s_pb[4];
   __shared__ uint32_t s_item;
@@ -756,9 +789,9 @@ __global__ __launch_bounds__(1024) void k_split(int round, Ws ws) {
     const uint32_t it = s_item;
     __syncthreads();  // every thread has read s_item before it is taken again
     if (it < nbig)
-      split_global(big[it], round, ws, s_cnt, s_off, s_red, s_pc, s_pb);
+      split_global(big[it], round, ws, s_cnt, s_off, s_grp, s_red, s_pc, s_pb);
     else if (it - nbig < nmid)
-      split_lds(mid[it - nbig], round, ws, s_e, s_cnt, s_off, s_red, s_pc, s_pb);
+      split_lds(mid[it - nbig], round, ws, s_e, s_cnt, s_off, s_grp, s_red, s_pc, s_pb);
     else
       break;
   }
