@@ -42,6 +42,18 @@ namespace {
 
 constexpr int kRunMax = 64;  // longest run of equal keys fixed in place
 
+// A segment descriptor is (first list position, count).  Bit 31 of the count
+// marks a segment whose pairs sit in the ping-pong buffer (xbucket) rather
+// than in the bucket array, at the same positions: a split through global
+// memory leaves its sub-segments where it scattered them.  Counts stay below
+// 2^31 (a tile holds at most one copy of each point).
+constexpr uint32_t kInX = 0x80000000u;
+__device__ __forceinline__ uint32_t seg_count(uint2 sg) { return sg.y & ~kInX; }
+template <typename P>
+__device__ __forceinline__ P* seg_pairs(P* bucket, P* xbucket, uint2 sg) {
+  return ((sg.y & kInX) ? xbucket : bucket) + sg.x;
+}
+
 template <bool WAVE_ONLY>
 __device__ __forceinline__ void bsync() {
   if constexpr (WAVE_ONLY) {
@@ -483,9 +495,11 @@ __device__ void sort_segment_lds(const uint2* __restrict__ seg, uint32_t n, cons
 // (key bit 31 is clear) counts as smaller, so the count runs over whole
 // groups of eight with 16-byte LDS reads.
 // The lane's pair of a segment of n <= 64 (all ones past the end).
-__device__ __forceinline__ uint2 small_pair(const uint2* __restrict__ bucket, uint2 sg) {
-  const uint32_t lane = __lane_id();
-  return sg.y <= 64u && lane < sg.y ? bucket[sg.x + lane] : make_uint2(0xffffffffu, 0xffffffffu);
+__device__ __forceinline__ uint2 small_pair(const uint2* __restrict__ bucket,
+                                            const uint2* __restrict__ xbucket, uint2 sg) {
+  const uint32_t lane = __lane_id(), n = seg_count(sg);
+  return n <= 64u && lane < n ? seg_pairs(bucket, xbucket, sg)[lane]
+                              : make_uint2(0xffffffffu, 0xffffffffu);
 }
 
 // `v`: the lane's pair (small_pair).
@@ -536,7 +550,8 @@ static_assert(kW_WORDS % 4 == 0, "wavefront arenas must stay 16-byte aligned");
 __global__ __launch_bounds__(256) void k_sort_wm(int gm, const uint2* __restrict__ seg_w,
                                                  const uint2* __restrict__ seg_m,
                                                  const uint32_t* __restrict__ flags,
-                                                 const uint2* __restrict__ bucket, ListOut out) {
+                                                 const uint2* __restrict__ bucket,
+                                                 const uint2* __restrict__ xbucket, ListOut out) {
   __shared__ __align__(16) uint32_t s_lds[kM_WORDS > 4 * kW_WORDS ? kM_WORDS : 4 * kW_WORDS];
   if (flags[kFlagOverflow]) return;
   if ((int)blockIdx.x < gm) {
@@ -546,9 +561,10 @@ __global__ __launch_bounds__(256) void k_sort_wm(int gm, const uint2* __restrict
     const uint32_t count = flags[kFlagCountM];
     for (uint32_t i = blockIdx.x; i < count; i += (uint32_t)gm) {
       const uint2 sg = seg_m[i];
-      if (!bucket_sort_segment<kM_NW, kM_ITEMS, kM_HB, false, kBucketMax>(bucket + sg.x, sg.y,
-                                                                            out, sg.x, sm))
-        sort_segment_lds<kM_NW, kM_ITEMS, false>(bucket + sg.x, sg.y, out, sg.x, sm);
+      const uint2* src = seg_pairs(bucket, xbucket, sg);
+      const uint32_t n = seg_count(sg);
+      if (!bucket_sort_segment<kM_NW, kM_ITEMS, kM_HB, false, kBucketMax>(src, n, out, sg.x, sm))
+        sort_segment_lds<kM_NW, kM_ITEMS, false>(src, n, out, sg.x, sm);
     }
   } else {
     const uint32_t w = threadIdx.x >> 6;
@@ -565,20 +581,21 @@ __global__ __launch_bounds__(256) void k_sort_wm(int gm, const uint2* __restrict
     uint32_t i = (blockIdx.x - (uint32_t)gm) * 4u + w;
     uint2 sg = i < count ? seg_w[i] : none;
     uint2 sg1 = i + stride < count ? seg_w[i + stride] : none;
-    uint2 v = small_pair(bucket, sg);
+    uint2 v = small_pair(bucket, xbucket, sg);
     for (; i < count; i += stride) {
       const uint2 sg2 = i + 2u * stride < count ? seg_w[i + 2u * stride] : none;
-      const uint2 v1 = small_pair(bucket, sg1);
+      const uint2 v1 = small_pair(bucket, xbucket, sg1);
       const uint2 cur = sg;
       const uint2 vc = v;
       sg = sg1;
       sg1 = sg2;
       v = v1;
-      if (cur.y <= 64)
-        rank_sort_wave(vc, cur.y, out, cur.x, reinterpret_cast<uint2*>(b));
-      else if (!bucket_sort_segment<1, kW_ITEMS, kW_HB, true, kBucketMax>(bucket + cur.x, cur.y,
-                                                                           out, cur.x, sm))
-        sort_segment_lds<1, kW_ITEMS, true>(bucket + cur.x, cur.y, out, cur.x, sm);
+      const uint32_t n = seg_count(cur);
+      const uint2* src = seg_pairs(bucket, xbucket, cur);
+      if (n <= 64)
+        rank_sort_wave(vc, n, out, cur.x, reinterpret_cast<uint2*>(b));
+      else if (!bucket_sort_segment<1, kW_ITEMS, kW_HB, true, kBucketMax>(src, n, out, cur.x, sm))
+        sort_segment_lds<1, kW_ITEMS, true>(src, n, out, cur.x, sm);
     }
   }
 }
@@ -595,12 +612,13 @@ enum SplitRound : int { kLdsRound0 = 0, kLdsRound1 = 1, kGlobalRound0 = 2, kGlob
 __device__ void push_segments(uint2 sg, int round, const Ws& ws, uint32_t* s_cnt,
                               uint32_t* s_base) {
   int c = 4;  // none
-  if (sg.y > 0) {
-    if (sg.y <= kSortCapW) c = 0;
-    else if (sg.y <= kSortCapM) c = 1;
+  const uint32_t n = seg_count(sg);
+  if (n > 0) {
+    if (n <= kSortCapW) c = 0;
+    else if (n <= kSortCapM) c = 1;
     else if (round == kLdsRound0) c = 2;
-    else if (round == kGlobalRound0) c = sg.y <= kSortCapL ? 2 : 3;
-    else c = sg.y <= kSortCapLB ? 2 : 3;  // second rounds
+    else if (round == kGlobalRound0) c = n <= kSortCapL ? 2 : 3;
+    else c = n <= kSortCapLB ? 2 : 3;  // second rounds
   }
   uint2* lists[4];
   int slots[4];
@@ -674,10 +692,11 @@ constexpr uint32_t kGroupCopies = 128;
 
 // Exclusive scan of the 256 digit counts into s_off (first wavefront), the
 // group starts into s_grp (s_grp[256]: the number of groups), and the
-// sub-segment of group threadIdx.x (threads below the group count), taken
-// before the offsets are consumed.
-__device__ __forceinline__ uint2 split_offsets(uint2 sg, const uint32_t* s_cnt, uint32_t* s_off,
-                                               uint32_t* s_grp) {
+// sub-segment of group threadIdx.x (threads below the group count; `in_x`
+// the buffer flag of where the split leaves it), taken before the offsets
+// are consumed.
+__device__ __forceinline__ uint2 split_offsets(uint2 sg, uint32_t in_x, const uint32_t* s_cnt,
+                                               uint32_t* s_off, uint32_t* s_grp) {
   const uint32_t lane = __lane_id(), w = threadIdx.x >> 6;
   if (w == 0) {
     uint32_t t4[4], o4[4], s = 0;
@@ -705,8 +724,8 @@ __device__ __forceinline__ uint2 split_offsets(uint2 sg, const uint32_t* s_cnt, 
   uint2 sub = make_uint2(0u, 0u);
   if (threadIdx.x < ng) {
     const uint32_t a = s_grp[threadIdx.x];
-    const uint32_t b = threadIdx.x + 1 < ng ? s_grp[threadIdx.x + 1] : sg.y;
-    sub = make_uint2(sg.x + a, b - a);
+    const uint32_t b = threadIdx.x + 1 < ng ? s_grp[threadIdx.x + 1] : seg_count(sg);
+    sub = make_uint2(sg.x + a, (b - a) | in_x);
   }
   __syncthreads();
   return sub;
@@ -716,8 +735,8 @@ __device__ __forceinline__ uint2 split_offsets(uint2 sg, const uint32_t* s_cnt, 
 __device__ void split_lds(uint2 sg, int round, const Ws& ws, uint2* s_e, uint32_t* s_cnt,
                           uint32_t* s_off, uint32_t* s_grp, uint32_t* s_red, uint32_t* s_pc,
                           uint32_t* s_pb) {
-  const uint32_t n = sg.y;
-  uint2* g = ws.bucket + sg.x;
+  const uint32_t n = seg_count(sg);
+  uint2* g = seg_pairs(ws.bucket, ws.xbucket, sg);  // split in place
   uint32_t kmin = 0xffffffffu, kmax = 0, imin = 0xffffffffu, imax = 0;
   for (uint32_t e = threadIdx.x; e < n; e += 1024) {
     const uint2 v = g[e];
@@ -729,7 +748,7 @@ __device__ void split_lds(uint2 sg, int round, const Ws& ws, uint2* s_e, uint32_
   const SplitDigit digit = split_digit(kmin, kmax, imin, imax, s_red);
   for (uint32_t e = threadIdx.x; e < n; e += 1024) atomicAdd(&s_cnt[digit(s_e[e])], 1u);
   __syncthreads();
-  const uint2 sub = split_offsets(sg, s_cnt, s_off, s_grp);
+  const uint2 sub = split_offsets(sg, sg.y & kInX, s_cnt, s_off, s_grp);
   for (uint32_t e = threadIdx.x; e < n; e += 1024) {
     const uint2 v = s_e[e];
     g[atomicAdd(&s_off[digit(v)], 1u)] = v;
@@ -738,13 +757,14 @@ __device__ void split_lds(uint2 sg, int round, const Ws& ws, uint2* s_e, uint32_
 }
 
 // MSD split of one segment of more than 16384 copies, through global memory:
-// the same digit, the segment scattered by digit into the ping-pong buffer
-// and copied back.
+// the same digit, the segment scattered by digit into the other buffer of
+// the pair (bucket, xbucket), where its sub-segments stay.
 __device__ void split_global(uint2 sg, int round, const Ws& ws, uint32_t* s_cnt, uint32_t* s_off,
                              uint32_t* s_grp, uint32_t* s_red, uint32_t* s_pc, uint32_t* s_pb) {
-  const uint32_t n = sg.y;
-  uint2* g = ws.bucket + sg.x;
-  uint2* x = ws.xbucket + sg.x;
+  const uint32_t n = seg_count(sg);
+  const uint2* g = seg_pairs(ws.bucket, ws.xbucket, sg);
+  const uint32_t to_x = (sg.y & kInX) ^ kInX;
+  uint2* x = (to_x ? ws.xbucket : ws.bucket) + sg.x;
   uint32_t kmin = 0xffffffffu, kmax = 0, imin = 0xffffffffu, imax = 0;
   for (uint32_t e = threadIdx.x; e < n; e += 1024) {
     const uint2 v = g[e];
@@ -755,15 +775,11 @@ __device__ void split_global(uint2 sg, int round, const Ws& ws, uint32_t* s_cnt,
   const SplitDigit digit = split_digit(kmin, kmax, imin, imax, s_red);
   for (uint32_t e = threadIdx.x; e < n; e += 1024) atomicAdd(&s_cnt[digit(g[e])], 1u);
   __syncthreads();
-  const uint2 sub = split_offsets(sg, s_cnt, s_off, s_grp);
+  const uint2 sub = split_offsets(sg, to_x, s_cnt, s_off, s_grp);
   for (uint32_t e = threadIdx.x; e < n; e += 1024) {
     const uint2 v = g[e];
     x[atomicAdd(&s_off[digit(v)], 1u)] = v;
   }
-  __threadfence_block();
-  __syncthreads();
-  for (uint32_t e = threadIdx.x; e < n; e += 1024) g[e] = x[e];
-  __threadfence_block();
   push_segments(sub, round == 0 ? kGlobalRound0 : kGlobalRound1, ws, s_pc, s_pb);
 }
 
@@ -812,10 +828,11 @@ __device__ void sort_x_blocks(const Ws& ws, const ListOut& out, uint32_t* s_hist
   const uint32_t count = ws.flags[kFlagCountX2];
   for (uint32_t i = b; i < count; i += nb) {
     const uint2 sg = ws.seg_x2[i];
-    const uint32_t s = sg.x, n = sg.y;
+    const uint32_t s = sg.x, n = seg_count(sg);
+    uint2* const src0 = seg_pairs(ws.bucket, ws.xbucket, sg);
     uint32_t kmin = 0xffffffffu, kmax = 0, imin = 0xffffffffu, imax = 0;
     for (uint32_t e = threadIdx.x; e < n; e += NW * 64) {
-      const uint2 v = ws.bucket[s + e];
+      const uint2 v = src0[e];
       kmin = min(kmin, v.x); kmax = max(kmax, v.x);
       imin = min(imin, v.y); imax = max(imax, v.y);
     }
@@ -838,8 +855,8 @@ __device__ void sort_x_blocks(const Ws& ws, const ListOut& out, uint32_t* s_hist
     dp.set_key(kmax - kmin);
     dp.set_idx(imax - imin);
     const int np = dp.passes();
-    uint2* src = ws.bucket + s;
-    uint2* dst = ws.xbucket + s;
+    uint2* src = src0;
+    uint2* dst = ((sg.y & kInX) ? ws.bucket : ws.xbucket) + s;
     for (int p = 0; p < np; ++p) {
       for (int k = threadIdx.x; k < 256; k += NW * 64) s_glob[k] = 0;
       __syncthreads();
@@ -884,7 +901,7 @@ __device__ void sort_x_blocks(const Ws& ws, const ListOut& out, uint32_t* s_hist
       dst = t;
     }
     if (np == 0) {
-      for (uint32_t e = threadIdx.x; e < n; e += NW * 64) out.put(s + e, ws.bucket[s + e].y);
+      for (uint32_t e = threadIdx.x; e < n; e += NW * 64) out.put(s + e, src0[e].y);
     }
     __syncthreads();
   }
@@ -912,9 +929,10 @@ __global__ __launch_bounds__(1024) void k_sort_lx(int gl, Ws ws, ListOut out) {
   const uint32_t count = ws.flags[kFlagCountL];
   for (uint32_t i = blockIdx.x; i < count; i += (uint32_t)gl) {
     const uint2 sg = ws.seg_l[i];
-    if (!bucket_sort_segment<kL_NW, kL_ITEMS, kL_HB, false, kBucketMax>(ws.bucket + sg.x, sg.y,
-                                                                        out, sg.x, sm))
-      sort_segment_lds<kL_NW, kL_ITEMS, false>(ws.bucket + sg.x, sg.y, out, sg.x, sm);
+    const uint2* src = seg_pairs(ws.bucket, ws.xbucket, sg);
+    const uint32_t n = seg_count(sg);
+    if (!bucket_sort_segment<kL_NW, kL_ITEMS, kL_HB, false, kBucketMax>(src, n, out, sg.x, sm))
+      sort_segment_lds<kL_NW, kL_ITEMS, false>(src, n, out, sg.x, sm);
   }
 }
 
@@ -936,7 +954,8 @@ hipError_t launch_sort(const Ws& ws, uint32_t* list, uint16_t* lpos, int64_t nt,
   const int grid_w = (int)std::min<int64_t>((nt + 3) / 4 + (int64_t)ws.cap / 256, 8192);
   const int grid_m = (int)std::min<int64_t>(nt + (int64_t)ws.cap / 2048, 4096);
   hipLaunchKernelGGL(k_sort_wm, dim3(std::max(grid_m, 1) + std::max(grid_w, 1)), dim3(256), 0,
-                     stream, std::max(grid_m, 1), ws.seg_w, ws.seg_m, ws.flags, ws.bucket, out);
+                     stream, std::max(grid_m, 1), ws.seg_w, ws.seg_m, ws.flags, ws.bucket,
+                     ws.xbucket, out);
   hipLaunchKernelGGL(k_sort_lx, dim3(grid_rare + 64), dim3(1024), 0, stream, grid_rare, ws, out);
   return hipGetLastError();
 }
