@@ -654,7 +654,8 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS,
                      "frac_of_copy": dom_gbs / copy_gbs,
                      "bytes_per_launch": dom_bytes, "ms_per_launch": per_launch_ms[dominant],
-                     "traffic": measured_traffic(dominant, args.config)},
+                     "traffic": measured_traffic(
+                         dominant, args.config + ("_ewa" if step.kind == "ewa" else ""))},
     }
     if args.errors and ring is None:
         res["errors"] = error_table(step, sc, args.tile)
