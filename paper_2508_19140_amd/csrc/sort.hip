@@ -547,7 +547,7 @@ constexpr int kM_WORDS = 2 * kM_CAP + kM_NW * 256 + 256 + 64;
 constexpr int kW_WORDS = 2 * kW_CAP + 256 + 256 + 64;  // per wavefront
 static_assert(kW_WORDS % 4 == 0, "wavefront arenas must stay 16-byte aligned");
 
-__global__ __launch_bounds__(256) void k_sort_wm(int gm, const uint2* __restrict__ seg_w,
+__global__ __launch_bounds__(256, 5) void k_sort_wm(int gm, const uint2* __restrict__ seg_w,
                                                  const uint2* __restrict__ seg_m,
                                                  const uint32_t* __restrict__ flags,
                                                  const uint2* __restrict__ bucket,
