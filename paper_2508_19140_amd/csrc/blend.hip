@@ -1331,14 +1331,20 @@ __device__ __forceinline__ void blend_bwd_bilinear8_tile(const BlendArgs& a, uin
   constexpr uint32_t SC = kSubs * 64;
   __shared__ float4 s_geo[64];
   __shared__ unsigned long long s_mask[64];
-  __shared__ uint2 s_sel[64];
   __shared__ uint32_t s_q1[64];
-  __shared__ float s_gf[64 * 4];                  // per (copy, corner): G . f
-  __shared__ __align__(16) float2 s_acc[64 * 4];  // per (copy, corner): (T alpha, dL/dalpha)
+  // per (copy, corner): (G . f, kNoAcc) from the staging until the corner's
+  // pixel replays the copy, then (T alpha, dL/dalpha); kNoAcc (a NaN payload
+  // that arithmetic never produces) marks a corner the pixel did not blend
+  __shared__ __align__(16) float2 s_acc[64 * 4];
+  constexpr uint32_t kNoAcc = 0x7fc0dea1u;
   __shared__ __align__(16) float s_G[64 * fpad(CP)];
   using PF = PointFetch<CP, FT, FULL>;
   __shared__ float4 s_prj[64];             // gathered projection records
   __shared__ uint4 s_fq[PF::QS * 64];      // gathered feature rows, row-major
+  // the selection of the next virtual chunk shares the projection records'
+  // space: it is published after the records were staged and read before
+  // the gather that overwrites them (one wavefront, in program order)
+  uint2* const s_sel = reinterpret_cast<uint2*>(s_prj);
 
   const uint32_t lane = threadIdx.x;
   const int tx = (int)(tile % (uint32_t)a.opts.ntx), ty = (int)(tile / (uint32_t)a.opts.ntx);
@@ -1453,8 +1459,7 @@ __device__ __forceinline__ void blend_bwd_bilinear8_tile(const BlendArgs& a, uin
               d = fmaf(g4.w, fv[4 * q + 3], d);
             }
           }
-          s_gf[lane * 4 + c4] = d;
-          s_acc[lane * 4 + c4] = make_float2(0.f, 0.f);
+          s_acc[lane * 4 + c4] = make_float2(d, __uint_as_float(kNoAcc));
         }
         uint64_t pm = splat_pixels8(cur_lp);
         const unsigned long long bit = 1ull << lane;
@@ -1496,7 +1501,7 @@ __device__ __forceinline__ void blend_bwd_bilinear8_tile(const BlendArgs& a, uin
           Tk = t_anchor;
         else
           Tk = __fdividef(Tcur, om);
-        const float gf = s_gf[kk * 4 + dy * 2 + dx];
+        const float gf = s_acc[kk * 4 + dy * 2 + dx].x;
         const float da = Tk * (gf - gB) - GT * Tk * Pi;
         s_acc[kk * 4 + dy * 2 + dx] = make_float2(Tk * al, da);
         gB = fmaf(al, gf, om * gB);
@@ -1516,7 +1521,8 @@ __device__ __forceinline__ void blend_bwd_bilinear8_tile(const BlendArgs& a, uin
           const int dx = c4 & 1, dy = c4 >> 1;
           const int qx = x0 + dx, qy = y0 + dy;
           if (qx < 0 || qx >= T || qy < 0 || qy >= T) continue;
-          const float2 acc = s_acc[lane * 4 + c4];
+          float2 acc = s_acc[lane * 4 + c4];
+          if (__float_as_uint(acc.y) == kNoAcc) acc = make_float2(0.f, 0.f);
           const float4* gp = reinterpret_cast<const float4*>(s_G + (qy * T + qx) * fpad(CP));
 #pragma unroll
           for (int q = 0; q < CP / 4; ++q) {
