@@ -731,6 +731,28 @@ __device__ __forceinline__ uint2 split_offsets(uint2 sg, uint32_t in_x, const ui
   return sub;
 }
 
+// f(e, pair e) for every pair of a segment, e ascending per thread, strided
+// over the 1024 threads of a split workgroup: the loads of U rounds are all
+// in flight before the first pair is used (one at a time, each of the up to
+// 35 rounds of a large segment would wait out a full memory latency).
+template <int U, typename F>
+__device__ __forceinline__ void for_each_pair(const uint2* __restrict__ g, uint32_t n, F&& f) {
+  for (uint32_t e0 = threadIdx.x; e0 < n; e0 += U * 1024u) {
+    uint2 v[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const uint32_t e = e0 + (uint32_t)k * 1024u;
+      v[k] = e < n ? g[e] : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const uint32_t e = e0 + (uint32_t)k * 1024u;
+      if (e < n) f(e, v[k]);
+    }
+  }
+}
+constexpr int kSplitUnroll = 8;
+
 // MSD split of one segment of 2048 < n <= 16384 copies in LDS (in place).
 __device__ void split_lds(uint2 sg, int round, const Ws& ws, uint2* s_e, uint32_t* s_cnt,
                           uint32_t* s_off, uint32_t* s_grp, uint32_t* s_red, uint32_t* s_pc,
@@ -738,12 +760,11 @@ __device__ void split_lds(uint2 sg, int round, const Ws& ws, uint2* s_e, uint32_
   const uint32_t n = seg_count(sg);
   uint2* g = seg_pairs(ws.bucket, ws.xbucket, sg);  // split in place
   uint32_t kmin = 0xffffffffu, kmax = 0, imin = 0xffffffffu, imax = 0;
-  for (uint32_t e = threadIdx.x; e < n; e += 1024) {
-    const uint2 v = g[e];
+  for_each_pair<kSplitUnroll>(g, n, [&](uint32_t e, uint2 v) {
     s_e[e] = v;
     kmin = min(kmin, v.x); kmax = max(kmax, v.x);
     imin = min(imin, v.y); imax = max(imax, v.y);
-  }
+  });
   if (threadIdx.x < 256) s_cnt[threadIdx.x] = 0;
   const SplitDigit digit = split_digit(kmin, kmax, imin, imax, s_red);
   for (uint32_t e = threadIdx.x; e < n; e += 1024) atomicAdd(&s_cnt[digit(s_e[e])], 1u);
@@ -766,20 +787,17 @@ __device__ void split_global(uint2 sg, int round, const Ws& ws, uint32_t* s_cnt,
   const uint32_t to_x = (sg.y & kInX) ^ kInX;
   uint2* x = (to_x ? ws.xbucket : ws.bucket) + sg.x;
   uint32_t kmin = 0xffffffffu, kmax = 0, imin = 0xffffffffu, imax = 0;
-  for (uint32_t e = threadIdx.x; e < n; e += 1024) {
-    const uint2 v = g[e];
+  for_each_pair<kSplitUnroll>(g, n, [&](uint32_t, uint2 v) {
     kmin = min(kmin, v.x); kmax = max(kmax, v.x);
     imin = min(imin, v.y); imax = max(imax, v.y);
-  }
+  });
   if (threadIdx.x < 256) s_cnt[threadIdx.x] = 0;
   const SplitDigit digit = split_digit(kmin, kmax, imin, imax, s_red);
-  for (uint32_t e = threadIdx.x; e < n; e += 1024) atomicAdd(&s_cnt[digit(g[e])], 1u);
+  for_each_pair<kSplitUnroll>(g, n, [&](uint32_t, uint2 v) { atomicAdd(&s_cnt[digit(v)], 1u); });
   __syncthreads();
   const uint2 sub = split_offsets(sg, to_x, s_cnt, s_off, s_grp);
-  for (uint32_t e = threadIdx.x; e < n; e += 1024) {
-    const uint2 v = g[e];
-    x[atomicAdd(&s_off[digit(v)], 1u)] = v;
-  }
+  for_each_pair<kSplitUnroll>(g, n,
+                              [&](uint32_t, uint2 v) { x[atomicAdd(&s_off[digit(v)], 1u)] = v; });
   push_segments(sub, round == 0 ? kGlobalRound0 : kGlobalRound1, ws, s_pc, s_pb);
 }
 
