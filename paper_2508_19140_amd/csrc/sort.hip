@@ -11,29 +11,34 @@
 // non-empty tile starts as one segment.  By size:
 //   n <= 64     rank sort by one wavefront (each lane counts the smaller
 //               (key, index) pairs)
-//   n <= 256    LSD radix sort by one wavefront, 4 elements per lane
-//   n <= 2048   LSD radix sort by a 256-thread block, 8 elements per lane
+//   n <= 256    bucket-rank sort by one wavefront, 4 elements per lane
+//   n <= 2048   bucket-rank sort by a 256-thread block, 8 elements per lane
+//               (both fall back to an LSD radix sort when a bucket is too
+//               full, see bucket_sort_segment)
 //   n <= 16384  MSD split: one 1024-thread block loads the segment into LDS,
 //               buckets it by the top 8 bits of the (key, index) pair
 //               relative to the segment's range, writes it back in place and
 //               queues the sub-segments (which are then sorted on their own;
 //               concatenated in digit order they give the sorted segment).
-//               Two split rounds; what is still larger is LSD-sorted by a
-//               1024-thread block (up to 8192 copies) or through global
-//               memory.
+//               Small digit buckets are queued as groups of neighbouring
+//               buckets rather than one by one.  Two split rounds; what is
+//               still larger is sorted by a 1024-thread block (up to 8192
+//               copies) or LSD-sorted through global memory.
 //   larger      the same MSD split through global memory (the segment is
-//               scattered into the ping-pong buffer and copied back), two
-//               rounds, before the LDS splits; whatever is still larger
-//               than 16384 copies after them is LSD-sorted through global
-//               memory by a 1024-thread block.  (Large Gaussian footprints
-//               give tiles of tens of thousands of copies.)
+//               scattered into the other buffer of the pair bucket/xbucket,
+//               where its sub-segments stay), two rounds, before the LDS
+//               splits; whatever is still larger than 16384 copies after
+//               them is LSD-sorted through global memory by a 1024-thread
+//               block.  (Large Gaussian footprints give tiles of tens of
+//               thousands of copies.)
 //
 // The LSD sorts rank elements inside a wavefront with one ballot per digit
 // bit (the lanes sharing a digit), so no order is decided by an atomic.  They
 // run on the depth key minus the segment's smallest key; equal keys are then
 // put in index order, and a segment with a long run of equal keys is re-sorted
-// on the full (key, index) pair.  Element placement by LDS atomics happens only
-// in the MSD split, whose sub-segments are fully sorted afterwards.
+// on the full (key, index) pair.  Element placement by LDS atomics happens
+// only in the bucketing passes (the splits and the bucket-rank sorts), whose
+// buckets are then fully ordered on their own.
 #include "common.h"
 #include "internal.h"
 
