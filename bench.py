@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--keep-lists", action="store_true",
                     help="backward reuses the forward's tile lists instead of recomputing them")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-zero-ahead", action="store_true",
+                    help="zero the gradients inside the backward blend, on the step's stream, "
+                         "instead of on a stream of their own ahead of it")
     ap.add_argument("--errors", action="store_true",
                     help="also compare every output with the oracle (max abs / rel / RMS), on "
                          "the stored features and on the original FP32 features")
@@ -87,7 +90,8 @@ ENTRY_KERNELS = {
     "bin": ("k_group_scan", "k_place", "k_scatter"),
     "sort": ("k_split", "k_sort_w", "k_sort_block", "k_sort_lx", "k_sort_x", "k_lpos"),
     "blend_fwd": ("k_blend_fwd",),
-    "blend_bwd": ("k_zero", "k_blend_bwd", "k_unpack_scalars", "k_bg_reduce"),
+    "backward_zero": ("k_zero",),
+    "blend_bwd": ("k_blend_bwd", "k_unpack_scalars", "k_bg_reduce"),
     "project_bwd": ("k_project_bwd",),
     "batch": ("k_batch_args", "k_batch_queue"),
     "background": ("k_view_dirs", "k_envmap_fwd", "k_envmap_bwd", "k_fill_zero"),
@@ -217,7 +221,8 @@ def summarize_pmc(fetch_dir, write_dir, entry, steps, command):
         print(f"sha256 {src} {h}")
 
 
-def make_step(sc, tile, keep_lists, dtype, dev, splat="auto", ring_counts=None):
+def make_step(sc, tile, keep_lists, dtype, dev, splat="auto", ring_counts=None,
+              zero_ahead=False):
     """The preallocated pipeline of one view (every buffer allocated here).
     Screen-space Gaussians (a scene with radii) and rings run forward only."""
     import torch
@@ -234,7 +239,7 @@ def make_step(sc, tile, keep_lists, dtype, dev, splat="auto", ring_counts=None):
                         ring_counts=ring_counts)
     st = inpc.RasterSettings(splat=kind, tile=tile, keep_lists=keep_lists,
                              max_radius=float(sc.radius.max()) if kind == "gaussian" else 0.0)
-    step = inpc.ViewPipeline(v, st)
+    step = inpc.ViewPipeline(v, st, zero_ahead=zero_ahead)
     step.kind = kind
     step.bf = 4 if dtype == "f32" else 2
     step.P = sc.camera.width * sc.camera.height
@@ -545,7 +550,8 @@ def main():
         ring_push = make_ring_push(step, ring, dev)
     else:
         sc = make_scene(CONFIGS[args.config])
-        step = make_step(sc, args.tile, args.keep_lists, dtype, dev, splat=args.splat)
+        step = make_step(sc, args.tile, args.keep_lists, dtype, dev, splat=args.splat,
+                         zero_ahead=not args.no_zero_ahead)
     h = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
     def phases():
@@ -654,7 +660,10 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS,
                      "frac_of_copy": dom_gbs / copy_gbs,
                      "bytes_per_launch": dom_bytes, "ms_per_launch": per_launch_ms[dominant],
-                     "traffic": measured_traffic(
+                     # the stored summaries count the backward blend without its zero
+                     # fill, which --no-zero-ahead runs inside it
+                     "traffic": None if (dominant == "blend_bwd" and args.no_zero_ahead)
+                     else measured_traffic(
                          dominant, args.config + ("_ewa" if step.kind == "ewa" else ""))},
     }
     if args.errors and ring is None:

@@ -288,6 +288,36 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
                                   size_t ws_bytes, void* stream);
 
 /*
+ * Step 5 split in two, so that the zero fill it starts with can run ahead on
+ * another stream, overlapped with the list build that precedes the backward
+ * (App. A, Eq. (2): the gradient rows are sums over blended fragments, and
+ * a point no fragment reaches keeps zero).
+ *
+ * inpc_backward_zero writes zeros to grad_feat [n][C] f32 and to the first
+ * 16 n bytes of `scratch` (the per-point scalar rows), on `stream`.  Both
+ * must be 16-byte aligned; scratch_bytes >= 16 n.  n == 0 does nothing.
+ * Errors: INPC_ERR_INVALID for n out of range, C outside [1, 32], a NULL or
+ * misaligned buffer, or a short scratch.
+ *
+ * inpc_blend_backward_prezeroed takes the arguments of inpc_blend_backward
+ * and gives its results, but does not zero grad_feat and the scalar rows
+ * itself: the caller has run inpc_backward_zero on the same grad_feat and
+ * scratch, ordered before this call (same stream, or an event wait), with
+ * nothing writing to them in between.  Without that the gradients are
+ * wrong; nothing checks it.
+ */
+inpc_status_t inpc_backward_zero(int64_t n, int32_t C, float* grad_feat, void* scratch,
+                                 size_t scratch_bytes, void* stream);
+inpc_status_t inpc_blend_backward_prezeroed(
+    const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n, const float* proj,
+    const void* feat, int32_t C, int32_t dtype, const float* bg, const uint32_t* ntiles,
+    const uint32_t* tile_ranges, const uint32_t* tile_order, const uint32_t* list,
+    const uint16_t* lpos, const float* t_final, const void* state, const float* grad_out,
+    const float* grad_t, float* grad_feat, float* grad_opacity, float* grad_uv, float* grad_z,
+    float* grad_bg, void* scratch, size_t scratch_bytes, void* ws, size_t ws_bytes,
+    void* stream);
+
+/*
  * Step 5 without allocation -- for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Same arguments, results and errors as

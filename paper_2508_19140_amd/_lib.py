@@ -35,6 +35,7 @@ EXPORTS = (
     "inpc_view_dirs", "inpc_envmap_forward", "inpc_envmap_backward",
     "inpc_batch_workspace_bytes", "inpc_rasterize_batched",
     "inpc_sh_features", "inpc_sh_features_backward",
+    "inpc_backward_zero", "inpc_blend_backward_prezeroed",
 )
 
 PASS_FORWARD = 0
@@ -107,6 +108,9 @@ def lib():
                                      P, SZ, P]),
         "inpc_blend_backward": (I32, [CP, OP, I64, P, P, I32, I32, P, P, P, P, P, P, P, P, P,
                                       P, P, P, P, P, P, P, SZ, P, SZ, P]),
+        "inpc_blend_backward_prezeroed": (I32, [CP, OP, I64, P, P, I32, I32, P, P, P, P, P, P,
+                                                P, P, P, P, P, P, P, P, P, P, SZ, P, SZ, P]),
+        "inpc_backward_zero": (I32, [I64, I32, P, P, SZ, P]),
         "inpc_blend_backward_noalloc": (I32, [CP, OP, I64, P, P, I32, I32, P, P, P, P, P, P, P,
                                               P, P, P, P, P, P, P, P, P, SZ, P]),
         "inpc_backward_scratch_bytes": (SZ, [I64, I32, CP, OP]),

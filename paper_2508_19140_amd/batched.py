@@ -39,6 +39,17 @@ def _p(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _external(s, device) -> torch.cuda.ExternalStream:
+    """A HIP stream handle (int or ctypes.c_void_p) as a torch stream."""
+    h = int((s.value if isinstance(s, ctypes.c_void_p) else s) or 0)
+    cur = torch.cuda.current_stream(device)
+    if cur.cuda_stream == h:
+        return cur
+    if h == 0:
+        return torch.cuda.default_stream(device)
+    return torch.cuda.ExternalStream(h, device=device)
+
+
 @dataclasses.dataclass
 class ViewInputs:
     """Device tensors of one view: pos [n,3] f32, opacity [n] f32, feat
@@ -57,9 +68,17 @@ class ViewInputs:
 
 
 class ViewPipeline:
-    """All buffers and ABI calls of one view; nothing is allocated per call."""
+    """All buffers and ABI calls of one view; nothing is allocated per call.
 
-    def __init__(self, v: ViewInputs, settings: RasterSettings):
+    zero_ahead: the backward's zero fill of the gradient rows runs on a
+    stream of its own, forked off the pass's stream just before the forward's
+    tile sort (so after everything issued before it, the previous pass's
+    backward included): the sort's kernels are bound by LDS and latency and
+    leave HBM mostly idle, so the fill's writes overlap with them.  The
+    backward blend waits for the fill.  The streams keep the default
+    priority."""
+
+    def __init__(self, v: ViewInputs, settings: RasterSettings, zero_ahead: bool = False):
         dev = v.pos.device
         self.v, self.settings = v, settings
         self.gauss = settings.splat != "bilinear"
@@ -101,6 +120,10 @@ class ViewPipeline:
                 self.gz = mk(n)
             self.scratch = mk(int(lib.inpc_backward_scratch_bytes(n, C, self.cb, self.ob)),
                               dt=torch.uint8)
+        self.zero_ahead = bool(zero_ahead) and self.backward_enabled
+        if self.zero_ahead:
+            self.zstream = torch.cuda.Stream(device=dev)
+            self.ev_fork, self.ev_join = torch.cuda.Event(), torch.cuda.Event()
 
     def fill_record(self, r: "L.ViewRecord") -> None:
         """This view's camera, points and buffers as an inpc_view_t record."""
@@ -160,9 +183,21 @@ class ViewPipeline:
                    None if self.gauss else _p(self.lpos), _p(self.out), _p(self.tf),
                    _p(self.nc), _p(self.state), _p(ws), ws.numel(), s)
 
+    def zero(self, s):
+        """The backward's zero fill, forked off stream s (zero_ahead)."""
+        self.ev_fork.record(_external(s, self.v.pos.device))
+        self.zstream.wait_event(self.ev_fork)
+        self._call("inpc_backward_zero", self.n, self.C, _p(self.gf), _p(self.scratch),
+                   self.scratch.numel(), self.zstream.cuda_stream)
+        self.ev_join.record(self.zstream)
+
     def blend_bwd(self, s):
         v, ws = self.v, self.ws
-        self._call("inpc_blend_backward", self.cb, self.ob, self.n, _p(self.proj), _p(v.feat),
+        entry = "inpc_blend_backward"
+        if self.zero_ahead:
+            _external(s, v.pos.device).wait_event(self.ev_join)
+            entry = "inpc_blend_backward_prezeroed"
+        self._call(entry, self.cb, self.ob, self.n, _p(self.proj), _p(v.feat),
                    self.C, self.dtype, None, _p(self.ntiles), _p(self.ranges), _p(self.order),
                    _p(self.list), _p(self.lpos), _p(self.tf), _p(self.state), _p(v.grad_out),
                    None, _p(self.gf), _p(self.go), _p(self.guv), _p(self.gz), None,
@@ -176,8 +211,9 @@ class ViewPipeline:
     def phases(self):
         """(entry point, fn(stream)) of one training pass: forward, then the
         backward with the lists recomputed (unless settings.keep_lists)."""
-        ph = [("project", self.project), ("bin", self.bin), ("sort", self.sort),
-              ("blend_fwd", self.blend_fwd)]
+        ph = [("project", self.project), ("bin", self.bin)]
+        ph += [("backward_zero", self.zero)] if self.zero_ahead else []
+        ph += [("sort", self.sort), ("blend_fwd", self.blend_fwd)]
         if self.backward_enabled:
             if not self.settings.keep_lists:
                 ph += [("project", self.project), ("bin", self.bin), ("sort", self.sort)]

@@ -278,7 +278,7 @@ static inpc_status_t blend_backward_impl(const char* who, const inpc_camera_t* c
                                   const float* grad_out, const float* grad_t, float* grad_feat,
                                   float* grad_opacity, float* grad_uv, float* grad_z,
                                   float* grad_bg, void* scratch, size_t scratch_size, void* ws,
-                                  size_t ws_bytes, void* stream) {
+                                  size_t ws_bytes, void* stream, bool prezeroed) {
   inpc_status_t st = blend_checks(cam, opts, n, C, dtype, ws, ws_bytes);
   if (st != INPC_OK) return st;
   REQUIRE(scratch, "scratch");
@@ -337,6 +337,7 @@ static inpc_status_t blend_backward_impl(const char* who, const inpc_camera_t* c
                                                 scratch_scalar_bytes(n))
                      : nullptr;
   a.flags = w.flags;
+  a.prezeroed = prezeroed;
   hipError_t e = launch_blend_backward(a, (hipStream_t)stream);
   return e == hipSuccess ? INPC_OK : hip_fail(e, who);
 }
@@ -544,7 +545,33 @@ inpc_status_t inpc_blend_backward(const inpc_camera_t* cam, const inpc_opts_t* o
   return blend_backward_impl("inpc_blend_backward", cam, opts, n, proj, feat, C, dtype, bg,
                              ntiles, tile_ranges, tile_order, list, lpos, t_final, state,
                              grad_out, grad_t, grad_feat, grad_opacity, grad_uv, grad_z, grad_bg,
-                             scratch, scratch_size, ws, ws_bytes, stream);
+                             scratch, scratch_size, ws, ws_bytes, stream, false);
+}
+
+inpc_status_t inpc_backward_zero(int64_t n, int32_t C, float* grad_feat, void* scratch,
+                                 size_t scratch_size, void* stream) {
+  if (n < 0 || n > (int64_t)0x7fffffff) return fail(INPC_ERR_INVALID, "n out of range%s", "");
+  if (C < 1 || C > 32) return fail(INPC_ERR_INVALID, "channels must be in [1, 32]%s", "");
+  if (n == 0) return INPC_OK;
+  REQUIRE_ALIGNED(grad_feat, "grad_feat", 16);
+  REQUIRE_ALIGNED(scratch, "scratch", 16);
+  if (scratch_size < scratch_scalar_bytes(n))
+    return fail(INPC_ERR_INVALID, "scratch smaller than 16 bytes per point%s", "");
+  hipError_t e = launch_backward_zero(grad_feat, n, C, scratch, (hipStream_t)stream);
+  return e == hipSuccess ? INPC_OK : hip_fail(e, "inpc_backward_zero");
+}
+
+inpc_status_t inpc_blend_backward_prezeroed(
+    const inpc_camera_t* cam, const inpc_opts_t* opts, int64_t n, const float* proj,
+    const void* feat, int32_t C, int32_t dtype, const float* bg, const uint32_t* ntiles,
+    const uint32_t* tile_ranges, const uint32_t* tile_order, const uint32_t* list,
+    const uint16_t* lpos, const float* t_final, const void* state, const float* grad_out,
+    const float* grad_t, float* grad_feat, float* grad_opacity, float* grad_uv, float* grad_z,
+    float* grad_bg, void* scratch, size_t scratch_size, void* ws, size_t ws_bytes, void* stream) {
+  return blend_backward_impl("inpc_blend_backward_prezeroed", cam, opts, n, proj, feat, C, dtype,
+                             bg, ntiles, tile_ranges, tile_order, list, lpos, t_final, state,
+                             grad_out, grad_t, grad_feat, grad_opacity, grad_uv, grad_z, grad_bg,
+                             scratch, scratch_size, ws, ws_bytes, stream, true);
 }
 
 inpc_status_t inpc_blend_backward_noalloc(
@@ -574,7 +601,7 @@ inpc_status_t inpc_blend_backward_noalloc(
   return blend_backward_impl("inpc_blend_backward_noalloc", cam, opts, n, proj, feat, C, dtype,
                              bg, ntiles, tile_ranges, tile_order, list, lpos, t_final, state,
                              grad_out, grad_t, grad_feat, grad_opacity, grad_uv, grad_z, grad_bg,
-                             scr, kStaticScratchBytes, ws, ws_bytes, stream);
+                             scr, kStaticScratchBytes, ws, ws_bytes, stream, false);
 }
 
 inpc_status_t inpc_project_backward(const inpc_camera_t* cam, int64_t n, const float* pos,

@@ -2054,6 +2054,7 @@ hipError_t fwd_launch(const BlendArgs& a, hipStream_t s) {
 // Every gradient starts at zero: points no blended fragment reached keep
 // it, single-tile points are overwritten, split points are added to.
 hipError_t bwd_pre(const BlendArgs& a, hipStream_t s) {
+  if (a.prezeroed) return hipSuccess;
   return launch_zero(a.grad_feat, (size_t)a.n * a.C, reinterpret_cast<float*>(a.gsc),
                      (size_t)a.n * 4, s);
 }
@@ -2258,6 +2259,9 @@ hipError_t launch_blend_backward(const BlendArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_blend_backward_pre(const BlendArgs& a, hipStream_t s) { return bwd_pre(a, s); }
+hipError_t launch_backward_zero(float* grad_feat, int64_t n, int C, void* scratch, hipStream_t s) {
+  return launch_zero(grad_feat, (size_t)n * C, static_cast<float*>(scratch), (size_t)n * 4, s);
+}
 hipError_t launch_blend_backward_post(const BlendArgs& a, hipStream_t s) { return bwd_post(a, s); }
 
 hipError_t launch_blend_batched(bool forward, const BlendArgs& shape, const BatchQueue& q,

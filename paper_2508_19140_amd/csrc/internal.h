@@ -44,6 +44,7 @@ struct BlendArgs {
                       // grad_opacity, grad_uv and grad_z at the end (one 16-byte row per
                       // point for the atomics)
   const uint32_t* flags;
+  int prezeroed;  // host side only: grad_feat and gsc are already zero (no fill before the tiles)
 };
 
 // A batch's work queue for the batched blend kernels: per-view arguments
@@ -163,6 +164,9 @@ hipError_t launch_envmap_forward(const Cam& c, const float* dirs, const float* e
 hipError_t launch_envmap_backward(const Cam& c, const float* dirs, const float* grad_bg, int Hm,
                                   int Wm, int C, float* grad_env, hipStream_t s);
 hipError_t launch_blend_backward_pre(const BlendArgs& a, hipStream_t s);
+// The fill the backward blend starts with: grad_feat [n][C] and the scalar
+// rows [n][4] at the start of its scratch, to zero.
+hipError_t launch_backward_zero(float* grad_feat, int64_t n, int C, void* scratch, hipStream_t s);
 hipError_t launch_blend_backward_post(const BlendArgs& a, hipStream_t s);
 hipError_t launch_blend_batched(bool forward, const BlendArgs& shape, const BatchQueue& q,
                                 hipStream_t s);

@@ -83,7 +83,7 @@ def test_summarize_counters_means(tmp_path, capsys):
     b.summarize_counters(str(tmp_path), "cmd")
     out = capsys.readouterr().out
     assert "| `k_sort_wm` | sort | 20 |" in out
-    assert "| `k_zero` | blend_bwd | 5 |" in out
+    assert "| `k_zero` | backward_zero | 5 |" in out
     assert "not_ours" not in out
 
 
