@@ -656,7 +656,11 @@ def main():
         "B_method_frac_of_copy": b_method / t_s / 1e9 / copy_gbs,
         "ms_per_step_median": ms_median,
         "phase_ms": phase_ms,
-        "roofline": {"bound": "hbm", "kernel": f"inpc_{dominant}", "achieved": dom_gbs,
+        "roofline": {"bound": "hbm", "kernel": f"inpc_{dominant}",
+                     # name prefixes of the kernels that entry point launches; their
+                     # rocprofv3 per-kernel times are in profiles/kernels_<workload>.md
+                     "kernels": list(ENTRY_KERNELS.get(dominant, ())),
+                     "achieved": dom_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS,
                      "frac_of_copy": dom_gbs / copy_gbs,
                      "bytes_per_launch": dom_bytes, "ms_per_launch": per_launch_ms[dominant],
