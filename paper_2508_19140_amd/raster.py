@@ -17,7 +17,7 @@ from __future__ import annotations
 import ctypes
 import dataclasses
 import math
-from typing import NamedTuple, Optional, Sequence
+from typing import Callable, Dict, NamedTuple, Optional, Sequence
 
 import torch
 
@@ -155,10 +155,12 @@ class Binning(NamedTuple):
 
 def project_bin_sort(pos: torch.Tensor, opacity: torch.Tensor, cam: L.Camera, opts: L.Opts,
                      ws: torch.Tensor, radius: Optional[torch.Tensor] = None,
-                     ring_counts: Optional[Sequence[int]] = None) -> Binning:
+                     ring_counts: Optional[Sequence[int]] = None,
+                     before_sort: Optional[Callable[[], None]] = None) -> Binning:
     """Steps 1-3: project, bin into tiles, sort every tile by (depth, index).
     ring_counts: the points are a ring of len(ring_counts) equal slots whose
-    first ring_counts[s] points are live (inpc_project_ring)."""
+    first ring_counts[s] points are live (inpc_project_ring).
+    before_sort: called after the binning is issued and before the sort."""
     dev = pos.device
     n = pos.shape[0]
     lib = L.lib()
@@ -186,6 +188,8 @@ def project_bin_sort(pos: torch.Tensor, opacity: torch.Tensor, cam: L.Camera, op
                _p(proj), _p(key), _p(ntiles), _p(ws), wsb, s)
     L.call("inpc_bin", cb, ob, n, _p(proj), _p(key), _p(ntiles), _p(ranges), _p(order), _p(ws),
            wsb, s)
+    if before_sort is not None:
+        before_sort()
     L.call("inpc_sort", cb, ob, n, _p(proj), _p(ranges), _p(order), _p(lst), _p(lpos), _p(ws),
            wsb, s)
     return Binning(proj, key, ntiles, ranges, lst, order, lpos)
@@ -225,10 +229,13 @@ class BlendGrads(NamedTuple):
 
 def blend_backward(b: Binning, feat, cam: L.Camera, opts: L.Opts, ws: torch.Tensor, t_final,
                    state, grad_out, grad_t=None, bg=None, scratch=None,
-                   outputs=None) -> BlendGrads:
+                   outputs=None, prezeroed=False) -> BlendGrads:
     """Step 5.  Returns BlendGrads (grad_z only for world-space Gaussians).
     outputs: optional preallocated (grad_feat, grad_opacity, grad_uv); every element is
-    overwritten."""
+    overwritten.  prezeroed: grad_feat and scratch were zeroed by zero_backward_ahead,
+    ordered before this call (then both must be given)."""
+    if prezeroed and (outputs is None or scratch is None):
+        raise ValueError("prezeroed needs the zeroed outputs and scratch")
     dev = feat.device
     n, C = feat.shape
     if outputs is not None:
@@ -248,12 +255,36 @@ def blend_backward(b: Binning, feat, cam: L.Camera, opts: L.Opts, ws: torch.Tens
     if scratch is None:
         scratch = torch.empty(backward_scratch_bytes(n, C, cam, opts), dtype=torch.uint8,
                               device=dev)
-    L.call("inpc_blend_backward", ctypes.byref(cam), ctypes.byref(opts), n, _p(b.proj), _p(feat),
+    entry = "inpc_blend_backward_prezeroed" if prezeroed else "inpc_blend_backward"
+    L.call(entry, ctypes.byref(cam), ctypes.byref(opts), n, _p(b.proj), _p(feat),
            C, _DTYPES[feat.dtype], _p(bg), _p(b.ntiles), _p(b.ranges), _p(b.order), _p(b.list),
            _p(b.lpos), _p(t_final), _p(state), _p(grad_out), _p(grad_t), _p(grad_feat),
            _p(grad_opacity), _p(grad_uv), _p(grad_z), _p(grad_bg), _p(scratch), scratch.numel(),
            _p(ws), ws.numel(), _stream(dev))
     return BlendGrads(grad_feat, grad_opacity, grad_uv, grad_z, grad_bg)
+
+
+_zero_streams: Dict[str, torch.cuda.Stream] = {}
+
+
+def zero_backward_ahead(grad_feat: torch.Tensor, scratch: torch.Tensor) -> torch.cuda.Event:
+    """The backward blend's zero fill (inpc_backward_zero) on a side stream of
+    the device (default priority), forked off the current stream: it runs
+    beside whatever the current stream does next.  Returns the event the
+    current stream must wait on before blend_backward(..., prezeroed=True)."""
+    dev = grad_feat.device
+    cur = torch.cuda.current_stream(dev)
+    side = _zero_streams.get(str(dev))
+    if side is None:
+        side = _zero_streams[str(dev)] = torch.cuda.Stream(device=dev)
+    fork, join = torch.cuda.Event(), torch.cuda.Event()
+    fork.record(cur)
+    side.wait_event(fork)
+    n, C = grad_feat.shape
+    L.call("inpc_backward_zero", n, C, _p(grad_feat), _p(scratch), scratch.numel(),
+           ctypes.c_void_p(side.cuda_stream))
+    join.record(side)
+    return join
 
 
 def project_backward(pos, b: Binning, cam: L.Camera, grad_uv, grad_z=None):
@@ -328,14 +359,28 @@ class _RasterizeFn(torch.autograd.Function):
         radius = radius if ctx.settings.splat == "gaussian" else None
         cam, opts = ctx.cam, ctx.settings.opts(ctx.bg_image, ctx.cam)
         ws = ctx.workspace.get(pos.shape[0], cam, opts, pos.device)
+        n, C = feat.shape
+        dev = pos.device
+        outs = (torch.empty(n, C, dtype=torch.float32, device=dev),
+                torch.empty(n, dtype=torch.float32, device=dev),
+                torch.empty(n, 2, dtype=torch.float32, device=dev))
+        scratch = torch.empty(backward_scratch_bytes(n, C, cam, opts), dtype=torch.uint8,
+                              device=dev)
+        joined = []
+        # the zero fill runs beside the tile sort (bound by LDS and latency)
+        fork = lambda: joined.append(zero_backward_ahead(outs[0], scratch))
         if ctx.settings.keep_lists:
             b = Binning(*saved[7:])
+            fork()
         else:
-            b = project_bin_sort(pos, opacity, cam, opts, ws, radius, ctx.ring_counts)
+            b = project_bin_sort(pos, opacity, cam, opts, ws, radius, ctx.ring_counts,
+                                 before_sort=fork)
         g_out = g_out.contiguous() if g_out is not None else torch.zeros(
             feat.shape[1], cam.height, cam.width, device=pos.device)
         g_t = g_t.contiguous() if g_t is not None else None
-        gr = blend_backward(b, feat, cam, opts, ws, t_final, state, g_out, g_t, bg)
+        torch.cuda.current_stream(dev).wait_event(joined[0])
+        gr = blend_backward(b, feat, cam, opts, ws, t_final, state, g_out, g_t, bg,
+                            scratch=scratch, outputs=outs, prezeroed=True)
         gpos = project_backward(pos, b, cam, gr.uv, gr.z)
         gf = gr.feat if feat.dtype == torch.float32 else gr.feat.to(feat.dtype)
         # screen-space radii are inputs without a gradient (as in the paper's inference use)

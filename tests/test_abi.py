@@ -197,3 +197,26 @@ def test_project_ring_checks():
     # the workspace is checked for n = slots * slot_cap points
     small = lib.inpc_workspace_bytes(cap, ctypes.byref(c), ctypes.byref(o))
     assert call(4, cap, ok, small) == L.INPC_ERR_INVALID
+
+
+def test_backward_zero_and_prezeroed_reject_bad_arguments():
+    """inpc_backward_zero checks sizes and buffers before any launch;
+    inpc_blend_backward_prezeroed takes inpc_blend_backward's checks."""
+    lib = L.lib()
+    n, C, sb = 100, 4, 1792  # 16 bytes per point, rounded up to 256
+    bad = L.INPC_ERR_INVALID
+    assert lib.inpc_backward_zero(-1, C, FAKE, FAKE, sb, None) == bad
+    assert lib.inpc_backward_zero(n, 0, FAKE, FAKE, sb, None) == bad
+    assert lib.inpc_backward_zero(n, 33, FAKE, FAKE, sb, None) == bad
+    assert lib.inpc_backward_zero(n, C, None, FAKE, sb, None) == bad
+    assert lib.inpc_backward_zero(n, C, FAKE, None, sb, None) == bad
+    assert lib.inpc_backward_zero(n, C, ctypes.c_void_p(0x1004), FAKE, sb, None) == bad
+    assert lib.inpc_backward_zero(n, C, FAKE, FAKE, sb - 1, None) == bad
+    assert lib.inpc_backward_zero(0, C, None, None, 0, None) == L.INPC_OK
+    c, o = cam(), L.make_opts(tile=8)
+    wsb = lib.inpc_workspace_bytes(10, ctypes.byref(c), ctypes.byref(o))
+    need = lib.inpc_backward_scratch_bytes(10, C, ctypes.byref(c), ctypes.byref(o))
+    args = [ctypes.byref(c), ctypes.byref(o), 10, FAKE, FAKE, C, L.DTYPE_F32, None, FAKE,
+            FAKE, None, FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, FAKE, None, None]
+    assert lib.inpc_blend_backward_prezeroed(*args, FAKE, need - 1, FAKE, wsb, None) == bad
+    assert lib.inpc_blend_backward_prezeroed(*args, None, need, FAKE, wsb, None) == bad

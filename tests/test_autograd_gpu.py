@@ -12,6 +12,8 @@ centres, so only points whose sub-pixel offsets stay clear of the kinks by
 far more than the step are perturbed.  Every fragment is blended
 (t_min = 0), so the loss has no termination jumps.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -49,8 +51,13 @@ def _loss_and_grads(sc, bg, st, pos=None, opacity=None, feat=None, grads=True):
                          for k, t in (("pos", pos), ("opacity", op), ("feat", ft), ("bg", bgt))}
 
 
-def test_autograd_matches_oracle():
+@pytest.mark.parametrize("keep_lists", [False, True])
+def test_autograd_matches_oracle(keep_lists):
+    """Lists recomputed in the backward or kept from the forward; either way
+    the backward's zero fill runs on a side stream beside the sort (or
+    before the blend) and the blend waits for it."""
     sc, bg, st = _setup()
+    st = dataclasses.replace(st, keep_lists=keep_lists)
     _, g = _loss_and_grads(sc, bg, st)
     rr = oracle.render(sc.camera, sc.pos, sc.opacity, sc.feat, bg=bg, t_min=0.0,
                        grad_out=sc.grad, grad_t=sc.grad_t)
