@@ -29,12 +29,33 @@ pytestmark = [pytest.mark.gpu,
               pytest.mark.timeout(600)]
 
 import oracle  # noqa: E402
+import paper_2508_19140_amd as inpc  # noqa: E402
 from gpu_helpers import (  # noqa: E402
     assert_backward, assert_binning_exact, assert_close, assert_forward, run_gpu, run_oracle,
     settings_opts)
 
 
-def _bilinear_full(config, feat_dtype=torch.float32):
+def _pipeline_outputs(sc, feat_dtype):
+    """Two passes of the preallocated pipeline in the form bench.py times
+    (zero fill forked onto its own stream before the forward's sort), the
+    second over the first's gradients."""
+    t = lambda a: torch.from_numpy(a).to("cuda:0")
+    v = inpc.ViewInputs(pos=t(sc.pos), opacity=t(sc.opacity),
+                        feat=t(sc.feat).to(feat_dtype).contiguous(), camera=sc.camera,
+                        grad_out=t(sc.grad))
+    p = inpc.ViewPipeline(v, inpc.RasterSettings(tile=8), zero_ahead=True)
+    h = torch.cuda.current_stream().cuda_stream
+    for _ in range(2):
+        p.step(h)
+    torch.cuda.synchronize()
+    g = {k: x.cpu().numpy() for k, x in p.outputs().items()}
+    g["n_contrib"] = g["n_contrib"].view(np.uint32)
+    del p, v
+    torch.cuda.empty_cache()
+    return g
+
+
+def _bilinear_full(config, feat_dtype=torch.float32, pipeline=False):
     print(f"case {config}: generating the scene", flush=True)
     sc = make_scene(CONFIGS[config])
     st = settings_opts(tile=8)
@@ -49,10 +70,17 @@ def _bilinear_full(config, feat_dtype=torch.float32):
     assert_binning_exact(g, proj, tl)
     assert_forward(g, rr)
     assert_backward(g, rr, sc.grad)
+    if pipeline:
+        del g
+        g = _pipeline_outputs(sc, feat_dtype)
+        print(f"case {config}: pipeline (bench form) done", flush=True)
+        assert_forward(g, rr)
+        assert_backward(g, rr, sc.grad)
 
 
 def test_h_full_forward_backward():
-    _bilinear_full("H")
+    """H through the functional calls and through the pipeline bench.py times."""
+    _bilinear_full("H", pipeline=True)
 
 
 def test_c2_full_forward_backward():
