@@ -348,7 +348,10 @@ size_t inpc_backward_scratch_bytes(int64_t n, int32_t C, const inpc_camera_t* ca
                                    const inpc_opts_t* opts);
 
 /*
- * Step 6 -- project backward: dL/dX = G_u fx/Z, dL/dY = G_v fy/Z,
+ * Step 6 -- project backward (Sec. 2: the chain rule through the pinhole
+ * projection of step 1, so that the position gradients of App. A Eq. (2)
+ * reach the points; Sec. 3.2 for the depth term of world-space Gaussians):
+ * dL/dX = G_u fx/Z, dL/dY = G_v fy/Z,
  * dL/dZ = G_Z - (G_u fx X + G_v fy Y)/Z^2, dL/dp = R^T (dL/dX, dL/dY, dL/dZ);
  * zero for culled points (ntiles == 0).
  *   grad_uv [n][2] f32; grad_z [n] f32 (the blend's dL/dZ at fixed (u, v),
