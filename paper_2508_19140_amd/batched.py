@@ -71,12 +71,14 @@ class ViewPipeline:
     """All buffers and ABI calls of one view; nothing is allocated per call.
 
     zero_ahead: the backward's zero fill of the gradient rows runs on a
-    stream of its own, forked off the pass's stream just before the forward's
-    tile sort (so after everything issued before it, the previous pass's
+    stream of its own, forked off the pass's stream just before the tile
+    sorts (so after everything issued before them, the previous pass's
     backward included): the sort's kernels are bound by LDS and latency and
-    leave HBM mostly idle, so the fill's writes overlap with them.  The
-    backward blend waits for the fill.  The streams keep the default
-    priority."""
+    leave HBM mostly idle, so the fill's writes overlap with them.  With the
+    lists recomputed, the first half of the rows is zeroed beside the
+    forward's sort and the second half beside the backward's; with the lists
+    kept, all of them beside the forward's sort.  The backward blend waits
+    for the fill.  The streams keep the default priority."""
 
     def __init__(self, v: ViewInputs, settings: RasterSettings, zero_ahead: bool = False):
         dev = v.pos.device
@@ -123,7 +125,12 @@ class ViewPipeline:
         self.zero_ahead = bool(zero_ahead) and self.backward_enabled
         if self.zero_ahead:
             self.zstream = torch.cuda.Stream(device=dev)
-            self.ev_fork, self.ev_join = torch.cuda.Event(), torch.cuda.Event()
+            self.ev_fork = [torch.cuda.Event(), torch.cuda.Event()]
+            self.ev_join = torch.cuda.Event()
+            # rows [0, split) with the forward's sort, [split, n) with the
+            # backward's; a multiple of 16 rows keeps both parts' scratch
+            # rows on the library's 256-byte size granule
+            self.zero_split = (n if settings.keep_lists else (n // 2) // 16 * 16)
 
     def fill_record(self, r: "L.ViewRecord") -> None:
         """This view's camera, points and buffers as an inpc_view_t record."""
@@ -183,13 +190,24 @@ class ViewPipeline:
                    None if self.gauss else _p(self.lpos), _p(self.out), _p(self.tf),
                    _p(self.nc), _p(self.state), _p(ws), ws.numel(), s)
 
+    def _zero_rows(self, s, part):
+        """Part 0 or 1 of the backward's zero fill (rows [0, zero_split) or
+        [zero_split, n)), forked off stream s (zero_ahead)."""
+        lo, hi = (0, self.zero_split) if part == 0 else (self.zero_split, self.n)
+        ev = self.ev_fork[part]
+        ev.record(_external(s, self.v.pos.device))
+        self.zstream.wait_event(ev)
+        self._call("inpc_backward_zero", hi - lo, self.C,
+                   ctypes.c_void_p(self.gf.data_ptr() + lo * self.C * 4),
+                   ctypes.c_void_p(self.scratch.data_ptr() + lo * 16),
+                   self.scratch.numel() - lo * 16, self.zstream.cuda_stream)
+        self.ev_join.record(self.zstream)  # the later part follows the earlier on zstream
+
     def zero(self, s):
-        """The backward's zero fill, forked off stream s (zero_ahead)."""
-        self.ev_fork.record(_external(s, self.v.pos.device))
-        self.zstream.wait_event(self.ev_fork)
-        self._call("inpc_backward_zero", self.n, self.C, _p(self.gf), _p(self.scratch),
-                   self.scratch.numel(), self.zstream.cuda_stream)
-        self.ev_join.record(self.zstream)
+        self._zero_rows(s, 0)
+
+    def zero_rest(self, s):
+        self._zero_rows(s, 1)
 
     def blend_bwd(self, s):
         v, ws = self.v, self.ws
@@ -216,7 +234,9 @@ class ViewPipeline:
         ph += [("sort", self.sort), ("blend_fwd", self.blend_fwd)]
         if self.backward_enabled:
             if not self.settings.keep_lists:
-                ph += [("project", self.project), ("bin", self.bin), ("sort", self.sort)]
+                ph += [("project", self.project), ("bin", self.bin)]
+                ph += [("backward_zero", self.zero_rest)] if self.zero_ahead else []
+                ph += [("sort", self.sort)]
             ph += [("blend_bwd", self.blend_bwd), ("project_bwd", self.project_bwd)]
         return ph
 

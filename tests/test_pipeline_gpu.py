@@ -32,21 +32,28 @@ def _outputs(p):
     return g
 
 
-def _pipeline(sc, zero_ahead):
+def _pipeline(sc, zero_ahead, keep_lists=False):
     t = lambda a: torch.from_numpy(a).to(DEV)
     v = inpc.ViewInputs(pos=t(sc.pos), opacity=t(sc.opacity), feat=t(sc.feat),
                         camera=sc.camera, grad_out=t(sc.grad))
-    return inpc.ViewPipeline(v, inpc.RasterSettings(tile=8), zero_ahead=zero_ahead)
+    return inpc.ViewPipeline(v, inpc.RasterSettings(tile=8, keep_lists=keep_lists),
+                             zero_ahead=zero_ahead)
 
 
-def test_zero_ahead_passes_match_oracle():
+@pytest.mark.parametrize("keep_lists", [False, True])
+def test_zero_ahead_passes_match_oracle(keep_lists):
     """Three passes in a row with the gradient rows and the scratch poisoned
     (NaN) before each; every pass against the oracle, on the current stream
-    given as an int and as a ctypes handle."""
+    given as an int and as a ctypes handle.  Lists recomputed: the fill in
+    two halves, beside the forward's and the backward's sorts; lists kept:
+    all of it beside the forward's sort."""
     sc = make_scene(SPEC)
     _, _, rr = run_oracle(sc, settings_opts(tile=8))
-    p = _pipeline(sc, zero_ahead=True)
-    assert [nm for nm, _ in p.phases()][:4] == ["project", "bin", "backward_zero", "sort"]
+    p = _pipeline(sc, zero_ahead=True, keep_lists=keep_lists)
+    names = [nm for nm, _ in p.phases()]
+    assert names[:4] == ["project", "bin", "backward_zero", "sort"]
+    assert names.count("backward_zero") == (1 if keep_lists else 2)
+    assert p.zero_split == (SPEC.n if keep_lists else SPEC.n // 2)
     h = torch.cuda.current_stream().cuda_stream
     for rep, s in enumerate((h, ctypes.c_void_p(h), h)):
         print(f"  pass {rep}", flush=True)
