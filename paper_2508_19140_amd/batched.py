@@ -39,7 +39,7 @@ def _p(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def _external(s, device) -> torch.cuda.ExternalStream:
+def _external(s, device) -> torch.cuda.Stream:
     """A HIP stream handle (int or ctypes.c_void_p) as a torch stream."""
     h = int((s.value if isinstance(s, ctypes.c_void_p) else s) or 0)
     cur = torch.cuda.current_stream(device)
