@@ -78,7 +78,9 @@ class ViewPipeline:
     lists recomputed, the first half of the rows is zeroed beside the
     forward's sort and the second half beside the backward's; with the lists
     kept, all of them beside the forward's sort.  The backward blend waits
-    for the fill.  The streams keep the default priority."""
+    for the fill.  The streams keep the default priority.  For eager use
+    only: a zero_ahead pipeline refuses to run under graph capture (the
+    multi-view graph keeps its pipelines' fills inline)."""
 
     def __init__(self, v: ViewInputs, settings: RasterSettings, zero_ahead: bool = False):
         dev = v.pos.device
@@ -193,6 +195,9 @@ class ViewPipeline:
     def _zero_rows(self, s, part):
         """Part 0 or 1 of the backward's zero fill (rows [0, zero_split) or
         [zero_split, n)), forked off stream s (zero_ahead)."""
+        if torch.cuda.is_current_stream_capturing():
+            raise RuntimeError("a zero_ahead ViewPipeline cannot be captured into a graph; "
+                               "build it with zero_ahead=False")
         lo, hi = (0, self.zero_split) if part == 0 else (self.zero_split, self.n)
         ev = self.ev_fork[part]
         ev.record(_external(s, self.v.pos.device))

@@ -87,3 +87,18 @@ def test_zero_ahead_on_a_side_stream_matches_the_inline_fill():
     np.testing.assert_array_equal(ga["grad_feat"][single], gb["grad_feat"][single])
     for k in ("grad_feat", "grad_opacity", "grad_uv", "grad_pos"):
         np.testing.assert_allclose(ga[k], gb[k], rtol=1e-4, atol=1e-5)
+
+
+def test_zero_ahead_refuses_graph_capture(monkeypatch):
+    """The forked fill is for eager use: under stream capture it raises before
+    it records or launches anything (capture status forced from the host)."""
+    sc = make_scene(SceneSpec(n=4096, s=4.0, z_lo=2.0, z_hi=20.0, width=64, height=48,
+                              focal=64.0, channels=4, feat_dist="normal",
+                              opacity_range=(0.05, 0.95), with_grad=True, seed=2))
+    p = _pipeline(sc, zero_ahead=True)
+    monkeypatch.setattr(torch.cuda, "is_current_stream_capturing", lambda: True)
+    with pytest.raises(RuntimeError, match="cannot be captured"):
+        p.zero(torch.cuda.current_stream().cuda_stream)
+    monkeypatch.undo()
+    p.step(torch.cuda.current_stream().cuda_stream)  # eager use still works
+    torch.cuda.synchronize()
