@@ -367,20 +367,24 @@ class _RasterizeFn(torch.autograd.Function):
         scratch = torch.empty(backward_scratch_bytes(n, C, cam, opts), dtype=torch.uint8,
                               device=dev)
         joined = []
-        # the zero fill runs beside the tile sort (bound by LDS and latency)
-        fork = lambda: joined.append(zero_backward_ahead(outs[0], scratch))
+        # the zero fill runs beside the tile sort (bound by LDS and latency);
+        # under graph capture it stays inside the backward blend
+        ahead = not torch.cuda.is_current_stream_capturing()
+        fork = (lambda: joined.append(zero_backward_ahead(outs[0], scratch))) if ahead else None
         if ctx.settings.keep_lists:
             b = Binning(*saved[7:])
-            fork()
+            if fork is not None:
+                fork()
         else:
             b = project_bin_sort(pos, opacity, cam, opts, ws, radius, ctx.ring_counts,
                                  before_sort=fork)
         g_out = g_out.contiguous() if g_out is not None else torch.zeros(
             feat.shape[1], cam.height, cam.width, device=pos.device)
         g_t = g_t.contiguous() if g_t is not None else None
-        torch.cuda.current_stream(dev).wait_event(joined[0])
+        if joined:
+            torch.cuda.current_stream(dev).wait_event(joined[0])
         gr = blend_backward(b, feat, cam, opts, ws, t_final, state, g_out, g_t, bg,
-                            scratch=scratch, outputs=outs, prezeroed=True)
+                            scratch=scratch, outputs=outs, prezeroed=bool(joined))
         gpos = project_backward(pos, b, cam, gr.uv, gr.z)
         gf = gr.feat if feat.dtype == torch.float32 else gr.feat.to(feat.dtype)
         # screen-space radii are inputs without a gradient (as in the paper's inference use)
